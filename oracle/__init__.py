@@ -1,0 +1,239 @@
+"""Plain FP64 CPU oracle for the fast Monte Carlo (KLE + LHS) method.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library never imports, links or calls it, and it shares no code with the GPU
+path: the arithmetic lives in ``fmc_oracle.c`` (plain C, scalar loops, OpenMP
+over samples only), this module only marshals arguments.
+
+Parity unpinned: nothing.  Every function here is pinned by a CPU test against
+a value fixed by mathematics or by a library routine (see tests/test_oracle_*.py).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fmc_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no GPU code, no shared sources)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC",
+               "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Problem(C.Structure):
+    _fields_ = [
+        ("n_gen", C.c_int32), ("f0_hz", C.c_double),
+        ("H", C.c_void_p), ("D", C.c_void_p), ("E", C.c_void_p),
+        ("delta0", C.c_void_p), ("Pm", C.c_void_p),
+        ("Y_re", C.c_void_p), ("Y_im", C.c_void_p),
+        ("infinite_bus", C.c_int32), ("V_inf", C.c_double),
+        ("Yinf_re", C.c_void_p), ("Yinf_im", C.c_void_p),
+        ("n_proc", C.c_int32), ("dist_gen", C.c_void_p),
+        ("theta", C.c_void_p), ("sigma", C.c_void_p), ("xi0", C.c_void_p),
+        ("T", C.c_double), ("dt", C.c_double), ("K", C.c_int32), ("N", C.c_int64),
+        ("seed", C.c_uint64),
+        ("basis", C.c_int32), ("sampler", C.c_int32), ("integrator", C.c_int32),
+        ("ddof", C.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.orc_philox4x64_10.argtypes = [P, P, P]
+        L.orc_u01.argtypes = [C.c_uint64]
+        L.orc_u01.restype = C.c_double
+        L.orc_lhs_stratum.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64]
+        L.orc_lhs_stratum.restype = C.c_int64
+        L.orc_ppnd16.argtypes = [C.c_double]
+        L.orc_ppnd16.restype = C.c_double
+        L.orc_lhs.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_int64, P, P, P]
+        L.orc_basis.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_double, P]
+        L.orc_kron.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P, C.c_int32, P, P, P, P]
+        L.orc_run.argtypes = [C.POINTER(_Problem), P, C.c_int64, P, P, P, P, P, P, P, P]
+        L.orc_rhs.argtypes = [C.POINTER(_Problem), P, P, P]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    o = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(c.ctypes.data, k.ctypes.data, o.ctypes.data)
+    return o
+
+
+def u01(x: int) -> float:
+    return float(lib().orc_u01(int(x)))
+
+
+def stratum(seed: int, i: int, N: int, n: int) -> int:
+    return int(lib().orc_lhs_stratum(seed, i, N, n))
+
+
+def ppnd16(p):
+    p = np.atleast_1d(np.asarray(p, dtype=np.float64))
+    return np.array([lib().orc_ppnd16(float(x)) for x in p])
+
+
+def lhs(seed: int, M: int, N: int, sampler: int = 0, sel=None):
+    """Strata [M][n_sel] (int32, -1 for SRS) and zeta [M][n_sel] (FP64)."""
+    s = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    n_sel = N if s is None else len(s)
+    strata = np.zeros((M, n_sel), dtype=np.int32)
+    zeta = np.zeros((M, n_sel), dtype=np.float64)
+    rc = lib().orc_lhs(seed, M, N, sampler, n_sel, _p(s), strata.ctypes.data, zeta.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_lhs failed: {rc}")
+    return strata, zeta
+
+
+def basis(kind: int, K: int, S: int, T: float):
+    Phi = np.zeros((K, 2 * S + 1), dtype=np.float64)
+    rc = lib().orc_basis(kind, K, S, T, Phi.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_basis failed: {rc}")
+    return Phi
+
+
+def kron(net: dict):
+    """Kron-reduced admittance (complex n_gen x n_gen) of a network dict."""
+    ng = int(net["n_gen"])
+    fr, to = _i32(net["br_from"]), _i32(net["br_to"])
+    r, x = _f64(net["br_r"]), _f64(net["br_x"])
+    b = _f64(net.get("br_b"))
+    lg, lb = _f64(net.get("load_g")), _f64(net.get("load_b"))
+    gb, xd = _i32(net["gen_bus"]), _f64(net["gen_xdp"])
+    Yr = np.zeros((ng, ng)); Yi = np.zeros((ng, ng))
+    rc = lib().orc_kron(int(net["n_bus"]), len(fr), _p(fr), _p(to), _p(r), _p(x), _p(b),
+                        _p(lg), _p(lb), ng, _p(gb), _p(xd), Yr.ctypes.data, Yi.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_kron failed: {rc}")
+    return Yr + 1j * Yi
+
+
+_SAMPLER = {"lhs": 0, "srs": 1}
+_BASIS = {"paper": 0, "eigen": 1}
+_INTEG = {"rk4": 0, "trap": 1}
+
+
+def _enum(v, table):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+class _Keep:
+    """Holds the numpy arrays referenced by a _Problem."""
+
+
+def problem(sc: dict):
+    """Build the C problem struct from a scenario dict (see workloads)."""
+    keep = _Keep()
+    n = int(sc["n_gen"])
+    Y = sc.get("Y")
+    if Y is None:
+        Y = kron(sc["net"])
+    Y = np.asarray(Y, dtype=np.complex128).reshape(n, n)
+    keep.Yr, keep.Yi = _f64(Y.real), _f64(Y.imag)
+    keep.H, keep.D, keep.E = _f64(sc["H"]), _f64(sc["D"]), _f64(sc["E"])
+    keep.d0 = _f64(sc.get("delta0"))
+    keep.Pm = _f64(sc.get("Pm"))
+    inf = bool(sc.get("infinite_bus", False))
+    if inf:
+        Yinf = np.asarray(sc["Yinf"], dtype=np.complex128).reshape(n)
+        keep.Yir, keep.Yii = _f64(Yinf.real), _f64(Yinf.imag)
+    else:
+        keep.Yir = keep.Yii = None
+    d = sc["dist"]
+    keep.dg = _i32(d["gen"])
+    keep.th, keep.sg = _f64(d["theta"]), _f64(d["sigma"])
+    keep.x0 = _f64(d.get("xi0"))
+    pb = _Problem(
+        n_gen=n, f0_hz=float(sc.get("f0", 60.0)),
+        H=_p(keep.H), D=_p(keep.D), E=_p(keep.E), delta0=_p(keep.d0), Pm=_p(keep.Pm),
+        Y_re=_p(keep.Yr), Y_im=_p(keep.Yi), infinite_bus=int(inf),
+        V_inf=float(sc.get("V_inf", 1.0)), Yinf_re=_p(keep.Yir), Yinf_im=_p(keep.Yii),
+        n_proc=len(keep.dg), dist_gen=_p(keep.dg), theta=_p(keep.th), sigma=_p(keep.sg),
+        xi0=_p(keep.x0), T=float(sc["T"]), dt=float(sc["dt"]), K=int(sc["K"]),
+        N=int(sc["N"]), seed=int(sc.get("seed", 0)),
+        basis=_enum(sc.get("basis", 0), _BASIS), sampler=_enum(sc.get("sampler", 0), _SAMPLER),
+        integrator=_enum(sc.get("integrator", 0), _INTEG), ddof=int(sc.get("ddof", 1)))
+    return pb, keep
+
+
+def steps(sc: dict) -> int:
+    return int(round(float(sc["T"]) / float(sc["dt"])))
+
+
+def run(sc: dict, zeta=None, sel=None, want_traj=False, allow_nonfinite=False):
+    """Run the method on a scenario.
+
+    Returns dict(mean, var [(S+1), V], traj [n_sel, S+1, V] or None, Pm, delta0,
+    nonfinite).  ``zeta`` ([M][n_sel]) replaces the LHS step; ``sel`` picks the
+    samples of the N-sample design to run (statistics are over them).
+    """
+    pb, keep = problem(sc)
+    n = pb.n_gen
+    S = steps(sc)
+    V = 2 * n + pb.n_proc
+    s = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    n_sel = pb.N if s is None else len(s)
+    z = None if zeta is None else np.ascontiguousarray(zeta, dtype=np.float64)
+    if z is not None:
+        assert z.shape == (pb.n_proc * pb.K, n_sel), z.shape
+    mean = np.zeros((S + 1, V)); var = np.zeros((S + 1, V))
+    traj = np.zeros((n_sel, S + 1, V)) if want_traj else None
+    nf = C.c_int64(0); nc = C.c_int64(0)
+    pm = np.zeros(n); d0 = np.zeros(n)
+    rc = lib().orc_run(C.byref(pb), _p(z), n_sel, _p(s), mean.ctypes.data, var.ctypes.data,
+                       _p(traj), C.addressof(nf), C.addressof(nc), pm.ctypes.data, d0.ctypes.data)
+    if rc not in (0, -5) or (rc == -5 and not allow_nonfinite):
+        raise RuntimeError(f"orc_run failed: {rc} (nonfinite={nf.value}, notconv={nc.value})")
+    return dict(mean=mean, var=var, traj=traj, Pm=pm, delta0=d0, nonfinite=nf.value)
+
+
+def rhs(sc: dict, y, w):
+    pb, keep = problem(sc)
+    y = _f64(y); w = _f64(w)
+    dy = np.zeros_like(y)
+    rc = lib().orc_rhs(C.byref(pb), y.ctypes.data, _p(w) if len(w) else None, dy.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_rhs failed: {rc}")
+    return dy

@@ -1,0 +1,737 @@
+/*
+ * fmc_oracle.c -- plain, slow, FP64 CPU oracle for the fast Monte Carlo method
+ * (Karhunen-Loeve expansion + Latin hypercube sampling) of Qiu, Lin, Chen, Liu
+ * and Song, "Fast Monte Carlo Simulation of Dynamic Power Systems Under
+ * Continuous Random Disturbances" (arXiv 2007.03847).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no source with the GPU path.
+ *
+ * Everything is FP64, scalar loops, one sample at a time (OpenMP over samples
+ * only).  Each function names the passage of the paper it follows.  Where the
+ * paper is silent the reading taken is stated at the function.
+ *
+ * Pins (checked by the CPU tests against values fixed by mathematics or a
+ * library routine, never against this file):
+ *   philox         -> numpy.random.Philox (Philox-4x64-10)
+ *   ppnd16         -> scipy.special.ndtri
+ *   lhs            -> one sample per stratum, stratum bounds, bijection
+ *   basis          -> orthonormality, Var W_K(t) closed form, eigen-KLE (Nystrom)
+ *   run (OU part)  -> OU closed-form mean/variance of the truncated KLE
+ *   run (swing)    -> SMIB linearised variance (Lyapunov / Van Loan), RK4 order
+ *   kron           -> SMIB reduction to E V sin(delta)/X, symmetry, full solve
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+#define ORC_ENONFINITE -5
+#define ORC_ENOTCONV -6
+
+/* ------------------------------------------------------------------------- */
+/* Philox-4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as  */
+/* easy as 1, 2, 3", SC'11): counter-based; ten rounds of a multiply-xor      */
+/* S-box with a Weyl-sequence key schedule.                                  */
+/* ------------------------------------------------------------------------- */
+static void mul_hi_lo(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo)
+{
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) { k0 += W0; k1 += W1; }
+        uint64_t h0, l0, h1, l1;
+        mul_hi_lo(M0, x0, &h0, &l0);
+        mul_hi_lo(M1, x2, &h1, &l1);
+        uint64_t y0 = h1 ^ x1 ^ k0;
+        uint64_t y1 = l1;
+        uint64_t y2 = h0 ^ x3 ^ k1;
+        uint64_t y3 = l0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Counter tags that keep the draws of the method apart. */
+#define TAG_PERM   1ULL
+#define TAG_JITTER 2ULL
+#define TAG_SRS    3ULL
+
+static uint64_t draw(uint64_t seed, uint64_t a, uint64_t b, uint64_t c, uint64_t tag)
+{
+    uint64_t ctr[4] = {a, b, c, tag}, key[2] = {seed, 0}, o[4];
+    orc_philox4x64_10(ctr, key, o);
+    return o[0];
+}
+
+/* Uniform strictly inside (0,1): top 52 bits, centred.  Every step is exact. */
+double orc_u01(uint64_t x)
+{
+    return ((double)(x >> 12) + 0.5) * 0x1.0p-52;
+}
+
+/* ------------------------------------------------------------------------- */
+/* LHS Step 2 (Sec. IV-B): a random permutation of the N strata of each row.  */
+/* The paper leaves the permutation algorithm open; the reading taken is a    */
+/* counter-based bijection: an 8-round balanced Feistel network on 2h bits,   */
+/* h = ceil(ceil(log2 N)/2) (at least 1), round function = low h bits of one  */
+/* Philox draw keyed on (row i, round r, right half R), restricted to [0,N)   */
+/* by cycle-walking.                                                          */
+/* ------------------------------------------------------------------------- */
+static int feistel_half_bits(int64_t N)
+{
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << b) < N) ++b;
+    int h = (b + 1) / 2;
+    return h < 1 ? 1 : h;
+}
+
+int64_t orc_lhs_stratum(uint64_t seed, int64_t i, int64_t N, int64_t n)
+{
+    const int h = feistel_half_bits(N);
+    const uint64_t mask = (1ULL << h) - 1ULL;
+    uint64_t x = (uint64_t)n;
+    do {
+        uint64_t L = x >> h, R = x & mask;
+        for (int r = 0; r < 8; ++r) {
+            uint64_t f = draw(seed, (uint64_t)i, (uint64_t)r, R, TAG_PERM) & mask;
+            uint64_t newL = R;
+            uint64_t newR = L ^ f;
+            L = newL;
+            R = newR;
+        }
+        x = (L << h) | R;
+    } while (x >= (uint64_t)N);
+    return (int64_t)x;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Inverse of the standard normal CDF: Wichura, Algorithm AS 241 (PPND16),    */
+/* Applied Statistics 37(3), 1988.  Rational approximations in three ranges;  */
+/* about 1e-16 relative accuracy.                                             */
+/* ------------------------------------------------------------------------- */
+static double ratio8(const double *num, const double *den, double r)
+{
+    double a = num[7], b = den[7];
+    for (int k = 6; k >= 0; --k) {
+        a = a * r + num[k];
+        b = b * r + den[k];
+    }
+    return a / b;
+}
+
+double orc_ppnd16(double p)
+{
+    static const double A[8] = {
+        3.3871328727963666080e0, 1.3314166789178437745e+2, 1.9715909503065514427e+3,
+        1.3731693765509461125e+4, 4.5921953931549871457e+4, 6.7265770927008700853e+4,
+        3.3430575583588128105e+4, 2.5090809287301226727e+3};
+    static const double B[8] = {
+        1.0, 4.2313330701600911252e+1, 6.8718700749205790830e+2,
+        5.3941960214247511077e+3, 2.1213794301586595867e+4, 3.9307895800092710610e+4,
+        2.8729085735721942674e+4, 5.2264952788528545610e+3};
+    static const double C[8] = {
+        1.42343711074968357734e0, 4.63033784615654529590e0, 5.76949722146069140550e0,
+        3.64784832476320460504e0, 1.27045825245236838258e0, 2.41780725177450611770e-1,
+        2.27238449892691845833e-2, 7.74545014278341407640e-4};
+    static const double D[8] = {
+        1.0, 2.05319162663775882187e0, 1.67638483018380384940e0,
+        6.89767334985100004550e-1, 1.48103976427480074590e-1, 1.51986665636164571966e-2,
+        5.47593808499534494600e-4, 1.05075007164441684324e-9};
+    static const double E[8] = {
+        6.65790464350110377720e0, 5.46378491116411436990e0, 1.78482653991729133580e0,
+        2.96560571828504891230e-1, 2.65321895265761230930e-2, 1.24266094738807843860e-3,
+        2.71155556874348757815e-5, 2.01033439929228813265e-7};
+    static const double F[8] = {
+        1.0, 5.99832206555887937690e-1, 1.36929880922735805310e-1,
+        1.48753612908506148525e-2, 7.86869131145613259100e-4, 1.84631831751005468180e-5,
+        1.42151175831644588870e-7, 2.04426310338993978564e-15};
+
+    if (!(p > 0.0 && p < 1.0)) {
+        if (p == 0.0) return -INFINITY;
+        if (p == 1.0) return INFINITY;
+        return NAN;
+    }
+    double q = p - 0.5;
+    if (fabs(q) <= 0.425) {
+        double r = 0.180625 - q * q;
+        return q * ratio8(A, B, r);
+    }
+    double r = q < 0.0 ? p : 1.0 - p;
+    r = sqrt(-log(r));
+    double val;
+    if (r <= 5.0) {
+        val = ratio8(C, D, r - 1.6);
+    } else {
+        val = ratio8(E, F, r - 5.0);
+    }
+    return q < 0.0 ? -val : val;
+}
+
+/* ------------------------------------------------------------------------- */
+/* LHS Step 1 + Step 2 (Sec. IV-B; Alg. 1 step 1).  Row i of the M x N        */
+/* sampling matrix is coefficient zeta_i (i = p*K + j, the reindexing of      */
+/* Sec. IV-A); column n is sample n.  The N equiprobable CDF strata are        */
+/* permuted, one uniform is drawn inside the chosen stratum, and the inverse  */
+/* normal CDF maps it to zeta.  With sampler = 1 (simple random sampling)     */
+/* the uniform is drawn on (0,1) and strata are reported as -1.               */
+/* Only the columns listed in sel (all N if sel is NULL) are produced; the    */
+/* output is [M][n_sel].                                                      */
+/* ------------------------------------------------------------------------- */
+static double lhs_p(int64_t s, double U, int64_t N)
+{
+    double p = ((double)s + U) / (double)N;
+    if (p >= 1.0) p = 0x1.fffffffffffffp-1; /* keep the top stratum finite */
+    return p;
+}
+
+int orc_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int64_t n_sel,
+            const int64_t *sel, int32_t *strata, double *zeta)
+{
+    if (M < 1 || N < 1) return ORC_EINVAL;
+    if (!sel) n_sel = N;
+    for (int64_t c = 0; c < n_sel; ++c) {
+        int64_t n = sel ? sel[c] : c;
+        if (n < 0 || n >= N) return ORC_EINVAL;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < n_sel; ++c) {
+        int64_t n = sel ? sel[c] : c;
+        for (int32_t i = 0; i < M; ++i) {
+            double z;
+            int32_t st;
+            if (sampler == 0) {
+                int64_t s = orc_lhs_stratum(seed, i, N, n);
+                double U = orc_u01(draw(seed, (uint64_t)i, (uint64_t)n, 0, TAG_JITTER));
+                z = orc_ppnd16(lhs_p(s, U, N));
+                st = (int32_t)s;
+            } else {
+                double U = orc_u01(draw(seed, (uint64_t)i, (uint64_t)n, 0, TAG_SRS));
+                z = orc_ppnd16(U);
+                st = -1;
+            }
+            if (strata) strata[(int64_t)i * n_sel + c] = st;
+            if (zeta) zeta[(int64_t)i * n_sel + c] = z;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* KLE basis (Sec. IV-A, eq. 7) sampled on the half-step grid t_c = c*dt/2,   */
+/* c = 0..2S (the RK4 stage times; the paper does not fix a grid).            */
+/* kind 0: the paper's functions m_1 = sqrt(1/T), m_j = sqrt(2/T) cos((j-1)   */
+/*         pi t / T) for j >= 2.                                              */
+/* kind 1: the eigenfunctions of the Wiener covariance min(s,t), whose        */
+/*         derivatives are sqrt(2/T) cos((j-1/2) pi t / T).                   */
+/* The cosine argument is reduced exactly in integers before the call.        */
+/* Output Phi[j][c], j = 0..K-1 (row j is the paper's m_{j+1}).               */
+/* ------------------------------------------------------------------------- */
+int orc_basis(int32_t kind, int32_t K, int64_t S, double T, double *Phi)
+{
+    if (K < 1 || S < 1 || !(T > 0.0)) return ORC_EINVAL;
+    const int64_t C = 2 * S + 1;
+    const double a1 = sqrt(1.0 / T), a2 = sqrt(2.0 / T);
+    for (int32_t j = 0; j < K; ++j) {
+        for (int64_t c = 0; c < C; ++c) {
+            double v;
+            if (kind == 0) {
+                if (j == 0) {
+                    v = a1;
+                } else {
+                    int64_t q = ((int64_t)j * c) % (4 * S);
+                    v = a2 * cos(M_PI * (double)q / (double)(2 * S));
+                }
+            } else {
+                int64_t q = ((int64_t)(2 * j + 1) * c) % (8 * S);
+                v = a2 * cos(M_PI * (double)q / (double)(4 * S));
+            }
+            Phi[(int64_t)j * C + c] = v;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Dense linear algebra: Gaussian elimination with partial pivoting.          */
+/* ------------------------------------------------------------------------- */
+/* Solve A X = B in place: A is n x n, B is n x m (row-major). */
+static int csolve(int n, int m, double complex *A, double complex *B)
+{
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        double best = cabs(A[(int64_t)k * n + k]);
+        for (int r = k + 1; r < n; ++r) {
+            double v = cabs(A[(int64_t)r * n + k]);
+            if (v > best) { best = v; piv = r; }
+        }
+        if (best == 0.0) return ORC_EINVAL;
+        if (piv != k) {
+            for (int c = 0; c < n; ++c) {
+                double complex t = A[(int64_t)k * n + c];
+                A[(int64_t)k * n + c] = A[(int64_t)piv * n + c];
+                A[(int64_t)piv * n + c] = t;
+            }
+            for (int c = 0; c < m; ++c) {
+                double complex t = B[(int64_t)k * m + c];
+                B[(int64_t)k * m + c] = B[(int64_t)piv * m + c];
+                B[(int64_t)piv * m + c] = t;
+            }
+        }
+        for (int r = k + 1; r < n; ++r) {
+            double complex f = A[(int64_t)r * n + k] / A[(int64_t)k * n + k];
+            if (f == 0.0) continue;
+            for (int c = k; c < n; ++c) A[(int64_t)r * n + c] -= f * A[(int64_t)k * n + c];
+            for (int c = 0; c < m; ++c) B[(int64_t)r * m + c] -= f * B[(int64_t)k * m + c];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        for (int c = 0; c < m; ++c) {
+            double complex acc = B[(int64_t)k * m + c];
+            for (int j = k + 1; j < n; ++j) acc -= A[(int64_t)k * n + j] * B[(int64_t)j * m + c];
+            B[(int64_t)k * m + c] = acc / A[(int64_t)k * n + k];
+        }
+    }
+    return ORC_OK;
+}
+
+static int rsolve(int n, double *A, double *b)
+{
+    for (int k = 0; k < n; ++k) {
+        int piv = k;
+        double best = fabs(A[k * n + k]);
+        for (int r = k + 1; r < n; ++r) {
+            double v = fabs(A[r * n + k]);
+            if (v > best) { best = v; piv = r; }
+        }
+        if (best == 0.0) return ORC_EINVAL;
+        if (piv != k) {
+            for (int c = 0; c < n; ++c) {
+                double t = A[k * n + c]; A[k * n + c] = A[piv * n + c]; A[piv * n + c] = t;
+            }
+            double t = b[k]; b[k] = b[piv]; b[piv] = t;
+        }
+        for (int r = k + 1; r < n; ++r) {
+            double f = A[r * n + k] / A[k * n + k];
+            for (int c = k; c < n; ++c) A[r * n + c] -= f * A[k * n + c];
+            b[r] -= f * b[k];
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        double acc = b[k];
+        for (int j = k + 1; j < n; ++j) acc -= A[k * n + j] * b[j];
+        b[k] = acc / A[k * n + k];
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Network reduction.  The algebraic equations (eq. 2) of a constant-         */
+/* impedance network are linear in the bus voltages, so they are eliminated   */
+/* exactly: nodes are the n_gen generator internal EMFs (behind jX'd) and the */
+/* n_bus buses; Y_red = Y_AA - Y_AB Y_BB^{-1} Y_BA.  Branch k contributes      */
+/* 1/(r+jx) in series plus jb/2 at each end; loads are shunts g + jb.         */
+/* ------------------------------------------------------------------------- */
+int orc_kron(int32_t n_bus, int32_t n_br, const int32_t *from, const int32_t *to,
+             const double *br_r, const double *br_x, const double *br_b,
+             const double *load_g, const double *load_b, int32_t n_gen,
+             const int32_t *gen_bus, const double *gen_xdp, double *Y_re, double *Y_im)
+{
+    if (n_bus < 1 || n_gen < 1 || n_br < 0) return ORC_EINVAL;
+    const int nb = n_bus, ng = n_gen;
+    double complex *Ybb = calloc((size_t)nb * nb, sizeof(double complex));
+    double complex *Yba = calloc((size_t)nb * ng, sizeof(double complex));
+    if (!Ybb || !Yba) { free(Ybb); free(Yba); return ORC_ENOMEM; }
+    for (int k = 0; k < n_br; ++k) {
+        int f = from[k], t = to[k];
+        if (f < 0 || f >= nb || t < 0 || t >= nb || f == t) { free(Ybb); free(Yba); return ORC_EINVAL; }
+        double complex y = 1.0 / (br_r[k] + I * br_x[k]);
+        double complex sh = br_b ? I * br_b[k] / 2.0 : 0.0;
+        Ybb[(int64_t)f * nb + f] += y + sh;
+        Ybb[(int64_t)t * nb + t] += y + sh;
+        Ybb[(int64_t)f * nb + t] -= y;
+        Ybb[(int64_t)t * nb + f] -= y;
+    }
+    for (int b = 0; b < nb; ++b)
+        Ybb[(int64_t)b * nb + b] += (load_g ? load_g[b] : 0.0) + I * (load_b ? load_b[b] : 0.0);
+    for (int g = 0; g < ng; ++g) {
+        int b = gen_bus[g];
+        if (b < 0 || b >= nb || !(gen_xdp[g] > 0.0)) { free(Ybb); free(Yba); return ORC_EINVAL; }
+        double complex yg = 1.0 / (I * gen_xdp[g]);
+        Ybb[(int64_t)b * nb + b] += yg;
+        Yba[(int64_t)b * ng + g] -= yg; /* Y_BA[b][g] = -yg */
+    }
+    int rc = csolve(nb, ng, Ybb, Yba); /* Yba <- Y_BB^{-1} Y_BA */
+    if (rc == ORC_OK) {
+        for (int i = 0; i < ng; ++i)
+            for (int k = 0; k < ng; ++k) {
+                double complex v = (i == k) ? 1.0 / (I * gen_xdp[i]) : 0.0; /* Y_AA */
+                /* Y_AB[i][b] = -yg_i at b = gen_bus[i] */
+                double complex yg = 1.0 / (I * gen_xdp[i]);
+                v -= (-yg) * Yba[(int64_t)gen_bus[i] * ng + k];
+                Y_re[i * ng + k] = creal(v);
+                Y_im[i * ng + k] = cimag(v);
+            }
+    }
+    free(Ybb);
+    free(Yba);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The problem: classical multimachine model (eqs. 1-2 instantiated as the    */
+/* swing equations on the Kron-reduced network) driven by Ornstein-Uhlenbeck  */
+/* disturbances (eq. 4 with mu = -theta xi, constant sigma; the Gaussian row  */
+/* of Table I), whose Wiener drivers are replaced by the truncated KLE        */
+/* (eqs. 8-9).                                                                */
+/* ------------------------------------------------------------------------- */
+typedef struct orc_problem {
+    int32_t n_gen;
+    double f0_hz;
+    const double *H, *D, *E, *delta0, *Pm; /* [n]; delta0 NULL -> solve; Pm NULL -> equilibrium */
+    const double *Y_re, *Y_im;             /* [n*n] reduced admittance */
+    int32_t infinite_bus;
+    double V_inf;
+    const double *Yinf_re, *Yinf_im; /* [n] coupling to the infinite bus */
+    int32_t n_proc;
+    const int32_t *dist_gen;
+    const double *theta, *sigma, *xi0;
+    double T, dt;
+    int32_t K;
+    int64_t N;
+    uint64_t seed;
+    int32_t basis, sampler, integrator, ddof;
+} orc_problem;
+
+typedef struct {
+    int n, P, V, ny;
+    double wb;
+    double *H, *D, *E, *d0, *Pm;
+    double complex *Y, *Yinf;
+    int inf;
+    double Vinf;
+    const int32_t *dgen;
+    const double *theta, *sigma, *xi0;
+} model_t;
+
+/* Electrical power of every machine: Pe_i = Re{ E~_i conj(I_i) },
+ * I = Y E~ (+ Yinf V_inf), E~_k = E_k exp(j delta_k). */
+static void electrical_power(const model_t *m, const double *delta, double *Pe)
+{
+    const int n = m->n;
+    double complex Et[512];
+    for (int k = 0; k < n; ++k) Et[k] = m->E[k] * cexp(I * delta[k]);
+    for (int i = 0; i < n; ++i) {
+        double complex cur = m->inf ? m->Yinf[i] * m->Vinf : 0.0;
+        for (int k = 0; k < n; ++k) cur += m->Y[(int64_t)i * n + k] * Et[k];
+        Pe[i] = creal(Et[i] * conj(cur));
+    }
+}
+
+/* d Pe_i / d delta_k (dense n x n). */
+static void electrical_power_jac(const model_t *m, const double *delta, double *J)
+{
+    const int n = m->n;
+    double complex Et[512];
+    for (int k = 0; k < n; ++k) Et[k] = m->E[k] * cexp(I * delta[k]);
+    for (int i = 0; i < n; ++i) {
+        double complex cur = m->inf ? m->Yinf[i] * m->Vinf : 0.0;
+        for (int k = 0; k < n; ++k) cur += m->Y[(int64_t)i * n + k] * Et[k];
+        for (int k = 0; k < n; ++k) {
+            double v = creal(Et[i] * conj(m->Y[(int64_t)i * n + k] * I * Et[k]));
+            if (k == i) v += creal(I * Et[i] * conj(cur));
+            J[i * n + k] = v;
+        }
+    }
+}
+
+/* Right-hand side. State y = (delta_1..n [rad, absolute], dw_1..n [pu],
+ * xi_1..P); w[p] is the KLE white-noise surrogate of eq. 8 at this time. */
+static void rhs(const model_t *m, const double *y, const double *w, double *dy)
+{
+    const int n = m->n, P = m->P;
+    double Pe[512];
+    electrical_power(m, y, Pe);
+    for (int i = 0; i < n; ++i) {
+        double pm = m->Pm[i];
+        for (int p = 0; p < P; ++p)
+            if (m->dgen[p] == i) pm += y[2 * n + p];
+        dy[i] = m->wb * y[n + i];
+        dy[n + i] = (pm - Pe[i] - m->D[i] * y[n + i]) / (2.0 * m->H[i]);
+    }
+    for (int p = 0; p < P; ++p)
+        dy[2 * n + p] = -m->theta[p] * y[2 * n + p] + m->sigma[p] * w[p];
+}
+
+static void rhs_jac(const model_t *m, const double *y, double *J)
+{
+    const int n = m->n, P = m->P, ny = m->ny;
+    double Jp[512 * 8];
+    double *JP = (n * n <= 512 * 8) ? Jp : malloc(sizeof(double) * n * n);
+    memset(J, 0, sizeof(double) * ny * ny);
+    electrical_power_jac(m, y, JP);
+    for (int i = 0; i < n; ++i) {
+        J[i * ny + n + i] = m->wb;
+        for (int k = 0; k < n; ++k) J[(n + i) * ny + k] = -JP[i * n + k] / (2.0 * m->H[i]);
+        J[(n + i) * ny + n + i] = -m->D[i] / (2.0 * m->H[i]);
+        for (int p = 0; p < P; ++p)
+            if (m->dgen[p] == i) J[(n + i) * ny + 2 * n + p] += 1.0 / (2.0 * m->H[i]);
+    }
+    for (int p = 0; p < P; ++p) J[(2 * n + p) * ny + 2 * n + p] = -m->theta[p];
+    if (JP != Jp) free(JP);
+}
+
+/* Operating point.  With delta0 given, Pm_i := Pe_i(delta0) (equilibrium by
+ * construction).  Without it (infinite-bus systems), delta0 solves
+ * Pe(delta) = Pm by Newton's method from delta = 0. */
+static int setup_model(const orc_problem *pb, model_t *m)
+{
+    const int n = pb->n_gen, P = pb->n_proc;
+    if (n < 1 || n > 512 || P < 0) return ORC_EINVAL;
+    memset(m, 0, sizeof(*m));
+    m->n = n; m->P = P; m->V = 2 * n + P; m->ny = 2 * n + P;
+    m->wb = 2.0 * M_PI * pb->f0_hz;
+    m->H = malloc(sizeof(double) * n); m->D = malloc(sizeof(double) * n);
+    m->E = malloc(sizeof(double) * n); m->d0 = malloc(sizeof(double) * n);
+    m->Pm = malloc(sizeof(double) * n);
+    m->Y = malloc(sizeof(double complex) * n * n);
+    m->Yinf = malloc(sizeof(double complex) * n);
+    for (int i = 0; i < n; ++i) {
+        m->H[i] = pb->H[i]; m->D[i] = pb->D[i]; m->E[i] = pb->E[i];
+        if (!(pb->H[i] > 0.0)) return ORC_EINVAL;
+        m->Yinf[i] = pb->infinite_bus ? pb->Yinf_re[i] + I * pb->Yinf_im[i] : 0.0;
+    }
+    for (int k = 0; k < n * n; ++k) m->Y[k] = pb->Y_re[k] + I * pb->Y_im[k];
+    m->inf = pb->infinite_bus;
+    m->Vinf = pb->V_inf;
+    m->dgen = pb->dist_gen; m->theta = pb->theta; m->sigma = pb->sigma; m->xi0 = pb->xi0;
+    for (int p = 0; p < P; ++p) {
+        if (pb->dist_gen[p] < 0 || pb->dist_gen[p] >= n) return ORC_EINVAL;
+        if (pb->theta[p] < 0.0 || pb->sigma[p] < 0.0) return ORC_EINVAL;
+    }
+    if (pb->delta0) {
+        for (int i = 0; i < n; ++i) m->d0[i] = pb->delta0[i];
+        if (pb->Pm) {
+            for (int i = 0; i < n; ++i) m->Pm[i] = pb->Pm[i];
+        } else {
+            electrical_power(m, m->d0, m->Pm);
+        }
+    } else {
+        if (!pb->Pm || !pb->infinite_bus) return ORC_EINVAL;
+        for (int i = 0; i < n; ++i) { m->Pm[i] = pb->Pm[i]; m->d0[i] = 0.0; }
+        double *J = malloc(sizeof(double) * n * n), *r = malloc(sizeof(double) * n);
+        double Pe[512];
+        int ok = 0;
+        for (int it = 0; it < 100; ++it) {
+            electrical_power(m, m->d0, Pe);
+            electrical_power_jac(m, m->d0, J);
+            double nrm = 0.0;
+            for (int i = 0; i < n; ++i) r[i] = m->Pm[i] - Pe[i];
+            if (rsolve(n, J, r) != ORC_OK) break;
+            for (int i = 0; i < n; ++i) { m->d0[i] += r[i]; nrm = fmax(nrm, fabs(r[i])); }
+            if (nrm <= 1e-15) { ok = 1; break; }
+        }
+        free(J); free(r);
+        if (!ok) return ORC_ENOTCONV;
+    }
+    return ORC_OK;
+}
+
+static void free_model(model_t *m)
+{
+    free(m->H); free(m->D); free(m->E); free(m->d0); free(m->Pm); free(m->Y); free(m->Yinf);
+}
+
+/* White-noise surrogate of eq. 8 for every process at stage column c:
+ * w_p(t_c) = sum_j zeta[p*K + j] * m_{j+1}(t_c). */
+static void kle_forcing(const double *zcol, int64_t zstride, const double *Phi, int K,
+                        int64_t C, int P, int64_t c, double *w)
+{
+    for (int p = 0; p < P; ++p) {
+        double acc = 0.0;
+        for (int j = 0; j < K; ++j)
+            acc += zcol[(int64_t)(p * K + j) * zstride] * Phi[(int64_t)j * C + c];
+        w[p] = acc;
+    }
+}
+
+/* One sample path (Alg. 1 steps 2-3): rebuild the disturbance from zeta via
+ * eq. 9 and integrate the swing equations over [0, T].  Integrator 0 is the
+ * classical fourth-order Runge-Kutta method with the forcing taken at the
+ * stage times; integrator 1 is the implicit trapezoidal rule solved by full
+ * Newton iterations.  Writes out[(S+1)][V]: delta (absolute), dw, xi. */
+static int simulate_one(const model_t *m, const double *zcol, int64_t zstride,
+                        const double *Phi, int K, int64_t S, double dt, int integrator,
+                        double *out)
+{
+    const int n = m->n, P = m->P, ny = m->ny;
+    const int64_t C = 2 * S + 1;
+    double *y = calloc(ny * 8 + ny * ny + 4 * P + 8, sizeof(double));
+    double *k1 = y + ny, *k2 = k1 + ny, *k3 = k2 + ny, *k4 = k3 + ny, *tmp = k4 + ny;
+    double *z = tmp + ny, *g = z + ny, *J = g + ny;
+    double *w0 = J + ny * ny, *w1 = w0 + P, *w2 = w1 + P;
+    int rc = ORC_OK;
+    for (int i = 0; i < n; ++i) { y[i] = m->d0[i]; y[n + i] = 0.0; }
+    for (int p = 0; p < P; ++p) y[2 * n + p] = m->xi0 ? m->xi0[p] : 0.0;
+    memcpy(out, y, sizeof(double) * ny);
+    for (int64_t s = 0; s < S; ++s) {
+        kle_forcing(zcol, zstride, Phi, K, C, P, 2 * s, w0);
+        kle_forcing(zcol, zstride, Phi, K, C, P, 2 * s + 2, w2);
+        if (integrator == 0) {
+            kle_forcing(zcol, zstride, Phi, K, C, P, 2 * s + 1, w1);
+            rhs(m, y, w0, k1);
+            for (int q = 0; q < ny; ++q) tmp[q] = y[q] + 0.5 * dt * k1[q];
+            rhs(m, tmp, w1, k2);
+            for (int q = 0; q < ny; ++q) tmp[q] = y[q] + 0.5 * dt * k2[q];
+            rhs(m, tmp, w1, k3);
+            for (int q = 0; q < ny; ++q) tmp[q] = y[q] + dt * k3[q];
+            rhs(m, tmp, w2, k4);
+            for (int q = 0; q < ny; ++q)
+                y[q] += dt / 6.0 * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+        } else {
+            /* z = y + dt/2 (f(y, w0) + f(z, w2)) */
+            rhs(m, y, w0, k1);
+            for (int q = 0; q < ny; ++q) z[q] = y[q] + dt * k1[q];
+            int conv = 0;
+            for (int it = 0; it < 20; ++it) {
+                rhs(m, z, w2, k2);
+                for (int q = 0; q < ny; ++q) g[q] = -(z[q] - y[q] - 0.5 * dt * (k1[q] + k2[q]));
+                rhs_jac(m, z, J);
+                for (int a = 0; a < ny * ny; ++a) J[a] = -0.5 * dt * J[a];
+                for (int q = 0; q < ny; ++q) J[q * ny + q] += 1.0;
+                if (rsolve(ny, J, g) != ORC_OK) break;
+                double dn = 0.0, zn = 0.0;
+                for (int q = 0; q < ny; ++q) {
+                    z[q] += g[q];
+                    dn = fmax(dn, fabs(g[q]));
+                    zn = fmax(zn, fabs(z[q]));
+                }
+                if (dn <= 1e-13 * (1.0 + zn)) { conv = 1; break; }
+            }
+            if (!conv) rc = ORC_ENOTCONV;
+            memcpy(y, z, sizeof(double) * ny);
+        }
+        memcpy(out + (s + 1) * ny, y, sizeof(double) * ny);
+    }
+    free(y);
+    return rc;
+}
+
+/* Neumaier-compensated sum. */
+typedef struct { double s, c; } ksum_t;
+static void kadd(ksum_t *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x; else a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The whole method (Alg. 1): LHS set (step 1), paths by eq. 9 (step 2),      */
+/* simulation (step 3), expectation and variance of the response at every     */
+/* output time (step 4; two passes with compensated sums, divisor N - ddof). */
+/* zeta_in (if given) replaces step 1 and is [M][n_sel] for the selected     */
+/* samples.  sel lists the samples of the design to run (all N if NULL); the  */
+/* statistics are over those samples.  traj (optional) is [n_sel][S+1][V].    */
+/* ------------------------------------------------------------------------- */
+int orc_run(const orc_problem *pb, const double *zeta_in, int64_t n_sel, const int64_t *sel,
+            double *mean, double *var, double *traj, int64_t *n_nonfinite, int64_t *n_notconv,
+            double *pm_out, double *delta0_out)
+{
+    if (!(pb->dt > 0.0) || !(pb->T > 0.0) || pb->K < 1 || pb->N < 1) return ORC_EINVAL;
+    const int64_t S = (int64_t)llround(pb->T / pb->dt);
+    if (S < 1 || fabs((double)S * pb->dt - pb->T) > 1e-9 * pb->T) return ORC_EINVAL;
+    const int64_t C = 2 * S + 1;
+    model_t m;
+    int rc = setup_model(pb, &m);
+    if (rc != ORC_OK) { free_model(&m); return rc; }
+    if (pm_out) memcpy(pm_out, m.Pm, sizeof(double) * m.n);
+    if (delta0_out) memcpy(delta0_out, m.d0, sizeof(double) * m.n);
+    if (!sel) n_sel = pb->N;
+    const int M = m.P * pb->K;
+    const int V = m.V;
+    double *Phi = malloc(sizeof(double) * pb->K * C);
+    orc_basis(pb->basis, pb->K, S, pb->T, Phi);
+    double *Z = NULL;
+    const double *Zuse = zeta_in;
+    if (!zeta_in && M > 0) {
+        Z = malloc(sizeof(double) * (size_t)M * n_sel);
+        rc = orc_lhs(pb->seed, M, pb->N, pb->sampler, n_sel, sel, NULL, Z);
+        if (rc != ORC_OK) { free(Phi); free(Z); free_model(&m); return rc; }
+        Zuse = Z;
+    }
+    double *tr = traj;
+    if (!tr) tr = malloc(sizeof(double) * (size_t)n_sel * (S + 1) * V);
+    if (!tr) { free(Phi); free(Z); free_model(&m); return ORC_ENOMEM; }
+    int64_t nonfin = 0, notconv = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nonfin, notconv)
+    for (int64_t c = 0; c < n_sel; ++c) {
+        double *o = tr + (size_t)c * (S + 1) * V;
+        int r = simulate_one(&m, Zuse ? Zuse + c : NULL, n_sel, Phi, pb->K, S, pb->dt,
+                             pb->integrator, o);
+        if (r == ORC_ENOTCONV) notconv++;
+        int bad = 0;
+        for (int64_t q = 0; q < (S + 1) * V; ++q)
+            if (!isfinite(o[q])) { bad = 1; break; }
+        nonfin += bad;
+    }
+    if (mean || var) {
+#pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < (S + 1) * V; ++q) {
+            ksum_t a = {0.0, 0.0};
+            for (int64_t c = 0; c < n_sel; ++c) kadd(&a, tr[(size_t)c * (S + 1) * V + q]);
+            double mu = (a.s + a.c) / (double)n_sel;
+            ksum_t b = {0.0, 0.0};
+            for (int64_t c = 0; c < n_sel; ++c) {
+                double d = tr[(size_t)c * (S + 1) * V + q] - mu;
+                kadd(&b, d * d);
+            }
+            if (mean) mean[q] = mu;
+            if (var) var[q] = (n_sel - pb->ddof > 0) ? (b.s + b.c) / (double)(n_sel - pb->ddof) : NAN;
+        }
+    }
+    if (!traj) free(tr);
+    free(Phi);
+    free(Z);
+    free_model(&m);
+    if (n_nonfinite) *n_nonfinite = nonfin;
+    if (n_notconv) *n_notconv = notconv;
+    if (notconv) return ORC_ENOTCONV;
+    return nonfin ? ORC_ENONFINITE : ORC_OK;
+}
+
+/* Right-hand side at one state, for tests of the model itself. */
+int orc_rhs(const orc_problem *pb, const double *y, const double *w, double *dy)
+{
+    model_t m;
+    int rc = setup_model(pb, &m);
+    if (rc == ORC_OK) rhs(&m, y, w, dy);
+    free_model(&m);
+    return rc;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
