@@ -1,0 +1,267 @@
+/*
+ * fmc.h -- C ABI of an MI355X (gfx950) library for the fast Monte Carlo method
+ * of Qiu, Lin, Chen, Liu and Song, "Fast Monte Carlo Simulation of Dynamic
+ * Power Systems Under Continuous Random Disturbances" (arXiv 2007.03847).
+ *
+ * The method (Alg. 1 of the paper): model each continuous disturbance as an
+ * Ito process (eq. 4; here Ornstein-Uhlenbeck, the Gaussian row of Table I),
+ * replace each driving Wiener increment by its Karhunen-Loeve expansion
+ * truncated at order K (eqs. 6-8), draw the M = P*K standard-normal
+ * coefficients by Latin hypercube sampling (Sec. IV-B), rebuild every
+ * disturbance path from the ODE with random coefficients (eq. 9), simulate the
+ * power system under it (eqs. 1-2, the classical swing equations on the
+ * Kron-reduced network), and take the expectation and variance of the response
+ * across the N samples at every output time (Alg. 1 step 4).
+ *
+ * Conventions shared by every entry point
+ *  - Status: FMC_OK (0) or a negative FMC_E* code; the message of the last
+ *    failure on the calling thread is returned by fmc_last_error() and stays
+ *    valid until the next call on that thread.  No C++ exception crosses the ABI.
+ *  - Ownership: the caller owns every buffer it passes.  Inputs are read only
+ *    during the call (fmc_submit copies its inputs before it returns).  The
+ *    library allocates device memory only inside a context, within the HBM
+ *    budget given at creation; it is released by fmc_context_destroy().
+ *  - Pointers: descriptor arrays (network, system, disturbance data, traj_idx)
+ *    are host memory.  Bulk arrays are device memory unless a mem_kind field
+ *    says otherwise.
+ *  - Layouts are row-major.  The time grid is t_s = s*dt, s = 0..S with
+ *    S = T/dt; stage times are t_c = c*dt/2, c = 0..2S.  The outputs of a
+ *    system with n machines and P disturbances are V = 2n + P variables per
+ *    time: delta_1..n (absolute rotor angle, rad), dw_1..n (speed deviation,
+ *    pu), xi_1..P (disturbance, pu).
+ *  - Streams: all work of a context is enqueued on the stream given at
+ *    creation (or set by fmc_set_stream); calls that return results to host
+ *    memory synchronise that stream.
+ *  - Threading: one context per device and thread, except fmc_submit,
+ *    fmc_poll, fmc_wait and fmc_cancel, which are thread-safe.
+ */
+#ifndef FMC_H
+#define FMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMC_ABI_VERSION 1
+
+/* Status codes. */
+#define FMC_OK 0
+#define FMC_EINVAL -1       /* invalid argument (see each entry point) */
+#define FMC_ENOMEM -2       /* the request can never fit the context's HBM budget */
+#define FMC_EBUSY -3        /* the request does not fit the budget free right now */
+#define FMC_EDEVICE -4      /* a HIP runtime call failed */
+#define FMC_ENONFINITE -5   /* some sample paths became non-finite; outputs written */
+#define FMC_ENOTCONV -6     /* a Newton solve did not converge */
+#define FMC_ECANCELLED -7   /* the ticket was cancelled */
+#define FMC_EAGAIN -8       /* the ticket is still pending */
+#define FMC_ETIMEDOUT -9    /* fmc_wait ran out of time */
+
+/* Arithmetic of the path. */
+#define FMC_F64 0    /* everything in FP64 */
+#define FMC_F32 1    /* KLE paths and integration in FP32; statistics in FP64 */
+#define FMC_BF16X3 2 /* KLE paths as BF16 hi+lo split products (3 MFMA, FP32
+                        accumulate); integration FP32; statistics FP64 */
+
+/* KLE basis (Sec. IV-A). */
+#define FMC_BASIS_PAPER 0 /* eq. 7: m_1 = sqrt(1/T), m_j = sqrt(2/T) cos((j-1) pi t/T) */
+#define FMC_BASIS_EIGEN 1 /* Wiener eigenfunctions: sqrt(2/T) cos((j-1/2) pi t/T) */
+
+/* Sampler of the KLE coefficients (Sec. IV-B). */
+#define FMC_LHS 0 /* Latin hypercube: one draw per stratum, permuted per row */
+#define FMC_SRS 1 /* simple random sampling (plain Monte Carlo of the coefficients) */
+
+/* Time integrator. */
+#define FMC_RK4 0  /* classical Runge-Kutta, forcing taken at the stage times */
+#define FMC_TRAP 1 /* implicit trapezoidal rule, Newton-solved */
+
+/* Generator model. */
+#define FMC_CLASSICAL 0        /* constant EMF behind X'd, swing equations */
+#define FMC_FLUXDECAY_IEEET1 1 /* one-axis flux decay + IEEE type-1 exciter */
+
+/* Memory kind of output arrays. */
+#define FMC_MEM_HOST 0
+#define FMC_MEM_DEVICE 1
+
+typedef struct fmc_context fmc_context;
+
+/* Network data for the reduction of eq. 2: buses, series branches (with
+ * optional total line charging b), constant-impedance load shunts g + jb (pu
+ * admittance at each bus, NULL = none), and each generator's internal node
+ * behind jX'd at bus gen_bus[g].  All arrays host memory. */
+typedef struct fmc_network {
+    int32_t n_bus, n_branch, n_gen;
+    const int32_t *br_from, *br_to; /* [n_branch], bus indices 0..n_bus-1 */
+    const double *br_r, *br_x;      /* [n_branch] series impedance, pu */
+    const double *br_b;             /* [n_branch] or NULL */
+    const double *load_g, *load_b;  /* [n_bus] or NULL */
+    const int32_t *gen_bus;         /* [n_gen] */
+    const double *gen_xdp;          /* [n_gen] transient reactance, pu */
+} fmc_network;
+
+/* Machine data (eq. 1 instantiated as the swing equations
+ *   d delta_i/dt = w_b dw_i,  2 H_i d dw_i/dt = Pm_i + sum_{p: gen[p]=i} xi_p
+ *                                              - Pe_i - D_i dw_i,
+ *   Pe_i = Re{ E~_i conj( sum_k Y_ik E~_k + Yinf_i V_inf ) },  E~_k = E_k e^{j delta_k},
+ * w_b = 2 pi f0).  Give either (delta0, Pm = NULL): Pm is set to Pe(delta0), an
+ * equilibrium by construction; or (delta0 = NULL, Pm) on an infinite-bus
+ * system: delta0 solves Pe(delta0) = Pm.  Give either the reduced admittance
+ * (Y_re, Y_im) or a network (net) to reduce.  All arrays host memory. */
+typedef struct fmc_system {
+    int32_t n_gen;
+    double f0_hz;                 /* 60 if <= 0 */
+    const double *H, *D, *E;      /* [n_gen] inertia (s), damping (pu), EMF (pu) */
+    const double *delta0, *Pm;    /* [n_gen] or NULL, see above */
+    const double *Y_re, *Y_im;    /* [n_gen*n_gen] or NULL */
+    const fmc_network *net;       /* used when Y_re is NULL */
+    int32_t infinite_bus;         /* nonzero: Yinf and V_inf are used */
+    double V_inf;                 /* infinite-bus voltage at angle 0 */
+    const double *Yinf_re, *Yinf_im; /* [n_gen] */
+    int32_t model;                /* FMC_CLASSICAL or FMC_FLUXDECAY_IEEET1 */
+    const double *model_params;   /* [n_gen][FMC_FD_NPARAM] for the flux-decay
+                                     model, NULL for the classical model */
+} fmc_system;
+
+/* Flux-decay + IEEE type-1 exciter parameters per machine, in this order. */
+#define FMC_FD_XD 0    /* synchronous reactance Xd */
+#define FMC_FD_TDO 1   /* open-circuit transient time constant T'do (s) */
+#define FMC_FD_KA 2    /* regulator gain */
+#define FMC_FD_TA 3    /* regulator time constant (s) */
+#define FMC_FD_KE 4    /* exciter constant */
+#define FMC_FD_TE 5    /* exciter time constant (s) */
+#define FMC_FD_KF 6    /* rate-feedback gain */
+#define FMC_FD_TF 7    /* rate-feedback time constant (s) */
+#define FMC_FD_NPARAM 8
+
+/* Ornstein-Uhlenbeck disturbances (eq. 4 with mu = -theta xi, constant
+ * sigma): d xi_p = -theta_p xi_p dt + sigma_p dW_p, added to Pm of machine
+ * gen[p].  Host arrays of length n_proc. */
+typedef struct fmc_disturbance {
+    int32_t n_proc;
+    const int32_t *gen;
+    const double *theta, *sigma;
+    const double *xi0; /* NULL: 0 */
+} fmc_disturbance;
+
+/* Alg. 1 inputs: truncation order K, sample size N, horizon T and step dt. */
+typedef struct fmc_params {
+    double T, dt;            /* S = T/dt must be an integer within 1e-9 S */
+    int32_t K;               /* KLE truncation order per process, >= 1 */
+    int64_t N;               /* samples, >= 2 */
+    uint64_t seed;           /* LHS design seed */
+    int32_t basis, sampler, integrator, precision;
+    int32_t ddof;            /* variance divisor N - ddof (1: unbiased) */
+    int32_t variant;         /* integrator kernel variant; -1 = choose (autotuner) */
+    int32_t time_chunk;      /* steps per chunk; 0 = choose */
+    const double *zeta_in;   /* device [M][N] FP64 coefficients replacing the
+                                sampler (M = n_proc*K), or NULL */
+} fmc_params;
+
+typedef struct fmc_report {
+    double t_total_s, t_lhs_s, t_gemm_s, t_integrate_s, t_stats_s; /* HIP events */
+    int64_t n_nonfinite;     /* samples whose path became non-finite */
+    int64_t first_nonfinite; /* smallest such sample index, -1 if none */
+    int32_t variant_id, lanes_per_traj, tile, time_chunk;
+    int64_t hbm_peak_bytes;  /* device bytes held for the call */
+    double queue_wait_s;     /* serving: admission delay */
+    double latency_s;        /* serving: submit to completion */
+} fmc_report;
+
+/* Results.  mean/var are [(S+1)][V] FP64; traj (optional) is
+ * [n_traj][S+1][V] FP64 for the samples listed in traj_idx (host); strata
+ * and zeta (optional) are the [M][N] design (int32 / FP64).  mem_kind applies
+ * to mean, var, traj, strata and zeta. */
+typedef struct fmc_outputs {
+    double *mean, *var;
+    int32_t n_traj;
+    const int64_t *traj_idx;
+    double *traj;
+    int32_t *strata;
+    double *zeta;
+    int32_t mem_kind;
+    fmc_report *report; /* host, optional */
+} fmc_outputs;
+
+typedef struct fmc_scenario {
+    const fmc_system *sys;
+    const fmc_disturbance *dist;
+    const fmc_params *par;
+} fmc_scenario;
+
+/* ABI version of the loaded library (FMC_ABI_VERSION). */
+int fmc_abi_version(void);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *fmc_last_error(void);
+
+/* Create a context on HIP device `device`.  hbm_budget bounds the device
+ * memory the context may hold (0: 90% of the free memory).  stream is a
+ * hipStream_t or NULL (the null stream).  FMC_EDEVICE if the device cannot be
+ * used, FMC_EINVAL for a NULL out. */
+int fmc_context_create(int device, size_t hbm_budget, void *stream, fmc_context **out);
+int fmc_context_destroy(fmc_context *ctx);
+int fmc_set_stream(fmc_context *ctx, void *stream);
+
+/* Kron reduction of the network equations (eq. 2 eliminated for a
+ * constant-impedance network), FP64 on the GPU: Y_red = Y_AA - Y_AB Y_BB^-1
+ * Y_BA with the generator internal nodes kept.  Y_re/Y_im: host
+ * [n_gen*n_gen].  FMC_EINVAL on bad indices, non-positive X'd or a singular
+ * Y_BB. */
+int fmc_kron_reduce(fmc_context *ctx, const fmc_network *net, double *Y_re, double *Y_im);
+
+/* LHS (Sec. IV-B, Alg. 1 step 1) of M coefficients over N samples: row i
+ * (i = p*K + j) is a Feistel-permuted assignment of the N equiprobable strata
+ * of the standard normal CDF, one uniform draw inside each, mapped by the
+ * inverse CDF.  strata (int32, may be NULL; -1 for FMC_SRS) and zeta (FP64)
+ * are device [M][N].  Bit-exact with the published counter-based definitions
+ * (Philox-4x64-10, AS 241). */
+int fmc_lhs(fmc_context *ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampler,
+            int32_t *strata, double *zeta);
+
+/* KLE basis (eq. 7, or the eigen basis) on the stage grid: phi device
+ * [K][2S+1] FP64. */
+int fmc_basis(fmc_context *ctx, int32_t basis, int32_t K, int64_t S, double T, double *phi);
+
+/* KLE path reconstruction (eqs. 8-9): w[c][p][n] = sum_j zeta[p*K+j][n] *
+ * phi[j][c0+c] for c = 0..C-1, p = 0..P-1, n = 0..N-1, as a dense
+ * contraction on the matrix cores.  zeta: device [P*K][N] FP64; phi: device
+ * [K][phi_ld] FP64; w: device [C][P][N], FP64 for FMC_F64, FP32 for FMC_F32
+ * and FMC_BF16X3 (BF16 hi+lo split products, FP32 accumulation). */
+int fmc_kle_paths(fmc_context *ctx, int32_t precision, int32_t P, int32_t K, int64_t N,
+                  int64_t C, int64_t c0, const double *zeta, const double *phi, int64_t phi_ld,
+                  void *w);
+
+/* The whole method (Alg. 1) for one scenario: LHS, basis, KLE paths,
+ * integration of every sample, mean and variance at every output time.
+ * FMC_EINVAL: dt <= 0, T/dt not an integer, K < 1, N < 2, theta < 0,
+ * sigma < 0, H <= 0, a machine index out of range, ddof outside [0, N).
+ * FMC_ENONFINITE: outputs are written, NaN propagates into the statistics,
+ * the report counts the samples. */
+int fmc_run(fmc_context *ctx, const fmc_system *sys, const fmc_disturbance *dist,
+            const fmc_params *par, fmc_outputs *out);
+
+/* Batched form: n scenarios of different sizes, horizons, K and N in one
+ * persistent launch; outs[i] receives scenario i (same results as fmc_run of
+ * scenario i alone, to the tolerance of its precision). */
+int fmc_run_batch(fmc_context *ctx, int32_t n, const fmc_scenario *scen, fmc_outputs *outs);
+
+/* Served form (continuous batching).  fmc_submit admits the request if its
+ * footprint fits the free HBM budget and a slot is free (FMC_EBUSY otherwise;
+ * FMC_ENOMEM if it can never fit), copies its inputs, and returns a ticket;
+ * admitted requests run together on the device.  outs must stay valid until
+ * fmc_poll/fmc_wait report completion. */
+int fmc_submit(fmc_context *ctx, const fmc_scenario *scen, fmc_outputs *out, uint64_t *ticket);
+int fmc_poll(fmc_context *ctx, uint64_t ticket);   /* FMC_OK done, FMC_EAGAIN pending */
+int fmc_wait(fmc_context *ctx, uint64_t ticket, double timeout_s);
+int fmc_cancel(fmc_context *ctx, uint64_t ticket); /* the ticket then reports FMC_ECANCELLED */
+
+/* Device bytes a scenario needs while it runs (the admission footprint). */
+int fmc_footprint(const fmc_scenario *scen, int64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMC_H */

@@ -237,3 +237,19 @@ def rhs(sc: dict, y, w):
     if rc != 0:
         raise RuntimeError(f"orc_rhs failed: {rc}")
     return dy
+
+
+def kle_paths(zeta, Phi, P: int, K: int, c0: int = 0, C_cols=None):
+    """KLE white-noise surrogates (eqs. 8-9): w[c][p][n] = sum_j zeta[pK+j][n] Phi[j][c0+c].
+
+    FP64 matrix products (numpy), one per process, nothing else.
+    """
+    zeta = np.asarray(zeta, dtype=np.float64)
+    Phi = np.asarray(Phi, dtype=np.float64)
+    if C_cols is None:
+        C_cols = Phi.shape[1] - c0
+    N = zeta.shape[1]
+    w = np.zeros((C_cols, P, N))
+    for p in range(P):
+        w[:, p, :] = Phi[:K, c0:c0 + C_cols].T @ zeta[p * K:(p + 1) * K, :]
+    return w

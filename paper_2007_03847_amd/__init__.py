@@ -1,0 +1,341 @@
+"""Python binding of libfmc (include/fmc.h): argument marshalling only.
+
+Every step of the method runs in the library's gfx950 kernels; this module
+converts scenario dicts (see ``workloads``) into the C structs, hands over
+device pointers of torch tensors and the current HIP stream, and returns
+torch tensors.  PyTorch supplies device memory and streams, nothing else.
+
+The library is required: importing this package raises if ``libfmc.so`` has
+not been built (``python -m paper_2007_03847_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2007_03847_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---------------------------------------------------------------- constants
+OK, EINVAL, ENOMEM, EBUSY, EDEVICE, ENONFINITE, ENOTCONV, ECANCELLED, EAGAIN, ETIMEDOUT = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+F64, F32, BF16X3 = 0, 1, 2
+BASIS = {"paper": 0, "eigen": 1}
+SAMPLER = {"lhs": 0, "srs": 1}
+INTEGRATOR = {"rk4": 0, "trap": 1}
+PRECISION = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
+MEM_HOST, MEM_DEVICE = 0, 1
+ABI_VERSION = 1
+
+_P = C.c_void_p
+
+
+class FmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fmc error {code}: {msg}")
+        self.code = code
+
+
+class Network(C.Structure):
+    _fields_ = [("n_bus", C.c_int32), ("n_branch", C.c_int32), ("n_gen", C.c_int32),
+                ("br_from", _P), ("br_to", _P), ("br_r", _P), ("br_x", _P), ("br_b", _P),
+                ("load_g", _P), ("load_b", _P), ("gen_bus", _P), ("gen_xdp", _P)]
+
+
+class System(C.Structure):
+    _fields_ = [("n_gen", C.c_int32), ("f0_hz", C.c_double),
+                ("H", _P), ("D", _P), ("E", _P), ("delta0", _P), ("Pm", _P),
+                ("Y_re", _P), ("Y_im", _P), ("net", C.POINTER(Network)),
+                ("infinite_bus", C.c_int32), ("V_inf", C.c_double),
+                ("Yinf_re", _P), ("Yinf_im", _P), ("model", C.c_int32), ("model_params", _P)]
+
+
+class Disturbance(C.Structure):
+    _fields_ = [("n_proc", C.c_int32), ("gen", _P), ("theta", _P), ("sigma", _P), ("xi0", _P)]
+
+
+class Params(C.Structure):
+    _fields_ = [("T", C.c_double), ("dt", C.c_double), ("K", C.c_int32), ("N", C.c_int64),
+                ("seed", C.c_uint64), ("basis", C.c_int32), ("sampler", C.c_int32),
+                ("integrator", C.c_int32), ("precision", C.c_int32), ("ddof", C.c_int32),
+                ("variant", C.c_int32), ("time_chunk", C.c_int32), ("zeta_in", _P)]
+
+
+class Report(C.Structure):
+    _fields_ = [("t_total_s", C.c_double), ("t_lhs_s", C.c_double), ("t_gemm_s", C.c_double),
+                ("t_integrate_s", C.c_double), ("t_stats_s", C.c_double),
+                ("n_nonfinite", C.c_int64), ("first_nonfinite", C.c_int64),
+                ("variant_id", C.c_int32), ("lanes_per_traj", C.c_int32), ("tile", C.c_int32),
+                ("time_chunk", C.c_int32), ("hbm_peak_bytes", C.c_int64),
+                ("queue_wait_s", C.c_double), ("latency_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Outputs(C.Structure):
+    _fields_ = [("mean", _P), ("var", _P), ("n_traj", C.c_int32), ("traj_idx", _P),
+                ("traj", _P), ("strata", _P), ("zeta", _P), ("mem_kind", C.c_int32),
+                ("report", C.POINTER(Report))]
+
+
+class Scenario(C.Structure):
+    _fields_ = [("sys", C.POINTER(System)), ("dist", C.POINTER(Disturbance)),
+                ("par", C.POINTER(Params))]
+
+
+_ctx_p = C.c_void_p
+_sig = {
+    "fmc_abi_version": ([], C.c_int),
+    "fmc_last_error": ([], C.c_char_p),
+    "fmc_context_create": ([C.c_int, C.c_size_t, _P, C.POINTER(_ctx_p)], C.c_int),
+    "fmc_context_destroy": ([_ctx_p], C.c_int),
+    "fmc_set_stream": ([_ctx_p, _P], C.c_int),
+    "fmc_kron_reduce": ([_ctx_p, C.POINTER(Network), _P, _P], C.c_int),
+    "fmc_lhs": ([_ctx_p, C.c_uint64, C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
+    "fmc_basis": ([_ctx_p, C.c_int32, C.c_int32, C.c_int64, C.c_double, _P], C.c_int),
+    "fmc_kle_paths": ([_ctx_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
+                       C.c_int64, _P, _P, C.c_int64, _P], C.c_int),
+    "fmc_run": ([_ctx_p, C.POINTER(System), C.POINTER(Disturbance), C.POINTER(Params),
+                 C.POINTER(Outputs)], C.c_int),
+    "fmc_run_batch": ([_ctx_p, C.c_int32, C.POINTER(Scenario), C.POINTER(Outputs)], C.c_int),
+    "fmc_submit": ([_ctx_p, C.POINTER(Scenario), C.POINTER(Outputs), C.POINTER(C.c_uint64)],
+                   C.c_int),
+    "fmc_poll": ([_ctx_p, C.c_uint64], C.c_int),
+    "fmc_wait": ([_ctx_p, C.c_uint64, C.c_double], C.c_int),
+    "fmc_cancel": ([_ctx_p, C.c_uint64], C.c_int),
+    "fmc_footprint": ([C.POINTER(Scenario), C.POINTER(C.c_int64)], C.c_int),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_sig)
+
+
+def last_error() -> str:
+    return _lib.fmc_last_error().decode()
+
+
+def _check(rc, allow=()):
+    if rc != OK and rc not in allow:
+        raise FmcError(rc, last_error())
+    return rc
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _dptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class _Keep(list):
+    """Keeps the numpy arrays and ctypes objects a call points into alive."""
+
+
+def _network(net, keep):
+    arrs = dict(br_from=_i32(net["br_from"]), br_to=_i32(net["br_to"]), br_r=_f64(net["br_r"]),
+                br_x=_f64(net["br_x"]), br_b=_f64(net.get("br_b")), load_g=_f64(net.get("load_g")),
+                load_b=_f64(net.get("load_b")), gen_bus=_i32(net["gen_bus"]),
+                gen_xdp=_f64(net["gen_xdp"]))
+    keep.append(arrs)
+    nw = Network(n_bus=int(net["n_bus"]), n_branch=len(arrs["br_from"]), n_gen=int(net["n_gen"]),
+                 **{k: _ptr(v) for k, v in arrs.items()})
+    keep.append(nw)
+    return nw
+
+
+def _enum(v, table):
+    return table[v] if isinstance(v, str) else int(v)
+
+
+def scenario_structs(sc: dict, precision="f64", variant=-1, time_chunk=0, zeta_in=None,
+                     keep=None):
+    """C structs (System, Disturbance, Params) for a scenario dict."""
+    keep = _Keep() if keep is None else keep
+    n = int(sc["n_gen"])
+    a = dict(H=_f64(sc["H"]), D=_f64(sc["D"]), E=_f64(sc["E"]), delta0=_f64(sc.get("delta0")),
+             Pm=_f64(sc.get("Pm")))
+    Y = sc.get("Y")
+    net_p = None
+    if Y is not None:
+        Y = np.asarray(Y, dtype=np.complex128).reshape(n, n)
+        a["Y_re"], a["Y_im"] = _f64(Y.real), _f64(Y.imag)
+    else:
+        a["Y_re"] = a["Y_im"] = None
+        net_p = C.pointer(_network(sc["net"], keep))
+    inf = bool(sc.get("infinite_bus", False))
+    if inf:
+        Yinf = np.asarray(sc["Yinf"], dtype=np.complex128).reshape(n)
+        a["Yinf_re"], a["Yinf_im"] = _f64(Yinf.real), _f64(Yinf.imag)
+    else:
+        a["Yinf_re"] = a["Yinf_im"] = None
+    keep.append(a)
+    sysd = System(n_gen=n, f0_hz=float(sc.get("f0", 60.0)), H=_ptr(a["H"]), D=_ptr(a["D"]),
+                  E=_ptr(a["E"]), delta0=_ptr(a["delta0"]), Pm=_ptr(a["Pm"]),
+                  Y_re=_ptr(a["Y_re"]), Y_im=_ptr(a["Y_im"]), net=net_p, infinite_bus=int(inf),
+                  V_inf=float(sc.get("V_inf", 1.0)), Yinf_re=_ptr(a["Yinf_re"]),
+                  Yinf_im=_ptr(a["Yinf_im"]), model=0, model_params=None)
+    d = sc["dist"]
+    b = dict(gen=_i32(d["gen"]), theta=_f64(d["theta"]), sigma=_f64(d["sigma"]),
+             xi0=_f64(d.get("xi0")))
+    keep.append(b)
+    dist = Disturbance(n_proc=len(b["gen"]), gen=_ptr(b["gen"]), theta=_ptr(b["theta"]),
+                       sigma=_ptr(b["sigma"]), xi0=_ptr(b["xi0"]))
+    par = Params(T=float(sc["T"]), dt=float(sc["dt"]), K=int(sc["K"]), N=int(sc["N"]),
+                 seed=int(sc.get("seed", 0)), basis=_enum(sc.get("basis", 0), BASIS),
+                 sampler=_enum(sc.get("sampler", 0), SAMPLER),
+                 integrator=_enum(sc.get("integrator", 0), INTEGRATOR),
+                 precision=_enum(precision, PRECISION), ddof=int(sc.get("ddof", 1)),
+                 variant=int(variant), time_chunk=int(time_chunk),
+                 zeta_in=_dptr(zeta_in))
+    keep.extend([sysd, dist, par])
+    return sysd, dist, par, keep
+
+
+def steps(sc: dict) -> int:
+    """Output steps S = T/dt for sizing outputs (0 if dt is not positive; the
+    library rejects such a scenario)."""
+    dt = float(sc["dt"])
+    if not dt > 0.0:
+        return 0
+    return max(int(round(float(sc["T"]) / dt)), 0)
+
+
+class Context:
+    """A library context on one device, bound to torch's current stream."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self._h = _ctx_p()
+        _check(_lib.fmc_context_create(device, hbm_budget, C.c_void_p(stream.cuda_stream),
+                                       C.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            _lib.fmc_context_destroy(self._h)
+            self._h = _ctx_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(_lib.fmc_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+
+    # ---------------------------------------------------------- single steps
+    def kron_reduce(self, net: dict):
+        keep = _Keep()
+        nw = _network(net, keep)
+        ng = int(net["n_gen"])
+        yr = np.zeros((ng, ng)); yi = np.zeros((ng, ng))
+        _check(_lib.fmc_kron_reduce(self._h, C.byref(nw), yr.ctypes.data, yi.ctypes.data))
+        return yr + 1j * yi
+
+    def lhs(self, seed: int, M: int, N: int, sampler="lhs", want_strata=True):
+        t = self.torch
+        zeta = t.empty((M, N), dtype=t.float64, device=self.device)
+        strata = t.empty((M, N), dtype=t.int32, device=self.device) if want_strata else None
+        _check(_lib.fmc_lhs(self._h, seed, M, N, _enum(sampler, SAMPLER), _dptr(strata),
+                            _dptr(zeta)))
+        return strata, zeta
+
+    def basis(self, kind, K: int, S: int, T: float):
+        t = self.torch
+        phi = t.empty((K, 2 * S + 1), dtype=t.float64, device=self.device)
+        _check(_lib.fmc_basis(self._h, _enum(kind, BASIS), K, S, T, _dptr(phi)))
+        return phi
+
+    def kle_paths(self, zeta, phi, P: int, K: int, C_cols: int, c0: int = 0, precision="f64"):
+        t = self.torch
+        assert zeta.dtype == t.float64 and zeta.is_contiguous() and zeta.shape[0] == P * K
+        assert phi.dtype == t.float64 and phi.is_contiguous() and phi.shape[0] >= K
+        N = zeta.shape[1]
+        prec = _enum(precision, PRECISION)
+        dt = t.float64 if prec == F64 else t.float32
+        w = t.empty((C_cols, P, N), dtype=dt, device=self.device)
+        _check(_lib.fmc_kle_paths(self._h, prec, P, K, N, C_cols, c0, _dptr(zeta), _dptr(phi),
+                                  phi.shape[1], _dptr(w)))
+        return w
+
+    # ------------------------------------------------------------ whole path
+    def run(self, sc: dict, precision="f64", traj_idx=None, want_design=False, variant=-1,
+            time_chunk=0, zeta_in=None, outputs=None, allow_nonfinite=False):
+        """Alg. 1 on the GPU.  Returns dict(mean, var[, traj, strata, zeta], report)."""
+        t = self.torch
+        n = int(sc["n_gen"]); P = len(sc["dist"]["gen"]); S = steps(sc)
+        V = 2 * n + P; M = P * int(sc["K"]); N = int(sc["N"])
+        sysd, dist, par, keep = scenario_structs(sc, precision, variant, time_chunk, zeta_in)
+        res = outputs or {}
+        mean = res.get("mean"); var = res.get("var")
+        if mean is None:
+            mean = t.empty((S + 1, V), dtype=t.float64, device=self.device)
+        if var is None:
+            var = t.empty((S + 1, V), dtype=t.float64, device=self.device)
+        traj = None
+        idx = None
+        if traj_idx is not None and len(traj_idx):
+            idx = np.ascontiguousarray(traj_idx, dtype=np.int64)
+            keep.append(idx)
+            traj = t.empty((len(idx), S + 1, V), dtype=t.float64, device=self.device)
+        strata = zeta = None
+        if want_design:
+            strata = t.empty((M, N), dtype=t.int32, device=self.device)
+            zeta = t.empty((M, N), dtype=t.float64, device=self.device)
+        rep = Report()
+        out = Outputs(mean=_dptr(mean), var=_dptr(var), n_traj=0 if idx is None else len(idx),
+                      traj_idx=_ptr(idx), traj=_dptr(traj), strata=_dptr(strata),
+                      zeta=_dptr(zeta), mem_kind=MEM_DEVICE, report=C.pointer(rep))
+        rc = _lib.fmc_run(self._h, C.byref(sysd), C.byref(dist), C.byref(par), C.byref(out))
+        _check(rc, allow=(ENONFINITE,) if allow_nonfinite else ())
+        r = dict(mean=mean, var=var, report=rep.as_dict(), rc=rc)
+        if traj is not None:
+            r["traj"] = traj
+        if want_design:
+            r["strata"] = strata
+            r["zeta"] = zeta
+        return r
+
+
+def footprint(sc: dict, precision="f64") -> int:
+    sysd, dist, par, keep = scenario_structs(sc, precision)
+    s = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))
+    b = C.c_int64(0)
+    _check(_lib.fmc_footprint(C.byref(s), C.byref(b)))
+    return int(b.value)
+
+
+_default_ctx = None
+
+
+def context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context(0)
+    return _default_ctx

@@ -1,0 +1,135 @@
+// fmc_internal.hpp -- launch interface between the host runtime and the
+// gfx950 kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fmc {
+
+// Layout of the FP64 operating-point block written by the setup kernel
+// ("canonical" coefficients; n machines, P processes, unpadded):
+//   [0, 2n^2)      Y_red re | im            (row-major n x n)
+//   c0[n] s0[n]    E_k cos(delta0_k), E_k sin(delta0_k)
+//   i0r[n] i0i[n]  I0 = Y E~0 + Yinf V_inf
+//   res[n]         Pm - Pe(delta0)
+//   dmp[n]         D
+//   inv2h[n]       1/(2H)
+//   delta0[n] pm[n]
+//   theta[P] sigma[P] xi0[P]
+struct CanonLayout {
+  int64_t n, P;
+  __host__ __device__ int64_t yre() const { return 0; }
+  __host__ __device__ int64_t yim() const { return n * n; }
+  __host__ __device__ int64_t c0() const { return 2 * n * n; }
+  __host__ __device__ int64_t s0() const { return c0() + n; }
+  __host__ __device__ int64_t i0r() const { return s0() + n; }
+  __host__ __device__ int64_t i0i() const { return i0r() + n; }
+  __host__ __device__ int64_t res() const { return i0i() + n; }
+  __host__ __device__ int64_t dmp() const { return res() + n; }
+  __host__ __device__ int64_t inv2h() const { return dmp() + n; }
+  __host__ __device__ int64_t delta0() const { return inv2h() + n; }
+  __host__ __device__ int64_t pm() const { return delta0() + n; }
+  __host__ __device__ int64_t theta() const { return pm() + n; }
+  __host__ __device__ int64_t sigma() const { return theta() + P; }
+  __host__ __device__ int64_t xi0() const { return sigma() + P; }
+  __host__ __device__ int64_t size() const { return xi0() + P; }
+};
+
+// Packed coefficients of one integrator variant (NG machines, PM processes,
+// padded with inert entries), in the variant's arithmetic type.
+struct PackLayout {
+  int NG, PM;
+  __host__ __device__ constexpr int yre() const { return 0; }
+  __host__ __device__ constexpr int yim() const { return NG * NG; }
+  __host__ __device__ constexpr int binc() const { return 2 * NG * NG; }  // [NG][PM] 0/1 injection
+  __host__ __device__ constexpr int c0() const { return binc() + NG * PM; }
+  __host__ __device__ constexpr int s0() const { return c0() + NG; }
+  __host__ __device__ constexpr int i0r() const { return s0() + NG; }
+  __host__ __device__ constexpr int i0i() const { return i0r() + NG; }
+  __host__ __device__ constexpr int res() const { return i0i() + NG; }
+  __host__ __device__ constexpr int dmp() const { return res() + NG; }
+  __host__ __device__ constexpr int inv2h() const { return dmp() + NG; }
+  __host__ __device__ constexpr int theta() const { return inv2h() + NG; }
+  __host__ __device__ constexpr int sigma() const { return theta() + PM; }
+  __host__ __device__ constexpr int xi0() const { return sigma() + PM; }
+  __host__ __device__ constexpr int size() const { return xi0() + PM; }
+};
+
+// Arguments of one time chunk of the batched integrator.
+template <typename R>
+struct IntegArgs {
+  const R* coef;            // PackLayout block
+  const R* w;               // [cols][P][N] KLE white-noise paths of this chunk
+  R* state;                 // [2*NG + PM][lanes] state between chunks
+  double* partial;          // [n_groups][S+1][V] (mean, M2) pairs
+  const double* delta0;     // [n] FP64 operating point (for trajectories)
+  const int32_t* traj_slot; // [N] output slot of each sample or -1 (may be null)
+  double* traj;             // [n_traj][S+1][V]
+  unsigned long long* nonfinite;
+  long long* first_bad;
+  int n, P, V;
+  int64_t N, S;
+  int64_t s_begin, s_end;   // steps [s_begin, s_end) of this chunk
+  int64_t c_base;           // global stage column of w's first column
+  int64_t lanes;            // state row stride
+  R dt, wb;
+};
+
+// ---- launchers (each returns hipError_t of the launch) ----
+hipError_t launch_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int32_t* strata,
+                      double* zeta, hipStream_t st);
+hipError_t launch_basis(int32_t kind, int32_t K, int64_t S, double T, double* phi, hipStream_t st);
+hipError_t launch_kle_f64(const double* zeta, const double* phi, int64_t phi_ld, int P, int K,
+                          int64_t N, int64_t C, int64_t c0, double* w, hipStream_t st);
+hipError_t launch_kle_f64_to_f32(const double* zeta, const double* phi, int64_t phi_ld, int P,
+                                 int K, int64_t N, int64_t C, int64_t c0, float* w,
+                                 hipStream_t st);
+hipError_t launch_kle_bf16x3(const double* zeta, const double* phi, int64_t phi_ld, int P, int K,
+                             int64_t N, int64_t C, int64_t c0, float* w, hipStream_t st);
+
+// Network reduction: device network arrays -> Y_red as (re, im) pairs [n_gen^2].
+struct NetDev {
+  int32_t n_bus, n_branch, n_gen;
+  const int32_t *from, *to, *gen_bus;
+  const double *r, *x, *b, *lg, *lb, *xdp;  // b, lg, lb may be null
+};
+hipError_t launch_kron(const NetDev& net, double2* work, double2* Yred, int* status,
+                       hipStream_t st);
+
+// Operating point and canonical coefficients.
+struct SetupDev {
+  int32_t n, P;
+  const double2* Y;           // [n*n]
+  const double *H, *D, *E;    // [n]
+  const double *delta0, *Pm;  // [n] or null
+  int32_t inf_bus;
+  double V_inf;
+  const double2* Yinf;        // [n] or null
+  const double *theta, *sigma, *xi0;  // [P], xi0 may be null
+  double* work;               // >= 3 n^2 + 8 n doubles
+  double* canon;              // CanonLayout
+  int* status;                // 0 ok, -6 Newton failure
+};
+hipError_t launch_setup(const SetupDev& s, hipStream_t st);
+
+template <typename R>
+hipError_t launch_pack(const double* canon, int n, int P, const int32_t* gen, int NG, int PM,
+                       R* coef, hipStream_t st);
+
+hipError_t launch_stats_merge(const double2* partial, int64_t n_groups, int group_size,
+                              int64_t N, int64_t S, int V, int n, int ddof,
+                              const double* delta0, double* mean, double* var, hipStream_t st);
+
+// Integrator variants: lanes_per_traj = 1, NG machines and PM processes per lane.
+struct VariantInfo {
+  int id, NG, PM, lanes_per_traj, prec;  // prec: 0 FP64, 1 FP32
+};
+int n_variants();
+const VariantInfo& variant(int i);
+hipError_t launch_integrate_f64(int variant_id, const IntegArgs<double>& a, int64_t n_groups,
+                                hipStream_t st);
+hipError_t launch_integrate_f32(int variant_id, const IntegArgs<float>& a, int64_t n_groups,
+                                hipStream_t st);
+
+}  // namespace fmc

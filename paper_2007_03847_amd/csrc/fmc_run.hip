@@ -1,0 +1,292 @@
+// fmc_run.hip -- one scenario through the whole method (Alg. 1) on the GPU:
+// setup (network reduction, operating point) -> LHS design (step 1) -> basis
+// -> per time chunk: KLE path contraction (step 2) and integration with fused
+// per-wave statistics (step 3) -> ordered merge of the statistics (step 4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fmc_runtime.hpp"
+
+namespace fmc {
+
+namespace {
+
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  bool on = false;
+  hipStream_t st = nullptr;
+  ~EventPool() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  int record() {
+    if (!on) return -1;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    (void)hipEventRecord(e, st);
+    ev.push_back(e);
+    return (int)ev.size() - 1;
+  }
+  double secs(int a, int b) const {
+    if (a < 0 || b < 0) return 0.0;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[a], ev[b]) != hipSuccess) return 0.0;
+    return ms * 1e-3;
+  }
+};
+
+struct ChunkTimes {
+  std::vector<int> gemm0, gemm1, int1;
+};
+
+template <typename R>
+int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t S, int64_t N,
+               double wb, const double* zeta, const double* phi, const R* coef,
+               const double* delta0, double* partial, const int32_t* slot_d, double* traj_d,
+               unsigned long long* cnt_d, int64_t Sc, EventPool& evp, ChunkTimes& ct) {
+  const VariantInfo& vi = variant(vid);
+  const int V = 2 * n + P;
+  const int64_t C = 2 * S + 1;
+  const int64_t n_groups = (N + 63) / 64;
+  const int64_t lanes = n_groups * 64;
+  const int bw = (int)sizeof(R);
+  void *w = nullptr, *state = nullptr;
+  int rc;
+  if ((rc = c->ensure("w", (size_t)(2 * Sc + 1) * P * N * bw, &w))) return rc;
+  if ((rc = c->ensure("state", (size_t)(2 * vi.NG + vi.PM) * lanes * bw, &state))) return rc;
+  IntegArgs<R> a{};
+  a.coef = coef;
+  a.w = (const R*)w;
+  a.state = (R*)state;
+  a.partial = partial;
+  a.delta0 = delta0;
+  a.traj_slot = slot_d;
+  a.traj = traj_d;
+  a.nonfinite = cnt_d;
+  a.first_bad = (long long*)(cnt_d + 1);
+  a.n = n;
+  a.P = P;
+  a.V = V;
+  a.N = N;
+  a.S = S;
+  a.lanes = lanes;
+  a.dt = (R)par->dt;
+  a.wb = (R)wb;
+  for (int64_t s0 = 0; s0 < S; s0 += Sc) {
+    const int64_t s1 = std::min<int64_t>(S, s0 + Sc);
+    const int64_t Cc = 2 * (s1 - s0) + 1;
+    ct.gemm0.push_back(evp.record());
+    hipError_t e;
+    if (par->precision == FMC_F64)
+      e = launch_kle_f64(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (double*)w, c->stream);
+    else if (par->precision == FMC_F32)
+      e = launch_kle_f64_to_f32(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w, c->stream);
+    else
+      e = launch_kle_bf16x3(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w, c->stream);
+    if (e != hipSuccess) return fail(FMC_EDEVICE, std::string("KLE launch: ") + hipGetErrorString(e));
+    ct.gemm1.push_back(evp.record());
+    a.s_begin = s0;
+    a.s_end = s1;
+    a.c_base = 2 * s0;
+    if constexpr (sizeof(R) == 8)
+      e = launch_integrate_f64(vid, a, n_groups, c->stream);
+    else
+      e = launch_integrate_f32(vid, a, n_groups, c->stream);
+    if (e != hipSuccess)
+      return fail(FMC_EDEVICE, std::string("integrator launch: ") + hipGetErrorString(e));
+    ct.int1.push_back(evp.record());
+  }
+  return FMC_OK;
+}
+
+}  // namespace
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(FMC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
+               const fmc_params* par, fmc_outputs* out) {
+  int64_t S = 0;
+  int rc = validate(sys, dist, par, &S);
+  if (rc) return rc;
+  if (!out->mean || !out->var) return fail(FMC_EINVAL, "mean and var outputs are required");
+  if (out->mem_kind != FMC_MEM_HOST && out->mem_kind != FMC_MEM_DEVICE)
+    return fail(FMC_EINVAL, "unknown mem_kind");
+  if (out->n_traj < 0 || (out->n_traj > 0 && (!out->traj_idx || !out->traj)))
+    return fail(FMC_EINVAL, "n_traj > 0 needs traj_idx and traj");
+  HIPCHK(hipSetDevice(c->device));
+  const int n = sys->n_gen, P = dist->n_proc, K = par->K;
+  const int64_t N = par->N, M = (int64_t)P * K, C = 2 * S + 1;
+  const int V = 2 * n + P;
+  const bool dev_out = out->mem_kind == FMC_MEM_DEVICE;
+  const bool f64 = par->precision == FMC_F64;
+  const int bw = f64 ? 8 : 4;
+  const int vid = par->variant >= 0 ? par->variant : choose_variant(n, P);
+  if (vid < 0 || vid >= n_variants())
+    return fail(FMC_EINVAL, "no integrator variant for n=" + std::to_string(n) + ", P=" + std::to_string(P));
+  const VariantInfo& vi = variant(vid);
+  if (vi.NG < n || vi.PM < P) return fail(FMC_EINVAL, "variant too small for the system");
+  const double f0 = sys->f0_hz > 0.0 ? sys->f0_hz : 60.0;
+  const double wb = 2.0 * M_PI * f0;
+
+  EventPool evp;
+  evp.on = out->report != nullptr;
+  evp.st = c->stream;
+  const size_t held0 = c->held;
+  const int ev_start = evp.record();
+
+  double* canon = nullptr;
+  int32_t* gen_d = nullptr;
+  int* status_d = nullptr;
+  if ((rc = stage_scenario(c, sys, dist, "run", &canon, &gen_d, &status_d))) return rc;
+  const CanonLayout CL{n, P};
+  const double* delta0_d = canon + CL.delta0();
+
+  void* coef = nullptr;
+  const PackLayout PL{vi.NG, vi.PM};
+  if ((rc = c->ensure("coef", (size_t)PL.size() * bw, &coef))) return rc;
+  HIPCHK(f64 ? launch_pack<double>(canon, n, P, gen_d, vi.NG, vi.PM, (double*)coef, c->stream)
+             : launch_pack<float>(canon, n, P, gen_d, vi.NG, vi.PM, (float*)coef, c->stream));
+
+  void* phi = nullptr;
+  if ((rc = c->ensure("phi", (size_t)K * C * sizeof(double), &phi))) return rc;
+  HIPCHK(launch_basis(par->basis, K, S, par->T, (double*)phi, c->stream));
+
+  const int ev_lhs0 = evp.record();
+  const double* zeta = par->zeta_in;
+  double* zeta_dev = nullptr;
+  int32_t* strata_dev = nullptr;
+  if (!zeta) {
+    void* p = nullptr;
+    if (out->zeta && dev_out) {
+      zeta_dev = out->zeta;
+    } else {
+      if ((rc = c->ensure("zeta", (size_t)M * N * sizeof(double), &p))) return rc;
+      zeta_dev = (double*)p;
+    }
+    if (out->strata) {
+      if (dev_out) {
+        strata_dev = out->strata;
+      } else {
+        if ((rc = c->ensure("strata", (size_t)M * N * sizeof(int32_t), &p))) return rc;
+        strata_dev = (int32_t*)p;
+      }
+    }
+    HIPCHK(launch_lhs(par->seed, (int32_t)M, N, par->sampler, strata_dev, zeta_dev, c->stream));
+    zeta = zeta_dev;
+  }
+  const int ev_lhs1 = evp.record();
+
+  // per-wave statistics partials, trajectory slots, counters
+  const int64_t n_groups = (N + 63) / 64;
+  void *partial = nullptr, *cnt = nullptr;
+  if ((rc = c->ensure("partial", (size_t)n_groups * (S + 1) * V * 2 * sizeof(double), &partial)))
+    return rc;
+  if ((rc = c->ensure("counters", 64, &cnt))) return rc;
+  {
+    const unsigned long long init[2] = {0ULL, (unsigned long long)LLONG_MAX};
+    HIPCHK(hipMemcpyAsync(cnt, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  int32_t* slot_d = nullptr;
+  double* traj_d = nullptr;
+  if (out->n_traj > 0) {
+    std::vector<int32_t> slot(N, -1);
+    for (int q = 0; q < out->n_traj; ++q) {
+      const int64_t idx = out->traj_idx[q];
+      if (idx < 0 || idx >= N) return fail(FMC_EINVAL, "traj_idx out of range");
+      if (slot[idx] >= 0) return fail(FMC_EINVAL, "traj_idx has a duplicate");
+      slot[idx] = q;
+    }
+    void* p = nullptr;
+    if ((rc = c->ensure("traj_slot", (size_t)N * sizeof(int32_t), &p))) return rc;
+    slot_d = (int32_t*)p;
+    HIPCHK(hipMemcpyAsync(slot_d, slot.data(), (size_t)N * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (dev_out) {
+      traj_d = out->traj;
+    } else {
+      if ((rc = c->ensure("traj", (size_t)out->n_traj * (S + 1) * V * sizeof(double), &p))) return rc;
+      traj_d = (double*)p;
+    }
+  }
+
+  const int64_t Sc = par->time_chunk > 0 ? std::min<int64_t>(par->time_chunk, S)
+                                         : auto_chunk(S, P, N, bw);
+  ChunkTimes ct;
+  if (f64)
+    rc = run_chunks<double>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
+                            (const double*)coef, delta0_d, (double*)partial, slot_d, traj_d,
+                            (unsigned long long*)cnt, Sc, evp, ct);
+  else
+    rc = run_chunks<float>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
+                           (const float*)coef, delta0_d, (double*)partial, slot_d, traj_d,
+                           (unsigned long long*)cnt, Sc, evp, ct);
+  if (rc) return rc;
+
+  const int ev_st0 = evp.record();
+  double *mean_d = out->mean, *var_d = out->var;
+  if (!dev_out) {
+    void *pm = nullptr, *pv = nullptr;
+    if ((rc = c->ensure("mean", (size_t)(S + 1) * V * sizeof(double), &pm))) return rc;
+    if ((rc = c->ensure("var", (size_t)(S + 1) * V * sizeof(double), &pv))) return rc;
+    mean_d = (double*)pm;
+    var_d = (double*)pv;
+  }
+  HIPCHK(launch_stats_merge((const double2*)partial, n_groups, 64, N, S, V, n, par->ddof, delta0_d,
+                            mean_d, var_d, c->stream));
+  const int ev_end = evp.record();
+
+  if (!dev_out) {
+    const size_t sv = (size_t)(S + 1) * V * sizeof(double);
+    HIPCHK(hipMemcpyAsync(out->mean, mean_d, sv, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(out->var, var_d, sv, hipMemcpyDeviceToHost, c->stream));
+    if (traj_d)
+      HIPCHK(hipMemcpyAsync(out->traj, traj_d, (size_t)out->n_traj * sv, hipMemcpyDeviceToHost, c->stream));
+    if (out->zeta && zeta_dev)
+      HIPCHK(hipMemcpyAsync(out->zeta, zeta_dev, (size_t)M * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (out->strata && strata_dev)
+      HIPCHK(hipMemcpyAsync(out->strata, strata_dev, (size_t)M * N * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  }
+  int status[2] = {0, 0};
+  unsigned long long cn[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(status, status_d, sizeof(status), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(cn, cnt, sizeof(cn), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (status[1] != 0) return fail(FMC_EINVAL, "network reduction failed (singular Y_BB)");
+  if (status[0] != 0) return fail(FMC_ENOTCONV, "operating-point Newton solve did not converge");
+
+  if (out->report) {
+    fmc_report* r = out->report;
+    std::memset(r, 0, sizeof(*r));
+    r->t_total_s = evp.secs(ev_start, ev_end);
+    r->t_lhs_s = evp.secs(ev_lhs0, ev_lhs1);
+    for (size_t q = 0; q < ct.gemm0.size(); ++q) {
+      r->t_gemm_s += evp.secs(ct.gemm0[q], ct.gemm1[q]);
+      r->t_integrate_s += evp.secs(ct.gemm1[q], ct.int1[q]);
+    }
+    r->t_stats_s = evp.secs(ev_st0, ev_end);
+    r->n_nonfinite = (int64_t)cn[0];
+    r->first_nonfinite = cn[0] ? (int64_t)cn[1] : -1;
+    r->variant_id = vid;
+    r->lanes_per_traj = vi.lanes_per_traj;
+    r->tile = 64;
+    r->time_chunk = (int32_t)Sc;
+    r->hbm_peak_bytes = (int64_t)std::max(c->held, held0);
+  }
+  if (cn[0] != 0)
+    return fail(FMC_ENONFINITE, std::to_string(cn[0]) + " sample paths became non-finite (first: " +
+                                    std::to_string((long long)cn[1]) + ")");
+  return FMC_OK;
+}
+
+}  // namespace fmc

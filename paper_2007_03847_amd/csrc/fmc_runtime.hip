@@ -1,0 +1,429 @@
+// fmc_runtime.hip -- host runtime behind the C ABI (include/fmc.h): argument
+// validation, device memory of a context, scenario staging, variant choice,
+// time chunking and the launch sequence of the method (Alg. 1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fmc.h"
+#include "fmc_internal.hpp"
+#include "fmc_runtime.hpp"
+#include "k_variants.hpp"
+
+namespace fmc {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+// ---------------------------------------------------------------------------
+// Variant table: the lane integrator compiled for (NG, PM) pairs.
+// ---------------------------------------------------------------------------
+static const std::vector<VariantInfo>& lane_table() {
+  static const std::vector<VariantInfo> t = [] {
+    std::vector<VariantInfo> v;
+    int id = 0;
+#define FMC_X(NG, PM) v.push_back(VariantInfo{id++, NG, PM, 1, 0});
+    FMC_LANE_VARIANTS(FMC_X)
+#undef FMC_X
+    return v;
+  }();
+  return t;
+}
+
+int n_variants() { return (int)lane_table().size(); }
+const VariantInfo& variant(int i) { return lane_table()[i]; }
+
+int choose_variant(int n, int P) {
+  int best = -1;
+  for (const auto& v : lane_table()) {
+    if (v.NG >= n && v.PM >= std::max(P, 1)) {
+      if (best < 0) {
+        best = v.id;
+      } else {
+        const auto& b = lane_table()[best];
+        const long cost_v = (long)v.NG * v.NG * 4 + v.PM;
+        const long cost_b = (long)b.NG * b.NG * 4 + b.PM;
+        if (cost_v < cost_b) best = v.id;
+      }
+    }
+  }
+  return best;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory of a context: named, grow-only buffers within the budget.
+// ---------------------------------------------------------------------------
+int Context::ensure(const char* name, size_t bytes, void** out) {
+  bytes = std::max<size_t>(bytes, 256);
+  bytes = (bytes + 255) & ~size_t(255);
+  DevBuf& b = bufs[name];
+  if (b.cap >= bytes) {
+    *out = b.p;
+    return FMC_OK;
+  }
+  const size_t new_held = held - b.cap + bytes;
+  if (new_held > budget)
+    return fail(FMC_ENOMEM, std::string("HBM budget exceeded allocating ") + name + " (" +
+                                std::to_string(bytes) + " bytes, budget " +
+                                std::to_string(budget) + ")");
+  if (b.p) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+    (void)hipFree(b.p);
+    held -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(FMC_ENOMEM, std::string("hipMalloc failed for ") + name + ": " + hipGetErrorString(e));
+  }
+  b.p = p;
+  b.cap = bytes;
+  held += bytes;
+  peak = std::max(peak, held);
+  *out = p;
+  return FMC_OK;
+}
+
+void Context::release_all() {
+  for (auto& kv : bufs)
+    if (kv.second.p) (void)hipFree(kv.second.p);
+  bufs.clear();
+  held = 0;
+}
+
+// Host staging of small arrays into one device upload.
+struct Stager {
+  std::vector<unsigned char> bytes;
+  std::vector<std::pair<size_t, void**>> fix;  // (offset, where to store device ptr)
+  template <typename T>
+  void add(const T* src, size_t count, const T** dst) {
+    if (!src || count == 0) {
+      *dst = nullptr;
+      return;
+    }
+    const size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + count * sizeof(T));
+    std::memcpy(bytes.data() + off, src, count * sizeof(T));
+    fix.push_back({off, (void**)dst});
+  }
+  int upload(Context* c, const char* name) {
+    if (bytes.empty()) return FMC_OK;
+    void* d = nullptr;
+    int rc = c->ensure(name, bytes.size(), &d);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(d, bytes.data(), bytes.size(), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+    // the host bytes must stay valid until the copy ends
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+    for (auto& f : fix) *f.second = (unsigned char*)d + f.first;
+    return FMC_OK;
+  }
+};
+
+static int check_network(const fmc_network* net) {
+  if (!net) return fail(FMC_EINVAL, "network is NULL");
+  if (net->n_bus < 1 || net->n_gen < 1 || net->n_branch < 0)
+    return fail(FMC_EINVAL, "network sizes must be n_bus >= 1, n_gen >= 1, n_branch >= 0");
+  if ((net->n_branch > 0 && (!net->br_from || !net->br_to || !net->br_r || !net->br_x)) ||
+      !net->gen_bus || !net->gen_xdp)
+    return fail(FMC_EINVAL, "network arrays missing");
+  for (int k = 0; k < net->n_branch; ++k) {
+    const int f = net->br_from[k], t = net->br_to[k];
+    if (f < 0 || f >= net->n_bus || t < 0 || t >= net->n_bus || f == t)
+      return fail(FMC_EINVAL, "branch " + std::to_string(k) + " has invalid end buses");
+  }
+  for (int g = 0; g < net->n_gen; ++g) {
+    if (net->gen_bus[g] < 0 || net->gen_bus[g] >= net->n_bus)
+      return fail(FMC_EINVAL, "generator " + std::to_string(g) + " bus out of range");
+    if (!(net->gen_xdp[g] > 0.0)) return fail(FMC_EINVAL, "X'd must be positive");
+  }
+  return FMC_OK;
+}
+
+// Reduce a network on the device into Yd (double2 [n_gen^2]); status to *st_dev.
+int kron_on_device(Context* c, const fmc_network* net, double2* Yd, int* st_dev) {
+  int rc = check_network(net);
+  if (rc) return rc;
+  Stager sg;
+  NetDev nd{};
+  nd.n_bus = net->n_bus;
+  nd.n_branch = net->n_branch;
+  nd.n_gen = net->n_gen;
+  sg.add(net->br_from, net->n_branch, &nd.from);
+  sg.add(net->br_to, net->n_branch, &nd.to);
+  sg.add(net->br_r, net->n_branch, &nd.r);
+  sg.add(net->br_x, net->n_branch, &nd.x);
+  sg.add(net->br_b, net->n_branch, &nd.b);
+  sg.add(net->load_g, net->n_bus, &nd.lg);
+  sg.add(net->load_b, net->n_bus, &nd.lb);
+  sg.add(net->gen_bus, net->n_gen, &nd.gen_bus);
+  sg.add(net->gen_xdp, net->n_gen, &nd.xdp);
+  if ((rc = sg.upload(c, "net"))) return rc;
+  void* work = nullptr;
+  const size_t wbytes = (size_t)net->n_bus * (net->n_bus + net->n_gen) * sizeof(double2);
+  if ((rc = c->ensure("kron_work", wbytes, &work))) return rc;
+  hipError_t e = launch_kron(nd, (double2*)work, Yd, st_dev, c->stream);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, std::string("kron launch: ") + hipGetErrorString(e));
+  return FMC_OK;
+}
+
+int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_params* par,
+             int64_t* S_out) {
+  if (!sys || !dist || !par) return fail(FMC_EINVAL, "NULL system, disturbance or params");
+  if (!(par->dt > 0.0) || !(par->T > 0.0)) return fail(FMC_EINVAL, "T and dt must be positive");
+  const double sd = par->T / par->dt;
+  const int64_t S = (int64_t)std::llround(sd);
+  if (S < 1 || std::fabs((double)S * par->dt - par->T) > 1e-9 * par->T)
+    return fail(FMC_EINVAL, "T/dt must be an integer number of steps");
+  if (par->K < 1) return fail(FMC_EINVAL, "K must be >= 1");
+  if (par->N < 2) return fail(FMC_EINVAL, "N must be >= 2");
+  if (par->ddof < 0 || par->ddof >= par->N) return fail(FMC_EINVAL, "ddof must be in [0, N)");
+  if (par->basis != FMC_BASIS_PAPER && par->basis != FMC_BASIS_EIGEN)
+    return fail(FMC_EINVAL, "unknown basis");
+  if (par->sampler != FMC_LHS && par->sampler != FMC_SRS) return fail(FMC_EINVAL, "unknown sampler");
+  if (par->integrator != FMC_RK4) return fail(FMC_EINVAL, "only the RK4 integrator runs on the GPU");
+  if (par->precision < FMC_F64 || par->precision > FMC_BF16X3)
+    return fail(FMC_EINVAL, "unknown precision");
+  const int n = sys->n_gen;
+  if (n < 1) return fail(FMC_EINVAL, "n_gen must be >= 1");
+  if (sys->model != FMC_CLASSICAL) return fail(FMC_EINVAL, "model not available on this path");
+  if (!sys->H || !sys->D || !sys->E) return fail(FMC_EINVAL, "H, D and E are required");
+  for (int i = 0; i < n; ++i) {
+    if (!(sys->H[i] > 0.0)) return fail(FMC_EINVAL, "H must be positive");
+    if (!std::isfinite(sys->D[i]) || !std::isfinite(sys->E[i])) return fail(FMC_EINVAL, "D, E must be finite");
+  }
+  if (!sys->delta0 && !(sys->Pm && sys->infinite_bus))
+    return fail(FMC_EINVAL, "delta0 is required unless Pm is given on an infinite-bus system");
+  if (!sys->Y_re && !sys->net) return fail(FMC_EINVAL, "give Y_re/Y_im or a network");
+  if (sys->Y_re && !sys->Y_im) return fail(FMC_EINVAL, "Y_im missing");
+  if (sys->net && !sys->Y_re && sys->net->n_gen != n) return fail(FMC_EINVAL, "network n_gen differs from system n_gen");
+  if (sys->infinite_bus && (!sys->Yinf_re || !sys->Yinf_im))
+    return fail(FMC_EINVAL, "infinite-bus coupling Yinf missing");
+  if (dist->n_proc < 1) return fail(FMC_EINVAL, "at least one disturbance process is required");
+  if (!dist->gen || !dist->theta || !dist->sigma) return fail(FMC_EINVAL, "disturbance arrays missing");
+  for (int p = 0; p < dist->n_proc; ++p) {
+    if (dist->gen[p] < 0 || dist->gen[p] >= n) return fail(FMC_EINVAL, "disturbance machine index out of range");
+    if (!(dist->theta[p] >= 0.0)) return fail(FMC_EINVAL, "theta must be >= 0");
+    if (!(dist->sigma[p] >= 0.0)) return fail(FMC_EINVAL, "sigma must be >= 0");
+  }
+  *S_out = S;
+  return FMC_OK;
+}
+
+// Stage the machine/disturbance data and run setup -> canonical coefficients.
+int stage_scenario(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
+                   const char* tag, double** canon_out, int32_t** gen_out, int** status_out) {
+  const int n = sys->n_gen, P = dist->n_proc;
+  int rc;
+  Stager sg;
+  SetupDev sd{};
+  sd.n = n;
+  sd.P = P;
+  std::vector<double2> Yh, Yinfh;
+  if (sys->Y_re) {
+    Yh.resize((size_t)n * n);
+    for (size_t q = 0; q < Yh.size(); ++q) Yh[q] = make_double2(sys->Y_re[q], sys->Y_im[q]);
+  }
+  if (sys->infinite_bus) {
+    Yinfh.resize(n);
+    for (int i = 0; i < n; ++i) Yinfh[i] = make_double2(sys->Yinf_re[i], sys->Yinf_im[i]);
+  }
+  const int32_t* gen_d = nullptr;
+  sg.add(sys->H, n, &sd.H);
+  sg.add(sys->D, n, &sd.D);
+  sg.add(sys->E, n, &sd.E);
+  sg.add(sys->delta0, n, &sd.delta0);
+  sg.add(sys->Pm, n, &sd.Pm);
+  sg.add(Yh.empty() ? nullptr : Yh.data(), Yh.size(), &sd.Y);
+  sg.add(Yinfh.empty() ? nullptr : Yinfh.data(), Yinfh.size(), &sd.Yinf);
+  sg.add(dist->theta, P, &sd.theta);
+  sg.add(dist->sigma, P, &sd.sigma);
+  sg.add(dist->xi0, P, &sd.xi0);
+  sg.add(dist->gen, P, &gen_d);
+  std::string nm = std::string("stage_") + tag;
+  if ((rc = sg.upload(c, nm.c_str()))) return rc;
+  sd.inf_bus = sys->infinite_bus ? 1 : 0;
+  sd.V_inf = sys->V_inf;
+  void *status = nullptr, *work = nullptr, *canon = nullptr, *ybuf = nullptr;
+  if ((rc = c->ensure((std::string("status_") + tag).c_str(), 64, &status))) return rc;
+  if ((rc = c->ensure((std::string("setup_work_") + tag).c_str(),
+                      (size_t)(3 * n * n + 8 * n + 64) * sizeof(double), &work)))
+    return rc;
+  CanonLayout L{n, P};
+  if ((rc = c->ensure((std::string("canon_") + tag).c_str(), (size_t)L.size() * sizeof(double), &canon)))
+    return rc;
+  hipError_t e = hipMemsetAsync(status, 0, 64, c->stream);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  if (!sd.Y) {
+    if ((rc = c->ensure((std::string("yred_") + tag).c_str(), (size_t)n * n * sizeof(double2), &ybuf)))
+      return rc;
+    if ((rc = kron_on_device(c, sys->net, (double2*)ybuf, (int*)status + 1))) return rc;
+    sd.Y = (const double2*)ybuf;
+  }
+  sd.work = (double*)work;
+  sd.canon = (double*)canon;
+  sd.status = (int*)status;
+  e = launch_setup(sd, c->stream);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, std::string("setup launch: ") + hipGetErrorString(e));
+  *canon_out = (double*)canon;
+  *gen_out = (int32_t*)gen_d;
+  *status_out = (int*)status;
+  return FMC_OK;
+}
+
+int64_t auto_chunk(int64_t S, int P, int64_t N, int bytes_per) {
+  const double target = 96.0 * 1024 * 1024;  // keep a chunk of paths in the 256 MB last-level cache
+  const double col = (double)P * (double)N * bytes_per;
+  int64_t cols = (int64_t)(target / col);
+  int64_t sc = std::max<int64_t>(8, (cols - 1) / 2);
+  return std::min<int64_t>(sc, S);
+}
+
+}  // namespace fmc
+
+using namespace fmc;
+
+extern "C" {
+
+int fmc_abi_version(void) { return FMC_ABI_VERSION; }
+
+const char* fmc_last_error(void) { return g_err.c_str(); }
+
+int fmc_context_create(int device, size_t hbm_budget, void* stream, fmc_context** out) {
+  if (!out) return fail(FMC_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) return fail(FMC_EDEVICE, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(FMC_EDEVICE, "device index out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  size_t free_b = 0, total_b = 0;
+  e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  Context* c = new Context();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  c->budget = hbm_budget ? hbm_budget : (size_t)(0.9 * (double)free_b);
+  for (auto& ev : c->ev) {
+    if (hipEventCreate(&ev) != hipSuccess) {
+      delete c;
+      return fail(FMC_EDEVICE, "hipEventCreate failed");
+    }
+  }
+  *out = reinterpret_cast<fmc_context*>(c);
+  return FMC_OK;
+}
+
+int fmc_context_destroy(fmc_context* ctx) {
+  if (!ctx) return FMC_OK;
+  Context* c = reinterpret_cast<Context*>(ctx);
+  (void)hipSetDevice(c->device);
+  serve_shutdown(c);
+  (void)hipStreamSynchronize(c->stream);
+  c->release_all();
+  for (auto& ev : c->ev) (void)hipEventDestroy(ev);
+  delete c;
+  return FMC_OK;
+}
+
+int fmc_set_stream(fmc_context* ctx, void* stream) {
+  if (!ctx) return fail(FMC_EINVAL, "ctx is NULL");
+  reinterpret_cast<Context*>(ctx)->stream = (hipStream_t)stream;
+  return FMC_OK;
+}
+
+int fmc_kron_reduce(fmc_context* ctx, const fmc_network* net, double* Y_re, double* Y_im) {
+  if (!ctx || !Y_re || !Y_im) return fail(FMC_EINVAL, "NULL argument");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  int rc = check_network(net);
+  if (rc) return rc;
+  (void)hipSetDevice(c->device);
+  void *yd = nullptr, *st = nullptr;
+  const int ng = net->n_gen;
+  if ((rc = c->ensure("kr_y", (size_t)ng * ng * sizeof(double2), &yd))) return rc;
+  if ((rc = c->ensure("kr_status", 64, &st))) return rc;
+  if ((rc = kron_on_device(c, net, (double2*)yd, (int*)st))) return rc;
+  std::vector<double2> h((size_t)ng * ng);
+  int status = 0;
+  hipError_t e = hipMemcpyAsync(h.data(), yd, h.size() * sizeof(double2), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&status, st, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  if (status != 0) return fail(FMC_EINVAL, "network reduction failed (singular Y_BB)");
+  for (size_t q = 0; q < h.size(); ++q) {
+    Y_re[q] = h[q].x;
+    Y_im[q] = h[q].y;
+  }
+  return FMC_OK;
+}
+
+int fmc_lhs(fmc_context* ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampler,
+            int32_t* strata, double* zeta) {
+  if (!ctx || !zeta) return fail(FMC_EINVAL, "NULL argument");
+  if (M < 1 || N < 1) return fail(FMC_EINVAL, "M and N must be >= 1");
+  if (sampler != FMC_LHS && sampler != FMC_SRS) return fail(FMC_EINVAL, "unknown sampler");
+  if (N > (int64_t)1 << 40) return fail(FMC_EINVAL, "N too large");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  (void)hipSetDevice(c->device);
+  hipError_t e = launch_lhs(seed, M, N, sampler, strata, zeta, c->stream);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  return FMC_OK;
+}
+
+int fmc_basis(fmc_context* ctx, int32_t basis, int32_t K, int64_t S, double T, double* phi) {
+  if (!ctx || !phi) return fail(FMC_EINVAL, "NULL argument");
+  if (K < 1 || S < 1 || !(T > 0.0)) return fail(FMC_EINVAL, "K >= 1, S >= 1, T > 0 required");
+  if (basis != FMC_BASIS_PAPER && basis != FMC_BASIS_EIGEN) return fail(FMC_EINVAL, "unknown basis");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  (void)hipSetDevice(c->device);
+  hipError_t e = launch_basis(basis, K, S, T, phi, c->stream);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  return FMC_OK;
+}
+
+int fmc_kle_paths(fmc_context* ctx, int32_t precision, int32_t P, int32_t K, int64_t N, int64_t C,
+                  int64_t c0, const double* zeta, const double* phi, int64_t phi_ld, void* w) {
+  if (!ctx || !zeta || !phi || !w) return fail(FMC_EINVAL, "NULL argument");
+  if (P < 1 || K < 1 || N < 1 || C < 1 || c0 < 0 || phi_ld < c0 + C)
+    return fail(FMC_EINVAL, "bad sizes (need P, K, N, C >= 1 and phi_ld >= c0 + C)");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  (void)hipSetDevice(c->device);
+  hipError_t e;
+  if (precision == FMC_F64)
+    e = launch_kle_f64(zeta, phi, phi_ld, P, K, N, C, c0, (double*)w, c->stream);
+  else if (precision == FMC_F32)
+    e = launch_kle_f64_to_f32(zeta, phi, phi_ld, P, K, N, C, c0, (float*)w, c->stream);
+  else if (precision == FMC_BF16X3)
+    e = launch_kle_bf16x3(zeta, phi, phi_ld, P, K, N, C, c0, (float*)w, c->stream);
+  else
+    return fail(FMC_EINVAL, "unknown precision");
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  return FMC_OK;
+}
+
+int fmc_run(fmc_context* ctx, const fmc_system* sys, const fmc_disturbance* dist,
+            const fmc_params* par, fmc_outputs* out) {
+  if (!ctx || !out) return fail(FMC_EINVAL, "NULL context or outputs");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  return run_single(c, sys, dist, par, out);
+}
+
+}  // extern "C"

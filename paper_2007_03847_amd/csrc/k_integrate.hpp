@@ -1,0 +1,298 @@
+// k_integrate.hpp -- batched fixed-step integrator of the classical
+// multimachine model driven by the KLE-rebuilt OU disturbances (eq. 9 in the
+// swing equations, Alg. 1 steps 2-3), with the cross-sample statistics of
+// Alg. 1 step 4 fused into its epilogue.
+//
+// One trajectory per lane.  The machine data (reduced admittance, operating
+// point) is identical for every lane of a wave, so it is read through uniform
+// (scalar) loads and feeds the FMAs as scalar operands: no LDS or VGPR traffic
+// for Y.
+//
+// The state is integrated as deviations from the operating point:
+//   y = (d_delta_i, dw_i, xi_p).
+// With E~_k = E~0_k exp(j d_delta_k), exp(j d) - 1 = -2 sin^2(d/2) + j sin d,
+// so dE~ = E~0 (exp(j d) - 1) is formed from one sincos of d/2 without
+// cancellation, and
+//   Pe_i - Pe0_i = Re(dE~_i conj(I0_i)) + Re(E~_i conj(dI_i)),  dI = Y dE~,
+// which keeps FP32 integration accurate to its own rounding of the deviation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fmc_internal.hpp"
+
+namespace fmc {
+
+// Read-only machine data seen through the constant address space: uniform
+// loads from it become scalar (SMEM) loads into SGPRs.
+template <typename R>
+using cptr = const __attribute__((address_space(4))) R*;
+
+// sin and cos together: Cody-Waite reduction x = k pi/2 + r, |r| <= pi/4,
+// with pi/2 split into two (FP64) or three (FP32) parts applied by FMA (exact
+// enough for |k| < 2^20, far beyond the angles met here), then the Taylor
+// polynomials of sin and cos in r^2 (terms through r^15 / r^16 in FP64, r^9 /
+// r^10 in FP32; truncation below half an ulp on |r| <= pi/4), and the quadrant
+// of k.
+__device__ __forceinline__ void sincos_r(double x, double& s, double& c) {
+  const double k = rint(x * 0.63661977236758134308);  // 2/pi
+  double r = fma(-k, 0x1.921fb54442d18p+0, x);
+  r = fma(-k, 0x1.1a62633145c07p-54, r);
+  const double r2 = r * r;
+  double ps = -1.0 / 1307674368000.0;
+  ps = fma(ps, r2, 1.0 / 6227020800.0);
+  ps = fma(ps, r2, -1.0 / 39916800.0);
+  ps = fma(ps, r2, 1.0 / 362880.0);
+  ps = fma(ps, r2, -1.0 / 5040.0);
+  ps = fma(ps, r2, 1.0 / 120.0);
+  ps = fma(ps, r2, -1.0 / 6.0);
+  const double sr = fma(r * r2, ps, r);
+  double pc = 1.0 / 20922789888000.0;
+  pc = fma(pc, r2, -1.0 / 87178291200.0);
+  pc = fma(pc, r2, 1.0 / 479001600.0);
+  pc = fma(pc, r2, -1.0 / 3628800.0);
+  pc = fma(pc, r2, 1.0 / 40320.0);
+  pc = fma(pc, r2, -1.0 / 720.0);
+  pc = fma(pc, r2, 1.0 / 24.0);
+  pc = fma(pc, r2, -0.5);
+  const double cr = fma(r2, pc, 1.0);
+  const int q = (int)k;
+  const double a = (q & 1) ? cr : sr;
+  const double b = (q & 1) ? sr : cr;
+  s = (q & 2) ? -a : a;
+  c = ((q + 1) & 2) ? -b : b;
+}
+
+__device__ __forceinline__ void sincos_r(float x, float& s, float& c) {
+  const float k = rintf(x * 0x1.45f306p-1f);  // 2/pi
+  float r = fmaf(-k, 0x1.921fb6p+0f, x);
+  r = fmaf(-k, -0x1.777a5cp-25f, r);
+  r = fmaf(-k, -0x1.ee59dap-50f, r);
+  const float r2 = r * r;
+  float ps = 1.0f / 362880.0f;
+  ps = fmaf(ps, r2, -1.0f / 5040.0f);
+  ps = fmaf(ps, r2, 1.0f / 120.0f);
+  ps = fmaf(ps, r2, -1.0f / 6.0f);
+  const float sr = fmaf(r * r2, ps, r);
+  float pc = -1.0f / 3628800.0f;
+  pc = fmaf(pc, r2, 1.0f / 40320.0f);
+  pc = fmaf(pc, r2, -1.0f / 720.0f);
+  pc = fmaf(pc, r2, 1.0f / 24.0f);
+  pc = fmaf(pc, r2, -0.5f);
+  const float cr = fmaf(r2, pc, 1.0f);
+  const int q = (int)k;
+  const float a = (q & 1) ? cr : sr;
+  const float b = (q & 1) ? sr : cr;
+  s = (q & 2) ? -a : a;
+  c = ((q + 1) & 2) ? -b : b;
+}
+
+// Right-hand side of the swing equations + OU disturbances in deviation form.
+template <typename R, int NG, int PM>
+__device__ __forceinline__ void swing_rhs(const R* cfg, const R wb, const R (&yd)[NG],
+                                          const R (&yw)[NG], const R (&yx)[PM],
+                                          const R (&wv)[PM], R (&kd)[NG], R (&kw)[NG],
+                                          R (&kx)[PM]) {
+  constexpr PackLayout L{NG, PM};
+  // Re-derive the pointer at every stage: the compiler then streams the
+  // machine data through scalar loads instead of keeping it live in (spilled)
+  // registers across stages and steps.
+  asm volatile("" : "+s"(cfg));
+  const cptr<R> cf = (cptr<R>)cfg;
+  R dc[NG], ds[NG];
+#pragma unroll
+  for (int k = 0; k < NG; ++k) {
+    R sh, ch;
+    sincos_r(yd[k] * R(0.5), sh, ch);
+    const R sd = R(2) * sh * ch;   // sin d
+    const R omc = R(2) * sh * sh;  // 1 - cos d
+    const R c0 = cf[L.c0() + k], s0 = cf[L.s0() + k];
+    dc[k] = -(c0 * omc + s0 * sd);
+    ds[k] = c0 * sd - s0 * omc;
+  }
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    R ir = R(0), ii = R(0);
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const R yr = cf[L.yre() + i * NG + k];
+      const R yi = cf[L.yim() + i * NG + k];
+      ir += yr * dc[k] - yi * ds[k];
+      ii += yr * ds[k] + yi * dc[k];
+    }
+    const R dpe = dc[i] * cf[L.i0r() + i] + ds[i] * cf[L.i0i() + i] +
+                  (cf[L.c0() + i] + dc[i]) * ir + (cf[L.s0() + i] + ds[i]) * ii;
+    R F = cf[L.res() + i] - dpe - cf[L.dmp() + i] * yw[i];
+#pragma unroll
+    for (int p = 0; p < PM; ++p) F += cf[L.binc() + i * PM + p] * yx[p];
+    kd[i] = wb * yw[i];
+    kw[i] = F * cf[L.inv2h() + i];
+  }
+#pragma unroll
+  for (int p = 0; p < PM; ++p) kx[p] = -cf[L.theta() + p] * yx[p] + cf[L.sigma() + p] * wv[p];
+}
+
+// Per-wave two-pass statistics of one output time through an LDS transpose:
+// lane v of the wave reduces variable v over the wave's valid trajectories.
+template <typename R, int NG, int PM>
+__device__ __forceinline__ void emit_step(const IntegArgs<R>& a, double (*tile)[65], int lane,
+                                          int cnt, int64_t s, int slot, const R (&yd)[NG],
+                                          const R (&yw)[NG], const R (&yx)[PM]) {
+  const int n = a.n, P = a.P, V = a.V;
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    if (i < n) {
+      tile[i][lane] = (double)yd[i];
+      tile[n + i][lane] = (double)yw[i];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PM; ++p)
+    if (p < P) tile[2 * n + p][lane] = (double)yx[p];
+  __syncthreads();
+  const int64_t S1 = a.S + 1;
+  for (int v = lane; v < V; v += 64) {
+    double sm = 0.0;
+    for (int j = 0; j < cnt; ++j) sm += tile[v][j];
+    const double mu = sm / (double)cnt;
+    double m2 = 0.0;
+    for (int j = 0; j < cnt; ++j) {
+      const double d = tile[v][j] - mu;
+      m2 += d * d;
+    }
+    double2* dst = reinterpret_cast<double2*>(a.partial);
+    dst[((int64_t)blockIdx.x * S1 + s) * V + v] = make_double2(mu, m2);
+  }
+  if (slot >= 0) {
+    double* o = a.traj + ((int64_t)slot * S1 + s) * V;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      if (i < n) {
+        o[i] = a.delta0[i] + (double)yd[i];
+        o[n + i] = (double)yw[i];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p)
+      if (p < P) o[2 * n + p] = (double)yx[p];
+  }
+  __syncthreads();
+}
+
+template <typename R, int NG, int PM>
+__global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
+  constexpr PackLayout L{NG, PM};
+  constexpr int VM = 2 * NG + PM;
+  __shared__ double tile[VM][65];
+  const int lane = threadIdx.x;
+  const int64_t gidx = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t N = a.N;
+  const bool valid = gidx < N;
+  const int64_t ns = valid ? gidx : N - 1;
+  const int64_t rem = N - (int64_t)blockIdx.x * 64;
+  const int cnt = rem < 64 ? (int)rem : 64;
+  const int P = a.P;
+  const R* __restrict__ cf = a.coef;
+  const R* __restrict__ w = a.w;
+  const int slot = (valid && a.traj_slot) ? a.traj_slot[ns] : -1;
+
+  R yd[NG], yw[NG], yx[PM];
+  if (a.s_begin == 0) {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      yd[i] = R(0);
+      yw[i] = R(0);
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) yx[p] = cf[L.xi0() + p];
+    emit_step<R, NG, PM>(a, tile, lane, cnt, 0, slot, yd, yw, yx);
+  } else {
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      yd[i] = a.state[(int64_t)i * a.lanes + gidx];
+      yw[i] = a.state[(int64_t)(NG + i) * a.lanes + gidx];
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) yx[p] = a.state[(int64_t)(2 * NG + p) * a.lanes + gidx];
+  }
+
+  const R dt = a.dt, h2 = a.dt * R(0.5), dt6 = a.dt / R(6), wb = a.wb;
+  R w0[PM];
+#pragma unroll
+  for (int p = 0; p < PM; ++p) w0[p] = (p < P) ? w[(int64_t)p * N + ns] : R(0);
+
+  for (int64_t s = a.s_begin; s < a.s_end; ++s) {
+    const int64_t cl = 2 * s - a.c_base;
+    R w1[PM], w2[PM];
+#pragma unroll
+    for (int p = 0; p < PM; ++p) {
+      w1[p] = (p < P) ? w[((cl + 1) * P + p) * N + ns] : R(0);
+      w2[p] = (p < P) ? w[((cl + 2) * P + p) * N + ns] : R(0);
+    }
+    R kd[NG], kw[NG], kx[PM];
+    R ad[NG], aw[NG], ax[PM];
+    R td[NG], tw[NG], tx[PM];
+    // stage 1
+    swing_rhs<R, NG, PM>(cf, wb, yd, yw, yx, w0, kd, kw, kx);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      ad[i] = kd[i]; aw[i] = kw[i];
+      td[i] = yd[i] + h2 * kd[i]; tw[i] = yw[i] + h2 * kw[i];
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) { ax[p] = kx[p]; tx[p] = yx[p] + h2 * kx[p]; }
+    // stage 2
+    swing_rhs<R, NG, PM>(cf, wb, td, tw, tx, w1, kd, kw, kx);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      ad[i] += R(2) * kd[i]; aw[i] += R(2) * kw[i];
+      td[i] = yd[i] + h2 * kd[i]; tw[i] = yw[i] + h2 * kw[i];
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) { ax[p] += R(2) * kx[p]; tx[p] = yx[p] + h2 * kx[p]; }
+    // stage 3
+    swing_rhs<R, NG, PM>(cf, wb, td, tw, tx, w1, kd, kw, kx);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      ad[i] += R(2) * kd[i]; aw[i] += R(2) * kw[i];
+      td[i] = yd[i] + dt * kd[i]; tw[i] = yw[i] + dt * kw[i];
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) { ax[p] += R(2) * kx[p]; tx[p] = yx[p] + dt * kx[p]; }
+    // stage 4
+    swing_rhs<R, NG, PM>(cf, wb, td, tw, tx, w2, kd, kw, kx);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      yd[i] += dt6 * (ad[i] + kd[i]);
+      yw[i] += dt6 * (aw[i] + kw[i]);
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) {
+      yx[p] += dt6 * (ax[p] + kx[p]);
+      w0[p] = w2[p];
+    }
+    emit_step<R, NG, PM>(a, tile, lane, cnt, s + 1, slot, yd, yw, yx);
+  }
+
+#pragma unroll
+  for (int i = 0; i < NG; ++i) {
+    a.state[(int64_t)i * a.lanes + gidx] = yd[i];
+    a.state[(int64_t)(NG + i) * a.lanes + gidx] = yw[i];
+  }
+#pragma unroll
+  for (int p = 0; p < PM; ++p) a.state[(int64_t)(2 * NG + p) * a.lanes + gidx] = yx[p];
+
+  if (a.s_end == a.S && valid) {
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) bad |= !isfinite(yd[i]) || !isfinite(yw[i]);
+#pragma unroll
+    for (int p = 0; p < PM; ++p) bad |= !isfinite(yx[p]);
+    if (bad) {
+      atomicAdd(a.nonfinite, 1ULL);
+      atomicMin(a.first_bad, (long long)gidx);
+    }
+  }
+}
+
+}  // namespace fmc

@@ -1,0 +1,22 @@
+// k_integrate_f64.hip -- FP64 instantiations of the lane integrator.
+#include "k_integrate.hpp"
+#include "k_variants.hpp"
+
+namespace fmc {
+
+hipError_t launch_integrate_f64(int variant_id, const IntegArgs<double>& a, int64_t n_groups,
+                                hipStream_t st) {
+  int id = 0;
+#define FMC_X(NG, PM)                                                                     \
+  if (variant_id == id) {                                                                 \
+    hipLaunchKernelGGL((k_rk4_lane<double, NG, PM>), dim3((unsigned)n_groups), dim3(64), 0, \
+                       st, a);                                                            \
+    return hipGetLastError();                                                             \
+  }                                                                                       \
+  ++id;
+  FMC_LANE_VARIANTS(FMC_X)
+#undef FMC_X
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fmc

@@ -1,0 +1,347 @@
+// k_setup.hip -- scenario setup on the GPU (FP64): Kron reduction of the
+// network equations, operating point, packed coefficients; and the ordered
+// cross-sample merge of the per-group statistics.
+#include <hip/hip_runtime.h>
+
+#include "fmc_internal.hpp"
+
+namespace fmc {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+  // Smith's algorithm
+  if (fabs(b.x) >= fabs(b.y)) {
+    const double r = b.y / b.x, d = b.x + b.y * r;
+    return make_double2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  const double r = b.x / b.y, d = b.x * r + b.y;
+  return make_double2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+__device__ __forceinline__ double cabs2(double2 a) { return sqrt(a.x * a.x + a.y * a.y); }
+
+// ---------------------------------------------------------------------------
+// Kron reduction (eq. 2 eliminated): one workgroup.  work holds the augmented
+// system [Y_BB | Y_BA] (n_bus rows, n_bus + n_gen columns).  Gaussian
+// elimination with partial pivoting, then back substitution gives
+// X = Y_BB^-1 Y_BA and Y_red = Y_AA - Y_AB X.  Stamps are applied by one
+// thread in a fixed order so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_kron(NetDev net, double2* __restrict__ A,
+                                              double2* __restrict__ Yred, int* status) {
+  const int nb = net.n_bus, ng = net.n_gen, W = nb + ng;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  __shared__ double s_val[256];
+  __shared__ int s_idx[256];
+  __shared__ int s_bad;
+  for (int64_t q = tid; q < (int64_t)nb * W; q += nt) A[q] = make_double2(0.0, 0.0);
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
+  if (tid == 0) {
+    int bad = 0;
+    for (int k = 0; k < net.n_branch; ++k) {
+      const int f = net.from[k], t = net.to[k];
+      if (f < 0 || f >= nb || t < 0 || t >= nb || f == t) { bad = 1; break; }
+      const double2 y = cdiv(make_double2(1.0, 0.0), make_double2(net.r[k], net.x[k]));
+      const double2 sh = make_double2(0.0, net.b ? 0.5 * net.b[k] : 0.0);
+      A[(int64_t)f * W + f] = cadd(A[(int64_t)f * W + f], cadd(y, sh));
+      A[(int64_t)t * W + t] = cadd(A[(int64_t)t * W + t], cadd(y, sh));
+      A[(int64_t)f * W + t] = csub(A[(int64_t)f * W + t], y);
+      A[(int64_t)t * W + f] = csub(A[(int64_t)t * W + f], y);
+    }
+    for (int b = 0; b < nb && !bad; ++b)
+      A[(int64_t)b * W + b] = cadd(A[(int64_t)b * W + b],
+                                   make_double2(net.lg ? net.lg[b] : 0.0, net.lb ? net.lb[b] : 0.0));
+    for (int g = 0; g < ng && !bad; ++g) {
+      const int b = net.gen_bus[g];
+      if (b < 0 || b >= nb || !(net.xdp[g] > 0.0)) { bad = 1; break; }
+      const double2 yg = make_double2(0.0, -1.0 / net.xdp[g]);  // 1/(j X'd)
+      A[(int64_t)b * W + b] = cadd(A[(int64_t)b * W + b], yg);
+      A[(int64_t)b * W + nb + g] = csub(A[(int64_t)b * W + nb + g], yg);  // Y_BA = -yg
+    }
+    s_bad = bad;
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) *status = -1;
+    return;
+  }
+  for (int k = 0; k < nb; ++k) {
+    // pivot: largest |A[r][k]|, lowest row on ties
+    double best = -1.0;
+    int bi = nb;
+    for (int r = k + tid; r < nb; r += nt) {
+      const double v = cabs2(A[(int64_t)r * W + k]);
+      if (v > best) { best = v; bi = r; }
+    }
+    s_val[tid] = best;
+    s_idx[tid] = bi;
+    __syncthreads();
+    for (int off = nt / 2; off > 0; off >>= 1) {
+      if (tid < off) {
+        const double v2 = s_val[tid + off];
+        const int i2 = s_idx[tid + off];
+        if (v2 > s_val[tid] || (v2 == s_val[tid] && i2 < s_idx[tid])) {
+          s_val[tid] = v2;
+          s_idx[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int piv = s_idx[0];
+    const double pv = s_val[0];
+    __syncthreads();
+    if (!(pv > 0.0)) {
+      if (tid == 0) *status = -1;
+      return;
+    }
+    if (piv != k) {
+      for (int c = k + tid; c < W; c += nt) {
+        const double2 t = A[(int64_t)k * W + c];
+        A[(int64_t)k * W + c] = A[(int64_t)piv * W + c];
+        A[(int64_t)piv * W + c] = t;
+      }
+    }
+    __syncthreads();
+    const double2 akk = A[(int64_t)k * W + k];
+    const int rows = nb - k - 1, cols = W - k - 1;
+    for (int64_t q = tid; q < (int64_t)rows * cols; q += nt) {
+      const int r = k + 1 + (int)(q / cols);
+      const int c = k + 1 + (int)(q % cols);
+      const double2 f = cdiv(A[(int64_t)r * W + k], akk);
+      A[(int64_t)r * W + c] = csub(A[(int64_t)r * W + c], cmul(f, A[(int64_t)k * W + c]));
+    }
+    __syncthreads();
+  }
+  // back substitution on the n_gen right-hand columns
+  for (int k = nb - 1; k >= 0; --k) {
+    for (int g = tid; g < ng; g += nt) {
+      double2 acc = A[(int64_t)k * W + nb + g];
+      for (int j = k + 1; j < nb; ++j) acc = csub(acc, cmul(A[(int64_t)k * W + j], A[(int64_t)j * W + nb + g]));
+      A[(int64_t)k * W + nb + g] = cdiv(acc, A[(int64_t)k * W + k]);
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < ng * ng; q += nt) {
+    const int i = q / ng, k = q % ng;
+    const double2 yg = make_double2(0.0, -1.0 / net.xdp[i]);
+    double2 v = (i == k) ? yg : make_double2(0.0, 0.0);
+    v = cadd(v, cmul(yg, A[(int64_t)net.gen_bus[i] * W + nb + k]));  // -(Y_AB X), Y_AB = -yg
+    Yred[q] = v;
+  }
+  if (tid == 0) *status = 0;
+}
+
+hipError_t launch_kron(const NetDev& net, double2* work, double2* Yred, int* status,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_kron, dim3(1), dim3(256), 0, st, net, work, Yred, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Operating point.  Pe_i = Re{E~_i conj(I_i)}, I = Y E~ + Yinf V_inf.  Given
+// delta0: Pm defaults to Pe(delta0) (equilibrium).  Without delta0 (infinite
+// bus): Newton on Pe(delta) = Pm from delta = 0, dense LU with partial
+// pivoting, serial in one thread (small n).
+// ---------------------------------------------------------------------------
+__device__ void op_currents(const SetupDev& s, const double* d, double2* Et, double2* I) {
+  const int n = s.n;
+  for (int k = 0; k < n; ++k) Et[k] = make_double2(s.E[k] * cos(d[k]), s.E[k] * sin(d[k]));
+  for (int i = 0; i < n; ++i) {
+    double2 c = (s.inf_bus && s.Yinf) ? make_double2(s.Yinf[i].x * s.V_inf, s.Yinf[i].y * s.V_inf)
+                                      : make_double2(0.0, 0.0);
+    for (int k = 0; k < n; ++k) c = cadd(c, cmul(s.Y[(int64_t)i * n + k], Et[k]));
+    I[i] = c;
+  }
+}
+
+__global__ void k_setup(SetupDev s) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int n = s.n, P = s.P;
+  CanonLayout L{n, P};
+  double* cn = s.canon;
+  double* d = cn + L.delta0();
+  double2* Et = (double2*)s.work;
+  double2* I = Et + n;
+  double* J = (double*)(I + n);
+  double* rhs = J + (int64_t)n * n;
+  int ok = 1;
+  if (s.delta0) {
+    for (int i = 0; i < n; ++i) d[i] = s.delta0[i];
+  } else {
+    for (int i = 0; i < n; ++i) d[i] = 0.0;
+    ok = 0;
+    for (int it = 0; it < 100; ++it) {
+      op_currents(s, d, Et, I);
+      for (int i = 0; i < n; ++i) {
+        const double pe = Et[i].x * I[i].x + Et[i].y * I[i].y;
+        rhs[i] = s.Pm[i] - pe;
+        for (int k = 0; k < n; ++k) {
+          // d Pe_i / d delta_k
+          const double2 yk = cmul(s.Y[(int64_t)i * n + k], make_double2(-Et[k].y, Et[k].x));
+          double v = Et[i].x * yk.x + Et[i].y * yk.y;
+          if (k == i) v += -Et[i].y * I[i].x + Et[i].x * I[i].y;
+          J[(int64_t)i * n + k] = v;
+        }
+      }
+      // solve J dx = rhs
+      int sing = 0;
+      for (int k = 0; k < n && !sing; ++k) {
+        int piv = k;
+        double best = fabs(J[(int64_t)k * n + k]);
+        for (int r = k + 1; r < n; ++r)
+          if (fabs(J[(int64_t)r * n + k]) > best) { best = fabs(J[(int64_t)r * n + k]); piv = r; }
+        if (best == 0.0) { sing = 1; break; }
+        if (piv != k) {
+          for (int c = 0; c < n; ++c) {
+            const double t = J[(int64_t)k * n + c];
+            J[(int64_t)k * n + c] = J[(int64_t)piv * n + c];
+            J[(int64_t)piv * n + c] = t;
+          }
+          const double t = rhs[k]; rhs[k] = rhs[piv]; rhs[piv] = t;
+        }
+        for (int r = k + 1; r < n; ++r) {
+          const double f = J[(int64_t)r * n + k] / J[(int64_t)k * n + k];
+          for (int c = k; c < n; ++c) J[(int64_t)r * n + c] -= f * J[(int64_t)k * n + c];
+          rhs[r] -= f * rhs[k];
+        }
+      }
+      if (sing) break;
+      double nrm = 0.0;
+      for (int k = n - 1; k >= 0; --k) {
+        double acc = rhs[k];
+        for (int j = k + 1; j < n; ++j) acc -= J[(int64_t)k * n + j] * rhs[j];
+        rhs[k] = acc / J[(int64_t)k * n + k];
+      }
+      for (int i = 0; i < n; ++i) {
+        d[i] += rhs[i];
+        nrm = fmax(nrm, fabs(rhs[i]));
+      }
+      if (nrm <= 1e-15) { ok = 1; break; }
+    }
+  }
+  op_currents(s, d, Et, I);
+  for (int i = 0; i < n; ++i) {
+    const double pe = Et[i].x * I[i].x + Et[i].y * I[i].y;
+    const double pm = s.Pm ? s.Pm[i] : pe;
+    cn[L.c0() + i] = Et[i].x;
+    cn[L.s0() + i] = Et[i].y;
+    cn[L.i0r() + i] = I[i].x;
+    cn[L.i0i() + i] = I[i].y;
+    cn[L.res() + i] = pm - pe;
+    cn[L.dmp() + i] = s.D[i];
+    cn[L.inv2h() + i] = 1.0 / (2.0 * s.H[i]);
+    cn[L.pm() + i] = pm;
+    for (int k = 0; k < n; ++k) {
+      cn[L.yre() + (int64_t)i * n + k] = s.Y[(int64_t)i * n + k].x;
+      cn[L.yim() + (int64_t)i * n + k] = s.Y[(int64_t)i * n + k].y;
+    }
+  }
+  for (int p = 0; p < P; ++p) {
+    cn[L.theta() + p] = s.theta[p];
+    cn[L.sigma() + p] = s.sigma[p];
+    cn[L.xi0() + p] = s.xi0 ? s.xi0[p] : 0.0;
+  }
+  *s.status = ok ? 0 : -6;
+}
+
+hipError_t launch_setup(const SetupDev& s, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup, dim3(1), dim3(64), 0, st, s);
+  return hipGetLastError();
+}
+
+// Packed, padded coefficients of a variant in its arithmetic type.
+template <typename R>
+__global__ void __launch_bounds__(256) k_pack(const double* __restrict__ cn, int n, int P,
+                                              const int32_t* __restrict__ gen, int NG, int PM,
+                                              R* __restrict__ coef) {
+  CanonLayout C{n, P};
+  PackLayout L{NG, PM};
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.size()) return;
+  double v = 0.0;
+  if (q < L.yim()) {
+    const int i = q / NG, k = q % NG;
+    if (i < n && k < n) v = cn[C.yre() + (int64_t)i * n + k];
+  } else if (q < L.binc()) {
+    const int e = q - L.yim(), i = e / NG, k = e % NG;
+    if (i < n && k < n) v = cn[C.yim() + (int64_t)i * n + k];
+  } else if (q < L.c0()) {
+    const int e = q - L.binc(), i = e / PM, p = e % PM;
+    v = (i < n && p < P && gen[p] == i) ? 1.0 : 0.0;
+  } else if (q < L.theta()) {
+    const int e = q - L.c0(), f = e / NG, i = e % NG;
+    // fields c0, s0, i0r, i0i, res, dmp, inv2h in canonical order
+    const int64_t base[7] = {C.c0(), C.s0(), C.i0r(), C.i0i(), C.res(), C.dmp(), C.inv2h()};
+    if (i < n) v = cn[base[f] + i];
+  } else {
+    const int e = q - L.theta(), f = e / PM, p = e % PM;
+    const int64_t base[3] = {C.theta(), C.sigma(), C.xi0()};
+    if (p < P) v = cn[base[f] + p];
+  }
+  coef[q] = (R)v;
+}
+
+template <typename R>
+hipError_t launch_pack(const double* canon, int n, int P, const int32_t* gen, int NG, int PM,
+                       R* coef, hipStream_t st) {
+  PackLayout L{NG, PM};
+  hipLaunchKernelGGL(k_pack<R>, dim3((L.size() + 255) / 256), dim3(256), 0, st, canon, n, P, gen,
+                     NG, PM, coef);
+  return hipGetLastError();
+}
+template hipError_t launch_pack<double>(const double*, int, int, const int32_t*, int, int,
+                                        double*, hipStream_t);
+template hipError_t launch_pack<float>(const double*, int, int, const int32_t*, int, int, float*,
+                                       hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Cross-sample statistics (Alg. 1 step 4).  Each sample group (a wave's
+// trajectories) left its exact two-pass (mean, M2) per output; they are merged
+// here in group order with Chan's pairwise update, so the result does not
+// depend on scheduling.  Angles get delta0 back (the integrator works in
+// deviations).  One thread per (step, variable).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_stats_merge(const double2* __restrict__ partial,
+                                                     int64_t n_groups, int group_size, int64_t N,
+                                                     int64_t SV, int V, int n, int ddof,
+                                                     const double* __restrict__ delta0,
+                                                     double* __restrict__ mean,
+                                                     double* __restrict__ var) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= SV) return;
+  double cnt = 0.0, m = 0.0, M2 = 0.0;
+  for (int64_t g = 0; g < n_groups; ++g) {
+    const int64_t rem = N - g * group_size;
+    const double nb = (double)(rem < group_size ? rem : group_size);
+    const double2 pt = partial[g * SV + q];
+    if (g == 0) {
+      cnt = nb;
+      m = pt.x;
+      M2 = pt.y;
+    } else {
+      const double tot = cnt + nb;
+      const double dlt = pt.x - m;
+      m += dlt * (nb / tot);
+      M2 += pt.y + dlt * dlt * (cnt * nb / tot);
+      cnt = tot;
+    }
+  }
+  const int v = (int)(q % V);
+  mean[q] = m + (v < n ? delta0[v] : 0.0);
+  var[q] = M2 / (double)(N - ddof);
+}
+
+hipError_t launch_stats_merge(const double2* partial, int64_t n_groups, int group_size,
+                              int64_t N, int64_t S, int V, int n, int ddof,
+                              const double* delta0, double* mean, double* var, hipStream_t st) {
+  const int64_t SV = (S + 1) * V;
+  hipLaunchKernelGGL(k_stats_merge, dim3((unsigned)((SV + 255) / 256)), dim3(256), 0, st, partial,
+                     n_groups, group_size, N, SV, V, n, ddof, delta0, mean, var);
+  return hipGetLastError();
+}
+
+}  // namespace fmc
