@@ -1,0 +1,182 @@
+"""Benchmark of the fast Monte Carlo hot path on one MI355X.
+
+One step = one pass of the whole method (setup, LHS design, basis, KLE path
+contraction, integration of every sample, statistics) on the 10-machine
+workload: classical swing model on a seeded 39-bus-shaped synthetic network,
+3 OU disturbances, K = 100 per process (M = 300), N = 1e4 samples,
+T = 20 s, dt = 5 ms (4000 RK4 steps).  Inputs are synthetic and seeded.
+
+Prints one JSON line.  value = N * S / (seconds per step) trajectory-steps/s of
+the plain FP64 form; the FP32 and BF16x3 forms of the same workload are
+reported under "forms" with their error against the FP64 oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_FP64_VECTOR = 78.6e12
+PEAK_FP32_VECTOR = 157.3e12
+PEAK_HBM = 8.0e12
+
+
+def integrator_flops_per_traj_step(n: int, P: int) -> float:
+    """Algorithmic flops of one RK4 step of one trajectory (classical model).
+
+    Per stage: complex matvec Y dE (n^2 complex MACs = 8 n^2 flops); per machine
+    25 flops (rotation 11, power deviation 9, accelerating power 3, derivatives
+    2) plus one sin/cos pair counted as 20 flops; per process 4 flops.  Per
+    step: 4 stages and 13 flops per state variable for the RK4 combination.
+    """
+    stage = 8 * n * n + (25 + 20) * n + 4 * P
+    return 4 * stage + 13 * (2 * n + P)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--forms", default="f64,f32,bf16x3")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; every box has one GPU, "
+                                   "run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2007_03847_amd as fmc
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    ctx = fmc.Context(0)
+    sc = workloads.config2()
+    n, P, N, K = sc["n_gen"], len(sc["dist"]["gen"]), sc["N"], sc["K"]
+    S = fmc.steps(sc)
+    sel = np.array([0, 1, 2345, 5000, 7777, N - 1])
+    forms = [f for f in args.forms.split(",") if f]
+
+    results = {}
+    tuned = {}
+    for form in forms:
+        # untimed: the autotuner picks the integrator variant for this workload
+        tuned[form] = ctx.autotune(sc, precision=form)
+        outs = None
+        for _ in range(args.warmup):
+            r = ctx.run(sc, precision=form)
+            outs = dict(mean=r["mean"], var=r["var"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t_int = 0.0
+        n_launch = 0
+        reps = []
+        for _ in range(args.steps):
+            r = ctx.run(sc, precision=form, outputs=outs)
+            outs = dict(mean=r["mean"], var=r["var"])
+            reps.append(r["report"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms = (t1 - t0) * 1e3 / args.steps
+        rep = reps[-1]
+        t_int = sum(x["t_integrate_s"] for x in reps) / args.steps
+        chunks = int(np.ceil(S / rep["time_chunk"]))
+        # sampled trajectories for the error report
+        rt = ctx.run(sc, precision=form, traj_idx=sel)
+        results[form] = dict(ms=ms, rep=rep, t_int=t_int, chunks=chunks,
+                             mean=rt["mean"].cpu().numpy(), var=rt["var"].cpu().numpy(),
+                             traj=rt["traj"].cpu().numpy())
+
+    # ---- CPU oracle: baseline timing and error reference
+    cpu = None
+    errs = {}
+    if not args.no_cpu:
+        import oracle
+        t0 = time.perf_counter()
+        probe = oracle.run(sc, sel=np.arange(64))
+        t_probe = time.perf_counter() - t0
+        n_cpu = int(min(N, max(64, 64 * args.cpu_seconds / max(t_probe, 1e-3))))
+        if n_cpu >= N:
+            t0 = time.perf_counter()
+            o = oracle.run(sc)
+            t_cpu = time.perf_counter() - t0
+            n_cpu = N
+        else:
+            cpu_sel = np.linspace(0, N - 1, n_cpu).round().astype(np.int64)
+            t0 = time.perf_counter()
+            o = oracle.run(sc, sel=cpu_sel)
+            t_cpu = time.perf_counter() - t0
+        cpu = {"value": n_cpu * S / t_cpu, "unit": "trajectory-steps/s",
+               "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"{n_cpu} of {N} samples of the same workload ({S} steps each), "
+                         f"FP64 C oracle with OpenMP over samples, {t_cpu:.1f} s"}
+        ot = oracle.run(sc, sel=sel, want_traj=True)["traj"]
+        for form, res in results.items():
+            tr = res["traj"]
+            num = np.abs(tr - ot).reshape(-1, tr.shape[-1]).max(axis=0)
+            den = np.abs(ot).reshape(-1, tr.shape[-1]).max(axis=0)
+            e = {"traj_rel": float((num / np.where(den == 0, 1, den)).max())}
+            if n_cpu == N:
+                dm = np.abs(res["mean"] - o["mean"]).max(axis=0)
+                sm = np.maximum(np.abs(o["mean"]).max(axis=0), np.sqrt(o["var"]).max(axis=0))
+                dv = np.abs(res["var"] - o["var"]).max(axis=0) / np.abs(o["var"]).max(axis=0)
+                e["mean_rel"] = float((dm / sm).max())
+                e["var_rel"] = float(dv.max())
+            errs[form] = e
+
+    head = "f64" if "f64" in results else forms[0]
+    res = results[head]
+    value = N * S / (res["ms"] * 1e-3)
+    flops_step = integrator_flops_per_traj_step(n, P)
+    # dominant kernel: the integrator; algorithmic flops per launch / mean launch time
+    flops_launch = flops_step * N * res["rep"]["time_chunk"]
+    achieved = flops_step * N * S / res["t_int"] if res["t_int"] > 0 else 0.0
+    peak = PEAK_FP64_VECTOR if head == "f64" else PEAK_FP32_VECTOR
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None, "kernel": "k_rk4_lane",
+            "flops_per_launch": flops_launch,
+            "mean_launch_ms": res["t_int"] / res["chunks"] * 1e3}
+    forms_out = {}
+    for form, r in results.items():
+        forms_out[form] = {"value": N * S / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
+                           "integrator_ms": r["t_int"] * 1e3,
+                           "integrator_tflops": flops_step * N * S / r["t_int"] / 1e12,
+                           "gemm_ms": r["rep"]["t_gemm_s"] * 1e3,
+                           "lhs_ms": r["rep"]["t_lhs_s"] * 1e3,
+                           "stats_ms": r["rep"]["t_stats_s"] * 1e3,
+                           "variant": r["rep"]["variant_id"],
+                           "lanes_per_traj": r["rep"]["lanes_per_traj"],
+                           "group_size": r["rep"]["tile"],
+                           "time_chunk": r["rep"]["time_chunk"],
+                           "error_vs_oracle": errs.get(form)}
+    line = {
+        "metric": "trajectory-steps/s", "value": value, "unit": "trajectory-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "bf16x3": "bf16x3+f32"}[head],
+        "data": "synthetic",
+        "config": {"workload": "10-machine classical swing model, seeded 39-bus synthetic "
+                               "network, 3 OU disturbances, K=100, N=1e4, T=20 s, dt=5 ms "
+                               "(4000 RK4 steps), LHS seed 2",
+                   "n_gen": n, "n_proc": P, "K": K, "N": N, "steps": S, "precision": head},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "forms": forms_out,
+    }
+    print(json.dumps(line))
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -257,6 +257,14 @@ int fmc_poll(fmc_context *ctx, uint64_t ticket);   /* FMC_OK done, FMC_EAGAIN pe
 int fmc_wait(fmc_context *ctx, uint64_t ticket, double timeout_s);
 int fmc_cancel(fmc_context *ctx, uint64_t ticket); /* the ticket then reports FMC_ECANCELLED */
 
+/* Autotuner: times every compiled integrator variant that fits the scenario
+ * (machines, processes; lanes per trajectory and workgroup size differ) on a
+ * short horizon at the scenario's N and precision, caches the fastest for the
+ * (n, P, N bucket, precision) key in the context (used by every later call
+ * with variant = -1), appends it to the JSON file named by the environment
+ * variable FMC_TUNE_CACHE if set, and returns it in *variant. */
+int fmc_autotune(fmc_context *ctx, const fmc_scenario *scen, int32_t *variant);
+
 /* Device bytes a scenario needs while it runs (the admission footprint). */
 int fmc_footprint(const fmc_scenario *scen, int64_t *bytes);
 

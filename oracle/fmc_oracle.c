@@ -91,9 +91,10 @@ double orc_u01(uint64_t x)
 /* LHS Step 2 (Sec. IV-B): a random permutation of the N strata of each row.  */
 /* The paper leaves the permutation algorithm open; the reading taken is a    */
 /* counter-based bijection: an 8-round balanced Feistel network on 2h bits,   */
-/* h = ceil(ceil(log2 N)/2) (at least 1), round function = low h bits of one  */
-/* Philox draw keyed on (row i, round r, right half R), restricted to [0,N)   */
-/* by cycle-walking.                                                          */
+/* h = ceil(ceil(log2 N)/2) (at least 1), restricted to [0,N) by              */
+/* cycle-walking.  Round r of row i uses the key k_{i,r} = one Philox draw    */
+/* keyed on (i, r); its round function is the low h bits of the splitmix64    */
+/* finaliser (Steele, Lea and Flood, OOPSLA 2014) of R xor k_{i,r}.           */
 /* ------------------------------------------------------------------------- */
 static int feistel_half_bits(int64_t N)
 {
@@ -103,15 +104,24 @@ static int feistel_half_bits(int64_t N)
     return h < 1 ? 1 : h;
 }
 
+static uint64_t splitmix64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
 int64_t orc_lhs_stratum(uint64_t seed, int64_t i, int64_t N, int64_t n)
 {
     const int h = feistel_half_bits(N);
     const uint64_t mask = (1ULL << h) - 1ULL;
+    uint64_t key[8];
+    for (int r = 0; r < 8; ++r) key[r] = draw(seed, (uint64_t)i, (uint64_t)r, 0, TAG_PERM);
     uint64_t x = (uint64_t)n;
     do {
         uint64_t L = x >> h, R = x & mask;
         for (int r = 0; r < 8; ++r) {
-            uint64_t f = draw(seed, (uint64_t)i, (uint64_t)r, R, TAG_PERM) & mask;
+            uint64_t f = splitmix64_mix(R ^ key[r]) & mask;
             uint64_t newL = R;
             uint64_t newR = L ^ f;
             L = newL;

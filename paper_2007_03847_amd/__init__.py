@@ -112,6 +112,7 @@ _sig = {
     "fmc_wait": ([_ctx_p, C.c_uint64, C.c_double], C.c_int),
     "fmc_cancel": ([_ctx_p, C.c_uint64], C.c_int),
     "fmc_footprint": ([C.POINTER(Scenario), C.POINTER(C.c_int64)], C.c_int),
+    "fmc_autotune": ([_ctx_p, C.POINTER(Scenario), C.POINTER(C.c_int32)], C.c_int),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -283,6 +284,14 @@ class Context:
         _check(_lib.fmc_kle_paths(self._h, prec, P, K, N, C_cols, c0, _dptr(zeta), _dptr(phi),
                                   phi.shape[1], _dptr(w)))
         return w
+
+    def autotune(self, sc: dict, precision="f64") -> int:
+        """Pick (and cache in the context) the fastest integrator variant."""
+        sysd, dist, par, keep = scenario_structs(sc, precision)
+        s = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))
+        v = C.c_int32(-1)
+        _check(_lib.fmc_autotune(self._h, C.byref(s), C.byref(v)))
+        return int(v.value)
 
     # ------------------------------------------------------------ whole path
     def run(self, sc: dict, precision="f64", traj_idx=None, want_design=False, variant=-1,

@@ -60,9 +60,11 @@ __device__ __forceinline__ double u01(uint64_t x) {
 
 // ---------------------------------------------------------------------------
 // Stratum permutation of one LHS row: an 8-round balanced Feistel network on
-// 2h bits (round function: low h bits of a Philox draw keyed on the row, the
-// round and the right half), cycle-walked into [0, N).  A bijection of [0, N)
-// computed per element, so no permutation is stored.
+// 2h bits, cycle-walked into [0, N).  Round r of row i xors the right half
+// with the low h bits of the splitmix64 finaliser (Steele, Lea and Flood 2014)
+// of R ^ k_{i,r}, where the round keys k_{i,r} are Philox draws keyed on
+// (i, r).  A bijection of [0, N) computed per element, so no permutation is
+// stored; the eight keys of a row are drawn once per workgroup.
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ int feistel_half_bits(int64_t N) {
   int b = 0;
@@ -71,15 +73,21 @@ __host__ __device__ __forceinline__ int feistel_half_bits(int64_t N) {
   return h < 1 ? 1 : h;
 }
 
-__device__ __forceinline__ int64_t lhs_stratum(uint64_t seed, uint64_t row, int64_t N, int h,
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int64_t lhs_stratum(const uint64_t (&key)[8], int64_t N, int h,
                                                int64_t n) {
   const uint64_t mask = (1ULL << h) - 1ULL;
   uint64_t x = (uint64_t)n;
   do {
     uint64_t L = x >> h, R = x & mask;
-#pragma unroll 1
-    for (uint64_t r = 0; r < 8; ++r) {
-      const uint64_t f = draw64(seed, row, r, R, kTagPerm) & mask;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const uint64_t f = mix64(R ^ key[r]) & mask;
       const uint64_t t = L ^ f;
       L = R;
       R = t;

@@ -121,9 +121,12 @@ hipError_t launch_stats_merge(const double2* partial, int64_t n_groups, int grou
                               int64_t N, int64_t S, int V, int n, int ddof,
                               const double* delta0, double* mean, double* var, hipStream_t st);
 
-// Integrator variants: lanes_per_traj = 1, NG machines and PM processes per lane.
+// Integrator variants: NG machines, PM processes, L lanes per trajectory,
+// WPB waves per workgroup; a workgroup integrates group_size() trajectories.
 struct VariantInfo {
-  int id, NG, PM, lanes_per_traj, prec;  // prec: 0 FP64, 1 FP32
+  int id, NG, PM, L, WPB;
+  int group_size() const { return (64 / L) * WPB; }
+  int G() const { return (NG + L - 1) / L; }
 };
 int n_variants();
 const VariantInfo& variant(int i);

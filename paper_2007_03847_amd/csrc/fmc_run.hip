@@ -52,8 +52,9 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
   const VariantInfo& vi = variant(vid);
   const int V = 2 * n + P;
   const int64_t C = 2 * S + 1;
-  const int64_t n_groups = (N + 63) / 64;
-  const int64_t lanes = n_groups * 64;
+  const int64_t gs = vi.group_size();
+  const int64_t n_groups = (N + gs - 1) / gs;
+  const int64_t lanes = n_groups * 64 * vi.WPB;
   const int bw = (int)sizeof(R);
   void *w = nullptr, *state = nullptr;
   int rc;
@@ -130,7 +131,7 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   const bool dev_out = out->mem_kind == FMC_MEM_DEVICE;
   const bool f64 = par->precision == FMC_F64;
   const int bw = f64 ? 8 : 4;
-  const int vid = par->variant >= 0 ? par->variant : choose_variant(n, P);
+  const int vid = par->variant >= 0 ? par->variant : pick_variant(c, n, P, N, par->precision);
   if (vid < 0 || vid >= n_variants())
     return fail(FMC_EINVAL, "no integrator variant for n=" + std::to_string(n) + ", P=" + std::to_string(P));
   const VariantInfo& vi = variant(vid);
@@ -186,16 +187,20 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   }
   const int ev_lhs1 = evp.record();
 
-  // per-wave statistics partials, trajectory slots, counters
-  const int64_t n_groups = (N + 63) / 64;
+  // per-workgroup statistics partials, trajectory slots, counters
+  const int64_t gsize = vi.group_size();
+  const int64_t n_groups = (N + gsize - 1) / gsize;
   void *partial = nullptr, *cnt = nullptr;
   if ((rc = c->ensure("partial", (size_t)n_groups * (S + 1) * V * 2 * sizeof(double), &partial)))
     return rc;
   if ((rc = c->ensure("counters", 64, &cnt))) return rc;
   {
-    const unsigned long long init[2] = {0ULL, (unsigned long long)LLONG_MAX};
-    HIPCHK(hipMemcpyAsync(cnt, init, sizeof(init), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    void* h = nullptr;
+    if ((rc = c->host_stage("counters", 64, &h))) return rc;
+    unsigned long long* init = (unsigned long long*)h;
+    init[0] = 0ULL;
+    init[1] = (unsigned long long)LLONG_MAX;
+    HIPCHK(hipMemcpyAsync(cnt, init, 2 * sizeof(unsigned long long), hipMemcpyHostToDevice, c->stream));
   }
   int32_t* slot_d = nullptr;
   double* traj_d = nullptr;
@@ -207,11 +212,12 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
       if (slot[idx] >= 0) return fail(FMC_EINVAL, "traj_idx has a duplicate");
       slot[idx] = q;
     }
-    void* p = nullptr;
+    void *p = nullptr, *h = nullptr;
     if ((rc = c->ensure("traj_slot", (size_t)N * sizeof(int32_t), &p))) return rc;
+    if ((rc = c->host_stage("traj_slot", (size_t)N * sizeof(int32_t), &h))) return rc;
+    std::memcpy(h, slot.data(), (size_t)N * sizeof(int32_t));
     slot_d = (int32_t*)p;
-    HIPCHK(hipMemcpyAsync(slot_d, slot.data(), (size_t)N * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpyAsync(slot_d, h, (size_t)N * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
     if (dev_out) {
       traj_d = out->traj;
     } else {
@@ -242,7 +248,7 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     mean_d = (double*)pm;
     var_d = (double*)pv;
   }
-  HIPCHK(launch_stats_merge((const double2*)partial, n_groups, 64, N, S, V, n, par->ddof, delta0_d,
+  HIPCHK(launch_stats_merge((const double2*)partial, n_groups, (int)gsize, N, S, V, n, par->ddof, delta0_d,
                             mean_d, var_d, c->stream));
   const int ev_end = evp.record();
 
@@ -257,10 +263,12 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     if (out->strata && strata_dev)
       HIPCHK(hipMemcpyAsync(out->strata, strata_dev, (size_t)M * N * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   }
-  int status[2] = {0, 0};
-  unsigned long long cn[2] = {0, 0};
-  HIPCHK(hipMemcpyAsync(status, status_d, sizeof(status), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(cn, cnt, sizeof(cn), hipMemcpyDeviceToHost, c->stream));
+  void* hb = nullptr;
+  if ((rc = c->host_stage("readback", 64, &hb))) return rc;
+  int* status = (int*)hb;
+  unsigned long long* cn = (unsigned long long*)((char*)hb + 16);
+  HIPCHK(hipMemcpyAsync(status, status_d, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(cn, cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   if (status[1] != 0) return fail(FMC_EINVAL, "network reduction failed (singular Y_BB)");
   if (status[0] != 0) return fail(FMC_ENOTCONV, "operating-point Newton solve did not converge");
@@ -278,8 +286,8 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     r->n_nonfinite = (int64_t)cn[0];
     r->first_nonfinite = cn[0] ? (int64_t)cn[1] : -1;
     r->variant_id = vid;
-    r->lanes_per_traj = vi.lanes_per_traj;
-    r->tile = 64;
+    r->lanes_per_traj = vi.L;
+    r->tile = (int32_t)gsize;
     r->time_chunk = (int32_t)Sc;
     r->hbm_peak_bytes = (int64_t)std::max(c->held, held0);
   }

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -34,8 +35,8 @@ static const std::vector<VariantInfo>& lane_table() {
   static const std::vector<VariantInfo> t = [] {
     std::vector<VariantInfo> v;
     int id = 0;
-#define FMC_X(NG, PM) v.push_back(VariantInfo{id++, NG, PM, 1, 0});
-    FMC_LANE_VARIANTS(FMC_X)
+#define FMC_X(NG, PM, L, WPB) v.push_back(VariantInfo{id++, NG, PM, L, WPB});
+    FMC_VARIANTS(FMC_X)
 #undef FMC_X
     return v;
   }();
@@ -45,21 +46,67 @@ static const std::vector<VariantInfo>& lane_table() {
 int n_variants() { return (int)lane_table().size(); }
 const VariantInfo& variant(int i) { return lane_table()[i]; }
 
-int choose_variant(int n, int P) {
+// Cost model used when no tuned choice is cached: per-step work of one
+// workgroup-wave times the number of waves that run back to back on the busiest
+// SIMD (1024 SIMDs, occupancy ignored), plus a padding penalty.
+int choose_variant(int n, int P, int64_t N) {
   int best = -1;
+  double best_cost = 0.0;
   for (const auto& v : lane_table()) {
-    if (v.NG >= n && v.PM >= std::max(P, 1)) {
-      if (best < 0) {
-        best = v.id;
-      } else {
-        const auto& b = lane_table()[best];
-        const long cost_v = (long)v.NG * v.NG * 4 + v.PM;
-        const long cost_b = (long)b.NG * b.NG * 4 + b.PM;
-        if (cost_v < cost_b) best = v.id;
-      }
+    if (v.NG < n || v.PM < std::max(P, 1)) continue;
+    const double G = v.G();
+    const double lane_work = G * v.NG * 4.0 + G * 40.0 + v.PM * 4.0 + (v.L > 1 ? v.NG * 2.0 : 0.0);
+    const double waves = std::ceil((double)N * v.L / 64.0);
+    const double rounds = std::ceil(waves / 1024.0);
+    // a wave alone on its SIMD runs about 4x slower than the issue rate
+    const double lat = waves < 2048.0 ? 4.0 : 1.0;
+    const double cost = lane_work * rounds * lat;
+    if (best < 0 || cost < best_cost) {
+      best = v.id;
+      best_cost = cost;
     }
   }
   return best;
+}
+
+std::string tune_key(int n, int P, int64_t N, int precision) {
+  int nb = 0;
+  while (((int64_t)1 << (nb + 1)) <= N) ++nb;  // floor(log2 N)
+  return std::to_string(n) + "/" + std::to_string(P) + "/" + std::to_string(nb) + "/" +
+         std::to_string(precision);
+}
+
+int pick_variant(Context* c, int n, int P, int64_t N, int precision) {
+  auto it = c->tuned.find(tune_key(n, P, N, precision));
+  if (it != c->tuned.end() && it->second >= 0 && it->second < n_variants()) {
+    const VariantInfo& v = variant(it->second);
+    if (v.NG >= n && v.PM >= P) return it->second;
+  }
+  return choose_variant(n, P, N);
+}
+
+// Tuner cache file: one {"key": ..., "variant": ...} object per line.
+static void load_tune_cache(Context* c) {
+  const char* path = std::getenv("FMC_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {
+    char key[256];
+    int vid = -1;
+    if (std::sscanf(line, " {\"key\": \"%255[^\"]\", \"variant\": %d", key, &vid) == 2) c->tuned[key] = vid;
+  }
+  std::fclose(f);
+}
+
+static void save_tune_entry(const std::string& key, int vid) {
+  const char* path = std::getenv("FMC_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"variant\": %d}\n", key.c_str(), vid);
+  std::fclose(f);
 }
 
 // ---------------------------------------------------------------------------
@@ -100,10 +147,37 @@ int Context::ensure(const char* name, size_t bytes, void** out) {
   return FMC_OK;
 }
 
+int Context::host_stage(const char* name, size_t bytes, void** out) {
+  bytes = std::max<size_t>(bytes, 256);
+  DevBuf& b = pinned[name];
+  if (b.cap < bytes) {
+    if (b.p) {
+      hipError_t e = hipStreamSynchronize(stream);
+      if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+      (void)hipHostFree(b.p);
+      b.p = nullptr;
+      b.cap = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(FMC_ENOMEM, std::string("hipHostMalloc failed for ") + name);
+    }
+    b.p = p;
+    b.cap = bytes;
+  }
+  *out = b.p;
+  return FMC_OK;
+}
+
 void Context::release_all() {
   for (auto& kv : bufs)
     if (kv.second.p) (void)hipFree(kv.second.p);
   bufs.clear();
+  for (auto& kv : pinned)
+    if (kv.second.p) (void)hipHostFree(kv.second.p);
+  pinned.clear();
   held = 0;
 }
 
@@ -124,13 +198,12 @@ struct Stager {
   }
   int upload(Context* c, const char* name) {
     if (bytes.empty()) return FMC_OK;
-    void* d = nullptr;
+    void *d = nullptr, *h = nullptr;
     int rc = c->ensure(name, bytes.size(), &d);
     if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(d, bytes.data(), bytes.size(), hipMemcpyHostToDevice, c->stream);
-    if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
-    // the host bytes must stay valid until the copy ends
-    e = hipStreamSynchronize(c->stream);
+    if ((rc = c->host_stage(name, bytes.size(), &h))) return rc;
+    std::memcpy(h, bytes.data(), bytes.size());
+    hipError_t e = hipMemcpyAsync(d, h, bytes.size(), hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
     for (auto& f : fix) *f.second = (unsigned char*)d + f.first;
     return FMC_OK;
@@ -328,6 +401,7 @@ int fmc_context_create(int device, size_t hbm_budget, void* stream, fmc_context*
       return fail(FMC_EDEVICE, "hipEventCreate failed");
     }
   }
+  load_tune_cache(c);
   *out = reinterpret_cast<fmc_context*>(c);
   return FMC_OK;
 }
@@ -419,11 +493,67 @@ int fmc_kle_paths(fmc_context* ctx, int32_t precision, int32_t P, int32_t K, int
   return FMC_OK;
 }
 
+int fmc_autotune(fmc_context* ctx, const fmc_scenario* scen, int32_t* variant_out) {
+  if (!ctx || !scen || !scen->sys || !scen->dist || !scen->par || !variant_out)
+    return fail(FMC_EINVAL, "NULL argument");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  int64_t S = 0;
+  int rc = validate(scen->sys, scen->dist, scen->par, &S);
+  if (rc) return rc;
+  const int n = scen->sys->n_gen, P = scen->dist->n_proc;
+  const int64_t N = scen->par->N;
+  const int V = 2 * n + P;
+  // short horizon at the real N: enough steps to amortise launch effects
+  const int64_t St = std::min<int64_t>(S, 96);
+  fmc_params par = *scen->par;
+  par.T = (double)St * par.dt;
+  par.time_chunk = 0;
+  void *m = nullptr, *v = nullptr;
+  if ((rc = c->ensure("tune_mean", (size_t)(St + 1) * V * sizeof(double), &m))) return rc;
+  if ((rc = c->ensure("tune_var", (size_t)(St + 1) * V * sizeof(double), &v))) return rc;
+  int best = -1;
+  double best_t = 0.0;
+  for (int id = 0; id < n_variants(); ++id) {
+    const VariantInfo& vi = variant(id);
+    if (vi.NG < n || vi.PM < P) continue;
+    par.variant = id;
+    fmc_report rep;
+    fmc_outputs out{};
+    out.mean = (double*)m;
+    out.var = (double*)v;
+    out.mem_kind = FMC_MEM_DEVICE;
+    out.report = &rep;
+    double t = 0.0;
+    for (int rep_i = 0; rep_i < 2; ++rep_i) {  // first run warms caches and allocations
+      rc = run_single(c, scen->sys, scen->dist, &par, &out);
+      if (rc != FMC_OK && rc != FMC_ENONFINITE) {
+        (void)hipStreamSynchronize(c->stream);
+        return rc;
+      }
+      t = rep.t_integrate_s;
+    }
+    if (best < 0 || t < best_t) {
+      best = id;
+      best_t = t;
+    }
+  }
+  if (best < 0) return fail(FMC_EINVAL, "no integrator variant fits the scenario");
+  const std::string key = tune_key(n, P, N, scen->par->precision);
+  c->tuned[key] = best;
+  save_tune_entry(key, best);
+  *variant_out = best;
+  return FMC_OK;
+}
+
 int fmc_run(fmc_context* ctx, const fmc_system* sys, const fmc_disturbance* dist,
             const fmc_params* par, fmc_outputs* out) {
   if (!ctx || !out) return fail(FMC_EINVAL, "NULL context or outputs");
   Context* c = reinterpret_cast<Context*>(ctx);
-  return run_single(c, sys, dist, par, out);
+  const int rc = run_single(c, sys, dist, par, out);
+  // a failed call may have left copies and kernels in flight that read staging
+  // buffers the next call rewrites: drain the stream before returning
+  if (rc != FMC_OK && rc != FMC_ENONFINITE) (void)hipStreamSynchronize(c->stream);
+  return rc;
 }
 
 }  // extern "C"

@@ -26,10 +26,16 @@ struct Context {
   hipStream_t stream = nullptr;
   size_t budget = 0, held = 0, peak = 0;
   std::map<std::string, DevBuf> bufs;
+  std::map<std::string, DevBuf> pinned;  // page-locked host staging, grow-only
   hipEvent_t ev[8] = {};
   ServeState* serve = nullptr;
+  std::map<std::string, int> tuned;  // autotuner cache: key -> variant id
 
   int ensure(const char* name, size_t bytes, void** out);
+  // Page-locked host buffer for asynchronous uploads.  A buffer is rewritten
+  // only by a later call on this context, and every call that uploads from it
+  // synchronises the stream before it returns, so no copy is in flight then.
+  int host_stage(const char* name, size_t bytes, void** out);
   void release_all();
 };
 
@@ -38,7 +44,9 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
 int stage_scenario(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
                    const char* tag, double** canon_out, int32_t** gen_out, int** status_out);
 int kron_on_device(Context* c, const fmc_network* net, double2* Yd, int* st_dev);
-int choose_variant(int n, int P);
+int choose_variant(int n, int P, int64_t N);
+std::string tune_key(int n, int P, int64_t N, int precision);
+int pick_variant(Context* c, int n, int P, int64_t N, int precision);
 int64_t auto_chunk(int64_t S, int P, int64_t N, int bytes_per);
 int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
                const fmc_params* par, fmc_outputs* out);

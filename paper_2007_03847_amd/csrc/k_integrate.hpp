@@ -217,17 +217,23 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
   }
 
   const R dt = a.dt, h2 = a.dt * R(0.5), dt6 = a.dt / R(6), wb = a.wb;
-  R w0[PM];
+  // KLE path values of the next step are loaded one step ahead.
+  R w0[PM], w1[PM], w2[PM];
 #pragma unroll
-  for (int p = 0; p < PM; ++p) w0[p] = (p < P) ? w[(int64_t)p * N + ns] : R(0);
+  for (int p = 0; p < PM; ++p) {
+    w0[p] = (p < P) ? w[(int64_t)p * N + ns] : R(0);
+    w1[p] = (p < P) ? w[((int64_t)1 * P + p) * N + ns] : R(0);
+    w2[p] = (p < P) ? w[((int64_t)2 * P + p) * N + ns] : R(0);
+  }
 
   for (int64_t s = a.s_begin; s < a.s_end; ++s) {
     const int64_t cl = 2 * s - a.c_base;
-    R w1[PM], w2[PM];
+    const bool more = s + 1 < a.s_end;
+    R n1[PM], n2[PM];
 #pragma unroll
     for (int p = 0; p < PM; ++p) {
-      w1[p] = (p < P) ? w[((cl + 1) * P + p) * N + ns] : R(0);
-      w2[p] = (p < P) ? w[((cl + 2) * P + p) * N + ns] : R(0);
+      n1[p] = (more && p < P) ? w[((cl + 3) * P + p) * N + ns] : R(0);
+      n2[p] = (more && p < P) ? w[((cl + 4) * P + p) * N + ns] : R(0);
     }
     R kd[NG], kw[NG], kx[PM];
     R ad[NG], aw[NG], ax[PM];
@@ -270,6 +276,8 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
     for (int p = 0; p < PM; ++p) {
       yx[p] += dt6 * (ax[p] + kx[p]);
       w0[p] = w2[p];
+      w1[p] = n1[p];
+      w2[p] = n2[p];
     }
     emit_step<R, NG, PM>(a, tile, lane, cnt, s + 1, slot, yd, yw, yx);
   }
@@ -291,6 +299,295 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
     if (bad) {
       atomicAdd(a.nonfinite, 1ULL);
       atomicMin(a.first_bad, (long long)gidx);
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Group variant: L lanes share one trajectory (any L <= 64; a wave holds
+// floor(64/L) trajectories and leaves the remaining lanes idle), lane g owns
+// the G = ceil(NG/L) machines g*G .. g*G+G-1 and the rows of Y for them (held
+// in registers, read once).  Per stage each lane rotates its own machines, the
+// (dRe E~, dIm E~) pairs of a trajectory are exchanged through LDS (the lanes
+// of a trajectory are in one wave, whose LDS operations complete in order, so
+// only a compiler-level wavefront fence is needed), and each lane forms the
+// network currents of its rows.  Every lane integrates the P disturbance
+// processes of its trajectory (cheap) so that each can add the injections of
+// its own machines.  A workgroup of WPB waves merges the statistics of its
+// trajectories once per step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename R> struct vec2;
+template <> struct vec2<double> { using type = double2; };
+template <> struct vec2<float> { using type = float2; };
+
+template <typename R, int NG, int PM, int L, int WPB>
+__global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
+  using R2 = typename vec2<R>::type;
+  constexpr PackLayout Lp{NG, PM};
+  constexpr int G = (NG + L - 1) / L;
+  constexpr int NGP = G * L;            // padded machine slots per trajectory
+  constexpr int TW = 64 / L;            // trajectories per wave
+  constexpr int TB = TW * WPB;          // trajectories per workgroup
+  constexpr int VM = 2 * NG + PM;
+  // statistics tile: the values of up to D consecutive output steps are
+  // buffered and reduced together, two workgroup barriers per D steps
+  constexpr int D = WPB == 1 ? 4 : 8;
+  __shared__ double tile[D][VM][TB + 1];
+  __shared__ R2 xch[TB + 1][NGP + 1];   // row TB: scratch of the idle lanes
+  __shared__ int bad_t[TB + 1];
+  const int tid = threadIdx.x;
+  const int wv = tid >> 6, ln = tid & 63;
+  const bool lane_on = ln < TW * L;
+  const int tl = lane_on ? wv * TW + ln / L : TB;
+  const int g = lane_on ? ln % L : 0;
+  const int64_t traj = (int64_t)blockIdx.x * TB + tl;
+  const int64_t N = a.N;
+  const bool valid = lane_on && traj < N;
+  const int64_t ns = valid ? traj : N - 1;
+  const int64_t rem = N - (int64_t)blockIdx.x * TB;
+  const int cnt = rem < TB ? (int)rem : TB;
+  const int n = a.n, P = a.P, V = a.V;
+  const R* __restrict__ cf = a.coef;
+  const R* __restrict__ w = a.w;
+  const int slot = (valid && g == 0 && a.traj_slot) ? a.traj_slot[ns] : -1;
+
+  // per-lane machine data (rows of Y and the operating point of my machines)
+  R yr[G][NG], yi[G][NG], c0[G], s0[G], i0r[G], i0i[G], res[G], dmp[G], inv2h[G], binc[G][PM];
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int i = g * G + q;
+    const bool on = i < NG;
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      yr[q][k] = on ? cf[Lp.yre() + i * NG + k] : R(0);
+      yi[q][k] = on ? cf[Lp.yim() + i * NG + k] : R(0);
+    }
+    c0[q] = on ? cf[Lp.c0() + i] : R(0);
+    s0[q] = on ? cf[Lp.s0() + i] : R(0);
+    i0r[q] = on ? cf[Lp.i0r() + i] : R(0);
+    i0i[q] = on ? cf[Lp.i0i() + i] : R(0);
+    res[q] = on ? cf[Lp.res() + i] : R(0);
+    dmp[q] = on ? cf[Lp.dmp() + i] : R(0);
+    inv2h[q] = on ? cf[Lp.inv2h() + i] : R(0);
+#pragma unroll
+    for (int p = 0; p < PM; ++p) binc[q][p] = on ? cf[Lp.binc() + i * PM + p] : R(0);
+  }
+  R theta[PM], sigma[PM];
+#pragma unroll
+  for (int p = 0; p < PM; ++p) {
+    theta[p] = cf[Lp.theta() + p];
+    sigma[p] = cf[Lp.sigma() + p];
+  }
+
+  auto rhs = [&](const R (&yd)[G], const R (&yw)[G], const R (&yx)[PM], const R (&wv)[PM],
+                 R (&kd)[G], R (&kw)[G], R (&kx)[PM]) {
+    R dc[G], ds[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      R sh, ch;
+      sincos_r(yd[q] * R(0.5), sh, ch);
+      const R sd = R(2) * sh * ch;
+      const R omc = R(2) * sh * sh;
+      dc[q] = -(c0[q] * omc + s0[q] * sd);
+      ds[q] = c0[q] * sd - s0[q] * omc;
+      xch[tl][g * G + q] = R2{dc[q], ds[q]};
+    }
+    wave_lds_sync();
+    // two accumulator pairs (even / odd columns) halve the FMA dependency chains
+    R ir[G], ii[G], jr[G], ji[G];
+#pragma unroll
+    for (int q = 0; q < G; ++q) { ir[q] = R(0); ii[q] = R(0); jr[q] = R(0); ji[q] = R(0); }
+#pragma unroll
+    for (int k = 0; k < NG; ++k) {
+      const R2 e = xch[tl][k];
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        if (k & 1) {
+          jr[q] += yr[q][k] * e.x - yi[q][k] * e.y;
+          ji[q] += yr[q][k] * e.y + yi[q][k] * e.x;
+        } else {
+          ir[q] += yr[q][k] * e.x - yi[q][k] * e.y;
+          ii[q] += yr[q][k] * e.y + yi[q][k] * e.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) { ir[q] += jr[q]; ii[q] += ji[q]; }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const R dpe = dc[q] * i0r[q] + ds[q] * i0i[q] + (c0[q] + dc[q]) * ir[q] + (s0[q] + ds[q]) * ii[q];
+      R F = res[q] - dpe - dmp[q] * yw[q];
+#pragma unroll
+      for (int p = 0; p < PM; ++p) F += binc[q][p] * yx[p];
+      kd[q] = a.wb * yw[q];
+      kw[q] = F * inv2h[q];
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) kx[p] = -theta[p] * yx[p] + sigma[p] * wv[p];
+  };
+
+  // Reduce the buffered steps [s_first, s_first + nb): thread q of the
+  // workgroup takes rows (step, variable) q, q + 64 WPB, ...
+  auto flush = [&](int64_t s_first, int nb) {
+    __syncthreads();
+    const int64_t S1 = a.S + 1;
+    for (int rv = tid; rv < nb * V; rv += 64 * WPB) {
+      const int b = rv / V, v = rv % V;
+      const double* row = tile[b][v];
+      double sm = 0.0;
+      for (int j = 0; j < cnt; ++j) sm += row[j];
+      const double mu = sm / (double)cnt;
+      double m2 = 0.0;
+      for (int j = 0; j < cnt; ++j) {
+        const double d = row[j] - mu;
+        m2 += d * d;
+      }
+      reinterpret_cast<double2*>(a.partial)[((int64_t)blockIdx.x * S1 + s_first + b) * V + v] =
+          make_double2(mu, m2);
+    }
+    if (slot >= 0) {
+      // lane g == 0 of a selected trajectory writes its rows from LDS
+      for (int b = 0; b < nb; ++b) {
+        double* o = a.traj + ((int64_t)slot * S1 + s_first + b) * V;
+        for (int v = 0; v < V; ++v) o[v] = tile[b][v][tl] + (v < n ? a.delta0[v] : 0.0);
+      }
+    }
+    __syncthreads();
+  };
+  int nbuf = 0;
+  int64_t s_first = 0;
+  auto emit = [&](int64_t s, const R (&yd)[G], const R (&yw)[G], const R (&yx)[PM]) {
+    if (nbuf == 0) s_first = s;
+    double (*tb)[TB + 1] = tile[nbuf];
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      const int i = g * G + q;
+      if (lane_on && i < n) {
+        tb[i][tl] = (double)yd[q];
+        tb[n + i][tl] = (double)yw[q];
+      }
+    }
+    if (lane_on && g == 0) {
+#pragma unroll
+      for (int p = 0; p < PM; ++p)
+        if (p < P) tb[2 * n + p][tl] = (double)yx[p];
+    }
+    if (++nbuf == D) {
+      flush(s_first, nbuf);
+      nbuf = 0;
+    }
+  };
+
+  R yd[G], yw[G], yx[PM];
+  const int64_t lane_id = (int64_t)blockIdx.x * 64 * WPB + tid;
+  if (a.s_begin == 0) {
+#pragma unroll
+    for (int q = 0; q < G; ++q) { yd[q] = R(0); yw[q] = R(0); }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) yx[p] = cf[Lp.xi0() + p];
+    emit(0, yd, yw, yx);
+  } else {
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      yd[q] = a.state[(int64_t)q * a.lanes + lane_id];
+      yw[q] = a.state[(int64_t)(G + q) * a.lanes + lane_id];
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) yx[p] = a.state[(int64_t)(2 * G + p) * a.lanes + lane_id];
+  }
+
+  const R dt = a.dt, h2 = a.dt * R(0.5), dt6 = a.dt / R(6);
+  // KLE path values: the two new stage columns of step s are loaded one step
+  // ahead so their memory latency overlaps the previous step's arithmetic.
+  R w0[PM], w1[PM], w2[PM];
+#pragma unroll
+  for (int p = 0; p < PM; ++p) {
+    w0[p] = (p < P) ? w[(int64_t)p * N + ns] : R(0);
+    w1[p] = (p < P) ? w[((int64_t)1 * P + p) * N + ns] : R(0);
+    w2[p] = (p < P) ? w[((int64_t)2 * P + p) * N + ns] : R(0);
+  }
+  for (int64_t s = a.s_begin; s < a.s_end; ++s) {
+    const int64_t cl = 2 * s - a.c_base;
+    const bool more = s + 1 < a.s_end;
+    R n1[PM], n2[PM];
+#pragma unroll
+    for (int p = 0; p < PM; ++p) {
+      n1[p] = (more && p < P) ? w[((cl + 3) * P + p) * N + ns] : R(0);
+      n2[p] = (more && p < P) ? w[((cl + 4) * P + p) * N + ns] : R(0);
+    }
+    R kd[G], kw[G], kx[PM], ad[G], aw[G], ax[PM], td[G], tw[G], tx[PM];
+    rhs(yd, yw, yx, w0, kd, kw, kx);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      ad[q] = kd[q]; aw[q] = kw[q];
+      td[q] = yd[q] + h2 * kd[q]; tw[q] = yw[q] + h2 * kw[q];
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) { ax[p] = kx[p]; tx[p] = yx[p] + h2 * kx[p]; }
+    rhs(td, tw, tx, w1, kd, kw, kx);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      ad[q] += R(2) * kd[q]; aw[q] += R(2) * kw[q];
+      td[q] = yd[q] + h2 * kd[q]; tw[q] = yw[q] + h2 * kw[q];
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) { ax[p] += R(2) * kx[p]; tx[p] = yx[p] + h2 * kx[p]; }
+    rhs(td, tw, tx, w1, kd, kw, kx);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      ad[q] += R(2) * kd[q]; aw[q] += R(2) * kw[q];
+      td[q] = yd[q] + dt * kd[q]; tw[q] = yw[q] + dt * kw[q];
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) { ax[p] += R(2) * kx[p]; tx[p] = yx[p] + dt * kx[p]; }
+    rhs(td, tw, tx, w2, kd, kw, kx);
+#pragma unroll
+    for (int q = 0; q < G; ++q) {
+      yd[q] += dt6 * (ad[q] + kd[q]);
+      yw[q] += dt6 * (aw[q] + kw[q]);
+    }
+#pragma unroll
+    for (int p = 0; p < PM; ++p) {
+      yx[p] += dt6 * (ax[p] + kx[p]);
+      w0[p] = w2[p];
+      w1[p] = n1[p];
+      w2[p] = n2[p];
+    }
+    emit(s + 1, yd, yw, yx);
+  }
+
+  if (nbuf > 0) flush(s_first, nbuf);  // nbuf is uniform over the workgroup
+
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    a.state[(int64_t)q * a.lanes + lane_id] = yd[q];
+    a.state[(int64_t)(G + q) * a.lanes + lane_id] = yw[q];
+  }
+#pragma unroll
+  for (int p = 0; p < PM; ++p) a.state[(int64_t)(2 * G + p) * a.lanes + lane_id] = yx[p];
+
+  if (a.s_end == a.S) {  // uniform over the workgroup: the barriers below are safe
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < G; ++q) bad |= !isfinite(yd[q]) || !isfinite(yw[q]);
+#pragma unroll
+    for (int p = 0; p < PM; ++p) bad |= !isfinite(yx[p]);
+    // one count per trajectory: the lanes of a trajectory combine through LDS
+    if (lane_on && g == 0) bad_t[tl] = 0;
+    __syncthreads();
+    if (lane_on && bad) bad_t[tl] = 1;
+    __syncthreads();
+    if (valid && g == 0 && bad_t[tl] != 0) {
+      atomicAdd(a.nonfinite, 1ULL);
+      atomicMin(a.first_bad, (long long)traj);
     }
   }
 }

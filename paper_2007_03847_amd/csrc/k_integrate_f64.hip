@@ -1,4 +1,4 @@
-// k_integrate_f64.hip -- FP64 instantiations of the lane integrator.
+// k_integrate_f64.hip -- FP64 instantiations of the integrator variants.
 #include "k_integrate.hpp"
 #include "k_variants.hpp"
 
@@ -7,14 +7,18 @@ namespace fmc {
 hipError_t launch_integrate_f64(int variant_id, const IntegArgs<double>& a, int64_t n_groups,
                                 hipStream_t st) {
   int id = 0;
-#define FMC_X(NG, PM)                                                                     \
-  if (variant_id == id) {                                                                 \
-    hipLaunchKernelGGL((k_rk4_lane<double, NG, PM>), dim3((unsigned)n_groups), dim3(64), 0, \
-                       st, a);                                                            \
-    return hipGetLastError();                                                             \
-  }                                                                                       \
+#define FMC_X(NG, PM, L, WPB)                                                              \
+  if (variant_id == id) {                                                                  \
+    if constexpr (L == 1)                                                                  \
+      hipLaunchKernelGGL((k_rk4_lane<double, NG, PM>), dim3((unsigned)n_groups), dim3(64), 0,   \
+                         st, a);                                                           \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_rk4_group<double, NG, PM, L, WPB>), dim3((unsigned)n_groups),       \
+                         dim3(64 * WPB), 0, st, a);                                        \
+    return hipGetLastError();                                                              \
+  }                                                                                        \
   ++id;
-  FMC_LANE_VARIANTS(FMC_X)
+  FMC_VARIANTS(FMC_X)
 #undef FMC_X
   return hipErrorInvalidValue;
 }

@@ -16,11 +16,19 @@ __global__ void __launch_bounds__(256) k_lhs(uint64_t seed, int32_t M, int64_t N
                                              double* __restrict__ zeta) {
   const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i = blockIdx.y;
+  __shared__ uint64_t s_key[8];
+  if (sampler == 0) {
+    if (threadIdx.x < 8) s_key[threadIdx.x] = draw64(seed, (uint64_t)i, threadIdx.x, 0, kTagPerm);
+    __syncthreads();
+  }
   if (n >= N || i >= M) return;
   double z;
   int32_t s_out;
   if (sampler == 0) {
-    const int64_t s = lhs_stratum(seed, (uint64_t)i, N, h, n);
+    uint64_t key[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) key[r] = s_key[r];
+    const int64_t s = lhs_stratum(key, N, h, n);
     const double U = u01(draw64(seed, (uint64_t)i, (uint64_t)n, 0, kTagJitter));
     z = ppnd16(stratum_prob(s, U, N));
     s_out = (int32_t)s;

@@ -24,79 +24,80 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
 __device__ __forceinline__ double cabs2(double2 a) { return sqrt(a.x * a.x + a.y * a.y); }
 
 // ---------------------------------------------------------------------------
-// Kron reduction (eq. 2 eliminated): one workgroup.  work holds the augmented
-// system [Y_BB | Y_BA] (n_bus rows, n_bus + n_gen columns).  Gaussian
-// elimination with partial pivoting, then back substitution gives
-// X = Y_BB^-1 Y_BA and Y_red = Y_AA - Y_AB X.  Stamps are applied by one
-// thread in a fixed order so the result does not depend on scheduling.
+// Kron reduction (eq. 2 eliminated): one workgroup of 256 threads.  The
+// augmented system [Y_BB | Y_BA] (n_bus rows, n_bus + n_gen columns) lives in
+// LDS when it fits (else in the global work buffer).  Thread b assembles row b
+// alone, scanning branches, loads and generators in index order, so the sums
+// are deterministic.  Gaussian elimination with partial pivoting (pivot: the
+// largest |a_rk|, lowest row on ties, found by wave shuffles), then back
+// substitution gives X = Y_BB^-1 Y_BA and Y_red = Y_AA - Y_AB X.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_kron(NetDev net, double2* __restrict__ A,
+constexpr int kKronLdsComplex = 4096;  // 64 KB of double2
+
+__device__ __forceinline__ void kron_pivot_reduce(double& v, int& idx) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double v2 = __shfl_xor(v, off);
+    const int i2 = __shfl_xor(idx, off);
+    if (v2 > v || (v2 == v && i2 < idx)) {
+      v = v2;
+      idx = i2;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_kron(NetDev net, double2* __restrict__ gwork,
                                               double2* __restrict__ Yred, int* status) {
   const int nb = net.n_bus, ng = net.n_gen, W = nb + ng;
   const int tid = threadIdx.x, nt = blockDim.x;
-  __shared__ double s_val[256];
-  __shared__ int s_idx[256];
+  __shared__ double2 lds[kKronLdsComplex];
+  __shared__ double s_val[4];
+  __shared__ int s_idx[4];
   __shared__ int s_bad;
-  for (int64_t q = tid; q < (int64_t)nb * W; q += nt) A[q] = make_double2(0.0, 0.0);
+  double2* A = ((int64_t)nb * W <= kKronLdsComplex) ? lds : gwork;
   if (tid == 0) s_bad = 0;
-  __syncthreads();
-  if (tid == 0) {
-    int bad = 0;
+  // assembly: thread b owns row b
+  for (int b = tid; b < nb; b += nt) {
+    double2* row = A + (int64_t)b * W;
+    for (int c = 0; c < W; ++c) row[c] = make_double2(0.0, 0.0);
     for (int k = 0; k < net.n_branch; ++k) {
       const int f = net.from[k], t = net.to[k];
-      if (f < 0 || f >= nb || t < 0 || t >= nb || f == t) { bad = 1; break; }
+      if (f != b && t != b) continue;
       const double2 y = cdiv(make_double2(1.0, 0.0), make_double2(net.r[k], net.x[k]));
       const double2 sh = make_double2(0.0, net.b ? 0.5 * net.b[k] : 0.0);
-      A[(int64_t)f * W + f] = cadd(A[(int64_t)f * W + f], cadd(y, sh));
-      A[(int64_t)t * W + t] = cadd(A[(int64_t)t * W + t], cadd(y, sh));
-      A[(int64_t)f * W + t] = csub(A[(int64_t)f * W + t], y);
-      A[(int64_t)t * W + f] = csub(A[(int64_t)t * W + f], y);
+      row[b] = cadd(row[b], cadd(y, sh));
+      const int o = (f == b) ? t : f;
+      row[o] = csub(row[o], y);
     }
-    for (int b = 0; b < nb && !bad; ++b)
-      A[(int64_t)b * W + b] = cadd(A[(int64_t)b * W + b],
-                                   make_double2(net.lg ? net.lg[b] : 0.0, net.lb ? net.lb[b] : 0.0));
-    for (int g = 0; g < ng && !bad; ++g) {
-      const int b = net.gen_bus[g];
-      if (b < 0 || b >= nb || !(net.xdp[g] > 0.0)) { bad = 1; break; }
+    row[b] = cadd(row[b], make_double2(net.lg ? net.lg[b] : 0.0, net.lb ? net.lb[b] : 0.0));
+    for (int g = 0; g < ng; ++g) {
+      if (net.gen_bus[g] != b) continue;
       const double2 yg = make_double2(0.0, -1.0 / net.xdp[g]);  // 1/(j X'd)
-      A[(int64_t)b * W + b] = cadd(A[(int64_t)b * W + b], yg);
-      A[(int64_t)b * W + nb + g] = csub(A[(int64_t)b * W + nb + g], yg);  // Y_BA = -yg
+      row[b] = cadd(row[b], yg);
+      row[nb + g] = csub(row[nb + g], yg);  // Y_BA = -yg
     }
-    s_bad = bad;
   }
   __syncthreads();
-  if (s_bad) {
-    if (tid == 0) *status = -1;
-    return;
-  }
   for (int k = 0; k < nb; ++k) {
-    // pivot: largest |A[r][k]|, lowest row on ties
     double best = -1.0;
     int bi = nb;
     for (int r = k + tid; r < nb; r += nt) {
       const double v = cabs2(A[(int64_t)r * W + k]);
-      if (v > best) { best = v; bi = r; }
+      if (v > best || (v == best && r < bi)) { best = v; bi = r; }
     }
-    s_val[tid] = best;
-    s_idx[tid] = bi;
-    __syncthreads();
-    for (int off = nt / 2; off > 0; off >>= 1) {
-      if (tid < off) {
-        const double v2 = s_val[tid + off];
-        const int i2 = s_idx[tid + off];
-        if (v2 > s_val[tid] || (v2 == s_val[tid] && i2 < s_idx[tid])) {
-          s_val[tid] = v2;
-          s_idx[tid] = i2;
-        }
-      }
-      __syncthreads();
+    kron_pivot_reduce(best, bi);
+    if ((tid & 63) == 0) {
+      s_val[tid >> 6] = best;
+      s_idx[tid >> 6] = bi;
     }
-    const int piv = s_idx[0];
-    const double pv = s_val[0];
     __syncthreads();
+    double pv = s_val[0];
+    int piv = s_idx[0];
+    for (int w = 1; w < nt / 64; ++w)
+      if (s_val[w] > pv || (s_val[w] == pv && s_idx[w] < piv)) { pv = s_val[w]; piv = s_idx[w]; }
     if (!(pv > 0.0)) {
       if (tid == 0) *status = -1;
-      return;
+      return;  // uniform: every thread saw the same pv
     }
     if (piv != k) {
       for (int c = k + tid; c < W; c += nt) {
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256) k_kron(NetDev net, double2* __restrict__ 
     v = cadd(v, cmul(yg, A[(int64_t)net.gen_bus[i] * W + nb + k]));  // -(Y_AB X), Y_AB = -yg
     Yred[q] = v;
   }
-  if (tid == 0) *status = 0;
+  if (tid == 0) *status = s_bad;
 }
 
 hipError_t launch_kron(const NetDev& net, double2* work, double2* Yred, int* status,

@@ -1,21 +1,37 @@
-// k_variants.hpp -- the compiled integrator variants (one trajectory per
-// lane): X(NG machines, PM processes).  A scenario with n <= NG machines and
-// P <= PM processes runs on a variant padded with inert machines/processes.
+// k_variants.hpp -- the compiled integrator variants X(NG, PM, L, WPB):
+// NG machines and PM processes (a scenario with n <= NG and P <= PM runs on a
+// variant padded with inert entries), L lanes per trajectory (L = 1: the lane
+// kernel, machine data through scalar loads), WPB waves per workgroup.
 #pragma once
 
-#define FMC_LANE_VARIANTS(X) \
-  X(1, 1)                    \
-  X(2, 4)                    \
-  X(4, 4)                    \
-  X(4, 8)                    \
-  X(6, 4)                    \
-  X(8, 4)                    \
-  X(8, 8)                    \
-  X(10, 4)                   \
-  X(12, 4)                   \
-  X(12, 8)                   \
-  X(16, 4)                   \
-  X(16, 8)                   \
-  X(20, 8)                   \
-  X(24, 8)                   \
-  X(32, 8)
+#define FMC_VARIANTS(X) \
+  X(1, 1, 1, 1)         \
+  X(2, 4, 1, 1)         \
+  X(4, 4, 1, 1)         \
+  X(4, 8, 1, 1)         \
+  X(6, 4, 1, 1)         \
+  X(8, 4, 1, 1)         \
+  X(8, 8, 1, 1)         \
+  X(10, 4, 1, 1)        \
+  X(12, 4, 1, 1)        \
+  X(12, 8, 1, 1)        \
+  X(16, 4, 1, 1)        \
+  X(16, 8, 1, 1)        \
+  X(20, 8, 1, 1)        \
+  X(24, 8, 1, 1)        \
+  X(32, 8, 1, 1)        \
+  X(10, 4, 2, 1)        \
+  X(10, 4, 4, 1)        \
+  X(10, 4, 8, 1)        \
+  X(10, 4, 16, 1)       \
+  X(10, 4, 4, 4)        \
+  X(10, 4, 8, 4)        \
+  X(10, 4, 16, 4)       \
+  X(10, 4, 10, 1)       \
+  X(10, 4, 10, 2)       \
+  X(10, 4, 10, 4)       \
+  X(10, 4, 5, 1)        \
+  X(10, 4, 5, 4)        \
+  X(10, 4, 16, 2)       \
+  X(10, 4, 10, 8)       \
+  X(10, 4, 16, 8)
