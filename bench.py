@@ -40,6 +40,24 @@ def integrator_flops_per_traj_step(n: int, P: int) -> float:
     return 4 * stage + 13 * (2 * n + P)
 
 
+def measured_traffic(variant: int, precision: str):
+    """HBM bytes per integrator launch from the committed counter summary, or
+    None when that summary is for another variant or the kernel source has
+    changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json")):
+        try:
+            info = json.load(open(path))
+            src = open(os.path.join(ROOT, info["source"]), "rb").read()
+        except (OSError, ValueError, KeyError):
+            continue
+        if (info.get("variant") == variant and info.get("precision") == precision
+                and hashlib.sha256(src).hexdigest() == info.get("source_sha256")):
+            return info["hbm_bytes_per_launch"], info.get("steps_per_launch")
+    return None, None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -48,6 +66,10 @@ def main():
     ap.add_argument("--forms", default="f64,f32,bf16x3")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="integrator variant; -1 lets the autotuner choose (untimed)")
+    ap.add_argument("--copy-check", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; every box has one GPU, "
@@ -72,10 +94,11 @@ def main():
     tuned = {}
     for form in forms:
         # untimed: the autotuner picks the integrator variant for this workload
-        tuned[form] = ctx.autotune(sc, precision=form)
+        vid = args.variant if args.variant >= 0 else ctx.autotune(sc, precision=form)
+        tuned[form] = vid
         outs = None
         for _ in range(args.warmup):
-            r = ctx.run(sc, precision=form)
+            r = ctx.run(sc, precision=form, variant=vid)
             outs = dict(mean=r["mean"], var=r["var"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -83,7 +106,7 @@ def main():
         n_launch = 0
         reps = []
         for _ in range(args.steps):
-            r = ctx.run(sc, precision=form, outputs=outs)
+            r = ctx.run(sc, precision=form, outputs=outs, variant=vid)
             outs = dict(mean=r["mean"], var=r["var"])
             reps.append(r["report"])
         torch.cuda.synchronize()
@@ -93,10 +116,19 @@ def main():
         t_int = sum(x["t_integrate_s"] for x in reps) / args.steps
         chunks = int(np.ceil(S / rep["time_chunk"]))
         # sampled trajectories for the error report
-        rt = ctx.run(sc, precision=form, traj_idx=sel)
+        rt = ctx.run(sc, precision=form, traj_idx=sel, variant=vid)
         results[form] = dict(ms=ms, rep=rep, t_int=t_int, chunks=chunks,
                              mean=rt["mean"].cpu().numpy(), var=rt["var"].cpu().numpy(),
                              traj=rt["traj"].cpu().numpy())
+
+    if args.copy_check:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale
+        # the integrator's to bytes
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     # ---- CPU oracle: baseline timing and error reference
     cpu = None
@@ -143,8 +175,12 @@ def main():
     flops_launch = flops_step * N * res["rep"]["time_chunk"]
     achieved = flops_step * N * S / res["t_int"] if res["t_int"] > 0 else 0.0
     peak = PEAK_FP64_VECTOR if head == "f64" else PEAK_FP32_VECTOR
+    traffic, traffic_steps = measured_traffic(res["rep"]["variant_id"], head)
+    if traffic is not None and traffic_steps != res["rep"]["time_chunk"]:
+        traffic = None
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "kernel": "k_rk4_lane",
+            "frac": achieved / peak, "traffic": traffic,
+            "kernel": "k_rk4_group" if res["rep"]["lanes_per_traj"] > 1 else "k_rk4_lane",
             "flops_per_launch": flops_launch,
             "mean_launch_ms": res["t_int"] / res["chunks"] * 1e3}
     forms_out = {}

@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
   const int n = a.n, P = a.P, V = a.V;
   const R* __restrict__ cf = a.coef;
   const R* __restrict__ w = a.w;
-  const int slot = (valid && g == 0 && a.traj_slot) ? a.traj_slot[ns] : -1;
+  const int slot = (valid && a.traj_slot) ? a.traj_slot[ns] : -1;
 
   // per-lane machine data (rows of Y and the operating point of my machines)
   R yr[G][NG], yi[G][NG], c0[G], s0[G], i0r[G], i0i[G], res[G], dmp[G], inv2h[G], binc[G][PM];
@@ -453,13 +453,6 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
       reinterpret_cast<double2*>(a.partial)[((int64_t)blockIdx.x * S1 + s_first + b) * V + v] =
           make_double2(mu, m2);
     }
-    if (slot >= 0) {
-      // lane g == 0 of a selected trajectory writes its rows from LDS
-      for (int b = 0; b < nb; ++b) {
-        double* o = a.traj + ((int64_t)slot * S1 + s_first + b) * V;
-        for (int v = 0; v < V; ++v) o[v] = tile[b][v][tl] + (v < n ? a.delta0[v] : 0.0);
-      }
-    }
     __syncthreads();
   };
   int nbuf = 0;
@@ -479,6 +472,23 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
 #pragma unroll
       for (int p = 0; p < PM; ++p)
         if (p < P) tb[2 * n + p][tl] = (double)yx[p];
+    }
+    if (slot >= 0) {
+      // every lane of a selected trajectory writes its own outputs
+      double* o = a.traj + ((int64_t)slot * (a.S + 1) + s) * V;
+#pragma unroll
+      for (int q = 0; q < G; ++q) {
+        const int i = g * G + q;
+        if (i < n) {
+          o[i] = a.delta0[i] + (double)yd[q];
+          o[n + i] = (double)yw[q];
+        }
+      }
+      if (g == 0) {
+#pragma unroll
+        for (int p = 0; p < PM; ++p)
+          if (p < P) o[2 * n + p] = (double)yx[p];
+      }
     }
     if (++nbuf == D) {
       flush(s_first, nbuf);
