@@ -332,6 +332,58 @@ class Context:
         return r
 
 
+def _outputs_for(ctx, sc, traj_idx, keep):
+    t = ctx.torch
+    n = int(sc["n_gen"]); P = len(sc["dist"]["gen"]); S = steps(sc)
+    V = 2 * n + P
+    mean = t.empty((S + 1, V), dtype=t.float64, device=ctx.device)
+    var = t.empty((S + 1, V), dtype=t.float64, device=ctx.device)
+    traj = None
+    idx = None
+    if traj_idx is not None and len(traj_idx):
+        idx = np.ascontiguousarray(traj_idx, dtype=np.int64)
+        keep.append(idx)
+        traj = t.empty((len(idx), S + 1, V), dtype=t.float64, device=ctx.device)
+    rep = Report()
+    keep.append(rep)
+    out = Outputs(mean=_dptr(mean), var=_dptr(var), n_traj=0 if idx is None else len(idx),
+                  traj_idx=_ptr(idx), traj=_dptr(traj), strata=None, zeta=None,
+                  mem_kind=MEM_DEVICE, report=C.pointer(rep))
+    return out, dict(mean=mean, var=var, traj=traj, report=rep)
+
+
+def _run_batch(ctx, scs, precision="f32", traj_idx=None, variant=-1, allow_nonfinite=False):
+    keep = _Keep()
+    n = len(scs)
+    arr = (Scenario * n)()
+    outs = (Outputs * n)()
+    res = []
+    for i, sc in enumerate(scs):
+        sysd, dist, par, _ = scenario_structs(sc, precision, variant, keep=keep)
+        arr[i] = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))
+        ti = None if traj_idx is None else traj_idx[i]
+        o, r = _outputs_for(ctx, sc, ti, keep)
+        outs[i] = o
+        res.append(r)
+    rc = _lib.fmc_run_batch(ctx._h, n, arr, outs)
+    _check(rc, allow=(ENONFINITE,) if allow_nonfinite else ())
+    for r in res:
+        rep = r.pop("report")
+        r["report"] = rep.as_dict()
+        r["rc"] = rc
+        if r["traj"] is None:
+            r.pop("traj")
+    return res
+
+
+Context.run_batch = lambda self, scs, precision="f32", traj_idx=None, variant=-1, \
+    allow_nonfinite=False: _run_batch(self, scs, precision, traj_idx, variant, allow_nonfinite)
+Context.run_batch.__doc__ = """Batched form: a list of scenario dicts in one persistent launch.
+
+Returns one dict(mean, var[, traj], report, rc) per scenario.  traj_idx, if
+given, is a list (one entry per scenario, None allowed) of sample indices."""
+
+
 def footprint(sc: dict, precision="f64") -> int:
     sysd, dist, par, keep = scenario_structs(sc, precision)
     s = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))

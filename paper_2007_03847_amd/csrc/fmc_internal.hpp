@@ -135,4 +135,27 @@ hipError_t launch_integrate_f64(int variant_id, const IntegArgs<double>& a, int6
 hipError_t launch_integrate_f32(int variant_id, const IntegArgs<float>& a, int64_t n_groups,
                                 hipStream_t st);
 
+// Persistent batched integrator (FP32).
+struct BatchItem {
+  double2* rows;        // statistics rows [S+1][V] of this item
+  int64_t tile0, tile1; // trajectory tiles [tile0, tile1) of the scenario
+  int32_t scen, variant;
+};
+struct BatchArgs {
+  const IntegArgs<float>* scen;  // one per scenario (whole horizon, no chunking)
+  const BatchItem* items;
+  const int32_t* order;          // queue position -> item
+  int32_t n_items;
+  int32_t* head;                 // queue counter, zero before the launch
+};
+struct BatchVariantInfo {
+  int id, NG, PM, L, TB, cls;
+};
+constexpr int kBatchClasses = 3;
+int n_batch_variants();
+BatchVariantInfo batch_variant(int i);
+int persistent_blocks_per_cu(int cls);
+hipError_t launch_persistent(int cls, const BatchArgs& b, int grid, hipStream_t st);
+hipError_t launch_fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);
+
 }  // namespace fmc

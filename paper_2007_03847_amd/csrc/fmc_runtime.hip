@@ -143,6 +143,7 @@ int Context::ensure(const char* name, size_t bytes, void** out) {
   b.cap = bytes;
   held += bytes;
   peak = std::max(peak, held);
+  ++alloc_gen;
   *out = p;
   return FMC_OK;
 }
@@ -181,34 +182,19 @@ void Context::release_all() {
   held = 0;
 }
 
-// Host staging of small arrays into one device upload.
-struct Stager {
-  std::vector<unsigned char> bytes;
-  std::vector<std::pair<size_t, void**>> fix;  // (offset, where to store device ptr)
-  template <typename T>
-  void add(const T* src, size_t count, const T** dst) {
-    if (!src || count == 0) {
-      *dst = nullptr;
-      return;
-    }
-    const size_t off = (bytes.size() + 255) & ~size_t(255);
-    bytes.resize(off + count * sizeof(T));
-    std::memcpy(bytes.data() + off, src, count * sizeof(T));
-    fix.push_back({off, (void**)dst});
-  }
-  int upload(Context* c, const char* name) {
-    if (bytes.empty()) return FMC_OK;
-    void *d = nullptr, *h = nullptr;
-    int rc = c->ensure(name, bytes.size(), &d);
-    if (rc) return rc;
-    if ((rc = c->host_stage(name, bytes.size(), &h))) return rc;
-    std::memcpy(h, bytes.data(), bytes.size());
-    hipError_t e = hipMemcpyAsync(d, h, bytes.size(), hipMemcpyHostToDevice, c->stream);
-    if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
-    for (auto& f : fix) *f.second = (unsigned char*)d + f.first;
-    return FMC_OK;
-  }
-};
+int Stager::upload(Context* c, const char* name, hipStream_t st) {
+  if (bytes.empty()) return FMC_OK;
+  if (!st) st = c->stream;
+  void *d = nullptr, *h = nullptr;
+  int rc = c->ensure(name, bytes.size(), &d);
+  if (rc) return rc;
+  if ((rc = c->host_stage(name, bytes.size(), &h))) return rc;
+  std::memcpy(h, bytes.data(), bytes.size());
+  hipError_t e = hipMemcpyAsync(d, h, bytes.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  for (auto& f : fix) *f.second = (unsigned char*)d + f.first;
+  return FMC_OK;
+}
 
 static int check_network(const fmc_network* net) {
   if (!net) return fail(FMC_EINVAL, "network is NULL");
@@ -342,7 +328,7 @@ int stage_scenario(Context* c, const fmc_system* sys, const fmc_disturbance* dis
   CanonLayout L{n, P};
   if ((rc = c->ensure((std::string("canon_") + tag).c_str(), (size_t)L.size() * sizeof(double), &canon)))
     return rc;
-  hipError_t e = hipMemsetAsync(status, 0, 64, c->stream);
+  hipError_t e = launch_fill_i64((int64_t*)status, 0, 8, c->stream);
   if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
   if (!sd.Y) {
     if ((rc = c->ensure((std::string("yred_") + tag).c_str(), (size_t)n * n * sizeof(double2), &ybuf)))
@@ -412,6 +398,10 @@ int fmc_context_destroy(fmc_context* ctx) {
   (void)hipSetDevice(c->device);
   serve_shutdown(c);
   (void)hipStreamSynchronize(c->stream);
+  if (c->bstream) (void)hipStreamSynchronize(c->bstream);
+  for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.second);
+  c->graphs.clear();
+  if (c->bstream) (void)hipStreamDestroy(c->bstream);
   c->release_all();
   for (auto& ev : c->ev) (void)hipEventDestroy(ev);
   delete c;

@@ -3,8 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <map>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/fmc.h"
 #include "fmc_internal.hpp"
@@ -30,6 +33,9 @@ struct Context {
   hipEvent_t ev[8] = {};
   ServeState* serve = nullptr;
   std::map<std::string, int> tuned;  // autotuner cache: key -> variant id
+  uint64_t alloc_gen = 0;            // bumped whenever a device buffer moves
+  hipStream_t bstream = nullptr;     // capture stream of the batched form
+  std::map<std::string, std::pair<uint64_t, hipGraphExec_t>> graphs;  // shape -> (gen, graph)
 
   int ensure(const char* name, size_t bytes, void** out);
   // Page-locked host buffer for asynchronous uploads.  A buffer is rewritten
@@ -37,6 +43,25 @@ struct Context {
   // synchronises the stream before it returns, so no copy is in flight then.
   int host_stage(const char* name, size_t bytes, void** out);
   void release_all();
+};
+
+// Host staging of small arrays into one device upload (through a pinned
+// buffer of the context, no stream synchronisation).
+struct Stager {
+  std::vector<unsigned char> bytes;
+  std::vector<std::pair<size_t, void**>> fix;  // (offset, where to store device ptr)
+  template <typename T>
+  void add(const T* src, size_t count, const T** dst) {
+    if (!src || count == 0) {
+      *dst = nullptr;
+      return;
+    }
+    const size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + count * sizeof(T));
+    std::memcpy(bytes.data() + off, src, count * sizeof(T));
+    fix.push_back({off, (void**)dst});
+  }
+  int upload(Context* c, const char* name, hipStream_t st = nullptr);
 };
 
 int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_params* par,

@@ -44,11 +44,6 @@ int fmc_footprint(const fmc_scenario* scen, int64_t* bytes) {
   return FMC_OK;
 }
 
-int fmc_run_batch(fmc_context* ctx, int32_t n, const fmc_scenario* scen, fmc_outputs* outs) {
-  (void)ctx; (void)n; (void)scen; (void)outs;
-  return fail(FMC_EINVAL, "fmc_run_batch: not available in this build");
-}
-
 int fmc_submit(fmc_context* ctx, const fmc_scenario* scen, fmc_outputs* out, uint64_t* ticket) {
   (void)ctx; (void)scen; (void)out; (void)ticket;
   return fail(FMC_EINVAL, "fmc_submit: not available in this build");

@@ -117,8 +117,11 @@ __device__ __forceinline__ void swing_rhs(const R* cfg, const R wb, const R (&yd
     for (int k = 0; k < NG; ++k) {
       const R yr = cf[L.yre() + i * NG + k];
       const R yi = cf[L.yim() + i * NG + k];
-      ir += yr * dc[k] - yi * ds[k];
-      ii += yr * ds[k] + yi * dc[k];
+      // complex MAC as four FMAs (no intermediate products)
+      ir = fma(yr, dc[k], ir);
+      ir = fma(-yi, ds[k], ir);
+      ii = fma(yr, ds[k], ii);
+      ii = fma(yi, dc[k], ii);
     }
     const R dpe = dc[i] * cf[L.i0r() + i] + ds[i] * cf[L.i0i() + i] +
                   (cf[L.c0() + i] + dc[i]) * ir + (cf[L.s0() + i] + ds[i]) * ii;
@@ -327,31 +330,62 @@ template <typename R> struct vec2;
 template <> struct vec2<double> { using type = double2; };
 template <> struct vec2<float> { using type = float2; };
 
-template <typename R, int NG, int PM, int L, int WPB>
-__global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
+// Sizes of one group variant and the LDS it needs: the statistics tile (the
+// values of up to D consecutive output steps, reduced together with two
+// workgroup barriers per D steps), the exchange rows (NGP machine slots and PM
+// process slots per trajectory; row TB is scratch for idle lanes) and the
+// non-finite flags.
+template <typename R, int NG, int PM, int L, int WPB, int D>
+struct GroupShape {
   using R2 = typename vec2<R>::type;
+  static constexpr int G = (NG + L - 1) / L;   // machines per lane
+  static constexpr int PQ = (PM + L - 1) / L;  // processes per lane
+  static constexpr int NGP = G * L;            // padded machine slots per trajectory
+  static constexpr int XW = NGP + PM + 1;      // exchange row width (R2 entries)
+  static constexpr int TW = 64 / L;            // trajectories per wave
+  static constexpr int TB = TW * WPB;          // trajectories per workgroup
+  static constexpr int VM = 2 * NG + PM;
+  static constexpr size_t tile_bytes = (size_t)D * VM * (TB + 1) * sizeof(double);
+  static constexpr size_t xch_bytes = (size_t)(TB + 1) * XW * sizeof(R2);
+  static constexpr size_t lds_bytes = tile_bytes + xch_bytes + (TB + 1) * sizeof(int);
+};
+
+// Where a group run leaves its statistics: rows[(s)*V + v] = (mean, M2) of the
+// group's samples; prev > 0 means the rows already hold the statistics of prev
+// earlier samples, and the group's are merged in with Chan's update (a fixed
+// order, so results do not depend on scheduling).
+struct GroupStats {
+  double2* rows;
+  int64_t prev;
+};
+
+// One workgroup integrates trajectories tile*TB .. tile*TB + TB - 1 of a
+// scenario over the steps [s_begin, s_end) of a.  Lane g of a trajectory owns
+// machines g*G .. g*G+G-1 (rows of Y in registers) and processes g, g+L, ...;
+// per stage the lanes exchange the rotated EMF deviations of their machines
+// and the stage values of their processes through LDS.  keep_state stores the
+// state for a following chunk.
+template <typename R, int NG, int PM, int L, int WPB, int D>
+__device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
+                                          unsigned char* lds, GroupStats st, bool keep_state) {
+  using Sh = GroupShape<R, NG, PM, L, WPB, D>;
+  using R2 = typename Sh::R2;
   constexpr PackLayout Lp{NG, PM};
-  constexpr int G = (NG + L - 1) / L;
-  constexpr int NGP = G * L;            // padded machine slots per trajectory
-  constexpr int TW = 64 / L;            // trajectories per wave
-  constexpr int TB = TW * WPB;          // trajectories per workgroup
-  constexpr int VM = 2 * NG + PM;
-  // statistics tile: the values of up to D consecutive output steps are
-  // buffered and reduced together, two workgroup barriers per D steps
-  constexpr int D = WPB == 1 ? 4 : 8;
-  __shared__ double tile[D][VM][TB + 1];
-  __shared__ R2 xch[TB + 1][NGP + 1];   // row TB: scratch of the idle lanes
-  __shared__ int bad_t[TB + 1];
+  constexpr int G = Sh::G, PQ = Sh::PQ, NGP = Sh::NGP, XW = Sh::XW, TW = Sh::TW, TB = Sh::TB,
+                VM = Sh::VM;
+  double (*tile_buf)[VM][TB + 1] = reinterpret_cast<double (*)[VM][TB + 1]>(lds);
+  R2 (*xch)[XW] = reinterpret_cast<R2 (*)[XW]>(lds + Sh::tile_bytes);
+  int* bad_t = reinterpret_cast<int*>(lds + Sh::tile_bytes + Sh::xch_bytes);
   const int tid = threadIdx.x;
   const int wv = tid >> 6, ln = tid & 63;
   const bool lane_on = ln < TW * L;
   const int tl = lane_on ? wv * TW + ln / L : TB;
   const int g = lane_on ? ln % L : 0;
-  const int64_t traj = (int64_t)blockIdx.x * TB + tl;
+  const int64_t traj = tile * TB + tl;
   const int64_t N = a.N;
   const bool valid = lane_on && traj < N;
   const int64_t ns = valid ? traj : N - 1;
-  const int64_t rem = N - (int64_t)blockIdx.x * TB;
+  const int64_t rem = N - tile * TB;
   const int cnt = rem < TB ? (int)rem : TB;
   const int n = a.n, P = a.P, V = a.V;
   const R* __restrict__ cf = a.coef;
@@ -379,15 +413,21 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
 #pragma unroll
     for (int p = 0; p < PM; ++p) binc[q][p] = on ? cf[Lp.binc() + i * PM + p] : R(0);
   }
-  R theta[PM], sigma[PM];
+  // my processes p = g + L r
+  R theta[PQ], sigma[PQ];
+  bool own[PQ];
+  int64_t wofs[PQ];
 #pragma unroll
-  for (int p = 0; p < PM; ++p) {
-    theta[p] = cf[Lp.theta() + p];
-    sigma[p] = cf[Lp.sigma() + p];
+  for (int r = 0; r < PQ; ++r) {
+    const int p = g + L * r;
+    own[r] = lane_on && p < P;
+    theta[r] = own[r] ? cf[Lp.theta() + p] : R(0);
+    sigma[r] = own[r] ? cf[Lp.sigma() + p] : R(0);
+    wofs[r] = own[r] ? (int64_t)p * N + ns : 0;
   }
 
-  auto rhs = [&](const R (&yd)[G], const R (&yw)[G], const R (&yx)[PM], const R (&wv)[PM],
-                 R (&kd)[G], R (&kw)[G], R (&kx)[PM]) {
+  auto rhs = [&](const R (&yd)[G], const R (&yw)[G], const R (&yx)[PQ], const R (&wv)[PQ],
+                 R (&kd)[G], R (&kw)[G], R (&kx)[PQ]) {
     R dc[G], ds[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -399,6 +439,9 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
       ds[q] = c0[q] * sd - s0[q] * omc;
       xch[tl][g * G + q] = R2{dc[q], ds[q]};
     }
+#pragma unroll
+    for (int r = 0; r < PQ; ++r)
+      if (own[r]) xch[tl][NGP + g + L * r] = R2{yx[r], R(0)};
     wave_lds_sync();
     // two accumulator pairs (even / odd columns) halve the FMA dependency chains
     R ir[G], ii[G], jr[G], ji[G];
@@ -406,42 +449,58 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
     for (int q = 0; q < G; ++q) { ir[q] = R(0); ii[q] = R(0); jr[q] = R(0); ji[q] = R(0); }
 #pragma unroll
     for (int k = 0; k < NG; ++k) {
+      // keep at most 8 exchange loads in flight: bounds the registers the
+      // scheduler would otherwise spend hoisting all NG loads
+      if ((k & 7) == 0 && k > 0) asm volatile("" ::: "memory");
       const R2 e = xch[tl][k];
 #pragma unroll
       for (int q = 0; q < G; ++q) {
+        // complex MAC as four FMAs (no intermediate products)
         if (k & 1) {
-          jr[q] += yr[q][k] * e.x - yi[q][k] * e.y;
-          ji[q] += yr[q][k] * e.y + yi[q][k] * e.x;
+          jr[q] = fma(yr[q][k], e.x, jr[q]);
+          jr[q] = fma(-yi[q][k], e.y, jr[q]);
+          ji[q] = fma(yr[q][k], e.y, ji[q]);
+          ji[q] = fma(yi[q][k], e.x, ji[q]);
         } else {
-          ir[q] += yr[q][k] * e.x - yi[q][k] * e.y;
-          ii[q] += yr[q][k] * e.y + yi[q][k] * e.x;
+          ir[q] = fma(yr[q][k], e.x, ir[q]);
+          ir[q] = fma(-yi[q][k], e.y, ir[q]);
+          ii[q] = fma(yr[q][k], e.y, ii[q]);
+          ii[q] = fma(yi[q][k], e.x, ii[q]);
         }
       }
     }
+    R inj[G];
 #pragma unroll
-    for (int q = 0; q < G; ++q) { ir[q] += jr[q]; ii[q] += ji[q]; }
+    for (int q = 0; q < G; ++q) inj[q] = R(0);
+#pragma unroll
+    for (int p = 0; p < PM; ++p) {
+      if (p < P) {
+        const R xp = xch[tl][NGP + p].x;
+#pragma unroll
+        for (int q = 0; q < G; ++q) inj[q] += binc[q][p] * xp;
+      }
+    }
     wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < G; ++q) {
+      ir[q] += jr[q];
+      ii[q] += ji[q];
       const R dpe = dc[q] * i0r[q] + ds[q] * i0i[q] + (c0[q] + dc[q]) * ir[q] + (s0[q] + ds[q]) * ii[q];
-      R F = res[q] - dpe - dmp[q] * yw[q];
-#pragma unroll
-      for (int p = 0; p < PM; ++p) F += binc[q][p] * yx[p];
+      const R F = res[q] - dpe - dmp[q] * yw[q] + inj[q];
       kd[q] = a.wb * yw[q];
       kw[q] = F * inv2h[q];
     }
 #pragma unroll
-    for (int p = 0; p < PM; ++p) kx[p] = -theta[p] * yx[p] + sigma[p] * wv[p];
+    for (int r = 0; r < PQ; ++r) kx[r] = -theta[r] * yx[r] + sigma[r] * wv[r];
   };
 
   // Reduce the buffered steps [s_first, s_first + nb): thread q of the
   // workgroup takes rows (step, variable) q, q + 64 WPB, ...
   auto flush = [&](int64_t s_first, int nb) {
     __syncthreads();
-    const int64_t S1 = a.S + 1;
     for (int rv = tid; rv < nb * V; rv += 64 * WPB) {
       const int b = rv / V, v = rv % V;
-      const double* row = tile[b][v];
+      const double* row = tile_buf[b][v];
       double sm = 0.0;
       for (int j = 0; j < cnt; ++j) sm += row[j];
       const double mu = sm / (double)cnt;
@@ -450,16 +509,23 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
         const double d = row[j] - mu;
         m2 += d * d;
       }
-      reinterpret_cast<double2*>(a.partial)[((int64_t)blockIdx.x * S1 + s_first + b) * V + v] =
-          make_double2(mu, m2);
+      double2* dst = st.rows + (s_first + b) * V + v;
+      if (st.prev == 0) {
+        *dst = make_double2(mu, m2);
+      } else {
+        const double2 old = *dst;
+        const double na = (double)st.prev, nb2 = (double)cnt, tot = na + nb2;
+        const double dl = mu - old.x;
+        *dst = make_double2(old.x + dl * (nb2 / tot), old.y + m2 + dl * dl * (na * nb2 / tot));
+      }
     }
     __syncthreads();
   };
   int nbuf = 0;
   int64_t s_first = 0;
-  auto emit = [&](int64_t s, const R (&yd)[G], const R (&yw)[G], const R (&yx)[PM]) {
+  auto emit = [&](int64_t s, const R (&yd)[G], const R (&yw)[G], const R (&yx)[PQ]) {
     if (nbuf == 0) s_first = s;
-    double (*tb)[TB + 1] = tile[nbuf];
+    double (*tb)[TB + 1] = tile_buf[nbuf];
 #pragma unroll
     for (int q = 0; q < G; ++q) {
       const int i = g * G + q;
@@ -468,11 +534,9 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
         tb[n + i][tl] = (double)yw[q];
       }
     }
-    if (lane_on && g == 0) {
 #pragma unroll
-      for (int p = 0; p < PM; ++p)
-        if (p < P) tb[2 * n + p][tl] = (double)yx[p];
-    }
+    for (int r = 0; r < PQ; ++r)
+      if (own[r]) tb[2 * n + g + L * r][tl] = (double)yx[r];
     if (slot >= 0) {
       // every lane of a selected trajectory writes its own outputs
       double* o = a.traj + ((int64_t)slot * (a.S + 1) + s) * V;
@@ -484,11 +548,9 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
           o[n + i] = (double)yw[q];
         }
       }
-      if (g == 0) {
 #pragma unroll
-        for (int p = 0; p < PM; ++p)
-          if (p < P) o[2 * n + p] = (double)yx[p];
-      }
+      for (int r = 0; r < PQ; ++r)
+        if (own[r]) o[2 * n + g + L * r] = (double)yx[r];
     }
     if (++nbuf == D) {
       flush(s_first, nbuf);
@@ -496,13 +558,13 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
     }
   };
 
-  R yd[G], yw[G], yx[PM];
-  const int64_t lane_id = (int64_t)blockIdx.x * 64 * WPB + tid;
+  R yd[G], yw[G], yx[PQ];
+  const int64_t lane_id = tile * 64 * WPB + tid;
   if (a.s_begin == 0) {
 #pragma unroll
     for (int q = 0; q < G; ++q) { yd[q] = R(0); yw[q] = R(0); }
 #pragma unroll
-    for (int p = 0; p < PM; ++p) yx[p] = cf[Lp.xi0() + p];
+    for (int r = 0; r < PQ; ++r) yx[r] = own[r] ? cf[Lp.xi0() + g + L * r] : R(0);
     emit(0, yd, yw, yx);
   } else {
 #pragma unroll
@@ -511,29 +573,30 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
       yw[q] = a.state[(int64_t)(G + q) * a.lanes + lane_id];
     }
 #pragma unroll
-    for (int p = 0; p < PM; ++p) yx[p] = a.state[(int64_t)(2 * G + p) * a.lanes + lane_id];
+    for (int r = 0; r < PQ; ++r) yx[r] = a.state[(int64_t)(2 * G + r) * a.lanes + lane_id];
   }
 
   const R dt = a.dt, h2 = a.dt * R(0.5), dt6 = a.dt / R(6);
-  // KLE path values: the two new stage columns of step s are loaded one step
-  // ahead so their memory latency overlaps the previous step's arithmetic.
-  R w0[PM], w1[PM], w2[PM];
+  const int64_t colstride = (int64_t)P * N;
+  // KLE path values of my processes: the two new stage columns of step s are
+  // loaded one step ahead so their latency overlaps the previous step.
+  R w0[PQ], w1[PQ], w2[PQ];
 #pragma unroll
-  for (int p = 0; p < PM; ++p) {
-    w0[p] = (p < P) ? w[(int64_t)p * N + ns] : R(0);
-    w1[p] = (p < P) ? w[((int64_t)1 * P + p) * N + ns] : R(0);
-    w2[p] = (p < P) ? w[((int64_t)2 * P + p) * N + ns] : R(0);
+  for (int r = 0; r < PQ; ++r) {
+    w0[r] = own[r] ? w[wofs[r]] : R(0);
+    w1[r] = own[r] ? w[colstride + wofs[r]] : R(0);
+    w2[r] = own[r] ? w[2 * colstride + wofs[r]] : R(0);
   }
   for (int64_t s = a.s_begin; s < a.s_end; ++s) {
     const int64_t cl = 2 * s - a.c_base;
     const bool more = s + 1 < a.s_end;
-    R n1[PM], n2[PM];
+    R n1[PQ], n2[PQ];
 #pragma unroll
-    for (int p = 0; p < PM; ++p) {
-      n1[p] = (more && p < P) ? w[((cl + 3) * P + p) * N + ns] : R(0);
-      n2[p] = (more && p < P) ? w[((cl + 4) * P + p) * N + ns] : R(0);
+    for (int r = 0; r < PQ; ++r) {
+      n1[r] = (more && own[r]) ? w[(cl + 3) * colstride + wofs[r]] : R(0);
+      n2[r] = (more && own[r]) ? w[(cl + 4) * colstride + wofs[r]] : R(0);
     }
-    R kd[G], kw[G], kx[PM], ad[G], aw[G], ax[PM], td[G], tw[G], tx[PM];
+    R kd[G], kw[G], kx[PQ], ad[G], aw[G], ax[PQ], td[G], tw[G], tx[PQ];
     rhs(yd, yw, yx, w0, kd, kw, kx);
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -541,7 +604,7 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
       td[q] = yd[q] + h2 * kd[q]; tw[q] = yw[q] + h2 * kw[q];
     }
 #pragma unroll
-    for (int p = 0; p < PM; ++p) { ax[p] = kx[p]; tx[p] = yx[p] + h2 * kx[p]; }
+    for (int r = 0; r < PQ; ++r) { ax[r] = kx[r]; tx[r] = yx[r] + h2 * kx[r]; }
     rhs(td, tw, tx, w1, kd, kw, kx);
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -549,7 +612,7 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
       td[q] = yd[q] + h2 * kd[q]; tw[q] = yw[q] + h2 * kw[q];
     }
 #pragma unroll
-    for (int p = 0; p < PM; ++p) { ax[p] += R(2) * kx[p]; tx[p] = yx[p] + h2 * kx[p]; }
+    for (int r = 0; r < PQ; ++r) { ax[r] += R(2) * kx[r]; tx[r] = yx[r] + h2 * kx[r]; }
     rhs(td, tw, tx, w1, kd, kw, kx);
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -557,7 +620,7 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
       td[q] = yd[q] + dt * kd[q]; tw[q] = yw[q] + dt * kw[q];
     }
 #pragma unroll
-    for (int p = 0; p < PM; ++p) { ax[p] += R(2) * kx[p]; tx[p] = yx[p] + dt * kx[p]; }
+    for (int r = 0; r < PQ; ++r) { ax[r] += R(2) * kx[r]; tx[r] = yx[r] + dt * kx[r]; }
     rhs(td, tw, tx, w2, kd, kw, kx);
 #pragma unroll
     for (int q = 0; q < G; ++q) {
@@ -565,31 +628,33 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
       yw[q] += dt6 * (aw[q] + kw[q]);
     }
 #pragma unroll
-    for (int p = 0; p < PM; ++p) {
-      yx[p] += dt6 * (ax[p] + kx[p]);
-      w0[p] = w2[p];
-      w1[p] = n1[p];
-      w2[p] = n2[p];
+    for (int r = 0; r < PQ; ++r) {
+      yx[r] += dt6 * (ax[r] + kx[r]);
+      w0[r] = w2[r];
+      w1[r] = n1[r];
+      w2[r] = n2[r];
     }
     emit(s + 1, yd, yw, yx);
   }
 
   if (nbuf > 0) flush(s_first, nbuf);  // nbuf is uniform over the workgroup
 
+  if (keep_state) {
 #pragma unroll
-  for (int q = 0; q < G; ++q) {
-    a.state[(int64_t)q * a.lanes + lane_id] = yd[q];
-    a.state[(int64_t)(G + q) * a.lanes + lane_id] = yw[q];
+    for (int q = 0; q < G; ++q) {
+      a.state[(int64_t)q * a.lanes + lane_id] = yd[q];
+      a.state[(int64_t)(G + q) * a.lanes + lane_id] = yw[q];
+    }
+#pragma unroll
+    for (int r = 0; r < PQ; ++r) a.state[(int64_t)(2 * G + r) * a.lanes + lane_id] = yx[r];
   }
-#pragma unroll
-  for (int p = 0; p < PM; ++p) a.state[(int64_t)(2 * G + p) * a.lanes + lane_id] = yx[p];
 
   if (a.s_end == a.S) {  // uniform over the workgroup: the barriers below are safe
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < G; ++q) bad |= !isfinite(yd[q]) || !isfinite(yw[q]);
 #pragma unroll
-    for (int p = 0; p < PM; ++p) bad |= !isfinite(yx[p]);
+    for (int r = 0; r < PQ; ++r) bad |= !isfinite(yx[r]);
     // one count per trajectory: the lanes of a trajectory combine through LDS
     if (lane_on && g == 0) bad_t[tl] = 0;
     __syncthreads();
@@ -599,7 +664,17 @@ __global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
       atomicAdd(a.nonfinite, 1ULL);
       atomicMin(a.first_bad, (long long)traj);
     }
+    __syncthreads();  // the flags may be reused by the workgroup's next run
   }
+}
+
+template <typename R, int NG, int PM, int L, int WPB>
+__global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
+  constexpr int D = WPB == 1 ? 4 : 8;
+  using Sh = GroupShape<R, NG, PM, L, WPB, D>;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[Sh::lds_bytes];
+  GroupStats st{reinterpret_cast<double2*>(a.partial) + (int64_t)blockIdx.x * (a.S + 1) * a.V, 0};
+  group_run<R, NG, PM, L, WPB, D>(a, blockIdx.x, lds, st, true);
 }
 
 }  // namespace fmc

@@ -35,3 +35,23 @@
   X(10, 4, 16, 2)       \
   X(10, 4, 10, 8)       \
   X(10, 4, 16, 8)
+
+// Variants of the persistent batched integrator (FP32, 4 waves per
+// workgroup): X(NG machines, PM processes, L lanes per trajectory), in three
+// size classes compiled as separate persistent kernels (the register
+// footprint of a kernel is that of its largest variant).
+#define FMC_BATCH_CLASS0(X) \
+  X(4, 8, 4)                \
+  X(6, 8, 6)                \
+  X(8, 8, 8)                \
+  X(10, 8, 10)
+#define FMC_BATCH_CLASS1(X) \
+  X(12, 8, 12)              \
+  X(16, 8, 16)              \
+  X(20, 8, 20)              \
+  X(24, 8, 24)
+#define FMC_BATCH_CLASS2(X) \
+  X(32, 8, 32)              \
+  X(40, 8, 40)              \
+  X(50, 8, 50)
+#define FMC_BATCH_VARIANTS(X) FMC_BATCH_CLASS0(X) FMC_BATCH_CLASS1(X) FMC_BATCH_CLASS2(X)

@@ -1,0 +1,112 @@
+"""Batched form: uneven scenarios in one persistent launch (per size class),
+replayed from a captured HIP graph, against the FP64 oracle.
+
+Tolerances: statistics 1e-4 (mean relative to max(|mean|, std), variance
+relative to max |var|, per output variable); FP32 trajectories 2e-3 of the
+variable's range (FP32 integration over hundreds of steps).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [(3, 1, 40, 300, 0.5), (7, 2, 60, 517, 0.6), (12, 4, 50, 250, 0.4),
+         (20, 6, 45, 130, 0.3), (33, 3, 40, 70, 0.25), (50, 5, 41, 66, 0.2)]
+
+
+def small_batch():
+    return [workloads.multimachine(n_gen=n, n_dist=P, N=N, K=K, T=T, dt=0.005, net_seed=100 + k,
+                                   seed=10 + k)
+            for k, (n, P, K, N, T) in enumerate(SPECS)]
+
+
+@pytest.fixture(scope="module")
+def ctx(fmc):
+    return fmc.Context(0)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def mean_err(a, m, v):
+    num = np.abs(a - m).max(axis=0)
+    den = np.maximum(np.abs(m).max(axis=0), np.sqrt(np.abs(v)).max(axis=0))
+    return float((num / np.where(den == 0, 1, den)).max())
+
+
+def rel_err(a, b):
+    num = np.abs(a - b).reshape(-1, a.shape[-1]).max(axis=0)
+    den = np.abs(b).reshape(-1, b.shape[-1]).max(axis=0)
+    return float((num / np.where(den == 0, 1, den)).max())
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_batch_matches_oracle(ctx, prec):
+    scs = small_batch()
+    sels = [np.array([0, sc["N"] - 1]) for sc in scs]
+    res = ctx.run_batch(scs, precision=prec, traj_idx=sels)
+    for sc, r, sel in zip(scs, res, sels):
+        o = oracle.run(sc, want_traj=True)
+        em = mean_err(_np(r["mean"]), o["mean"], o["var"])
+        ev = rel_err(_np(r["var"]), o["var"])
+        et = rel_err(_np(r["traj"]), o["traj"][sel])
+        assert em <= 1e-4 and ev <= 1e-4 and et <= 2e-3, (sc["n_gen"], em, ev, et)
+        assert r["report"]["n_nonfinite"] == 0
+
+
+def test_batch_alone_equals_mix(ctx):
+    """A scenario's statistics do not depend on the rest of the batch."""
+    scs = small_batch()
+    mix = ctx.run_batch(scs, precision="f32")
+    for i in [0, 3, 5]:
+        alone = ctx.run_batch([scs[i]], precision="f32")[0]
+        assert np.array_equal(_np(alone["mean"]), _np(mix[i]["mean"]))
+        assert np.array_equal(_np(alone["var"]), _np(mix[i]["var"]))
+
+
+def test_batch_graph_replay_is_deterministic(ctx):
+    scs = small_batch()[:4]
+    a = ctx.run_batch(scs, precision="bf16x3")
+    b = ctx.run_batch(scs, precision="bf16x3")  # replays the captured graph
+    c = ctx.run_batch(scs, precision="bf16x3")
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(_np(x["var"]), _np(y["var"]))
+        assert np.array_equal(_np(x["mean"]), _np(z["mean"]))
+
+
+def test_batch_rejects_fp64(ctx, fmc):
+    with pytest.raises(fmc.FmcError) as e:
+        ctx.run_batch(small_batch()[:2], precision="f64")
+    assert e.value.code == fmc.EINVAL
+
+
+def test_batch_every_variant(ctx, fmc):
+    """Each batched variant on the scenarios it fits, forced, against the oracle."""
+    import ctypes as C
+    n_var = 11
+    sc = workloads.multimachine(n_gen=3, n_dist=2, N=97, K=30, T=0.2, dt=0.005, net_seed=7, seed=5)
+    o = oracle.run(sc)
+    for vid in range(n_var):
+        r = ctx.run_batch([sc], precision="f32", variant=vid)[0]
+        assert mean_err(_np(r["mean"]), o["mean"], o["var"]) <= 1e-4, vid
+        assert rel_err(_np(r["var"]), o["var"]) <= 1e-4, vid
+        assert r["report"]["variant_id"] == vid
+
+
+def test_uneven_64_scenarios_sampled(ctx):
+    """The full 64-scenario set (n 3-50, P 1-6, T 5-30 s, K 40-150, N 500-2e4):
+    sampled trajectories of three scenarios against the oracle, properties of all."""
+    scs = workloads.uneven_batch()
+    pick = [0, 17, 40]
+    sels = [np.array([1, sc["N"] // 2]) if i in pick else None for i, sc in enumerate(scs)]
+    res = ctx.run_batch(scs, precision="bf16x3", traj_idx=sels)
+    for i in pick:
+        o = oracle.run(scs[i], sel=sels[i], want_traj=True)
+        assert rel_err(_np(res[i]["traj"]), o["traj"]) <= 2e-3, i
+    for r in res:
+        v = _np(r["var"])
+        assert np.all(np.isfinite(v)) and np.all(v >= 0) and np.all(v[0] == 0)
