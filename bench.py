@@ -28,6 +28,11 @@ PEAK_FP32_VECTOR = 157.3e12
 PEAK_HBM = 8.0e12
 
 
+def say(msg: str):
+    """Progress line on stderr (the JSON result line goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def integrator_flops_per_traj_step(n: int, P: int) -> float:
     """Algorithmic flops of one RK4 step of one trajectory (classical model).
 
@@ -38,6 +43,11 @@ def integrator_flops_per_traj_step(n: int, P: int) -> float:
     """
     stage = 8 * n * n + (25 + 20) * n + 4 * P
     return 4 * stage + 13 * (2 * n + P)
+
+
+def oracle_mod():
+    import oracle
+    return oracle
 
 
 def measured_traffic(variant: int, precision: str):
@@ -58,6 +68,138 @@ def measured_traffic(variant: int, precision: str):
     return None, None
 
 
+def batched_leg(ctx, fmc, workloads, oracle_mod, steps: int, with_fp64: bool):
+    """The 64-scenario uneven set (n 3-50, P 1-6, T 5-30 s, K 40-150, N 500-2e4):
+    batched forms (one graph replay = one pass over all scenarios) and, as the
+    plain reference, FP64 fmc_run of every scenario in turn."""
+    import numpy as np
+    import torch
+    scs = workloads.uneven_batch()
+    ts = sum(sc["N"] * fmc.steps(sc) for sc in scs)
+    out = {"workload": "64 uneven scenarios: seeded synthetic networks, n 3-50 machines, "
+                       "P 1-6 OU processes, T 5-30 s, dt 5 ms, K 40-150, N 500-2e4 "
+                       "(log-uniform), LHS seeds 4000-4063",
+           "trajectory_steps": ts}
+    pick = [0, 17, 40]
+    sels = [np.array([1, sc["N"] // 2]) if i in pick else None for i, sc in enumerate(scs)]
+    small = int(np.argmin([sc["N"] * fmc.steps(sc) * sc["n_gen"] ** 2 for sc in scs]))
+    ref_small = ref_traj = None
+    if oracle_mod is not None:
+        ref_small = oracle_mod.run(scs[small])
+        ref_traj = {i: oracle_mod.run(scs[i], sel=sels[i], want_traj=True)["traj"] for i in pick}
+    say("batched: oracle references done" if oracle_mod is not None else "batched: start")
+    for form in ("bf16x3", "f32"):
+        res = ctx.run_batch(scs, precision=form, traj_idx=sels)  # tunes, captures the graph
+        say(f"batched {form}: tuned and captured")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = ctx.run_batch(scs, precision=form, traj_idx=sels)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        say(f"batched {form}: {sec * 1e3:.1f} ms per pass")
+        entry = {"value": ts / sec, "unit": "trajectory-steps/s", "ms_per_pass": sec * 1e3,
+                 "variants": sorted({r["report"]["variant_id"] for r in res})}
+        if oracle_mod is not None:
+            r = res[small]
+            m, v = r["mean"].cpu().numpy(), r["var"].cpu().numpy()
+            om, ov = ref_small["mean"], ref_small["var"]
+            sm = np.maximum(np.abs(om).max(axis=0), np.sqrt(ov).max(axis=0))
+            et = 0.0
+            for i in pick:
+                a = res[i]["traj"].cpu().numpy()
+                b = ref_traj[i]
+                num = np.abs(a - b).reshape(-1, a.shape[-1]).max(axis=0)
+                den = np.abs(b).reshape(-1, a.shape[-1]).max(axis=0)
+                et = max(et, float((num / np.where(den == 0, 1, den)).max()))
+            entry["error_vs_oracle"] = {
+                "scenario": small,
+                "mean_rel": float((np.abs(m - om).max(axis=0) / sm).max()),
+                "var_rel": float((np.abs(v - ov).max(axis=0) / np.abs(ov).max(axis=0)).max()),
+                "traj_rel_sampled": et}
+        out[form] = entry
+    if with_fp64:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for sc in scs:
+            ctx.run(sc, precision="f64")
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        say(f"plain f64 sequential: {sec * 1e3:.1f} ms")
+        out["plain_f64_sequential"] = {"value": ts / sec, "unit": "trajectory-steps/s",
+                                       "ms_per_pass": sec * 1e3}
+    return out
+
+
+def served_leg(ctx, fmc, workloads, oracle_mod, rates, n_max: int, seed: int = 11):
+    """Served form: a seeded Poisson request stream per rate; each request is a
+    scenario drawn from the 64-scenario uneven set.  A request refused for
+    lack of HBM or slots (EBUSY) is retried by the client every millisecond;
+    its latency runs from its scheduled arrival to the moment the client sees
+    it complete."""
+    import numpy as np
+    import torch
+    scs = workloads.uneven_batch()
+    rng = np.random.default_rng(seed)
+    out = {"workload": "Poisson requests drawn uniformly from the 64 uneven scenarios "
+                       "(classical machines; the large flux-decay requests are not part "
+                       "of this stream)",
+           "precision": "bf16x3", "time_chunk": 200, "rates": []}
+    # warm-up: one request of every size class
+    for i in (0, 17, 40):
+        ctx.submit(scs[i], precision="bf16x3").wait(timeout=300)
+    if oracle_mod is not None:
+        small = int(np.argmin([sc["N"] * fmc.steps(sc) * sc["n_gen"] ** 2 for sc in scs]))
+        r = ctx.submit(scs[small], precision="bf16x3").wait(timeout=300)
+        o = oracle_mod.run(scs[small])
+        m, v = r["mean"].cpu().numpy(), r["var"].cpu().numpy()
+        sm = np.maximum(np.abs(o["mean"]).max(axis=0), np.sqrt(o["var"]).max(axis=0))
+        out["error_vs_oracle"] = {
+            "scenario": small,
+            "mean_rel": float((np.abs(m - o["mean"]).max(axis=0) / sm).max()),
+            "var_rel": float((np.abs(v - o["var"]).max(axis=0)
+                              / np.abs(o["var"]).max(axis=0)).max())}
+    for rate in rates:
+        n_req = int(max(8, min(n_max, 8 * rate)))
+        gaps = rng.exponential(1.0 / rate, size=n_req)
+        arrive = np.cumsum(gaps) - gaps[0]
+        pick = rng.integers(0, len(scs), size=n_req)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pending = {}   # index -> ticket
+        done_at = np.zeros(n_req)
+        wait_q = list(range(n_req))
+        refused = 0
+        while wait_q or pending:
+            now = time.perf_counter() - t0
+            while wait_q and arrive[wait_q[0]] <= now:
+                i = wait_q[0]
+                try:
+                    pending[i] = ctx.submit(scs[pick[i]], precision="bf16x3")
+                    wait_q.pop(0)
+                except fmc.FmcError as e:
+                    if e.code != fmc.EBUSY:
+                        raise
+                    refused += 1
+                    break
+            for i in list(pending):
+                if pending[i].poll() is not None:
+                    done_at[i] = time.perf_counter() - t0
+                    del pending[i]
+            time.sleep(0.001)
+        lat = done_at - arrive
+        span = float(done_at.max())
+        ts = float(sum(scs[k]["N"] * fmc.steps(scs[k]) for k in pick))
+        out["rates"].append({
+            "rate_req_per_s": rate, "requests": n_req, "p50_latency_s": float(np.median(lat)),
+            "p99_latency_s": float(np.quantile(lat, 0.99)), "max_latency_s": float(lat.max()),
+            "makespan_s": span, "completed_req_per_s": n_req / span,
+            "trajectory_steps_per_s": ts / span, "ebusy_retries": refused})
+        say(f"served rate {rate}/s: {n_req} requests, p50 {np.median(lat):.3f} s, "
+            f"p99 {np.quantile(lat, 0.99):.3f} s, {ts / span:.3e} traj-steps/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +210,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--variant", type=int, default=-1,
                     help="integrator variant; -1 lets the autotuner choose (untimed)")
+    ap.add_argument("--batch-steps", type=int, default=2,
+                    help="timed passes over the 64-scenario batched workload (0: skip)")
+    ap.add_argument("--serve-rates", default="1,10,50,200",
+                    help="Poisson request rates of the served leg (empty: skip)")
+    ap.add_argument("--serve-max", type=int, default=48,
+                    help="requests per rate of the served leg (at most)")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -96,6 +244,7 @@ def main():
         # untimed: the autotuner picks the integrator variant for this workload
         vid = args.variant if args.variant >= 0 else ctx.autotune(sc, precision=form)
         tuned[form] = vid
+        say(f"{form}: variant {vid}")
         outs = None
         for _ in range(args.warmup):
             r = ctx.run(sc, precision=form, variant=vid)
@@ -117,6 +266,7 @@ def main():
         chunks = int(np.ceil(S / rep["time_chunk"]))
         # sampled trajectories for the error report
         rt = ctx.run(sc, precision=form, traj_idx=sel, variant=vid)
+        say(f"{form}: {ms:.2f} ms per step, integrator {t_int * 1e3:.2f} ms")
         results[form] = dict(ms=ms, rep=rep, t_int=t_int, chunks=chunks,
                              mean=rt["mean"].cpu().numpy(), var=rt["var"].cpu().numpy(),
                              traj=rt["traj"].cpu().numpy())
@@ -149,6 +299,7 @@ def main():
             t0 = time.perf_counter()
             o = oracle.run(sc, sel=cpu_sel)
             t_cpu = time.perf_counter() - t0
+        say(f"cpu oracle: {n_cpu} samples in {t_cpu:.1f} s")
         cpu = {"value": n_cpu * S / t_cpu, "unit": "trajectory-steps/s",
                "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"{n_cpu} of {N} samples of the same workload ({S} steps each), "
@@ -166,6 +317,17 @@ def main():
                 e["mean_rel"] = float((dm / sm).max())
                 e["var_rel"] = float(dv.max())
             errs[form] = e
+
+    batched = None
+    if args.batch_steps > 0:
+        batched = batched_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(),
+                              args.batch_steps, "f64" in forms)
+
+    served = None
+    rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
+    if rates:
+        served = served_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), rates,
+                            args.serve_max)
 
     head = "f64" if "f64" in results else forms[0]
     res = results[head]
@@ -209,6 +371,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": forms_out,
+        "batched": batched,
+        "served": served,
     }
     print(json.dumps(line))
     ctx.close()

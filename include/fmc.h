@@ -247,15 +247,37 @@ int fmc_run(fmc_context *ctx, const fmc_system *sys, const fmc_disturbance *dist
  * scenario i alone, to the tolerance of its precision). */
 int fmc_run_batch(fmc_context *ctx, int32_t n, const fmc_scenario *scen, fmc_outputs *outs);
 
-/* Served form (continuous batching).  fmc_submit admits the request if its
- * footprint fits the free HBM budget and a slot is free (FMC_EBUSY otherwise;
- * FMC_ENOMEM if it can never fit), copies its inputs, and returns a ticket;
- * admitted requests run together on the device.  outs must stay valid until
- * fmc_poll/fmc_wait report completion. */
+/* Served form (continuous batching).  A server thread of the context runs
+ * every admitted request together: each tick rebuilds the next time chunk of
+ * KLE paths (par->time_chunk steps, 0: 200) of every active request and runs
+ * all of their work items in one persistent integrator launch per size class,
+ * with the trajectory state resident on the device between ticks; requests
+ * submitted meanwhile join at the next tick.  A request's result depends only
+ * on the request (the same alone and in any mix, bit for bit).
+ *
+ * fmc_submit validates the scenario (as fmc_run; precision FMC_F32 or
+ * FMC_BF16X3, zeta_in NULL, outputs mean and var only: n_traj 0, strata and
+ * zeta NULL), copies its inputs, and admits it if its footprint (see
+ * fmc_footprint) fits the free part of the context's serving arena and one of
+ * 256 slots is free: FMC_EBUSY otherwise, FMC_ENOMEM if it is larger than the
+ * whole arena.  The arena is taken from the HBM budget at the first submit:
+ * the environment variable FMC_SERVE_ARENA_BYTES, else half of the free budget
+ * up to 32 GiB.  outs (mean, var, report) must stay valid until completion is
+ * reported; the report's queue_wait_s and latency_s are measured from the
+ * submit.  Returns a ticket.
+ *
+ * fmc_poll returns FMC_EAGAIN while the request runs, then its final status
+ * once (FMC_OK, or FMC_ENONFINITE / FMC_ENOTCONV / FMC_EINVAL (singular
+ * network) / FMC_ECANCELLED / FMC_EDEVICE); after that the ticket is unknown
+ * (FMC_EINVAL).  fmc_wait blocks until then (timeout_s < 0: no limit;
+ * FMC_ETIMEDOUT leaves the ticket pending).  fmc_cancel marks a pending
+ * ticket; it leaves at the next tick boundary and reports FMC_ECANCELLED.
+ * These four calls are thread-safe.  fmc_context_destroy stops the server;
+ * no call on the context may be in progress then. */
 int fmc_submit(fmc_context *ctx, const fmc_scenario *scen, fmc_outputs *out, uint64_t *ticket);
-int fmc_poll(fmc_context *ctx, uint64_t ticket);   /* FMC_OK done, FMC_EAGAIN pending */
+int fmc_poll(fmc_context *ctx, uint64_t ticket);
 int fmc_wait(fmc_context *ctx, uint64_t ticket, double timeout_s);
-int fmc_cancel(fmc_context *ctx, uint64_t ticket); /* the ticket then reports FMC_ECANCELLED */
+int fmc_cancel(fmc_context *ctx, uint64_t ticket);
 
 /* Autotuner: times every compiled integrator variant that fits the scenario
  * (machines, processes; lanes per trajectory and workgroup size differ) on a
@@ -265,7 +287,10 @@ int fmc_cancel(fmc_context *ctx, uint64_t ticket); /* the ticket then reports FM
  * variable FMC_TUNE_CACHE if set, and returns it in *variant. */
 int fmc_autotune(fmc_context *ctx, const fmc_scenario *scen, int32_t *variant);
 
-/* Device bytes a scenario needs while it runs (the admission footprint). */
+/* Device bytes a scenario needs while it runs.  FMC_F32 / FMC_BF16X3: the
+ * admission footprint of the served form (staged inputs, design, basis, one
+ * time chunk of paths, state, statistics rows, results); FMC_F64: the
+ * single-run form's working set.  Validation as fmc_run. */
 int fmc_footprint(const fmc_scenario *scen, int64_t *bytes);
 
 #ifdef __cplusplus

@@ -384,6 +384,73 @@ Returns one dict(mean, var[, traj], report, rc) per scenario.  traj_idx, if
 given, is a list (one entry per scenario, None allowed) of sample indices."""
 
 
+class Ticket:
+    """A served request: its outputs (device tensors) stay referenced here
+    until the library reports completion (poll or wait)."""
+
+    def __init__(self, ctx, tid, mean, var, rep, keep):
+        self.ctx, self.id, self.mean, self.var = ctx, tid, mean, var
+        self._rep, self._keep = rep, keep
+        self.rc = None
+
+    def _final(self, rc, allow):
+        self.rc = rc
+        _check(rc, allow=allow)
+        return dict(mean=self.mean, var=self.var, report=self._rep.as_dict(), rc=rc)
+
+    def poll(self, allow_nonfinite=False):
+        """None while the request runs, else its result dict."""
+        rc = _lib.fmc_poll(self.ctx._h, self.id)
+        if rc == EAGAIN:
+            return None
+        return self._final(rc, (ENONFINITE,) if allow_nonfinite else ())
+
+    def wait(self, timeout=-1.0, allow_nonfinite=False):
+        rc = _lib.fmc_wait(self.ctx._h, self.id, float(timeout))
+        if rc == ETIMEDOUT:
+            raise FmcError(rc, last_error())
+        return self._final(rc, (ENONFINITE,) if allow_nonfinite else ())
+
+    def cancel(self):
+        _check(_lib.fmc_cancel(self.ctx._h, self.id))
+
+    def __del__(self):
+        # the library writes into this ticket's tensors until it completes:
+        # a ticket dropped early is cancelled and waited for
+        try:
+            if self.rc is None and self.ctx._h:
+                _lib.fmc_cancel(self.ctx._h, self.id)
+                _lib.fmc_wait(self.ctx._h, self.id, -1.0)
+        except Exception:
+            pass
+
+
+def _submit(ctx, sc, precision="f32", variant=-1, time_chunk=0):
+    keep = _Keep()
+    sysd, dist, par, _ = scenario_structs(sc, precision, variant, time_chunk, keep=keep)
+    s = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))
+    t = ctx.torch
+    n = int(sc["n_gen"]); P = len(sc["dist"]["gen"]); S = steps(sc)
+    V = 2 * n + P
+    mean = t.empty((S + 1, V), dtype=t.float64, device=ctx.device)
+    var = t.empty((S + 1, V), dtype=t.float64, device=ctx.device)
+    # the server writes on its own stream: the tensors must exist before it runs
+    t.cuda.current_stream(ctx.device).synchronize()
+    rep = Report()
+    out = Outputs(mean=_dptr(mean), var=_dptr(var), n_traj=0, traj_idx=None, traj=None,
+                  strata=None, zeta=None, mem_kind=MEM_DEVICE, report=C.pointer(rep))
+    keep.extend([s, out, rep])
+    tid = C.c_uint64(0)
+    _check(_lib.fmc_submit(ctx._h, C.byref(s), C.byref(out), C.byref(tid)))
+    return Ticket(ctx, int(tid.value), mean, var, rep, keep)
+
+
+Context.submit = lambda self, sc, precision="f32", variant=-1, time_chunk=0: \
+    _submit(self, sc, precision, variant, time_chunk)
+Context.submit.__doc__ = """Served form: admit one request (FmcError EBUSY / ENOMEM if it
+does not fit now / ever) and return its Ticket (poll / wait / cancel)."""
+
+
 def footprint(sc: dict, precision="f64") -> int:
     sysd, dist, par, keep = scenario_structs(sc, precision)
     s = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))

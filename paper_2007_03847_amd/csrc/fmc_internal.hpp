@@ -120,6 +120,12 @@ hipError_t launch_pack(const double* canon, int n, int P, const int32_t* gen, in
 hipError_t launch_stats_merge(const double2* partial, int64_t n_groups, int group_size,
                               int64_t N, int64_t S, int V, int n, int ddof,
                               const double* delta0, double* mean, double* var, hipStream_t st);
+// The same over `rows` consecutive rows: partial points at the first row of
+// group 0, groups are gstride elements apart; mean/var point at the first row.
+hipError_t launch_stats_merge_rows(const double2* partial, int64_t gstride, int64_t n_groups,
+                                   int group_size, int64_t N, int64_t rows, int V, int n,
+                                   int ddof, const double* delta0, double* mean, double* var,
+                                   hipStream_t st);
 
 // Integrator variants: NG machines, PM processes, L lanes per trajectory,
 // WPB waves per workgroup; a workgroup integrates group_size() trajectories.

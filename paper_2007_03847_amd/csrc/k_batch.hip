@@ -49,7 +49,8 @@ __device__ __forceinline__ void batch_tiles(const IntegArgs<float>& a, const Bat
   using Sh = GroupShape<float, NG, PM, L, kBatchWPB, kBatchD>;
   for (int64_t t = it.tile0; t < it.tile1; ++t) {
     GroupStats st{it.rows, (t - it.tile0) * Sh::TB};
-    group_run<float, NG, PM, L, kBatchWPB, kBatchD>(a, t, lds, st, false);
+    // a state buffer means the scenario runs in time chunks (served form)
+    group_run<float, NG, PM, L, kBatchWPB, kBatchD>(a, t, lds, st, a.state != nullptr);
   }
 }
 

@@ -307,8 +307,9 @@ template hipError_t launch_pack<float>(const double*, int, int, const int32_t*, 
 // deviations).  One thread per (step, variable).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_stats_merge(const double2* __restrict__ partial,
-                                                     int64_t n_groups, int group_size, int64_t N,
-                                                     int64_t SV, int V, int n, int ddof,
+                                                     int64_t gstride, int64_t n_groups,
+                                                     int group_size, int64_t N, int64_t SV,
+                                                     int V, int n, int ddof,
                                                      const double* __restrict__ delta0,
                                                      double* __restrict__ mean,
                                                      double* __restrict__ var) {
@@ -318,7 +319,7 @@ __global__ void __launch_bounds__(256) k_stats_merge(const double2* __restrict__
   for (int64_t g = 0; g < n_groups; ++g) {
     const int64_t rem = N - g * group_size;
     const double nb = (double)(rem < group_size ? rem : group_size);
-    const double2 pt = partial[g * SV + q];
+    const double2 pt = partial[g * gstride + q];
     if (g == 0) {
       cnt = nb;
       m = pt.x;
@@ -336,13 +337,22 @@ __global__ void __launch_bounds__(256) k_stats_merge(const double2* __restrict__
   var[q] = M2 / (double)(N - ddof);
 }
 
+hipError_t launch_stats_merge_rows(const double2* partial, int64_t gstride, int64_t n_groups,
+                                   int group_size, int64_t N, int64_t rows, int V, int n,
+                                   int ddof, const double* delta0, double* mean, double* var,
+                                   hipStream_t st) {
+  const int64_t SV = rows * V;
+  if (SV <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stats_merge, dim3((unsigned)((SV + 255) / 256)), dim3(256), 0, st, partial,
+                     gstride, n_groups, group_size, N, SV, V, n, ddof, delta0, mean, var);
+  return hipGetLastError();
+}
+
 hipError_t launch_stats_merge(const double2* partial, int64_t n_groups, int group_size,
                               int64_t N, int64_t S, int V, int n, int ddof,
                               const double* delta0, double* mean, double* var, hipStream_t st) {
-  const int64_t SV = (S + 1) * V;
-  hipLaunchKernelGGL(k_stats_merge, dim3((unsigned)((SV + 255) / 256)), dim3(256), 0, st, partial,
-                     n_groups, group_size, N, SV, V, n, ddof, delta0, mean, var);
-  return hipGetLastError();
+  return launch_stats_merge_rows(partial, (S + 1) * V, n_groups, group_size, N, S + 1, V, n, ddof,
+                                 delta0, mean, var, st);
 }
 
 }  // namespace fmc

@@ -34,7 +34,11 @@
   X(10, 4, 5, 4)        \
   X(10, 4, 16, 2)       \
   X(10, 4, 10, 8)       \
-  X(10, 4, 16, 8)
+  X(10, 4, 16, 8)       \
+  X(16, 8, 16, 4)       \
+  X(24, 8, 24, 4)       \
+  X(32, 8, 32, 4)       \
+  X(50, 8, 50, 4)
 
 // Variants of the persistent batched integrator (FP32, 4 waves per
 // workgroup): X(NG machines, PM processes, L lanes per trajectory), in three

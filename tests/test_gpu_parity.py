@@ -188,7 +188,7 @@ def test_repeat_runs_bit_identical(ctx):
     assert np.array_equal(_np(a["var"]), _np(b["var"]))
 
 
-@pytest.mark.parametrize("vid", [7, 8, 9, 10, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29])
+@pytest.mark.parametrize("vid", [7, 8, 9, 10, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 32, 33])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_variants_agree(ctx, vid, prec):
     """Every integrator variant (padded lane variants, lanes-per-trajectory

@@ -1,0 +1,165 @@
+"""Served form (continuous batching) on the GPU, through the C ABI.
+
+Each request's result is checked against the FP64 oracle (statistics 1e-4,
+as the batched form), is bit-identical alone and in a mix of requests that
+overlap on the device, and admission, cancellation and rejection behave as
+the header states."""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [(3, 1, 40, 300, 0.5), (7, 2, 60, 517, 0.6), (12, 4, 50, 250, 0.4),
+         (20, 6, 45, 130, 0.3), (33, 3, 40, 70, 0.25), (50, 5, 41, 66, 0.2)]
+
+
+def small_requests():
+    return [workloads.multimachine(n_gen=n, n_dist=P, N=N, K=K, T=T, dt=0.005, net_seed=100 + k,
+                                   seed=10 + k)
+            for k, (n, P, K, N, T) in enumerate(SPECS)]
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def mean_err(a, m, v):
+    num = np.abs(a - m).max(axis=0)
+    den = np.maximum(np.abs(m).max(axis=0), np.sqrt(np.abs(v)).max(axis=0))
+    return float((num / np.where(den == 0, 1, den)).max())
+
+
+def rel_err(a, b):
+    num = np.abs(a - b).reshape(-1, a.shape[-1]).max(axis=0)
+    den = np.abs(b).reshape(-1, b.shape[-1]).max(axis=0)
+    return float((num / np.where(den == 0, 1, den)).max())
+
+
+@pytest.fixture(scope="module")
+def ctx(fmc):
+    c = fmc.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_served_matches_oracle(ctx, prec):
+    scs = small_requests()
+    tickets = [ctx.submit(sc, precision=prec, time_chunk=37) for sc in scs]
+    for sc, tk in zip(scs, tickets):
+        r = tk.wait(timeout=120)
+        o = oracle.run(sc)
+        em = mean_err(_np(r["mean"]), o["mean"], o["var"])
+        ev = rel_err(_np(r["var"]), o["var"])
+        assert em <= 1e-4 and ev <= 1e-4, (sc["n_gen"], em, ev)
+        assert r["report"]["n_nonfinite"] == 0
+        assert r["report"]["time_chunk"] == 37
+        assert r["report"]["latency_s"] >= r["report"]["queue_wait_s"] >= 0
+
+
+def test_served_alone_equals_mix(ctx):
+    """Requests that run together give bit for bit what each gives alone."""
+    scs = small_requests()
+    mix = [ctx.submit(sc, time_chunk=50) for sc in scs]
+    mix = [t.wait(timeout=120) for t in mix]
+    for i in [0, 2, 5]:
+        alone = ctx.submit(scs[i], time_chunk=50).wait(timeout=120)
+        assert np.array_equal(_np(alone["mean"]), _np(mix[i]["mean"]))
+        assert np.array_equal(_np(alone["var"]), _np(mix[i]["var"]))
+
+
+def test_served_equals_batched_form(ctx):
+    """The served chunks (state kept on the device between ticks) give the
+    batched form's whole-horizon result for the same variant."""
+    sc = small_requests()[1]
+    s = ctx.submit(sc, precision="f32", time_chunk=29).wait(timeout=120)
+    vid = s["report"]["variant_id"]
+    b = ctx.run_batch([sc], precision="f32", variant=vid)[0]
+    assert rel_err(_np(s["var"]), _np(b["var"])) <= 1e-12
+    assert mean_err(_np(s["mean"]), _np(b["mean"]), _np(b["var"])) <= 1e-12
+
+
+def test_requests_overlap_on_the_device(ctx):
+    """A request submitted while a long one runs joins it and finishes first."""
+    long_sc = workloads.multimachine(n_gen=50, n_dist=5, N=20000, K=60, T=20.0, dt=0.005,
+                                     net_seed=3, seed=3)
+    short_sc = small_requests()[0]
+    t0 = time.monotonic()
+    a = ctx.submit(long_sc, time_chunk=100)
+    time.sleep(0.02)
+    b = ctx.submit(short_sc, time_chunk=100)
+    rb = b.wait(timeout=120)
+    tb = time.monotonic()
+    assert a.poll() is None, "the long request should still be running"
+    ra = a.wait(timeout=300)
+    ta = time.monotonic()
+    assert tb < ta
+    # the short one did not queue behind the long one
+    assert rb["report"]["queue_wait_s"] < 0.5 * (ta - t0)
+    alone = ctx.submit(short_sc, time_chunk=100).wait(timeout=120)
+    assert np.array_equal(_np(alone["var"]), _np(rb["var"]))
+    o = oracle.run(short_sc)
+    assert mean_err(_np(rb["mean"]), o["mean"], o["var"]) <= 1e-4
+    assert np.all(np.isfinite(_np(ra["var"])))
+
+
+def test_cancel(ctx, fmc):
+    long_sc = workloads.multimachine(n_gen=50, n_dist=5, N=20000, K=60, T=20.0, dt=0.005,
+                                     net_seed=4, seed=4)
+    t = ctx.submit(long_sc, time_chunk=50)
+    t.cancel()
+    with pytest.raises(fmc.FmcError) as e:
+        t.wait(timeout=120)
+    assert e.value.code == fmc.ECANCELLED
+    # the ticket is forgotten once reported
+    with pytest.raises(fmc.FmcError) as e:
+        t.wait(timeout=1)
+    assert e.value.code == fmc.EINVAL
+
+
+def test_rejections(ctx, fmc):
+    sc = small_requests()[0]
+    with pytest.raises(fmc.FmcError) as e:
+        ctx.submit(sc, precision="f64")
+    assert e.value.code == fmc.EINVAL
+    with pytest.raises(fmc.FmcError) as e:
+        ctx.submit(dict(sc, dt=0.0033))
+    assert e.value.code == fmc.EINVAL
+
+
+def test_admission_by_footprint(fmc):
+    """A small arena (2.5 footprints of a mid-size request): a request larger
+    than it is refused for good (ENOMEM), two mid-size requests fill it and the
+    third must wait (EBUSY), and memory comes back when they finish."""
+    mid = workloads.multimachine(n_gen=10, n_dist=3, N=20000, K=100, T=4.0, dt=0.005,
+                                 net_seed=6, seed=6)
+    big = workloads.multimachine(n_gen=10, n_dist=3, N=100000, K=100, T=2.0, dt=0.005,
+                                 net_seed=5, seed=5)
+    fp = fmc.footprint(mid, "f32")
+    arena = int(2.5 * fp)
+    assert fmc.footprint(big, "f32") > arena
+    os.environ["FMC_SERVE_ARENA_BYTES"] = str(arena)
+    c = fmc.Context(0)
+    try:
+        with pytest.raises(fmc.FmcError) as e:
+            c.submit(big)
+        assert e.value.code == fmc.ENOMEM
+        tickets = []
+        with pytest.raises(fmc.FmcError) as e:
+            for _ in range(4):
+                tickets.append(c.submit(mid))
+        assert e.value.code == fmc.EBUSY
+        assert len(tickets) == 2
+        res = [t.wait(timeout=300) for t in tickets]
+        again = c.submit(mid).wait(timeout=300)
+        assert np.array_equal(_np(again["var"]), _np(res[0]["var"]))
+        assert again["report"]["hbm_peak_bytes"] == fp
+    finally:
+        os.environ.pop("FMC_SERVE_ARENA_BYTES", None)
+        c.close()
