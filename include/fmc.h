@@ -26,9 +26,10 @@
  *    says otherwise.
  *  - Layouts are row-major.  The time grid is t_s = s*dt, s = 0..S with
  *    S = T/dt; stage times are t_c = c*dt/2, c = 0..2S.  The outputs of a
- *    system with n machines and P disturbances are V = 2n + P variables per
- *    time: delta_1..n (absolute rotor angle, rad), dw_1..n (speed deviation,
- *    pu), xi_1..P (disturbance, pu).
+ *    classical system with n machines and P disturbances are V = 2n + P
+ *    variables per time: delta_1..n (absolute rotor angle, rad), dw_1..n
+ *    (speed deviation, pu), xi_1..P (disturbance, pu); a flux-decay system
+ *    has V = 6n + P (see FMC_FD_*).
  *  - Streams: all work of a context is enqueued on the stream given at
  *    creation (or set by fmc_set_stream); calls that return results to host
  *    memory synchronise that stream.
@@ -124,16 +125,27 @@ typedef struct fmc_system {
                                      model, NULL for the classical model */
 } fmc_system;
 
-/* Flux-decay + IEEE type-1 exciter parameters per machine, in this order. */
+/* One-axis (flux-decay) machine with an IEEE type-1 exciter, per machine, in
+ * this order (no saturation, no regulator limits).  With E~'_k = E'q_k
+ * e^{j delta_k} behind jX'd on the reduced network, I = Y E~' + Yinf V_inf,
+ * Id + jIq = j I e^{-j delta}, Pe = E'q Iq, Vt = |E~' - jX'd I|:
+ *   d delta/dt = w_b dw,      2H d dw/dt = Pm + xi - Pe - D dw,
+ *   T'do dE'q/dt = -E'q - (Xd - X'd) Id + Efd,
+ *   TE dEfd/dt = -KE Efd + VR,
+ *   TF dRF/dt = -RF + (KF/TF) Efd,
+ *   TA dVR/dt = -VR + KA RF - (KA KF/TF) Efd + KA (Vref - Vt).
+ * E is E'q at t = 0; Efd, VR, RF and Vref are set so that t = 0 is an
+ * equilibrium.  Outputs per time: delta, dw, E'q, Efd, VR, RF (n each), xi. */
 #define FMC_FD_XD 0    /* synchronous reactance Xd */
-#define FMC_FD_TDO 1   /* open-circuit transient time constant T'do (s) */
-#define FMC_FD_KA 2    /* regulator gain */
-#define FMC_FD_TA 3    /* regulator time constant (s) */
-#define FMC_FD_KE 4    /* exciter constant */
-#define FMC_FD_TE 5    /* exciter time constant (s) */
-#define FMC_FD_KF 6    /* rate-feedback gain */
-#define FMC_FD_TF 7    /* rate-feedback time constant (s) */
-#define FMC_FD_NPARAM 8
+#define FMC_FD_XDP 1   /* transient reactance X'd (the one behind E~') */
+#define FMC_FD_TDO 2   /* open-circuit transient time constant T'do (s) */
+#define FMC_FD_KA 3    /* regulator gain */
+#define FMC_FD_TA 4    /* regulator time constant (s) */
+#define FMC_FD_KE 5    /* exciter constant */
+#define FMC_FD_TE 6    /* exciter time constant (s) */
+#define FMC_FD_KF 7    /* rate-feedback gain */
+#define FMC_FD_TF 8    /* rate-feedback time constant (s) */
+#define FMC_FD_NPARAM 9
 
 /* Ornstein-Uhlenbeck disturbances (eq. 4 with mu = -theta xi, constant
  * sigma): d xi_p = -theta_p xi_p dt + sigma_p dW_p, added to Pm of machine

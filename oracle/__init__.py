@@ -47,6 +47,7 @@ class _Problem(C.Structure):
         ("seed", C.c_uint64),
         ("basis", C.c_int32), ("sampler", C.c_int32), ("integrator", C.c_int32),
         ("ddof", C.c_int32),
+        ("model", C.c_int32), ("model_params", C.c_void_p),
     ]
 
 
@@ -72,6 +73,7 @@ def lib():
         L.orc_kron.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P, C.c_int32, P, P, P, P]
         L.orc_run.argtypes = [C.POINTER(_Problem), P, C.c_int64, P, P, P, P, P, P, P, P]
         L.orc_rhs.argtypes = [C.POINTER(_Problem), P, P, P]
+        L.orc_initial_state.argtypes = [C.POINTER(_Problem), P, P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -153,6 +155,7 @@ def kron(net: dict):
 _SAMPLER = {"lhs": 0, "srs": 1}
 _BASIS = {"paper": 0, "eigen": 1}
 _INTEG = {"rk4": 0, "trap": 1}
+_MODEL = {"classical": 0, "fluxdecay": 1}
 
 
 def _enum(v, table):
@@ -185,6 +188,8 @@ def problem(sc: dict):
     keep.dg = _i32(d["gen"])
     keep.th, keep.sg = _f64(d["theta"]), _f64(d["sigma"])
     keep.x0 = _f64(d.get("xi0"))
+    model = _enum(sc.get("model", 0), _MODEL)
+    keep.mp = _f64(sc.get("model_params")) if model == 1 else None
     pb = _Problem(
         n_gen=n, f0_hz=float(sc.get("f0", 60.0)),
         H=_p(keep.H), D=_p(keep.D), E=_p(keep.E), delta0=_p(keep.d0), Pm=_p(keep.Pm),
@@ -194,8 +199,15 @@ def problem(sc: dict):
         xi0=_p(keep.x0), T=float(sc["T"]), dt=float(sc["dt"]), K=int(sc["K"]),
         N=int(sc["N"]), seed=int(sc.get("seed", 0)),
         basis=_enum(sc.get("basis", 0), _BASIS), sampler=_enum(sc.get("sampler", 0), _SAMPLER),
-        integrator=_enum(sc.get("integrator", 0), _INTEG), ddof=int(sc.get("ddof", 1)))
+        integrator=_enum(sc.get("integrator", 0), _INTEG), ddof=int(sc.get("ddof", 1)),
+        model=model, model_params=_p(keep.mp))
     return pb, keep
+
+
+def n_out(sc: dict) -> int:
+    """Output variables per time: 2n + P (classical) or 6n + P (flux decay)."""
+    n = int(sc["n_gen"]); P = len(sc["dist"]["gen"])
+    return (6 * n if _enum(sc.get("model", 0), _MODEL) == 1 else 2 * n) + P
 
 
 def steps(sc: dict) -> int:
@@ -212,7 +224,7 @@ def run(sc: dict, zeta=None, sel=None, want_traj=False, allow_nonfinite=False):
     pb, keep = problem(sc)
     n = pb.n_gen
     S = steps(sc)
-    V = 2 * n + pb.n_proc
+    V = n_out(sc)
     s = None if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
     n_sel = pb.N if s is None else len(s)
     z = None if zeta is None else np.ascontiguousarray(zeta, dtype=np.float64)
@@ -237,6 +249,17 @@ def rhs(sc: dict, y, w):
     if rc != 0:
         raise RuntimeError(f"orc_rhs failed: {rc}")
     return dy
+
+
+def initial_state(sc: dict):
+    """Operating point (initial state [ny]) and exciter references Vref [n]
+    (zeros for the classical model)."""
+    pb, keep = problem(sc)
+    y0 = np.zeros(n_out(sc)); vref = np.zeros(int(sc["n_gen"]))
+    rc = lib().orc_initial_state(C.byref(pb), y0.ctypes.data, vref.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_initial_state failed: {rc}")
+    return y0, vref
 
 
 def kle_paths(zeta, Phi, P: int, K: int, c0: int = 0, C_cols=None):

@@ -428,7 +428,12 @@ typedef struct orc_problem {
     int64_t N;
     uint64_t seed;
     int32_t basis, sampler, integrator, ddof;
+    int32_t model;               /* 0 classical, 1 flux decay + IEEE type-1 exciter */
+    const double *model_params;  /* [n][9] for model 1 (order of FD_* below) */
 } orc_problem;
+
+/* Flux-decay parameters per machine, in this order. */
+enum { FD_XD, FD_XDP, FD_TDO, FD_KA, FD_TA, FD_KE, FD_TE, FD_KF, FD_TF, FD_NPARAM };
 
 typedef struct {
     int n, P, V, ny;
@@ -439,6 +444,10 @@ typedef struct {
     double Vinf;
     const int32_t *dgen;
     const double *theta, *sigma, *xi0;
+    int fd;           /* flux-decay model */
+    double *fdp;      /* [n][FD_NPARAM] */
+    double *Vref;     /* [n] exciter reference */
+    double *y0;       /* [ny] initial state (the operating point) */
 } model_t;
 
 /* Electrical power of every machine: Pe_i = Re{ E~_i conj(I_i) },
@@ -474,8 +483,14 @@ static void electrical_power_jac(const model_t *m, const double *delta, double *
 
 /* Right-hand side. State y = (delta_1..n [rad, absolute], dw_1..n [pu],
  * xi_1..P); w[p] is the KLE white-noise surrogate of eq. 8 at this time. */
+static void rhs_fd(const model_t *m, const double *y, const double *w, double *dy);
+
 static void rhs(const model_t *m, const double *y, const double *w, double *dy)
 {
+    if (m->fd) {
+        rhs_fd(m, y, w, dy);
+        return;
+    }
     const int n = m->n, P = m->P;
     double Pe[512];
     electrical_power(m, y, Pe);
@@ -508,15 +523,103 @@ static void rhs_jac(const model_t *m, const double *y, double *J)
     if (JP != Jp) free(JP);
 }
 
+/* ------------------------------------------------------------------------- */
+/* One-axis (flux-decay) machine with an IEEE type-1 exciter (no saturation,  */
+/* no limits).  The paper's case study names this exciter type but gives no   */
+/* equations; they are written here from the standard one-axis machine model */
+/* with X'q = X'd (so E'd = 0 and E~' = E'q e^{j delta} behind jX'd) and the  */
+/* IEEE (1968) type-1 block diagram:                                          */
+/*   VR = KA/(1 + s TA) (Vref - Vt - VF),  Efd = VR/(KE + s TE),              */
+/*   VF = s KF/(1 + s TF) Efd,  with the state RF = (KF/TF)/(1 + s TF) Efd.   */
+/* State y = (delta, dw, E'q, Efd, VR, RF) per machine (blocks of n), then xi. */
+/* ------------------------------------------------------------------------- */
+
+/* Network quantities at (delta, E'q): I_i = sum_k Y_ik E~'_k + Yinf_i V_inf,
+ * Id + jIq = j I e^{-j delta}, Pe = Re(E~' conj I), Vt = |E~' - j X'd I|. */
+static void fd_network(const model_t *m, const double *delta, const double *eq, double *Pe,
+                       double *Id, double *Vt)
+{
+    const int n = m->n;
+    double complex Et[512];
+    for (int k = 0; k < n; ++k) Et[k] = eq[k] * cexp(I * delta[k]);
+    for (int i = 0; i < n; ++i) {
+        double complex cur = m->inf ? m->Yinf[i] * m->Vinf : 0.0;
+        for (int k = 0; k < n; ++k) cur += m->Y[(int64_t)i * n + k] * Et[k];
+        const double complex dq = I * cur * cexp(-I * delta[i]); /* Id + j Iq */
+        Pe[i] = creal(Et[i] * conj(cur));
+        Id[i] = creal(dq);
+        Vt[i] = cabs(Et[i] - I * m->fdp[i * FD_NPARAM + FD_XDP] * cur);
+    }
+}
+
+static void rhs_fd(const model_t *m, const double *y, const double *w, double *dy)
+{
+    const int n = m->n, P = m->P;
+    const double *delta = y, *dw = y + n, *eq = y + 2 * n, *efd = y + 3 * n, *vr = y + 4 * n,
+                 *rf = y + 5 * n, *xi = y + 6 * n;
+    double Pe[512], Id[512], Vt[512];
+    fd_network(m, delta, eq, Pe, Id, Vt);
+    for (int i = 0; i < n; ++i) {
+        const double *q = m->fdp + i * FD_NPARAM;
+        double pm = m->Pm[i];
+        for (int p = 0; p < P; ++p)
+            if (m->dgen[p] == i) pm += xi[p];
+        dy[i] = m->wb * dw[i];
+        dy[n + i] = (pm - Pe[i] - m->D[i] * dw[i]) / (2.0 * m->H[i]);
+        dy[2 * n + i] = (-eq[i] - (q[FD_XD] - q[FD_XDP]) * Id[i] + efd[i]) / q[FD_TDO];
+        dy[3 * n + i] = (-q[FD_KE] * efd[i] + vr[i]) / q[FD_TE];
+        dy[5 * n + i] = (-rf[i] + q[FD_KF] / q[FD_TF] * efd[i]) / q[FD_TF];
+        dy[4 * n + i] = (-vr[i] + q[FD_KA] * rf[i] - q[FD_KA] * q[FD_KF] / q[FD_TF] * efd[i] +
+                         q[FD_KA] * (m->Vref[i] - Vt[i])) / q[FD_TA];
+    }
+    for (int p = 0; p < P; ++p) dy[6 * n + p] = -m->theta[p] * xi[p] + m->sigma[p] * w[p];
+}
+
+/* Exciter and field states at the operating point (delta0, E'q0 = E): every
+ * derivative vanishes. */
+static int fd_operating_point(model_t *m)
+{
+    const int n = m->n;
+    double Pe[512], Id[512], Vt[512];
+    for (int i = 0; i < n; ++i) {
+        const double *q = m->fdp + i * FD_NPARAM;
+        if (!(q[FD_XDP] > 0.0) || !(q[FD_TDO] > 0.0) || !(q[FD_TA] > 0.0) || !(q[FD_TE] > 0.0) ||
+            !(q[FD_TF] > 0.0) || q[FD_KA] < 0.0)
+            return ORC_EINVAL;
+    }
+    fd_network(m, m->d0, m->E, Pe, Id, Vt);
+    for (int i = 0; i < n; ++i) {
+        const double *q = m->fdp + i * FD_NPARAM;
+        const double efd = m->E[i] + (q[FD_XD] - q[FD_XDP]) * Id[i];
+        const double vr = q[FD_KE] * efd;
+        m->y0[i] = m->d0[i];
+        m->y0[n + i] = 0.0;
+        m->y0[2 * n + i] = m->E[i];
+        m->y0[3 * n + i] = efd;
+        m->y0[4 * n + i] = vr;
+        m->y0[5 * n + i] = q[FD_KF] / q[FD_TF] * efd;
+        m->Vref[i] = Vt[i] + (q[FD_KA] > 0.0 ? vr / q[FD_KA] : 0.0);
+    }
+    return ORC_OK;
+}
+
 /* Operating point.  With delta0 given, Pm_i := Pe_i(delta0) (equilibrium by
  * construction).  Without it (infinite-bus systems), delta0 solves
  * Pe(delta) = Pm by Newton's method from delta = 0. */
 static int setup_model(const orc_problem *pb, model_t *m)
 {
     const int n = pb->n_gen, P = pb->n_proc;
-    if (n < 1 || n > 512 || P < 0) return ORC_EINVAL;
     memset(m, 0, sizeof(*m));
-    m->n = n; m->P = P; m->V = 2 * n + P; m->ny = 2 * n + P;
+    if (n < 1 || n > 512 || P < 0) return ORC_EINVAL;
+    m->fd = pb->model == 1;
+    if (pb->model != 0 && pb->model != 1) return ORC_EINVAL;
+    if (m->fd && !pb->model_params) return ORC_EINVAL;
+    m->n = n; m->P = P;
+    m->ny = m->V = (m->fd ? 6 * n : 2 * n) + P;
+    m->y0 = calloc(m->ny, sizeof(double));
+    m->Vref = calloc(n, sizeof(double));
+    m->fdp = calloc((size_t)n * FD_NPARAM, sizeof(double));
+    if (m->fd) memcpy(m->fdp, pb->model_params, sizeof(double) * n * FD_NPARAM);
     m->wb = 2.0 * M_PI * pb->f0_hz;
     m->H = malloc(sizeof(double) * n); m->D = malloc(sizeof(double) * n);
     m->E = malloc(sizeof(double) * n); m->d0 = malloc(sizeof(double) * n);
@@ -561,12 +664,16 @@ static int setup_model(const orc_problem *pb, model_t *m)
         free(J); free(r);
         if (!ok) return ORC_ENOTCONV;
     }
+    if (m->fd) return fd_operating_point(m);
+    for (int i = 0; i < n; ++i) m->y0[i] = m->d0[i];
+    for (int p = 0; p < P; ++p) m->y0[2 * n + p] = pb->xi0 ? pb->xi0[p] : 0.0;
     return ORC_OK;
 }
 
 static void free_model(model_t *m)
 {
     free(m->H); free(m->D); free(m->E); free(m->d0); free(m->Pm); free(m->Y); free(m->Yinf);
+    free(m->y0); free(m->Vref); free(m->fdp);
 }
 
 /* White-noise surrogate of eq. 8 for every process at stage column c:
@@ -591,15 +698,15 @@ static int simulate_one(const model_t *m, const double *zcol, int64_t zstride,
                         const double *Phi, int K, int64_t S, double dt, int integrator,
                         double *out)
 {
-    const int n = m->n, P = m->P, ny = m->ny;
+    const int P = m->P, ny = m->ny;
     const int64_t C = 2 * S + 1;
     double *y = calloc(ny * 8 + ny * ny + 4 * P + 8, sizeof(double));
     double *k1 = y + ny, *k2 = k1 + ny, *k3 = k2 + ny, *k4 = k3 + ny, *tmp = k4 + ny;
     double *z = tmp + ny, *g = z + ny, *J = g + ny;
     double *w0 = J + ny * ny, *w1 = w0 + P, *w2 = w1 + P;
     int rc = ORC_OK;
-    for (int i = 0; i < n; ++i) { y[i] = m->d0[i]; y[n + i] = 0.0; }
-    for (int p = 0; p < P; ++p) y[2 * n + p] = m->xi0 ? m->xi0[p] : 0.0;
+    memcpy(y, m->y0, sizeof(double) * ny);
+    for (int p = 0; p < P; ++p) y[ny - P + p] = m->xi0 ? m->xi0[p] : 0.0;
     memcpy(out, y, sizeof(double) * ny);
     for (int64_t s = 0; s < S; ++s) {
         kle_forcing(zcol, zstride, Phi, K, C, P, 2 * s, w0);
@@ -669,6 +776,7 @@ int orc_run(const orc_problem *pb, const double *zeta_in, int64_t n_sel, const i
     const int64_t S = (int64_t)llround(pb->T / pb->dt);
     if (S < 1 || fabs((double)S * pb->dt - pb->T) > 1e-9 * pb->T) return ORC_EINVAL;
     const int64_t C = 2 * S + 1;
+    if (pb->model == 1 && pb->integrator != 0) return ORC_EINVAL; /* RK4 only */
     model_t m;
     int rc = setup_model(pb, &m);
     if (rc != ORC_OK) { free_model(&m); return rc; }
@@ -733,6 +841,20 @@ int orc_rhs(const orc_problem *pb, const double *y, const double *w, double *dy)
     model_t m;
     int rc = setup_model(pb, &m);
     if (rc == ORC_OK) rhs(&m, y, w, dy);
+    free_model(&m);
+    return rc;
+}
+
+/* The operating point (initial state, [ny]) and, for the flux-decay model,
+ * the exciter references Vref [n] (may be NULL). */
+int orc_initial_state(const orc_problem *pb, double *y0, double *vref)
+{
+    model_t m;
+    int rc = setup_model(pb, &m);
+    if (rc == ORC_OK) {
+        memcpy(y0, m.y0, sizeof(double) * m.ny);
+        if (vref) memcpy(vref, m.Vref, sizeof(double) * m.n);
+    }
     free_model(&m);
     return rc;
 }

@@ -17,7 +17,8 @@ Scenario dict keys (consumed by both ``oracle.run`` and the product binding):
   infinite_bus, V_inf, Yinf (complex [n]),
   dist = {gen [P] int, theta [P], sigma [P], xi0 [P] or None},
   T, dt, K, N, seed, basis ('paper'|'eigen'), sampler ('lhs'|'srs'),
-  integrator ('rk4'|'trap'), ddof.
+  integrator ('rk4'|'trap'), ddof, and optionally model ('classical' |
+  'fluxdecay') with model_params [n, 9] (Xd, X'd, T'do, KA, TA, KE, TE, KF, TF).
 Network dict keys: n_bus, n_gen, br_from, br_to, br_r, br_x, br_b, load_g,
   load_b, gen_bus, gen_xdp.
 """
@@ -123,6 +124,55 @@ def multimachine(n_gen=10, n_dist=3, N=10_000, K=100, T=20.0, dt=0.005, net_seed
         dist=dict(gen=gen, theta=theta, sigma=sigma, xi0=None),
         T=T, dt=dt, K=K, N=N, seed=seed, basis=basis, sampler=sampler,
         integrator=integrator, ddof=1)
+
+
+def fluxdecay(n_gen=200, n_dist=10, N=50_000, K=100, T=30.0, dt=0.005, net_seed=200, seed=6,
+              n_bus=None, n_branch=None, basis="paper", sampler="lhs"):
+    """One-axis (flux-decay) machines with IEEE type-1 exciters on a seeded
+    synthetic network: the large requests of the served workload (200
+    machines, 10 OU disturbances, T = 30 s, N = 5e4, K = 100 by default).
+
+    Machine data as ``multimachine`` (E is E'q at t = 0) plus, per machine,
+    X'd from the network, Xd = X'd * U[4, 8], T'do ~ U[4, 8] s, KA ~ U[10, 25],
+    TA ~ U[0.02, 0.1] s, KE = 1, TE ~ U[0.3, 0.8] s, KF ~ U[0.08, 0.15],
+    TF ~ U[0.5, 1.5] s (gains chosen so that the linearised systems are stable).
+    The method sets Efd, VR, RF and Vref at equilibrium.
+    """
+    sc = multimachine(n_gen=n_gen, n_dist=n_dist, N=N, K=K, T=T, dt=dt, net_seed=net_seed,
+                      seed=seed, n_bus=n_bus, n_branch=n_branch, basis=basis, sampler=sampler)
+    rng = np.random.default_rng(net_seed + 2_000_029)
+    xdp = sc["net"]["gen_xdp"]
+    mp = np.zeros((n_gen, 9))
+    mp[:, 0] = xdp * rng.uniform(4.0, 8.0, size=n_gen)
+    mp[:, 1] = xdp
+    mp[:, 2] = rng.uniform(4.0, 8.0, size=n_gen)
+    mp[:, 3] = rng.uniform(10.0, 25.0, size=n_gen)
+    mp[:, 4] = rng.uniform(0.02, 0.1, size=n_gen)
+    mp[:, 5] = 1.0
+    mp[:, 6] = rng.uniform(0.3, 0.8, size=n_gen)
+    mp[:, 7] = rng.uniform(0.08, 0.15, size=n_gen)
+    mp[:, 8] = rng.uniform(0.5, 1.5, size=n_gen)
+    sc.update(model="fluxdecay", model_params=mp)
+    return sc
+
+
+def smib_fluxdecay(Xe=0.4, Xd=1.6, Xdp=0.3, Tdo=6.0, KA=30.0, TA=0.05, KE=1.0, TE=0.5,
+                   KF=0.05, TF=1.0, H=3.5, D=2.0, E=1.1, delta0=0.6, V_inf=1.0, **kw):
+    """One flux-decay machine behind X'd against an infinite bus through Xe
+    (reduced to the internal node), one OU disturbance on Pm."""
+    X = Xdp + Xe
+    y = 1.0 / (1j * X)
+    d = dict(N=64, K=20, T=1.0, dt=0.01, seed=1, theta=0.5, sigma=0.05)
+    d.update(kw)
+    return dict(
+        n_gen=1, f0=60.0, H=np.array([H]), D=np.array([D]), E=np.array([E]),
+        delta0=np.array([delta0]), Pm=None, Y=np.array([[y]]), net=None,
+        infinite_bus=True, V_inf=V_inf, Yinf=np.array([-y]),
+        dist=dict(gen=np.array([0], dtype=np.int32), theta=np.array([d["theta"]]),
+                  sigma=np.array([d["sigma"]]), xi0=None),
+        T=d["T"], dt=d["dt"], K=d["K"], N=d["N"], seed=d["seed"], basis="paper",
+        sampler="lhs", integrator="rk4", ddof=1, model="fluxdecay",
+        model_params=np.array([[Xd, Xdp, Tdo, KA, TA, KE, TE, KF, TF]]))
 
 
 def config1(**kw):
