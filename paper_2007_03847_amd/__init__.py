@@ -31,6 +31,9 @@ BASIS = {"paper": 0, "eigen": 1}
 SAMPLER = {"lhs": 0, "srs": 1}
 INTEGRATOR = {"rk4": 0, "trap": 1}
 PRECISION = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
+CLASSICAL, FLUXDECAY_IEEET1 = 0, 1
+MODEL = {"classical": CLASSICAL, "fluxdecay": FLUXDECAY_IEEET1}
+FD_NPARAM = 9  # Xd, X'd, T'do, KA, TA, KE, TE, KF, TF
 MEM_HOST, MEM_DEVICE = 0, 1
 ABI_VERSION = 1
 
@@ -189,12 +192,15 @@ def scenario_structs(sc: dict, precision="f64", variant=-1, time_chunk=0, zeta_i
         a["Yinf_re"], a["Yinf_im"] = _f64(Yinf.real), _f64(Yinf.imag)
     else:
         a["Yinf_re"] = a["Yinf_im"] = None
+    model = _enum(sc.get("model", 0), MODEL)
+    a["model_params"] = (np.ascontiguousarray(sc["model_params"], dtype=np.float64).reshape(n, -1)
+                         if model == FLUXDECAY_IEEET1 else None)
     keep.append(a)
     sysd = System(n_gen=n, f0_hz=float(sc.get("f0", 60.0)), H=_ptr(a["H"]), D=_ptr(a["D"]),
                   E=_ptr(a["E"]), delta0=_ptr(a["delta0"]), Pm=_ptr(a["Pm"]),
                   Y_re=_ptr(a["Y_re"]), Y_im=_ptr(a["Y_im"]), net=net_p, infinite_bus=int(inf),
                   V_inf=float(sc.get("V_inf", 1.0)), Yinf_re=_ptr(a["Yinf_re"]),
-                  Yinf_im=_ptr(a["Yinf_im"]), model=0, model_params=None)
+                  Yinf_im=_ptr(a["Yinf_im"]), model=model, model_params=_ptr(a["model_params"]))
     d = sc["dist"]
     b = dict(gen=_i32(d["gen"]), theta=_f64(d["theta"]), sigma=_f64(d["sigma"]),
              xi0=_f64(d.get("xi0")))
@@ -210,6 +216,12 @@ def scenario_structs(sc: dict, precision="f64", variant=-1, time_chunk=0, zeta_i
                  zeta_in=_dptr(zeta_in))
     keep.extend([sysd, dist, par])
     return sysd, dist, par, keep
+
+
+def n_out(sc: dict) -> int:
+    """Output variables per time: 2n + P (classical) or 6n + P (flux decay)."""
+    n = int(sc["n_gen"]); P = len(sc["dist"]["gen"])
+    return (6 * n if _enum(sc.get("model", 0), MODEL) == FLUXDECAY_IEEET1 else 2 * n) + P
 
 
 def steps(sc: dict) -> int:
@@ -299,7 +311,7 @@ class Context:
         """Alg. 1 on the GPU.  Returns dict(mean, var[, traj, strata, zeta], report)."""
         t = self.torch
         n = int(sc["n_gen"]); P = len(sc["dist"]["gen"]); S = steps(sc)
-        V = 2 * n + P; M = P * int(sc["K"]); N = int(sc["N"])
+        V = n_out(sc); M = P * int(sc["K"]); N = int(sc["N"])
         sysd, dist, par, keep = scenario_structs(sc, precision, variant, time_chunk, zeta_in)
         res = outputs or {}
         mean = res.get("mean"); var = res.get("var")
@@ -335,7 +347,7 @@ class Context:
 def _outputs_for(ctx, sc, traj_idx, keep):
     t = ctx.torch
     n = int(sc["n_gen"]); P = len(sc["dist"]["gen"]); S = steps(sc)
-    V = 2 * n + P
+    V = n_out(sc)
     mean = t.empty((S + 1, V), dtype=t.float64, device=ctx.device)
     var = t.empty((S + 1, V), dtype=t.float64, device=ctx.device)
     traj = None
@@ -431,7 +443,7 @@ def _submit(ctx, sc, precision="f32", variant=-1, time_chunk=0):
     s = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))
     t = ctx.torch
     n = int(sc["n_gen"]); P = len(sc["dist"]["gen"]); S = steps(sc)
-    V = 2 * n + P
+    V = n_out(sc)
     mean = t.empty((S + 1, V), dtype=t.float64, device=ctx.device)
     var = t.empty((S + 1, V), dtype=t.float64, device=ctx.device)
     # the server writes on its own stream: the tensors must exist before it runs

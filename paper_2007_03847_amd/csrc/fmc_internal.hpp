@@ -164,4 +164,69 @@ int persistent_blocks_per_cu(int cls);
 hipError_t launch_persistent(int cls, const BatchArgs& b, int grid, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);
 
+// ---- flux-decay machines with IEEE type-1 exciters ----
+// Parameter order per machine (as in the C ABI).
+constexpr int kFdXd = 0, kFdXdp = 1, kFdTdo = 2, kFdKa = 3, kFdTa = 4, kFdKe = 5, kFdTe = 6,
+              kFdKf = 7, kFdTf = 8, kFdParams = 9;
+constexpr int kFdMaxProc = 32;  // processes per flux-decay system
+constexpr int kFdMaxGen = 256;  // machines (16 per wave, 16 waves per workgroup)
+
+// FP64 operating point block of the flux-decay model (n machines):
+// e^{j delta0}, J0 = I0 e^{-j delta0}, Vt0 = E~0 - jX'd I0 and |Vt0|, then the
+// output offsets [6n] (delta0, 0, E, Efd0, VR0, RF0 per block of n).
+struct FdLayout {
+  int64_t n;
+  __host__ __device__ int64_t u0r() const { return 0; }
+  __host__ __device__ int64_t u0i() const { return n; }
+  __host__ __device__ int64_t j0r() const { return 2 * n; }
+  __host__ __device__ int64_t j0i() const { return 3 * n; }
+  __host__ __device__ int64_t vt0r() const { return 4 * n; }
+  __host__ __device__ int64_t vt0i() const { return 5 * n; }
+  __host__ __device__ int64_t vt0a() const { return 6 * n; }
+  __host__ __device__ int64_t off() const { return 7 * n; }
+  __host__ __device__ int64_t size() const { return 13 * n; }
+};
+
+// FP32 constants of the flux-decay integrator, machine-major [n_pad][kStride]
+// (a machine's fields are immediate offsets from one address; the odd stride
+// spreads the four machines a wave reads at once over distinct LDS banks),
+// then the process block theta, sigma, xi0, machine index [4][kFdMaxProc].
+struct FdPack {
+  enum Field {
+    C0, S0, U0R, U0I, I0R, I0I, J0R, J0I, VT0R, VT0I, VT0A, RES, DMP, INV2H, XDP, XDD_T, ITDO,
+    KE_TE, ITE, ITF, KF_TF2, KA_TA, ITA, KAKF, NFIELD
+  };
+  static constexpr int kStride = 25;
+  int n_pad;
+  __host__ __device__ int at(int m, int f) const { return m * kStride + f; }
+  __host__ __device__ int proc() const { return n_pad * kStride; }
+  __host__ __device__ int size() const { return n_pad * kStride + 4 * kFdMaxProc; }
+};
+
+struct FdArgs {
+  const float* coef;          // FdPack block
+  const float2* ap;           // Y in A-operand order [n_pad/16][n_pad/2][64]
+  const float* w;             // [cols][P][N] KLE paths of this chunk
+  float* state;               // [tiles][ceil(NB/2)][48][64] deviations between chunks
+  float* xstate;              // [tiles][kFdMaxProc][16]
+  const double* off;          // [6n] FP64 output offsets
+  const int32_t* traj_slot;   // [N] or null
+  double* traj;               // [n_traj][S+1][V]
+  unsigned long long* nonfinite;
+  long long* first_bad;
+  double2* rows;              // statistics rows [n_items][row_stride]
+  int64_t row_stride;         // elements between items' rows
+  int64_t row_base;           // step held by the first row
+  int n, P, V, n_pad;
+  int64_t N, S, s_begin, s_end, c_base;
+  int64_t tiles, tiles_per_item;
+  float dt, wb;
+};
+hipError_t launch_setup_fd(const double* canon, int n, int P, const double* E, const double* prm,
+                           double* fd, hipStream_t st);
+hipError_t launch_pack_fd(const double* canon, int n, int P, const double* prm, const double* fd,
+                          const int32_t* gen, int n_pad, float* coef, float2* ap, hipStream_t st);
+size_t fd_lds_bytes(int n_pad);
+hipError_t launch_rk4_fd(const FdArgs& a, int64_t n_items, hipStream_t st);
+
 }  // namespace fmc

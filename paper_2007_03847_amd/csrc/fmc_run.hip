@@ -125,6 +125,7 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   if (out->n_traj < 0 || (out->n_traj > 0 && (!out->traj_idx || !out->traj)))
     return fail(FMC_EINVAL, "n_traj > 0 needs traj_idx and traj");
   HIPCHK(hipSetDevice(c->device));
+  if (sys->model == FMC_FLUXDECAY_IEEET1) return run_fd(c, sys, dist, par, out, S);
   const int n = sys->n_gen, P = dist->n_proc, K = par->K;
   const int64_t N = par->N, M = (int64_t)P * K, C = 2 * S + 1;
   const int V = 2 * n + P;

@@ -262,7 +262,26 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
     return fail(FMC_EINVAL, "unknown precision");
   const int n = sys->n_gen;
   if (n < 1) return fail(FMC_EINVAL, "n_gen must be >= 1");
-  if (sys->model != FMC_CLASSICAL) return fail(FMC_EINVAL, "model not available on this path");
+  if (sys->model != FMC_CLASSICAL && sys->model != FMC_FLUXDECAY_IEEET1)
+    return fail(FMC_EINVAL, "unknown generator model");
+  if (sys->model == FMC_FLUXDECAY_IEEET1) {
+    if (!sys->model_params) return fail(FMC_EINVAL, "the flux-decay model needs model_params");
+    if (par->precision == FMC_F64)
+      return fail(FMC_EINVAL, "the flux-decay model integrates in FP32 (FMC_F32 or FMC_BF16X3)");
+    if (n > kFdMaxGen) return fail(FMC_EINVAL, "the flux-decay model takes at most 256 machines");
+    const int nw = ((n + 15) / 16 + 1) / 2;  // waves of the flux-decay integrator
+    if (dist->n_proc > std::min(kFdMaxProc, 4 * nw))
+      return fail(FMC_EINVAL, "too many disturbance processes for the flux-decay model (at most "
+                              "min(32, 4 ceil(ceil(n/16)/2)))");
+    for (int i = 0; i < n; ++i) {
+      const double* q = sys->model_params + (int64_t)i * kFdParams;
+      for (int k = 0; k < kFdParams; ++k)
+        if (!std::isfinite(q[k])) return fail(FMC_EINVAL, "flux-decay parameters must be finite");
+      if (!(q[kFdXdp] > 0.0) || !(q[kFdTdo] > 0.0) || !(q[kFdTa] > 0.0) || !(q[kFdTe] > 0.0) ||
+          !(q[kFdTf] > 0.0) || q[kFdKa] < 0.0)
+        return fail(FMC_EINVAL, "flux-decay parameters: X'd, T'do, TA, TE, TF > 0 and KA >= 0");
+    }
+  }
   if (!sys->H || !sys->D || !sys->E) return fail(FMC_EINVAL, "H, D and E are required");
   for (int i = 0; i < n; ++i) {
     if (!(sys->H[i] > 0.0)) return fail(FMC_EINVAL, "H must be positive");

@@ -77,4 +77,13 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
                const fmc_params* par, fmc_outputs* out);
 void serve_shutdown(Context* c);
 
+// Flux-decay path: tiles of 16 trajectories, contiguous work items of
+// tiles_per_item tiles, one workgroup per item.
+struct FdPlan {
+  int64_t tiles, tiles_per_item, n_items;
+};
+int fd_plan(int64_t N, int n_cu, FdPlan* p);
+int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const fmc_params* par,
+           fmc_outputs* out, int64_t S);
+
 }  // namespace fmc

@@ -1,0 +1,520 @@
+// k_fluxdecay.hip -- one-axis (flux-decay) machines with IEEE type-1 exciters
+// (FP32 integration, FP64 setup and statistics).
+//
+// Model (per machine, X'q = X'd so the machine is E~' = E'q e^{j delta}
+// behind jX'd on the reduced network; IEEE type-1 exciter without saturation
+// or limits):
+//   d delta/dt = w_b dw,  2H d dw/dt = Pm + xi - Pe - D dw,
+//   T'do dE'q/dt = -E'q - (Xd - X'd) Id + Efd,   TE dEfd/dt = -KE Efd + VR,
+//   TF dRF/dt = -RF + (KF/TF) Efd,
+//   TA dVR/dt = -VR + KA RF - (KA KF/TF) Efd + KA (Vref - Vt),
+// with I = Y E~' + Yinf V_inf, Id + jIq = j I e^{-j delta}, Pe = Re(E~' conj I),
+// Vt = |E~' - jX'd I|.  The OU disturbances and their KLE paths are those of
+// the classical model.
+//
+// The integrator works in deviations from the operating point.  Per RK4 stage
+// the network current deviation of a tile of 16 trajectories is one dense
+// product dI = Y dE' (n x n complex by n x 16), done on the matrix cores as a
+// real product [Re dI; Im dI] = [Yr -Yi; Yi Yr] [Re dE'; Im dE'] with
+// v_mfma_f32_16x16x4f32.  Wave w of a workgroup computes the 16 x 16 output
+// blocks of the machine blocks 2w and 2w+1 (16 machines each; one LDS
+// fragment feeds four products), and the accumulator layout (lane l holds
+// rows 4(l/16)+r, r = 0..3, of column l%16) makes lane l the owner of
+// machines 16b + 4(l/16) + r of trajectory l%16: the lane that receives a
+// current also holds that machine's state.  Y is
+// packed once into the A-operand order of each wave and streamed from L2;
+// the dE' tile (the B operand) lives in LDS.  Each lane's RK4 sums live in
+// LDS too: with 8 machines a lane holds 48 state values and 48 stage values
+// in registers, and the sums would not fit beside them.
+#include <hip/hip_runtime.h>
+
+#include "fmc_internal.hpp"
+#include "k_integrate.hpp"
+
+namespace fmc {
+
+namespace {
+
+constexpr int kT = 16;  // trajectories per tile
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// FP64 operating point of the flux-decay machines (one thread per machine),
+// after the common setup kernel has solved delta0 and I0 = Y E~0 + Yinf V:
+//   J0 = I0 e^{-j delta0}, Id0 = -Im J0, Vt0 = E~0 - jX'd I0,
+//   Efd0 = E + (Xd - X'd) Id0, VR0 = KE Efd0, RF0 = (KF/TF) Efd0,
+// and the FP64 output offsets (delta0, 0, E, Efd0, VR0, RF0 per block).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_setup_fd(const double* __restrict__ canon, int n, int P,
+                                                  const double* __restrict__ E,
+                                                  const double* __restrict__ prm,
+                                                  double* __restrict__ fd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const CanonLayout C{n, P};
+  const FdLayout F{n};
+  const double* q = prm + (int64_t)i * kFdParams;
+  const double d0 = canon[C.delta0() + i];
+  const double ur = cos(d0), ui = sin(d0);
+  const double i0r = canon[C.i0r() + i], i0i = canon[C.i0i() + i];
+  const double j0r = i0r * ur + i0i * ui, j0i = i0i * ur - i0r * ui;  // I0 e^{-j d0}
+  const double id0 = -j0i;
+  const double c0 = canon[C.c0() + i], s0 = canon[C.s0() + i];
+  const double xdp = q[kFdXdp];
+  const double vtr = c0 + xdp * i0i, vti = s0 - xdp * i0r;  // E~0 - j X'd I0
+  const double efd0 = E[i] + (q[kFdXd] - xdp) * id0;
+  fd[F.u0r() + i] = ur;
+  fd[F.u0i() + i] = ui;
+  fd[F.j0r() + i] = j0r;
+  fd[F.j0i() + i] = j0i;
+  fd[F.vt0r() + i] = vtr;
+  fd[F.vt0i() + i] = vti;
+  fd[F.vt0a() + i] = sqrt(vtr * vtr + vti * vti);
+  fd[F.off() + i] = d0;
+  fd[F.off() + n + i] = 0.0;
+  fd[F.off() + 2 * n + i] = E[i];
+  fd[F.off() + 3 * n + i] = efd0;
+  fd[F.off() + 4 * n + i] = q[kFdKe] * efd0;
+  fd[F.off() + 5 * n + i] = q[kFdKf] / q[kFdTf] * efd0;
+}
+
+// FP32 constants [n_pad][kStride] (padding machines are zero except |Vt0| = 1,
+// hence inert)
+// and the per-process block (theta, sigma, xi0, machine index).
+__global__ void __launch_bounds__(256) k_pack_fd(const double* __restrict__ canon, int n, int P,
+                                                 const double* __restrict__ prm,
+                                                 const double* __restrict__ fd,
+                                                 const int32_t* __restrict__ gen, int n_pad,
+                                                 float* __restrict__ cf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const CanonLayout C{n, P};
+  const FdLayout F{n};
+  const FdPack K{n_pad};
+  if (i < n_pad) {
+    const bool on = i < n;
+    const double* q = prm + (int64_t)(on ? i : 0) * kFdParams;
+    auto put = [&](int field, double v) { cf[K.at(i, field)] = on ? (float)v : 0.0f; };
+    put(FdPack::C0, on ? canon[C.c0() + i] : 0.0);
+    put(FdPack::S0, on ? canon[C.s0() + i] : 0.0);
+    put(FdPack::U0R, on ? fd[F.u0r() + i] : 0.0);
+    put(FdPack::U0I, on ? fd[F.u0i() + i] : 0.0);
+    put(FdPack::I0R, on ? canon[C.i0r() + i] : 0.0);
+    put(FdPack::I0I, on ? canon[C.i0i() + i] : 0.0);
+    put(FdPack::J0R, on ? fd[F.j0r() + i] : 0.0);
+    put(FdPack::J0I, on ? fd[F.j0i() + i] : 0.0);
+    put(FdPack::VT0R, on ? fd[F.vt0r() + i] : 0.0);
+    put(FdPack::VT0I, on ? fd[F.vt0i() + i] : 0.0);
+    cf[K.at(i, FdPack::VT0A)] = on ? (float)fd[F.vt0a() + i] : 1.0f;  // padding: no 0/0 below
+    put(FdPack::RES, on ? canon[C.res() + i] : 0.0);
+    put(FdPack::DMP, on ? canon[C.dmp() + i] : 0.0);
+    put(FdPack::INV2H, on ? canon[C.inv2h() + i] : 0.0);
+    put(FdPack::XDP, q[kFdXdp]);
+    put(FdPack::XDD_T, (q[kFdXd] - q[kFdXdp]) / q[kFdTdo]);
+    put(FdPack::ITDO, 1.0 / q[kFdTdo]);
+    put(FdPack::KE_TE, q[kFdKe] / q[kFdTe]);
+    put(FdPack::ITE, 1.0 / q[kFdTe]);
+    put(FdPack::ITF, 1.0 / q[kFdTf]);
+    put(FdPack::KF_TF2, q[kFdKf] / q[kFdTf] / q[kFdTf]);
+    put(FdPack::KA_TA, q[kFdKa] / q[kFdTa]);
+    put(FdPack::ITA, 1.0 / q[kFdTa]);
+    put(FdPack::KAKF, q[kFdKa] * q[kFdKf] / q[kFdTf] / q[kFdTa]);
+  }
+  if (i < P) {
+    cf[K.proc() + i] = (float)canon[C.theta() + i];
+    cf[K.proc() + kFdMaxProc + i] = (float)canon[C.sigma() + i];
+    cf[K.proc() + 2 * kFdMaxProc + i] = (float)canon[C.xi0() + i];
+    cf[K.proc() + 3 * kFdMaxProc + i] = (float)gen[i];  // exact for any machine index < 2^24
+  }
+}
+
+// Y in the A-operand order of v_mfma_f32_16x16x4f32: for machine block b,
+// k-step s and lane l, the pair (A_re, A_im)[16b + l%16][4s + l/16] of
+//   A_re = [Yr  -Yi],  A_im = [Yi  Yr]   (columns: Re dE' rows, then Im dE').
+__global__ void __launch_bounds__(256) k_pack_fd_y(const double* __restrict__ canon, int n,
+                                                   int n_pad, float2* __restrict__ ap) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int KS = n_pad / 2;
+  const int64_t total = (int64_t)(n_pad / 16) * KS * 64;
+  if (q >= total) return;
+  const int l = (int)(q % 64);
+  const int s = (int)((q / 64) % KS);
+  const int b = (int)(q / (64 * KS));
+  const int i = 16 * b + l % 16;
+  const int kk = 4 * s + l / 16;  // 0 .. 2 n_pad - 1
+  const int k = kk < n_pad ? kk : kk - n_pad;
+  float ar = 0.0f, ai = 0.0f;
+  if (i < n && k < n) {
+    const double yr = canon[(int64_t)i * n + k], yi = canon[(int64_t)n * n + (int64_t)i * n + k];
+    ar = kk < n_pad ? (float)yr : (float)-yi;
+    ai = kk < n_pad ? (float)yi : (float)yr;
+  }
+  ap[q] = make_float2(ar, ai);
+}
+
+// Sum over the 16 lanes of a row (lanes l with equal l/16).
+__device__ __forceinline__ double row16_sum(double v) {
+  v += __shfl_xor(v, 8, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 1, 16);
+  return v;
+}
+
+// Mean and M2 of a row's 16 values (invalid lanes excluded), Chan-merged into
+// the statistics row by the row's first lane.
+__device__ __forceinline__ void row_stats(double x, bool valid, double cnt, bool writer,
+                                          double2* dst, double prev) {
+  const double mu = row16_sum(valid ? x : 0.0) / cnt;
+  const double d = valid ? x - mu : 0.0;
+  const double m2 = row16_sum(d * d);
+  if (writer) {
+    if (prev == 0.0) {
+      *dst = make_double2(mu, m2);
+    } else {
+      const double2 old = *dst;
+      const double tot = prev + cnt, dl = mu - old.x;
+      *dst = make_double2(old.x + dl * (cnt / tot), old.y + m2 + dl * dl * (prev * cnt / tot));
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Integrator.  Grid: one workgroup per work item (a contiguous range of
+// tiles, run one after another); block: NW = ceil(NB/2) waves, wave w owning
+// the machine blocks 2w and 2w+1 (NB = n_pad/16 blocks of 16 machines).  Lane
+// l of wave w owns machines 16(2w+j) + 4(l/16) + r (j = 0..1, r = 0..3) of
+// trajectory l%16, slot q = 4j + r, and process (64w + l)/16 if that is < P.
+// ---------------------------------------------------------------------------
+constexpr int kQ = 8;  // machines per lane
+
+__global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int n_pad = a.n_pad, n = a.n, P = a.P, V = a.V;
+  const int NB = n_pad / 16, NW = (NB + 1) / 2, KS = n_pad / 2;
+  const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, g = l >> 4, t = l & 15;
+  const bool two = 2 * wv + 1 < NB;  // wave-uniform: the second block exists
+  const FdPack K{n_pad};
+  // LDS: constants + process block, the dE' tile [2 n_pad][16], xi stage
+  // values (2 buffers of [kFdMaxProc][16]), flags [16], then the RK4 sums of
+  // every lane [NW][6 kQ][64] (kept here rather than in registers)
+  float* cst = reinterpret_cast<float*>(smem);
+  float* bs = cst + K.size();
+  float* xs = bs + 2 * n_pad * kT;
+  int* bad_t = reinterpret_cast<int*>(xs + 2 * kFdMaxProc * kT);
+  float* accl = reinterpret_cast<float*>(bad_t + kT) + (int64_t)wv * 6 * kQ * 64 + l;
+  for (int q = tid; q < K.size(); q += blockDim.x) cst[q] = a.coef[q];
+  __syncthreads();
+
+  auto mach = [&](int q) { return 16 * (2 * wv + (q >> 2)) + 4 * g + (q & 3); };
+  const float dt = a.dt, h2 = 0.5f * a.dt, dt6 = a.dt / 6.0f, wb = a.wb;
+  const int item = blockIdx.x;
+  const int64_t tile0 = (int64_t)item * a.tiles_per_item;
+  const int64_t tile1 = tile0 + a.tiles_per_item < a.tiles ? tile0 + a.tiles_per_item : a.tiles;
+  const int pg = (wv * 64 + l) >> 4;
+  const bool proc = pg < P;  // uniform over a row of 16 lanes
+  const float th = proc ? cst[K.proc() + pg] : 0.0f;
+  const float sg = proc ? cst[K.proc() + kFdMaxProc + pg] : 0.0f;
+  const int64_t colstride = (int64_t)P * a.N;
+  double2* rows = a.rows + (int64_t)item * a.row_stride;
+  const float2* apw = a.ap + (int64_t)(2 * wv) * KS * 64 + l;
+  const float* B0 = bs + (l >> 4) * kT + (l & 15);
+  int buf = 0;
+
+  for (int64_t tile = tile0; tile < tile1; ++tile) {
+    const int64_t traj = tile * kT + t;
+    const bool valid = traj < a.N;
+    const int64_t ns = valid ? traj : a.N - 1;
+    const int64_t rem = a.N - tile * kT;
+    const double cnt = (double)(rem < kT ? rem : kT);
+    const double prev = (double)((tile - tile0) * kT);
+    const int slot = (valid && a.traj_slot) ? a.traj_slot[ns] : -1;
+    // state: deviations of (delta, dw, E'q, Efd, VR, RF) of my machines; xi
+    float y[6][kQ], x = 0.0f;
+    const int64_t sbase = ((tile * NW + wv) * 6 * kQ) * 64 + l;
+    const int64_t xbase = (tile * kFdMaxProc + (proc ? pg : 0)) * kT + t;
+    if (a.s_begin == 0) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) y[c][q] = 0.0f;
+      x = proc ? cst[K.proc() + 2 * kFdMaxProc + pg] : 0.0f;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) y[c][q] = a.state[sbase + (c * kQ + q) * 64];
+      if (proc) x = a.xstate[xbase];
+    }
+    const int64_t wofs = (int64_t)(proc ? pg : 0) * a.N + ns;
+
+    // statistics and sampled outputs of step s (deviations + FP64 offsets)
+    auto emit = [&](int64_t s) {
+      // n and the offset table pass through an empty asm so that the
+      // compiler recomputes the (c, machine) addresses here instead of
+      // keeping 48 loop-invariant 64-bit addresses live across the steps
+      int nl = n;
+      const double* offl = a.off;
+      asm volatile("" : "+s"(nl), "+s"(offl));
+      double2* row = rows + (s - a.row_base) * V;
+      double* o = slot >= 0 ? a.traj + ((int64_t)slot * (a.S + 1) + s) * V : nullptr;
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const int m = mach(q);  // uniform over the row of 16 lanes
+        if (m < nl) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            row_stats((double)y[c][q], valid, cnt, t == 0, row + c * nl + m, prev);
+            if (o) o[c * nl + m] = offl[c * nl + m] + (double)y[c][q];
+          }
+        }
+      }
+      if (proc) {
+        row_stats((double)x, valid, cnt, t == 0, row + 6 * n + pg, prev);
+        if (o) o[6 * n + pg] = (double)x;
+      }
+    };
+    if (a.s_begin == 0) emit(0);
+
+    const float* w = a.w;
+    float w0 = proc ? w[wofs] : 0.0f, w1 = proc ? w[colstride + wofs] : 0.0f,
+          w2 = proc ? w[2 * colstride + wofs] : 0.0f;
+    for (int64_t s = a.s_begin; s < a.s_end; ++s) {
+      const int64_t cl = 2 * s - a.c_base;
+      const bool more = s + 1 < a.s_end;
+      const float n1 = (more && proc) ? w[(cl + 3) * colstride + wofs] : 0.0f;
+      const float n2 = (more && proc) ? w[(cl + 4) * colstride + wofs] : 0.0f;
+      float ys[6][kQ], xsg = x, ax = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) ys[c][q] = y[c][q];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        // RK4 weights: stage st enters the sum with wgt, the next stage's input
+        // is y + hn k
+        const float wgt = (st == 0 || st == 3) ? 1.0f : 2.0f;
+        const float hn = st < 2 ? h2 : dt;
+        const float wst = st == 0 ? w0 : (st == 3 ? w2 : w1);
+        float* Bw = bs;
+        float* X = xs + buf * (kFdMaxProc * kT);
+        // -- before the product: EMF deviations, the derivatives that do not
+        //    need the network current, and the parts of those that do
+        float omc[kQ], sd[kQ], dEr[kQ], dEi[kQ], pw[kQ], pe[kQ], pv[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          if (q >= 4 && !two) continue;
+          const int m = mach(q);
+          int mo = K.at(m, 0), bo = m * kT + t;
+          asm volatile("" : "+v"(mo), "+v"(bo));  // recompute, do not keep live
+          const float* cm = cst + mo;
+          float sh, ch;
+          sincos_r(0.5f * ys[0][q], sh, ch);
+          sd[q] = 2.0f * sh * ch;   // sin d
+          omc[q] = 2.0f * sh * sh;  // 1 - cos d
+          const float c0 = cm[FdPack::C0], s0 = cm[FdPack::S0];
+          const float ur = cm[FdPack::U0R], ui = cm[FdPack::U0I];
+          const float de = ys[2][q];
+          // dE' = E~0 (e^{jd} - 1) + dE'q e^{j delta}
+          dEr[q] = -c0 * omc[q] - s0 * sd[q] + de * (ur * (1.0f - omc[q]) - ui * sd[q]);
+          dEi[q] = c0 * sd[q] - s0 * omc[q] + de * (ui * (1.0f - omc[q]) + ur * sd[q]);
+          // padding machines contribute exact zeros (Y's padding columns are
+          // zero, and 0 * NaN would still poison the product)
+          Bw[bo] = m < n ? dEr[q] : 0.0f;
+          Bw[bo + n_pad * kT] = m < n ? dEi[q] : 0.0f;
+          const float kd = wb * ys[1][q];
+          const float kf = -cm[FdPack::KE_TE] * ys[3][q] + cm[FdPack::ITE] * ys[4][q];
+          const float kr = -cm[FdPack::ITF] * ys[5][q] + cm[FdPack::KF_TF2] * ys[3][q];
+          pw[q] = cm[FdPack::RES] - cm[FdPack::DMP] * ys[1][q];
+          pe[q] = (ys[3][q] - ys[2][q]) * cm[FdPack::ITDO];
+          pv[q] = -cm[FdPack::ITA] * ys[4][q] + cm[FdPack::KA_TA] * ys[5][q] -
+                  cm[FdPack::KAKF] * ys[3][q];
+          accl[(0 * kQ + q) * 64] = st == 0 ? kd : accl[(0 * kQ + q) * 64] + wgt * kd;
+          accl[(3 * kQ + q) * 64] = st == 0 ? kf : accl[(3 * kQ + q) * 64] + wgt * kf;
+          accl[(5 * kQ + q) * 64] = st == 0 ? kr : accl[(5 * kQ + q) * 64] + wgt * kr;
+          if (st < 3) {
+            ys[0][q] = y[0][q] + hn * kd;
+            ys[3][q] = y[3][q] + hn * kf;
+            ys[5][q] = y[5][q] + hn * kr;
+          }
+        }
+        if (proc) X[pg * kT + t] = xsg;
+        __syncthreads();
+        // -- dI = Y dE' for my machine blocks over the tile's 16 trajectories
+        f32x4 ar0 = {0.f, 0.f, 0.f, 0.f}, ai0 = ar0, ar1 = ar0, ai1 = ar0;
+        const float* bp = B0;
+        if (two) {
+          constexpr int PF = 4;
+          float2 p0[PF], p1[PF];
+#pragma unroll
+          for (int u = 0; u < PF; ++u) {
+            p0[u] = apw[(int64_t)u * 64];
+            p1[u] = apw[(int64_t)(KS + u) * 64];
+          }
+          for (int k0 = 0; k0 < KS; k0 += PF) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+              const int k = k0 + u;
+              const float2 a0 = p0[u], a1 = p1[u];
+              if (k + PF < KS) {
+                p0[u] = apw[(int64_t)(k + PF) * 64];
+                p1[u] = apw[(int64_t)(KS + k + PF) * 64];
+              }
+              const float bv = bp[k * 4 * kT];
+              ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, bv, ar0, 0, 0, 0);
+              ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, bv, ai0, 0, 0, 0);
+              ar1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, bv, ar1, 0, 0, 0);
+              ai1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, bv, ai1, 0, 0, 0);
+            }
+          }
+        } else {
+          constexpr int PF = 8;
+          float2 p0[PF];
+#pragma unroll
+          for (int u = 0; u < PF; ++u) p0[u] = apw[(int64_t)u * 64];
+          for (int k0 = 0; k0 < KS; k0 += PF) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u) {
+              const int k = k0 + u;
+              const float2 a0 = p0[u];
+              if (k + PF < KS) p0[u] = apw[(int64_t)(k + PF) * 64];
+              const float bv = bp[k * 4 * kT];
+              ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, bv, ar0, 0, 0, 0);
+              ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, bv, ai0, 0, 0, 0);
+            }
+          }
+        }
+        __syncthreads();  // every wave is done reading the dE' tile
+        // -- after the product: injections, dPe, dId, d|Vt|
+        float inj[kQ];
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) inj[q] = 0.0f;
+        for (int p = 0; p < P; ++p) {
+          const int gm = (int)cst[K.proc() + 3 * kFdMaxProc + p];
+          const float xp = X[p * kT + t];
+#pragma unroll
+          for (int q = 0; q < kQ; ++q)
+            if (gm == mach(q)) inj[q] += xp;
+        }
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          if (q >= 4 && !two) continue;
+          const int m = mach(q);
+          int mo = K.at(m, 0);
+          asm volatile("" : "+v"(mo));
+          const float* cm = cst + mo;
+          const int r = q & 3;
+          const float dIr = q < 4 ? ar0[r] : ar1[r], dIi = q < 4 ? ai0[r] : ai1[r];
+          const float c0 = cm[FdPack::C0], s0 = cm[FdPack::S0];
+          const float ur = cm[FdPack::U0R], ui = cm[FdPack::U0I];
+          const float i0r = cm[FdPack::I0R], i0i = cm[FdPack::I0I];
+          const float j0r = cm[FdPack::J0R], j0i = cm[FdPack::J0I];
+          // dPe = Re(dE' conj I0) + Re(E~' conj dI)
+          const float dpe = dEr[q] * i0r + dEi[q] * i0i + (c0 + dEr[q]) * dIr + (s0 + dEi[q]) * dIi;
+          // dId = -Im(J0 (e^{-jd} - 1) + dI e^{-j delta0} e^{-jd})
+          const float djr = dIr * ur + dIi * ui, dji = dIi * ur - dIr * ui;
+          const float did = j0i * omc[q] + j0r * sd[q] - dji * (1.0f - omc[q]) + djr * sd[q];
+          // d|Vt| with dVt = dE' - j X'd dI
+          const float xdp = cm[FdPack::XDP];
+          const float vr_ = dEr[q] + xdp * dIi, vi_ = dEi[q] - xdp * dIr;
+          const float v0r = cm[FdPack::VT0R], v0i = cm[FdPack::VT0I];
+          const float vr1 = v0r + vr_, vi1 = v0i + vi_;
+          const float va = sqrtf(vr1 * vr1 + vi1 * vi1);
+          const float dva = (2.0f * (v0r * vr_ + v0i * vi_) + vr_ * vr_ + vi_ * vi_) /
+                            (va + cm[FdPack::VT0A]);
+          const float kw = (pw[q] - dpe + inj[q]) * cm[FdPack::INV2H];
+          const float ke = pe[q] - cm[FdPack::XDD_T] * did;
+          const float kv = pv[q] - cm[FdPack::KA_TA] * dva;
+          accl[(1 * kQ + q) * 64] = st == 0 ? kw : accl[(1 * kQ + q) * 64] + wgt * kw;
+          accl[(2 * kQ + q) * 64] = st == 0 ? ke : accl[(2 * kQ + q) * 64] + wgt * ke;
+          accl[(4 * kQ + q) * 64] = st == 0 ? kv : accl[(4 * kQ + q) * 64] + wgt * kv;
+          if (st < 3) {
+            ys[1][q] = y[1][q] + hn * kw;
+            ys[2][q] = y[2][q] + hn * ke;
+            ys[4][q] = y[4][q] + hn * kv;
+          }
+        }
+        const float kx = -th * xsg + sg * wst;
+        ax = st == 0 ? kx : ax + wgt * kx;
+        if (st < 3) xsg = x + hn * kx;
+        buf ^= 1;
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q)
+          if (q < 4 || two) y[c][q] += dt6 * accl[(c * kQ + q) * 64];
+      x += dt6 * ax;
+      w0 = w2; w1 = n1; w2 = n2;
+      emit(s + 1);
+    }
+
+    if (a.state) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) a.state[sbase + (c * kQ + q) * 64] = y[c][q];
+      if (proc) a.xstate[xbase] = x;
+    }
+    if (a.s_end == a.S) {  // uniform over the workgroup
+      bool bad = proc && !isfinite(x);
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) bad |= (mach(q) < n) && !isfinite(y[c][q]);
+      if (tid < kT) bad_t[tid] = 0;
+      __syncthreads();
+      if (bad) bad_t[t] = 1;
+      __syncthreads();
+      if (tid < kT && tile * kT + tid < a.N && bad_t[tid] != 0) {
+        atomicAdd(a.nonfinite, 1ULL);
+        atomicMin(a.first_bad, (long long)(tile * kT + tid));
+      }
+    }
+    __syncthreads();  // LDS buffers and flags are reused by the next tile
+  }
+}
+
+hipError_t launch_setup_fd(const double* canon, int n, int P, const double* E, const double* prm,
+                           double* fd, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup_fd, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, canon, n, P,
+                     E, prm, fd);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_fd(const double* canon, int n, int P, const double* prm, const double* fd,
+                          const int32_t* gen, int n_pad, float* coef, float2* ap,
+                          hipStream_t st) {
+  const int m = n_pad > P ? n_pad : P;
+  hipLaunchKernelGGL(k_pack_fd, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, canon, n, P,
+                     prm, fd, gen, n_pad, coef);
+  const int64_t total = (int64_t)(n_pad / 16) * (n_pad / 2) * 64;
+  hipLaunchKernelGGL(k_pack_fd_y, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, canon,
+                     n, n_pad, ap);
+  return hipGetLastError();
+}
+
+size_t fd_lds_bytes(int n_pad) {
+  const FdPack K{n_pad};
+  const int nw = (n_pad / 16 + 1) / 2;
+  return (size_t)K.size() * 4 + (size_t)2 * n_pad * kT * 4 + (size_t)2 * kFdMaxProc * kT * 4 +
+         kT * 4 + (size_t)nw * 6 * kQ * 64 * 4;
+}
+
+hipError_t launch_rk4_fd(const FdArgs& a, int64_t n_items, hipStream_t st) {
+  const size_t lds = fd_lds_bytes(a.n_pad);
+  static size_t lds_set = 0;  // dynamic LDS above 64 KB must be allowed explicitly
+  if (lds > lds_set) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_rk4_fd,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    lds_set = lds;
+  }
+  const int nw = (a.n_pad / 16 + 1) / 2;
+  hipLaunchKernelGGL(k_rk4_fd, dim3((unsigned)n_items), dim3((unsigned)(nw * 64)), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace fmc
