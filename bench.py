@@ -132,22 +132,28 @@ def batched_leg(ctx, fmc, workloads, oracle_mod, steps: int, with_fp64: bool):
 
 
 def served_leg(ctx, fmc, workloads, oracle_mod, rates, n_max: int, seed: int = 11):
-    """Served form: a seeded Poisson request stream per rate; each request is a
-    scenario drawn from the 64-scenario uneven set.  A request refused for
-    lack of HBM or slots (EBUSY) is retried by the client every millisecond;
-    its latency runs from its scheduled arrival to the moment the client sees
-    it complete."""
+    """Served form: a seeded Poisson request stream per rate.  Nine requests in
+    ten are drawn from the 64-scenario uneven set (classical machines); every
+    tenth (index 5, 15, ...) is a large flux-decay request (200 machines with
+    IEEE type-1 exciters, 10 OU processes, T = 30 s, N = 5e4, K = 100).  A
+    request refused for lack of HBM or slots (EBUSY) is retried by the client
+    every millisecond; its latency runs from its scheduled arrival to the
+    moment the client sees it complete."""
     import numpy as np
     import torch
     scs = workloads.uneven_batch()
+    large = workloads.fluxdecay()
     rng = np.random.default_rng(seed)
-    out = {"workload": "Poisson requests drawn uniformly from the 64 uneven scenarios "
-                       "(classical machines; the large flux-decay requests are not part "
-                       "of this stream)",
-           "precision": "bf16x3", "time_chunk": 200, "rates": []}
-    # warm-up: one request of every size class
+    out = {"workload": "Poisson requests: 90% drawn uniformly from the 64 uneven classical "
+                       "scenarios, 10% large flux-decay + IEEE type-1 requests (n=200, P=10, "
+                       "T=30 s, N=5e4, K=100)",
+           "precision": "bf16x3", "time_chunk": {"classical": 200, "flux_decay": 25},
+           "rates": []}
+    # warm-up: one request of every size class and one short flux-decay request
     for i in (0, 17, 40):
         ctx.submit(scs[i], precision="bf16x3").wait(timeout=300)
+    ctx.submit(workloads.fluxdecay(T=0.25), precision="bf16x3").wait(timeout=300)
+    say("served: warm")
     if oracle_mod is not None:
         small = int(np.argmin([sc["N"] * fmc.steps(sc) * sc["n_gen"] ** 2 for sc in scs]))
         r = ctx.submit(scs[small], precision="bf16x3").wait(timeout=300)
@@ -164,6 +170,8 @@ def served_leg(ctx, fmc, workloads, oracle_mod, rates, n_max: int, seed: int = 1
         gaps = rng.exponential(1.0 / rate, size=n_req)
         arrive = np.cumsum(gaps) - gaps[0]
         pick = rng.integers(0, len(scs), size=n_req)
+        is_large = np.array([i % 10 == 5 for i in range(n_req)])
+        req = [large if is_large[i] else scs[pick[i]] for i in range(n_req)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pending = {}   # index -> ticket
@@ -175,7 +183,7 @@ def served_leg(ctx, fmc, workloads, oracle_mod, rates, n_max: int, seed: int = 1
             while wait_q and arrive[wait_q[0]] <= now:
                 i = wait_q[0]
                 try:
-                    pending[i] = ctx.submit(scs[pick[i]], precision="bf16x3")
+                    pending[i] = ctx.submit(req[i], precision="bf16x3")
                     wait_q.pop(0)
                 except fmc.FmcError as e:
                     if e.code != fmc.EBUSY:
@@ -189,14 +197,20 @@ def served_leg(ctx, fmc, workloads, oracle_mod, rates, n_max: int, seed: int = 1
             time.sleep(0.001)
         lat = done_at - arrive
         span = float(done_at.max())
-        ts = float(sum(scs[k]["N"] * fmc.steps(scs[k]) for k in pick))
-        out["rates"].append({
-            "rate_req_per_s": rate, "requests": n_req, "p50_latency_s": float(np.median(lat)),
-            "p99_latency_s": float(np.quantile(lat, 0.99)), "max_latency_s": float(lat.max()),
-            "makespan_s": span, "completed_req_per_s": n_req / span,
-            "trajectory_steps_per_s": ts / span, "ebusy_retries": refused})
-        say(f"served rate {rate}/s: {n_req} requests, p50 {np.median(lat):.3f} s, "
-            f"p99 {np.quantile(lat, 0.99):.3f} s, {ts / span:.3e} traj-steps/s")
+        ts = float(sum(r["N"] * fmc.steps(r) for r in req))
+        ent = {"rate_req_per_s": rate, "requests": n_req, "large_requests": int(is_large.sum()),
+               "p50_latency_s": float(np.median(lat)), "p99_latency_s": float(np.quantile(lat, 0.99)),
+               "max_latency_s": float(lat.max()), "makespan_s": span,
+               "completed_req_per_s": n_req / span, "trajectory_steps_per_s": ts / span,
+               "ebusy_retries": refused}
+        if (~is_large).any():
+            ent["small_p50_latency_s"] = float(np.median(lat[~is_large]))
+            ent["small_p99_latency_s"] = float(np.quantile(lat[~is_large], 0.99))
+        if is_large.any():
+            ent["large_p50_latency_s"] = float(np.median(lat[is_large]))
+        out["rates"].append(ent)
+        say(f"served rate {rate}/s: {n_req} requests ({int(is_large.sum())} large), p50 "
+            f"{np.median(lat):.3f} s, p99 {np.quantile(lat, 0.99):.3f} s, {ts / span:.3e} traj-steps/s")
     return out
 
 
@@ -214,7 +228,7 @@ def main():
                     help="timed passes over the 64-scenario batched workload (0: skip)")
     ap.add_argument("--serve-rates", default="1,10,50,200",
                     help="Poisson request rates of the served leg (empty: skip)")
-    ap.add_argument("--serve-max", type=int, default=48,
+    ap.add_argument("--serve-max", type=int, default=20,
                     help="requests per rate of the served leg (at most)")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")

@@ -133,6 +133,10 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     p.par = scen[i].par;
     p.out = &outs[i];
     if ((rc = validate(p.sys, p.dist, p.par, &p.S))) return fail(rc, "scenario " + std::to_string(i) + ": " + g_err);
+    if (p.sys->model != FMC_CLASSICAL)
+      return fail(FMC_EINVAL, "scenario " + std::to_string(i) +
+                                  ": the batched form runs classical machines (flux-decay "
+                                  "systems go through fmc_run or fmc_submit)");
     if (p.par->precision == FMC_F64)
       return fail(FMC_EINVAL, "scenario " + std::to_string(i) + ": the batched form integrates in FP32 (FMC_F32 or FMC_BF16X3)");
     if (!p.out->mean || !p.out->var) return fail(FMC_EINVAL, "mean and var outputs are required");

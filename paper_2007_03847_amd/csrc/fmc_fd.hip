@@ -25,7 +25,7 @@ namespace fmc {
 
 int fd_plan(int64_t N, int n_cu, FdPlan* p) {
   p->tiles = (N + 15) / 16;
-  const int64_t slots = std::max(1, n_cu);  // one workgroup per CU
+  const int64_t slots = std::max(1, n_cu);  // one workgroup per CU (256 on MI355X)
   p->tiles_per_item = (p->tiles + slots - 1) / slots;
   p->n_items = (p->tiles + p->tiles_per_item - 1) / p->tiles_per_item;
   return FMC_OK;
@@ -57,7 +57,7 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
   void *fd = nullptr, *coef = nullptr, *ap = nullptr;
   if ((rc = c->ensure("fd_block", (size_t)FdLayout{n}.size() * 8, &fd))) return rc;
   if ((rc = c->ensure("fd_coef", (size_t)FdPack{n_pad}.size() * 4, &coef))) return rc;
-  if ((rc = c->ensure("fd_ap", (size_t)NB * (n_pad / 2) * 64 * sizeof(float2), &ap))) return rc;
+  if ((rc = c->ensure("fd_ap", (size_t)NB * (n_pad / 4) * 64 * sizeof(float2), &ap))) return rc;
   HIPCHK(launch_setup_fd(canon, n, P, E_d, prm_d, (double*)fd, c->stream));
   HIPCHK(launch_pack_fd(canon, n, P, prm_d, (const double*)fd, gen_d, n_pad, (float*)coef,
                         (float2*)ap, c->stream));
@@ -88,10 +88,10 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
     zeta = zeta_dev;
   }
 
-  hipDeviceProp_t prop;
-  HIPCHK(hipGetDeviceProperties(&prop, c->device));
+  // the plan is fixed (not taken from the device) so that a request gives the
+  // same bits here and in the served form
   FdPlan pl{};
-  fd_plan(N, prop.multiProcessorCount, &pl);
+  fd_plan(N, kFdItems, &pl);
   const int64_t Sc = par->time_chunk > 0 ? std::min<int64_t>(par->time_chunk, S)
                                          : std::min<int64_t>(S, auto_chunk(S, P, N, 4));
   void *w = nullptr, *state = nullptr, *xstate = nullptr, *rows = nullptr, *cnt = nullptr;

@@ -205,7 +205,7 @@ struct FdPack {
 
 struct FdArgs {
   const float* coef;          // FdPack block
-  const float2* ap;           // Y in A-operand order [n_pad/16][n_pad/2][64]
+  const float2* ap;           // (Yr, Yi) in A-operand order [n_pad/16][n_pad/4][64]
   const float* w;             // [cols][P][N] KLE paths of this chunk
   float* state;               // [tiles][ceil(NB/2)][48][64] deviations between chunks
   float* xstate;              // [tiles][kFdMaxProc][16]

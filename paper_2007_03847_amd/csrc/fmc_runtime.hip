@@ -509,6 +509,8 @@ int fmc_autotune(fmc_context* ctx, const fmc_scenario* scen, int32_t* variant_ou
   int64_t S = 0;
   int rc = validate(scen->sys, scen->dist, scen->par, &S);
   if (rc) return rc;
+  if (scen->sys->model != FMC_CLASSICAL)
+    return fail(FMC_EINVAL, "the flux-decay model has a single integrator: nothing to tune");
   const int n = scen->sys->n_gen, P = scen->dist->n_proc;
   const int64_t N = scen->par->N;
   const int V = 2 * n + P;

@@ -82,6 +82,7 @@ void serve_shutdown(Context* c);
 struct FdPlan {
   int64_t tiles, tiles_per_item, n_items;
 };
+constexpr int kFdItems = 256;  // work items of a flux-decay run: one per CU of an MI355X
 int fd_plan(int64_t N, int n_cu, FdPlan* p);
 int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const fmc_params* par,
            fmc_outputs* out, int64_t S);

@@ -43,6 +43,7 @@ constexpr size_t kTickBytes = size_t(16) << 20;  // per-tick upload region (args
 constexpr int64_t kMaxItems = 1024;             // work items per request
 constexpr int kMaxActive = 256;                 // requests admitted at once
 constexpr int64_t kDefaultChunk = 200;          // steps per tick
+constexpr int64_t kDefaultChunkFd = 25;         // steps per tick of a flux-decay request
 constexpr size_t kAlign = serve::kAlign;
 
 size_t al(size_t x) { return serve::align_up(x); }
@@ -62,6 +63,14 @@ struct Request {
   SetupDev sd{};
   NetDev nd{};
   const int32_t* gen_d = nullptr;
+  // flux-decay request (its own integrator; no batched variant)
+  bool fd = false;
+  int n_pad = 0, NW = 0;
+  const double *E_d = nullptr, *prm_d = nullptr;  // staged E and parameters
+  double* fdblk = nullptr;
+  float* fdcoef = nullptr;
+  float2* fdap = nullptr;
+  float* xstate = nullptr;
   // plan
   int vid = -1;
   BatchVariantInfo bv{};
@@ -88,18 +97,26 @@ using ReqP = std::shared_ptr<Request>;
 
 // Device sizes of one request, in carve order.
 enum { B_IN, B_CANON, B_COEF, B_PHI, B_ZETA, B_W, B_STATE, B_PART, B_MEAN, B_VAR, B_WORK,
-       B_YBUF, B_KWORK, B_STATUS, B_COUNT };
+       B_YBUF, B_KWORK, B_STATUS, B_FDBLK, B_FDAP, B_XSTATE, B_COUNT };
 
 std::vector<size_t> parts_of(const Request& r) {
-  const int G = (r.bv.NG + r.bv.L - 1) / r.bv.L, PQ = (r.bv.PM + r.bv.L - 1) / r.bv.L;
-  std::vector<size_t> z(B_COUNT);
+  std::vector<size_t> z(B_COUNT, 0);
   z[B_IN] = r.sg.bytes.size();
   z[B_CANON] = (size_t)CanonLayout{r.n, r.P}.size() * 8;
-  z[B_COEF] = (size_t)PackLayout{r.bv.NG, r.bv.PM}.size() * 4;
   z[B_PHI] = (size_t)r.K * r.C * 8;
   z[B_ZETA] = (size_t)r.M * r.N * 8;
   z[B_W] = (size_t)(2 * r.Sc + 1) * r.P * r.N * 4;
-  z[B_STATE] = (size_t)(2 * G + PQ) * r.tiles * 64 * 4 * 4;  // rows x lanes (4 waves per tile)
+  if (r.fd) {
+    z[B_COEF] = (size_t)FdPack{r.n_pad}.size() * 4;
+    z[B_FDBLK] = (size_t)FdLayout{r.n}.size() * 8;
+    z[B_FDAP] = (size_t)(r.n_pad / 16) * (r.n_pad / 4) * 64 * sizeof(float2);
+    z[B_STATE] = (size_t)r.tiles * r.NW * 48 * 64 * 4;
+    z[B_XSTATE] = (size_t)r.tiles * kFdMaxProc * 16 * 4;
+  } else {
+    const int G = (r.bv.NG + r.bv.L - 1) / r.bv.L, PQ = (r.bv.PM + r.bv.L - 1) / r.bv.L;
+    z[B_COEF] = (size_t)PackLayout{r.bv.NG, r.bv.PM}.size() * 4;
+    z[B_STATE] = (size_t)(2 * G + PQ) * r.tiles * 64 * 4 * 4;  // rows x lanes (4 waves per tile)
+  }
   z[B_PART] = (size_t)r.n_items * (r.Sc + 1) * r.V * 16;  // statistics rows of one chunk
   z[B_MEAN] = z[B_VAR] = (size_t)(r.S + 1) * r.V * 8;
   z[B_WORK] = (size_t)(3 * r.n * r.n + 8 * r.n + 64) * 8;
@@ -119,7 +136,8 @@ int plan_request(Request& r, const fmc_system* s, const fmc_disturbance* d, cons
   r.n = s->n_gen;
   r.P = d->n_proc;
   r.K = p->K;
-  r.V = 2 * r.n + r.P;
+  r.fd = s->model == FMC_FLUXDECAY_IEEET1;
+  r.V = (r.fd ? 6 * r.n : 2 * r.n) + r.P;
   r.N = p->N;
   r.S = S;
   r.C = 2 * S + 1;
@@ -132,6 +150,20 @@ int plan_request(Request& r, const fmc_system* s, const fmc_disturbance* d, cons
   if (p->precision != FMC_F32 && p->precision != FMC_BF16X3)
     return fail(FMC_EINVAL, "the served form integrates in FP32 (FMC_F32 or FMC_BF16X3)");
   if (p->zeta_in) return fail(FMC_EINVAL, "served requests draw their own design (zeta_in must be NULL)");
+  if (r.fd) {
+    // the flux-decay integrator: 16-trajectory tiles in contiguous items
+    // (kFdItems of them), a short default chunk so
+    // that a large request does not stretch every tick
+    r.n_pad = 16 * ((r.n + 15) / 16);
+    r.NW = (r.n_pad / 16 + 1) / 2;
+    r.Sc = std::min<int64_t>(S, p->time_chunk > 0 ? p->time_chunk : kDefaultChunkFd);
+    FdPlan pl{};
+    fd_plan(r.N, kFdItems, &pl);
+    r.tiles = pl.tiles;
+    r.tiles_per_item = pl.tiles_per_item;
+    r.n_items = pl.n_items;
+    return FMC_OK;
+  }
   int vid = p->variant;
   if (vid < 0) {
     for (int i = 0; i < n_batch_variants(); ++i) {
@@ -194,6 +226,10 @@ void stage_inputs(Request& r, const fmc_system* s, const fmc_disturbance* d) {
     sg.add(nt->gen_bus, nt->n_gen, &r.nd.gen_bus);
     sg.add(nt->gen_xdp, nt->n_gen, &r.nd.xdp);
   }
+  if (r.fd) {
+    sg.add(s->E, n, &r.E_d);
+    sg.add(s->model_params, (size_t)n * kFdParams, &r.prm_d);
+  }
   r.sd.inf_bus = r.inf_bus ? 1 : 0;
   r.sd.V_inf = r.V_inf;
 }
@@ -248,6 +284,9 @@ int admit(ServeState* ss, Request& r) {
   r.kwork = (double2*)ptr[B_KWORK];
   r.status = (int*)ptr[B_STATUS];
   r.cnt = (unsigned long long*)((char*)r.status + 32);
+  r.fdblk = (double*)ptr[B_FDBLK];
+  r.fdap = (float2*)ptr[B_FDAP];
+  r.xstate = (float*)ptr[B_XSTATE];
   r.footprint = (int64_t)serve::footprint(z);
   return FMC_OK;
 }
@@ -298,7 +337,12 @@ int start_request(ServeState* ss, Request& r, size_t* pin_off) {
   r.sd.canon = r.canon;
   r.sd.status = r.status;
   SCHK(launch_setup(r.sd, st));
-  SCHK(launch_pack<float>(r.canon, r.n, r.P, r.gen_d, r.bv.NG, r.bv.PM, r.coef, st));
+  if (r.fd) {
+    SCHK(launch_setup_fd(r.canon, r.n, r.P, r.E_d, r.prm_d, r.fdblk, st));
+    SCHK(launch_pack_fd(r.canon, r.n, r.P, r.prm_d, r.fdblk, r.gen_d, r.n_pad, r.coef, r.fdap, st));
+  } else {
+    SCHK(launch_pack<float>(r.canon, r.n, r.P, r.gen_d, r.bv.NG, r.bv.PM, r.coef, st));
+  }
   SCHK(launch_basis(r.par.basis, r.K, r.S, r.par.T, r.phi, st));
   SCHK(launch_lhs(r.par.seed, (int32_t)r.M, r.N, r.par.sampler, nullptr, r.zeta, st));
   return FMC_OK;
@@ -311,8 +355,9 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
              std::vector<ReqP>& finishing) {
   hipStream_t st = ss->st;
   const int na = (int)act.size();
-  int64_t n_items = 0;
-  for (auto& r : act) n_items += r->n_items;
+  int64_t n_items = 0;  // items of the batched (classical) integrator
+  for (auto& r : act)
+    if (!r->fd) n_items += r->n_items;
   const size_t up_bytes = al(sizeof(IntegArgs<float>) * na) + al(sizeof(BatchItem) * n_items) +
                           al(sizeof(int32_t) * n_items);
   if (up_bytes + kAlign > kTickBytes) return fail(FMC_EINVAL, "too many work items in one tick");
@@ -330,6 +375,7 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
   std::vector<std::vector<int32_t>> order(kBatchClasses);
   std::vector<double> icost;
   icost.reserve(n_items);
+  std::vector<std::pair<FdArgs, int64_t>> fd_launch;
   for (int i = 0; i < na; ++i) {
     Request& r = *act[i];
     const int64_t s0 = r.s_next, s1 = std::min<int64_t>(r.S, s0 + r.Sc);
@@ -338,6 +384,38 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
       SCHK(launch_kle_f64_to_f32(r.zeta, r.phi, r.C, r.P, r.K, r.N, cols, 2 * s0, r.w, st));
     else
       SCHK(launch_kle_bf16x3(r.zeta, r.phi, r.C, r.P, r.K, r.N, cols, 2 * s0, r.w, st));
+    if (r.fd) {
+      FdArgs f{};
+      f.coef = r.coef;
+      f.ap = r.fdap;
+      f.w = r.w;
+      f.state = r.state;
+      f.xstate = r.xstate;
+      f.off = r.fdblk + FdLayout{r.n}.off();
+      f.nonfinite = r.cnt;
+      f.first_bad = (long long*)r.cnt + 1;
+      f.rows = r.part;
+      f.row_stride = (r.Sc + 1) * r.V;
+      f.row_base = s0;
+      f.n = r.n;
+      f.P = r.P;
+      f.V = r.V;
+      f.n_pad = r.n_pad;
+      f.N = r.N;
+      f.S = r.S;
+      f.s_begin = s0;
+      f.s_end = s1;
+      f.c_base = 2 * s0;
+      f.tiles = r.tiles;
+      f.tiles_per_item = r.tiles_per_item;
+      f.dt = (float)r.par.dt;
+      f.wb = (float)(2.0 * M_PI * r.f0);
+      fd_launch.push_back({f, r.n_items});
+      r.s_prev = s0;
+      r.s_next = s1;
+      if (s1 == r.S) finishing.push_back(act[i]);
+      continue;
+    }
     IntegArgs<float>& a = args[i];
     a.coef = r.coef;
     a.w = r.w;
@@ -413,13 +491,18 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
     BatchArgs b{args_d, items_d, order_d + off[k], (int32_t)nk, heads + 2 * k};
     SCHK(launch_persistent(k, b, grid, st));
   }
+  for (auto& f : fd_launch) SCHK(launch_rk4_fd(f.first, f.second, st));
   // rows completed by this tick: s0+1..s1 (and row 0 in a request's first chunk)
   for (int i = 0; i < na; ++i) {
     Request& r = *act[i];
     const int64_t first = r.s_prev == 0 ? 0 : r.s_prev + 1, rows = r.s_next - first + 1;
+    // FP64 offsets added back: delta0 (classical), or the 6n operating-point
+    // values of the flux-decay states
+    const double* offs = r.fd ? r.fdblk + FdLayout{r.n}.off() : r.canon + CanonLayout{r.n, r.P}.delta0();
+    const int n_off = r.fd ? 6 * r.n : r.n;
+    const int tile = (int)(r.tiles_per_item * (r.fd ? 16 : r.bv.TB));
     SCHK(launch_stats_merge_rows(r.part + (first - r.s_prev) * r.V, (r.Sc + 1) * r.V, r.n_items,
-                                 (int)(r.tiles_per_item * r.bv.TB), r.N, rows, r.V, r.n,
-                                 r.par.ddof, r.canon + CanonLayout{r.n, r.P}.delta0(),
+                                 tile, r.N, rows, r.V, n_off, r.par.ddof, offs,
                                  r.mean + first * r.V, r.var + first * r.V, st));
   }
   for (auto& rp : finishing) {
@@ -457,9 +540,9 @@ void write_report(ServeState* ss, Request& r) {
     std::memset(rep, 0, sizeof(*rep));
     rep->n_nonfinite = nbad;
     rep->first_nonfinite = first;
-    rep->variant_id = r.vid;
-    rep->lanes_per_traj = r.bv.L;
-    rep->tile = (int32_t)(r.tiles_per_item * r.bv.TB);
+    rep->variant_id = r.fd ? -1 : r.vid;
+    rep->lanes_per_traj = r.fd ? 1 : r.bv.L;
+    rep->tile = (int32_t)(r.tiles_per_item * (r.fd ? 16 : r.bv.TB));
     rep->time_chunk = (int32_t)r.Sc;
     rep->hbm_peak_bytes = r.footprint;
     rep->queue_wait_s = std::chrono::duration<double>(r.t_start - r.t_submit).count();

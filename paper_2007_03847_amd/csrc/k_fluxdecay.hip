@@ -129,27 +129,27 @@ __global__ void __launch_bounds__(256) k_pack_fd(const double* __restrict__ cano
 }
 
 // Y in the A-operand order of v_mfma_f32_16x16x4f32: for machine block b,
-// k-step s and lane l, the pair (A_re, A_im)[16b + l%16][4s + l/16] of
-//   A_re = [Yr  -Yi],  A_im = [Yi  Yr]   (columns: Re dE' rows, then Im dE').
+// k-step s < n_pad/4 and lane l, the pair (Yr, Yi)[16b + l%16][4s + l/16].
+// The real product [Yr -Yi; Yi Yr][Re dE'; Im dE'] uses each pair twice: as
+// (Yr, Yi) against the Re dE' rows 4s.. and as (-Yi, Yr) against the Im dE'
+// rows n_pad + 4s.., so Y is read once per stage.
 __global__ void __launch_bounds__(256) k_pack_fd_y(const double* __restrict__ canon, int n,
                                                    int n_pad, float2* __restrict__ ap) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int KS = n_pad / 2;
-  const int64_t total = (int64_t)(n_pad / 16) * KS * 64;
+  const int KH = n_pad / 4;
+  const int64_t total = (int64_t)(n_pad / 16) * KH * 64;
   if (q >= total) return;
   const int l = (int)(q % 64);
-  const int s = (int)((q / 64) % KS);
-  const int b = (int)(q / (64 * KS));
+  const int s = (int)((q / 64) % KH);
+  const int b = (int)(q / (64 * KH));
   const int i = 16 * b + l % 16;
-  const int kk = 4 * s + l / 16;  // 0 .. 2 n_pad - 1
-  const int k = kk < n_pad ? kk : kk - n_pad;
-  float ar = 0.0f, ai = 0.0f;
+  const int k = 4 * s + l / 16;
+  float yr = 0.0f, yi = 0.0f;
   if (i < n && k < n) {
-    const double yr = canon[(int64_t)i * n + k], yi = canon[(int64_t)n * n + (int64_t)i * n + k];
-    ar = kk < n_pad ? (float)yr : (float)-yi;
-    ai = kk < n_pad ? (float)yi : (float)yr;
+    yr = (float)canon[(int64_t)i * n + k];
+    yi = (float)canon[(int64_t)n * n + (int64_t)i * n + k];
   }
-  ap[q] = make_float2(ar, ai);
+  ap[q] = make_float2(yr, yi);
 }
 
 // Sum over the 16 lanes of a row (lanes l with equal l/16).
@@ -193,7 +193,7 @@ constexpr int kQ = 8;  // machines per lane
 __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int n_pad = a.n_pad, n = a.n, P = a.P, V = a.V;
-  const int NB = n_pad / 16, NW = (NB + 1) / 2, KS = n_pad / 2;
+  const int NB = n_pad / 16, NW = (NB + 1) / 2, KH = n_pad / 4;
   const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, g = l >> 4, t = l & 15;
   const bool two = 2 * wv + 1 < NB;  // wave-uniform: the second block exists
   const FdPack K{n_pad};
@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
   const float sg = proc ? cst[K.proc() + kFdMaxProc + pg] : 0.0f;
   const int64_t colstride = (int64_t)P * a.N;
   double2* rows = a.rows + (int64_t)item * a.row_stride;
-  const float2* apw = a.ap + (int64_t)(2 * wv) * KS * 64 + l;
+  const float2* apw = a.ap + (int64_t)(2 * wv) * KH * 64 + l;
   const float* B0 = bs + (l >> 4) * kT + (l & 15);
   int buf = 0;
 
@@ -351,38 +351,44 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
 #pragma unroll
           for (int u = 0; u < PF; ++u) {
             p0[u] = apw[(int64_t)u * 64];
-            p1[u] = apw[(int64_t)(KS + u) * 64];
+            p1[u] = apw[(int64_t)(KH + u) * 64];
           }
-          for (int k0 = 0; k0 < KS; k0 += PF) {
+          for (int k0 = 0; k0 < KH; k0 += PF) {
 #pragma unroll
             for (int u = 0; u < PF; ++u) {
               const int k = k0 + u;
               const float2 a0 = p0[u], a1 = p1[u];
-              if (k + PF < KS) {
+              if (k + PF < KH) {
                 p0[u] = apw[(int64_t)(k + PF) * 64];
-                p1[u] = apw[(int64_t)(KS + k + PF) * 64];
+                p1[u] = apw[(int64_t)(KH + k + PF) * 64];
               }
-              const float bv = bp[k * 4 * kT];
-              ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, bv, ar0, 0, 0, 0);
-              ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, bv, ai0, 0, 0, 0);
-              ar1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, bv, ar1, 0, 0, 0);
-              ai1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, bv, ai1, 0, 0, 0);
+              const float br = bp[k * 4 * kT], bi = bp[(k * 4 + n_pad) * kT];
+              ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, br, ar0, 0, 0, 0);
+              ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, br, ai0, 0, 0, 0);
+              ar1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, br, ar1, 0, 0, 0);
+              ai1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, br, ai1, 0, 0, 0);
+              ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-a0.y, bi, ar0, 0, 0, 0);
+              ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, bi, ai0, 0, 0, 0);
+              ar1 = __builtin_amdgcn_mfma_f32_16x16x4f32(-a1.y, bi, ar1, 0, 0, 0);
+              ai1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, bi, ai1, 0, 0, 0);
             }
           }
         } else {
-          constexpr int PF = 8;
+          constexpr int PF = 4;
           float2 p0[PF];
 #pragma unroll
           for (int u = 0; u < PF; ++u) p0[u] = apw[(int64_t)u * 64];
-          for (int k0 = 0; k0 < KS; k0 += PF) {
+          for (int k0 = 0; k0 < KH; k0 += PF) {
 #pragma unroll
             for (int u = 0; u < PF; ++u) {
               const int k = k0 + u;
               const float2 a0 = p0[u];
-              if (k + PF < KS) p0[u] = apw[(int64_t)(k + PF) * 64];
-              const float bv = bp[k * 4 * kT];
-              ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, bv, ar0, 0, 0, 0);
-              ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, bv, ai0, 0, 0, 0);
+              if (k + PF < KH) p0[u] = apw[(int64_t)(k + PF) * 64];
+              const float br = bp[k * 4 * kT], bi = bp[(k * 4 + n_pad) * kT];
+              ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, br, ar0, 0, 0, 0);
+              ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, br, ai0, 0, 0, 0);
+              ar0 = __builtin_amdgcn_mfma_f32_16x16x4f32(-a0.y, bi, ar0, 0, 0, 0);
+              ai0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, bi, ai0, 0, 0, 0);
             }
           }
         }
@@ -490,7 +496,7 @@ hipError_t launch_pack_fd(const double* canon, int n, int P, const double* prm, 
   const int m = n_pad > P ? n_pad : P;
   hipLaunchKernelGGL(k_pack_fd, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, canon, n, P,
                      prm, fd, gen, n_pad, coef);
-  const int64_t total = (int64_t)(n_pad / 16) * (n_pad / 2) * 64;
+  const int64_t total = (int64_t)(n_pad / 16) * (n_pad / 4) * 64;
   hipLaunchKernelGGL(k_pack_fd_y, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, canon,
                      n, n_pad, ap);
   return hipGetLastError();

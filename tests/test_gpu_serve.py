@@ -163,3 +163,23 @@ def test_admission_by_footprint(fmc):
     finally:
         os.environ.pop("FMC_SERVE_ARENA_BYTES", None)
         c.close()
+
+
+def test_served_fluxdecay_request(ctx):
+    """A flux-decay request served beside classical ones: it matches the
+    oracle and gives bit for bit what the same request gives alone."""
+    fd = workloads.fluxdecay(n_gen=37, n_dist=6, N=50, K=25, T=0.4, dt=0.005, net_seed=337,
+                             seed=5)
+    scs = small_requests()[:3]
+    mix = [ctx.submit(fd, time_chunk=11)] + [ctx.submit(sc, time_chunk=40) for sc in scs]
+    res = [t.wait(timeout=120) for t in mix]
+    o = oracle.run(fd)
+    assert mean_err(_np(res[0]["mean"]), o["mean"], o["var"]) <= 1e-4
+    assert rel_err(_np(res[0]["var"]), o["var"]) <= 1e-4
+    alone = ctx.submit(fd, time_chunk=11).wait(timeout=120)
+    assert np.array_equal(_np(alone["var"]), _np(res[0]["var"]))
+    direct = ctx.run(fd, precision="f32", time_chunk=11)
+    assert np.array_equal(_np(direct["var"]), _np(res[0]["var"]))
+    for sc, r in zip(scs, res[1:]):
+        o = oracle.run(sc)
+        assert mean_err(_np(r["mean"]), o["mean"], o["var"]) <= 1e-4
