@@ -26,6 +26,7 @@ if ROOT not in sys.path:
 PEAK_FP64_VECTOR = 78.6e12
 PEAK_FP32_VECTOR = 157.3e12
 PEAK_HBM = 8.0e12
+PEAK_FP32_MATRIX = 157.3e12
 
 
 def say(msg: str):
@@ -43,6 +44,15 @@ def integrator_flops_per_traj_step(n: int, P: int) -> float:
     """
     stage = 8 * n * n + (25 + 20) * n + 4 * P
     return 4 * stage + 13 * (2 * n + P)
+
+
+def fd_flops_per_traj_step(n: int, P: int) -> float:
+    """Algorithmic flops of one RK4 step of one flux-decay trajectory: per
+    stage the complex network product (8 n^2), about 90 flops per machine
+    (EMF rotation with one sin/cos pair counted as 20, electrical power, d-axis
+    current, terminal voltage, six derivatives) and 4 per process; 13 per state
+    variable for the RK4 combination."""
+    return 4.0 * (8.0 * n * n + 90.0 * n + 4.0 * P) + 13.0 * (6 * n + P)
 
 
 def oracle_mod():
@@ -214,6 +224,51 @@ def served_leg(ctx, fmc, workloads, oracle_mod, rates, n_max: int, seed: int = 1
     return out
 
 
+def fd_leg(ctx, fmc, workloads, oracle_mod, steps: int, reps: int = 2):
+    """Large-request shape of the flux-decay model (200 machines with IEEE
+    type-1 exciters, 10 OU processes, N = 5e4, K = 100) on a horizon of
+    `steps` steps: throughput and the network product's rate against the FP32
+    matrix-core peak; sampled trajectories against the oracle."""
+    import numpy as np
+    import torch
+    sc = workloads.fluxdecay(T=steps * 0.005)
+    n, P, N = sc["n_gen"], len(sc["dist"]["gen"]), sc["N"]
+    S = fmc.steps(sc)
+    out = {"workload": "flux-decay + IEEE type-1, n=200, P=10, K=100, N=5e4, dt=5 ms, "
+                       f"{S} steps (the large served request's shape on a short horizon)",
+           "flops_per_traj_step": fd_flops_per_traj_step(n, P)}
+    sel = np.array([7, N // 2, N - 1])
+    ref = None
+    if oracle_mod is not None:
+        ref = oracle_mod.run(sc, sel=sel, want_traj=True)["traj"]
+    for form in ("f32", "bf16x3"):
+        ctx.run(sc, precision=form)  # warm
+        torch.cuda.synchronize()
+        t_int = 0.0
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = ctx.run(sc, precision=form)
+            t_int += r["report"]["t_integrate_s"]
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / reps
+        t_int /= reps
+        ent = {"trajectory_steps_per_s": N * S / sec, "ms_per_run": sec * 1e3,
+               "integrator_ms": t_int * 1e3,
+               "integrator_traj_steps_per_s": N * S / t_int,
+               "network_product_tflops": 8.0 * n * n * 4 * N * S / t_int / 1e12,
+               "frac_of_fp32_matrix_peak": 8.0 * n * n * 4 * N * S / t_int / PEAK_FP32_MATRIX}
+        if ref is not None:
+            rt = ctx.run(sc, precision=form, traj_idx=sel)["traj"].cpu().numpy()
+            d = ref - ref[:, :1, :]
+            num = np.abs(rt - ref).reshape(-1, rt.shape[-1]).max(axis=0)
+            den = np.maximum(np.abs(d).reshape(-1, rt.shape[-1]).max(axis=0), 1e-6)
+            ent["traj_rel_sampled"] = float((num / den).max())
+        out[form] = ent
+        say(f"flux-decay {form}: {sec * 1e3:.1f} ms per run, integrator {t_int * 1e3:.1f} ms, "
+            f"{ent['network_product_tflops']:.1f} TFLOP/s network product")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,6 +285,8 @@ def main():
                     help="Poisson request rates of the served leg (empty: skip)")
     ap.add_argument("--serve-max", type=int, default=20,
                     help="requests per rate of the served leg (at most)")
+    ap.add_argument("--fd-steps", type=int, default=100,
+                    help="horizon of the flux-decay leg in steps (0: skip)")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -337,6 +394,10 @@ def main():
         batched = batched_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(),
                               args.batch_steps, "f64" in forms)
 
+    fdl = None
+    if args.fd_steps > 0:
+        fdl = fd_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), args.fd_steps)
+
     served = None
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
@@ -387,6 +448,7 @@ def main():
         "forms": forms_out,
         "batched": batched,
         "served": served,
+        "flux_decay": fdl,
     }
     print(json.dumps(line))
     ctx.close()
