@@ -1,6 +1,9 @@
 // fmc_batch.hip -- batched form of the method: many scenarios of different
-// sizes, horizons, K and N in one persistent launch per size class, all
-// device work of a batch captured once into a HIP graph and replayed while the
+// sizes, horizons, K and N advance together in time chunks ("ticks"); each
+// tick is one persistent launch per size class over the work items of every
+// scenario that still has steps, with the trajectory state kept on the device
+// between ticks and the chunk's statistics rows merged after it.  All device
+// work of a batch is captured once into a HIP graph and replayed while the
 // batch keeps its shape.
 #include <hip/hip_runtime.h>
 
@@ -20,6 +23,9 @@ namespace fmc {
 
 namespace {
 
+constexpr int64_t kBatchChunk = 250;     // steps per chunk (tick)
+constexpr int64_t kBatchMaxItems = 512;  // work items per scenario
+
 #define HIPCHK(expr)                                                                          \
   do {                                                                                        \
     hipError_t e_ = (expr);                                                                   \
@@ -38,6 +44,7 @@ struct Plan {
   int vid;
   BatchVariantInfo bv;
   int64_t tiles, tiles_per_item, n_items, item0;
+  int64_t Sc = 0, ticks = 0, lanes = 0;  // time chunk, chunks, state row stride
   double cost_tile;
   // device
   SetupDev sd{};
@@ -45,7 +52,7 @@ struct Plan {
   bool kron = false;
   double *canon = nullptr, *phi = nullptr, *zeta = nullptr, *mean = nullptr, *var = nullptr;
   double2 *ybuf = nullptr, *kwork = nullptr, *part = nullptr;
-  float *coef = nullptr, *w = nullptr;
+  float *coef = nullptr, *w = nullptr, *state = nullptr;
   int32_t *strata = nullptr, *slot = nullptr;
   double* traj = nullptr;
   const int32_t* gen_d = nullptr;
@@ -188,18 +195,24 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
                   p.dist->xi0 ? 1 : 0, p.out->strata ? 1 : 0);
     shape_key += b4;
   }
-  // ---- work items: a scenario is cut into items of about a fixed amount of
-  // work (2^34 flop-units), so its partition, and with it the merge order of
-  // its statistics, does not depend on the other scenarios of the batch
-  const double target = 17179869184.0;
-  int64_t n_items = 0;
+  // ---- time chunks and work items.  Every scenario advances in chunks of
+  // Sc steps (its time_chunk, else kBatchChunk); chunk k of every scenario
+  // that still has steps left forms tick k of the batch.  A scenario is cut
+  // into at most kBatchMaxItems items of consecutive tiles, fixed by the
+  // scenario alone, so its statistics (merged per chunk, items in order) do
+  // not depend on the other scenarios of the batch.
+  int64_t n_ticks = 0, n_items = 0;
   for (auto& p : plans) {
-    int64_t want = (int64_t)std::llround(p.cost_tile * p.tiles / target);
-    want = std::max<int64_t>(1, std::min<int64_t>(want, p.tiles));
-    p.tiles_per_item = (p.tiles + want - 1) / want;
+    p.Sc = std::min<int64_t>(p.S, p.par->time_chunk > 0 ? p.par->time_chunk : kBatchChunk);
+    p.ticks = (p.S + p.Sc - 1) / p.Sc;
+    n_ticks = std::max(n_ticks, p.ticks);
+    p.tiles_per_item = (p.tiles + kBatchMaxItems - 1) / kBatchMaxItems;
     p.n_items = (p.tiles + p.tiles_per_item - 1) / p.tiles_per_item;
     p.item0 = n_items;
     n_items += p.n_items;
+    char b5[48];
+    std::snprintf(b5, sizeof(b5), "c%lld|", (long long)p.Sc);
+    shape_key += b5;
   }
   // ---- device buffers
   for (int i = 0; i < nsc; ++i) {
@@ -207,6 +220,7 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     void* q = nullptr;
     const CanonLayout CL{p.n, p.P};
     const PackLayout PL{p.bv.NG, p.bv.PM};
+    const int G = (p.bv.NG + p.bv.L - 1) / p.bv.L, PQ = (p.bv.PM + p.bv.L - 1) / p.bv.L;
     if ((rc = c->ensure(nm(i, "canon").c_str(), (size_t)CL.size() * 8, &q))) return rc;
     p.canon = (double*)q;
     if ((rc = c->ensure(nm(i, "coef").c_str(), (size_t)PL.size() * 4, &q))) return rc;
@@ -221,9 +235,12 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
         p.strata = (int32_t*)q;
       }
     }
-    if ((rc = c->ensure(nm(i, "w").c_str(), (size_t)p.C * p.P * p.N * 4, &q))) return rc;
+    if ((rc = c->ensure(nm(i, "w").c_str(), (size_t)(2 * p.Sc + 1) * p.P * p.N * 4, &q))) return rc;
     p.w = (float*)q;
-    if ((rc = c->ensure(nm(i, "part").c_str(), (size_t)p.n_items * (p.S + 1) * p.V * 16, &q))) return rc;
+    p.lanes = p.tiles * 64 * 4;
+    if ((rc = c->ensure(nm(i, "state").c_str(), (size_t)(2 * G + PQ) * p.lanes * 4, &q))) return rc;
+    p.state = (float*)q;
+    if ((rc = c->ensure(nm(i, "part").c_str(), (size_t)p.n_items * (p.Sc + 1) * p.V * 16, &q))) return rc;
     p.part = (double2*)q;
     if ((rc = c->ensure(nm(i, "work").c_str(), (size_t)(3 * p.n * p.n + 8 * p.n + 64) * 8, &q))) return rc;
     p.sd.work = (double*)q;
@@ -258,36 +275,40 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
   void *status = nullptr, *counters = nullptr, *heads = nullptr;
   if ((rc = c->ensure("b_status", (size_t)nsc * 16, &status))) return rc;
   if ((rc = c->ensure("b_counters", (size_t)nsc * 16, &counters))) return rc;
-  if ((rc = c->ensure("b_heads", 64, &heads))) return rc;
-  // ---- items and queue orders (longest first, per size class)
+  if ((rc = c->ensure("b_heads", (size_t)n_ticks * 8 * 4, &heads))) return rc;
+  // ---- items (static) and, per tick and size class, the queue of the items
+  // of the scenarios active in that tick (longest first)
   std::vector<BatchItem> items(n_items);
-  std::vector<std::vector<int32_t>> order(kBatchClasses);
   std::vector<double> icost(n_items);
+  std::vector<std::vector<int32_t>> by_cls(kBatchClasses);
   for (int i = 0; i < nsc; ++i) {
     Plan& p = plans[i];
     for (int64_t k = 0; k < p.n_items; ++k) {
       BatchItem& it = items[p.item0 + k];
-      it.rows = p.part + k * (p.S + 1) * p.V;
+      it.rows = p.part + k * (p.Sc + 1) * p.V;
       it.tile0 = k * p.tiles_per_item;
       it.tile1 = std::min<int64_t>(p.tiles, it.tile0 + p.tiles_per_item);
       it.scen = i;
       it.variant = p.vid;
-      icost[p.item0 + k] = p.cost_tile * (double)(it.tile1 - it.tile0);
-      order[p.bv.cls].push_back((int32_t)(p.item0 + k));
+      icost[p.item0 + k] = p.cost_tile / (double)p.S * (double)p.Sc * (double)(it.tile1 - it.tile0);
+      by_cls[p.bv.cls].push_back((int32_t)(p.item0 + k));
     }
   }
-  for (auto& o : order)
+  for (auto& o : by_cls)
     std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return icost[a] > icost[b]; });
   std::vector<int32_t> order_flat;
-  int64_t ord_off[kBatchClasses + 1] = {0};
-  for (int k = 0; k < kBatchClasses; ++k) {
-    ord_off[k] = (int64_t)order_flat.size();
-    order_flat.insert(order_flat.end(), order[k].begin(), order[k].end());
+  std::vector<int64_t> ord_off((size_t)n_ticks * kBatchClasses + 1, 0);
+  for (int64_t k = 0; k < n_ticks; ++k) {
+    for (int cl = 0; cl < kBatchClasses; ++cl) {
+      ord_off[k * kBatchClasses + cl] = (int64_t)order_flat.size();
+      for (int32_t q : by_cls[cl])
+        if (plans[items[q].scen].ticks > k) order_flat.push_back(q);
+    }
   }
-  ord_off[kBatchClasses] = (int64_t)order_flat.size();
-  // ---- one upload: scenario inputs, integrator arguments, items, orders
+  ord_off[(size_t)n_ticks * kBatchClasses] = (int64_t)order_flat.size();
+  // ---- one upload: scenario inputs, per-tick integrator arguments, items, queues
   Stager sg;
-  std::vector<IntegArgs<float>> args(nsc);
+  std::vector<IntegArgs<float>> args((size_t)n_ticks * nsc);
   for (int i = 0; i < nsc; ++i) {
     Plan& p = plans[i];
     const fmc_system* s = p.sys;
@@ -332,27 +353,29 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     p.sd.V_inf = s->V_inf;
     p.sd.canon = p.canon;
     p.sd.status = (int*)status + 4 * i;  // [0]: setup, [1]: reduction
-    IntegArgs<float>& a = args[i];
-    a.coef = p.coef;
-    a.w = p.w;
-    a.state = nullptr;
-    a.partial = nullptr;
-    a.delta0 = p.canon + CanonLayout{p.n, p.P}.delta0();
-    a.traj_slot = p.slot;
-    a.traj = p.traj;
-    a.nonfinite = (unsigned long long*)counters + 2 * i;
-    a.first_bad = (long long*)counters + 2 * i + 1;
-    a.n = p.n;
-    a.P = p.P;
-    a.V = p.V;
-    a.N = p.N;
-    a.S = p.S;
-    a.s_begin = 0;
-    a.s_end = p.S;
-    a.c_base = 0;
-    a.lanes = 0;
-    a.dt = (float)p.par->dt;
-    a.wb = (float)(2.0 * M_PI * (s->f0_hz > 0.0 ? s->f0_hz : 60.0));
+    for (int64_t k = 0; k < p.ticks; ++k) {
+      IntegArgs<float>& a = args[(size_t)k * nsc + i];
+      a.coef = p.coef;
+      a.w = p.w;
+      a.state = p.state;
+      a.partial = nullptr;
+      a.delta0 = p.canon + CanonLayout{p.n, p.P}.delta0();
+      a.traj_slot = p.slot;
+      a.traj = p.traj;
+      a.nonfinite = (unsigned long long*)counters + 2 * i;
+      a.first_bad = (long long*)counters + 2 * i + 1;
+      a.n = p.n;
+      a.P = p.P;
+      a.V = p.V;
+      a.N = p.N;
+      a.S = p.S;
+      a.s_begin = k * p.Sc;
+      a.s_end = std::min<int64_t>(p.S, (k + 1) * p.Sc);
+      a.c_base = 2 * a.s_begin;
+      a.lanes = p.lanes;
+      a.dt = (float)p.par->dt;
+      a.wb = (float)(2.0 * M_PI * (s->f0_hz > 0.0 ? s->f0_hz : 60.0));
+    }
   }
   const IntegArgs<float>* args_d = nullptr;
   const BatchItem* items_d = nullptr;
@@ -373,11 +396,8 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
   // ---- device work: captured once per batch shape, then replayed
   hipDeviceProp_t prop;
   HIPCHK(hipGetDeviceProperties(&prop, c->device));
-  int grid[kBatchClasses];
-  for (int k = 0; k < kBatchClasses; ++k) {
-    const int64_t nk = ord_off[k + 1] - ord_off[k];
-    grid[k] = (int)std::min<int64_t>(nk, (int64_t)persistent_blocks_per_cu(k) * prop.multiProcessorCount);
-  }
+  int bpc[kBatchClasses];
+  for (int k = 0; k < kBatchClasses; ++k) bpc[k] = persistent_blocks_per_cu(k);
   auto enqueue = [&]() -> int {
     HIPCHK(launch_fill_i64((int64_t*)status, 0, 2 * nsc, st));
     for (int i = 0; i < nsc; ++i) {
@@ -389,32 +409,44 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
       HIPCHK(launch_setup(p.sd, st));
       HIPCHK(launch_pack<float>(p.canon, p.n, p.P, p.gen_d, p.bv.NG, p.bv.PM, p.coef, st));
       HIPCHK(launch_basis(p.par->basis, p.K, p.S, p.par->T, p.phi, st));
-      const double* zeta = p.par->zeta_in;
-      if (!zeta) {
+      if (!p.par->zeta_in)
         HIPCHK(launch_lhs(p.par->seed, (int32_t)p.M, p.N, p.par->sampler, p.strata, p.zeta, st));
-        zeta = p.zeta;
-      }
-      if (p.par->precision == FMC_F32)
-        HIPCHK(launch_kle_f64_to_f32(zeta, p.phi, p.C, p.P, p.K, p.N, p.C, 0, p.w, st));
-      else
-        HIPCHK(launch_kle_bf16x3(zeta, p.phi, p.C, p.P, p.K, p.N, p.C, 0, p.w, st));
     }
     // counters: (nonfinite = 0, first = max) per scenario; queue heads = 0
     for (int i = 0; i < nsc; ++i) {
       HIPCHK(launch_fill_i64((int64_t*)counters + 2 * i, 0, 1, st));
       HIPCHK(launch_fill_i64((int64_t*)counters + 2 * i + 1, LLONG_MAX, 1, st));
     }
-    HIPCHK(launch_fill_i64((int64_t*)heads, 0, 8, st));
-    for (int k = 0; k < kBatchClasses; ++k) {
-      const int64_t nk = ord_off[k + 1] - ord_off[k];
-      if (nk == 0) continue;
-      BatchArgs b{args_d, items_d, order_d + ord_off[k], (int32_t)nk, (int32_t*)heads + 2 * k};
-      HIPCHK(launch_persistent(k, b, grid[k], st));
+    HIPCHK(launch_fill_i64((int64_t*)heads, 0, n_ticks * 4, st));
+    for (int64_t k = 0; k < n_ticks; ++k) {
+      for (auto& p : plans) {
+        if (p.ticks <= k) continue;
+        const int64_t s0 = k * p.Sc, s1 = std::min<int64_t>(p.S, s0 + p.Sc);
+        const double* zeta = p.par->zeta_in ? p.par->zeta_in : p.zeta;
+        if (p.par->precision == FMC_F32)
+          HIPCHK(launch_kle_f64_to_f32(zeta, p.phi, p.C, p.P, p.K, p.N, 2 * (s1 - s0) + 1, 2 * s0, p.w, st));
+        else
+          HIPCHK(launch_kle_bf16x3(zeta, p.phi, p.C, p.P, p.K, p.N, 2 * (s1 - s0) + 1, 2 * s0, p.w, st));
+      }
+      for (int cl = 0; cl < kBatchClasses; ++cl) {
+        const int64_t o0 = ord_off[k * kBatchClasses + cl], o1 = ord_off[k * kBatchClasses + cl + 1];
+        if (o1 == o0) continue;
+        const int grid = (int)std::min<int64_t>(o1 - o0, (int64_t)bpc[cl] * prop.multiProcessorCount);
+        BatchArgs b{args_d + (size_t)k * nsc, items_d, order_d + o0, (int32_t)(o1 - o0),
+                    (int32_t*)heads + k * 8 + 2 * cl};
+        HIPCHK(launch_persistent(cl, b, grid, st));
+      }
+      // rows completed by this tick: s0+1..s1 (and row 0 in the first chunk)
+      for (auto& p : plans) {
+        if (p.ticks <= k) continue;
+        const int64_t s0 = k * p.Sc, s1 = std::min<int64_t>(p.S, s0 + p.Sc);
+        const int64_t first = s0 == 0 ? 0 : s0 + 1;
+        HIPCHK(launch_stats_merge_rows(p.part + (first - s0) * p.V, (p.Sc + 1) * p.V, p.n_items,
+                                       (int)(p.tiles_per_item * p.bv.TB), p.N, s1 - first + 1, p.V,
+                                       p.n, p.par->ddof, p.canon + CanonLayout{p.n, p.P}.delta0(),
+                                       p.mean + first * p.V, p.var + first * p.V, st));
+      }
     }
-    for (auto& p : plans)
-      HIPCHK(launch_stats_merge(p.part, p.n_items, (int)(p.tiles_per_item * p.bv.TB), p.N, p.S, p.V,
-                                p.n, p.par->ddof, p.canon + CanonLayout{p.n, p.P}.delta0(), p.mean,
-                                p.var, st));
     return FMC_OK;
   };
   hipEvent_t e0 = c->ev[0], e1 = c->ev[1];
@@ -497,7 +529,7 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
       r->variant_id = p.vid;
       r->lanes_per_traj = p.bv.L;
       r->tile = (int32_t)(p.tiles_per_item * p.bv.TB);
-      r->time_chunk = (int32_t)p.S;
+      r->time_chunk = (int32_t)p.Sc;
       r->hbm_peak_bytes = (int64_t)c->held;
     }
   }

@@ -143,12 +143,13 @@ hipError_t launch_integrate_f32(int variant_id, const IntegArgs<float>& a, int64
 
 // Persistent batched integrator (FP32).
 struct BatchItem {
-  double2* rows;        // statistics rows [S+1][V] of this item
+  double2* rows;        // statistics rows of this item: [S+1][V], or [chunk+1][V]
+                        // (steps s_begin..s_end) when the scenario has a state buffer
   int64_t tile0, tile1; // trajectory tiles [tile0, tile1) of the scenario
   int32_t scen, variant;
 };
 struct BatchArgs {
-  const IntegArgs<float>* scen;  // one per scenario (whole horizon, no chunking)
+  const IntegArgs<float>* scen;  // one per scenario (this launch's steps)
   const BatchItem* items;
   const int32_t* order;          // queue position -> item
   int32_t n_items;

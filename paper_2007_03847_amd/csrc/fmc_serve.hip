@@ -440,10 +440,7 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
     const double frac = (double)(s1 - s0) / (double)r.S;
     for (int64_t k = 0; k < r.n_items; ++k) {
       BatchItem it;
-      // the item's rows hold this chunk's steps s0..s1; the kernel indexes
-      // them by global step, so the base is shifted back by s0 rows
-      it.rows = (double2*)((uintptr_t)(r.part + k * (r.Sc + 1) * r.V) -
-                           (uintptr_t)(s0 * r.V) * sizeof(double2));
+      it.rows = r.part + k * (r.Sc + 1) * r.V;  // this chunk's rows (steps s0..s1)
       it.tile0 = k * r.tiles_per_item;
       it.tile1 = std::min<int64_t>(r.tiles, it.tile0 + r.tiles_per_item);
       it.scen = i;

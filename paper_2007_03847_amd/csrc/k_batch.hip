@@ -47,9 +47,12 @@ template <int NG, int PM, int L>
 __device__ __forceinline__ void batch_tiles(const IntegArgs<float>& a, const BatchItem& it,
                                             unsigned char* lds) {
   using Sh = GroupShape<float, NG, PM, L, kBatchWPB, kBatchD>;
+  // With a state buffer the scenario runs in time chunks: the item's rows then
+  // hold the chunk's steps s_begin..s_end, and the kernel addresses them by
+  // global step.
+  double2* rows = a.state ? it.rows - a.s_begin * a.V : it.rows;
   for (int64_t t = it.tile0; t < it.tile1; ++t) {
-    GroupStats st{it.rows, (t - it.tile0) * Sh::TB};
-    // a state buffer means the scenario runs in time chunks (served form)
+    GroupStats st{rows, (t - it.tile0) * Sh::TB};
     group_run<float, NG, PM, L, kBatchWPB, kBatchD>(a, t, lds, st, a.state != nullptr);
   }
 }
