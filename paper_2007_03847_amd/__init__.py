@@ -193,8 +193,9 @@ def scenario_structs(sc: dict, precision="f64", variant=-1, time_chunk=0, zeta_i
     else:
         a["Yinf_re"] = a["Yinf_im"] = None
     model = _enum(sc.get("model", 0), MODEL)
-    a["model_params"] = (np.ascontiguousarray(sc["model_params"], dtype=np.float64).reshape(n, -1)
-                         if model == FLUXDECAY_IEEET1 else None)
+    mp = sc.get("model_params")
+    a["model_params"] = (np.ascontiguousarray(mp, dtype=np.float64).reshape(n, -1)
+                         if model == FLUXDECAY_IEEET1 and mp is not None else None)
     keep.append(a)
     sysd = System(n_gen=n, f0_hz=float(sc.get("f0", 60.0)), H=_ptr(a["H"]), D=_ptr(a["D"]),
                   E=_ptr(a["E"]), delta0=_ptr(a["delta0"]), Pm=_ptr(a["Pm"]),

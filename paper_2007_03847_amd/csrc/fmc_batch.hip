@@ -248,7 +248,7 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
       p.kron = true;
       if ((rc = c->ensure(nm(i, "ybuf").c_str(), (size_t)p.n * p.n * 16, &q))) return rc;
       p.ybuf = (double2*)q;
-      if ((rc = c->ensure("b_kron_work", (size_t)p.sys->net->n_bus * (p.sys->net->n_bus + p.n) * 16, &q))) return rc;
+      if ((rc = c->ensure("b_kron_work", kron_work_bytes(p.sys->net->n_bus, p.n), &q))) return rc;
     }
     // the captured graph touches context buffers only; results are copied out
     // after each replay (caller pointers may change between calls)

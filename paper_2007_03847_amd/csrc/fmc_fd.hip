@@ -61,6 +61,14 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
   HIPCHK(launch_setup_fd(canon, n, P, E_d, prm_d, (double*)fd, c->stream));
   HIPCHK(launch_pack_fd(canon, n, P, prm_d, (const double*)fd, gen_d, n_pad, (float*)coef,
                         (float2*)ap, c->stream));
+  // FMC_BF16X3: the network product in BF16 x3 on the matrix cores too
+  const bool bf = par->precision == FMC_BF16X3;
+  const int n_padk = 32 * ((n + 31) / 32);
+  void* ap16 = nullptr;
+  if (bf) {
+    if ((rc = c->ensure("fd_ap16", fd_ap16_bytes(n_pad, n_padk), &ap16))) return rc;
+    HIPCHK(launch_pack_fd_y16(canon, n, n_pad, n_padk, ap16, c->stream));
+  }
 
   void* phi = nullptr;
   if ((rc = c->ensure("phi", (size_t)K * C * sizeof(double), &phi))) return rc;
@@ -140,6 +148,8 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
   FdArgs a{};
   a.coef = (const float*)coef;
   a.ap = (const float2*)ap;
+  a.ap16 = ap16;
+  a.n_padk = n_padk;
   a.w = (const float*)w;
   a.state = (float*)state;
   a.xstate = (float*)xstate;

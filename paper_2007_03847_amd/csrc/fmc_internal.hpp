@@ -96,6 +96,7 @@ struct NetDev {
 };
 hipError_t launch_kron(const NetDev& net, double2* work, double2* Yred, int* status,
                        hipStream_t st);
+size_t kron_work_bytes(int n_bus, int n_gen);  // device work buffer of launch_kron
 
 // Operating point and canonical coefficients.
 struct SetupDev {
@@ -207,6 +208,9 @@ struct FdPack {
 struct FdArgs {
   const float* coef;          // FdPack block
   const float2* ap;           // (Yr, Yi) in A-operand order [n_pad/16][n_pad/4][64]
+  const void* ap16;           // BF16 x3 product: Y hi/lo [n_pad/16][n_padk/32][64][4] x 16 B,
+                              // or null for the FP32 product
+  int n_padk;                 // n rounded up to 32 (K dimension of the BF16 product)
   const float* w;             // [cols][P][N] KLE paths of this chunk
   float* state;               // [tiles][ceil(NB/2)][48][64] deviations between chunks
   float* xstate;              // [tiles][kFdMaxProc][16]
@@ -227,7 +231,12 @@ hipError_t launch_setup_fd(const double* canon, int n, int P, const double* E, c
                            double* fd, hipStream_t st);
 hipError_t launch_pack_fd(const double* canon, int n, int P, const double* prm, const double* fd,
                           const int32_t* gen, int n_pad, float* coef, float2* ap, hipStream_t st);
-size_t fd_lds_bytes(int n_pad);
+size_t fd_lds_bytes(int n_pad, int n_padk, bool bf16);
 hipError_t launch_rk4_fd(const FdArgs& a, int64_t n_items, hipStream_t st);
+hipError_t launch_pack_fd_y16(const double* canon, int n, int n_pad, int n_padk, void* ap16,
+                              hipStream_t st);
+inline size_t fd_ap16_bytes(int n_pad, int n_padk) {
+  return (size_t)(n_pad / 16) * (n_padk / 32) * 64 * 64;
+}
 
 }  // namespace fmc

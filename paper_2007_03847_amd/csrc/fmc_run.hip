@@ -1,7 +1,8 @@
 // fmc_run.hip -- one scenario through the whole method (Alg. 1) on the GPU:
 // setup (network reduction, operating point) -> LHS design (step 1) -> basis
-// -> per time chunk: KLE path contraction (step 2) and integration with fused
-// per-wave statistics (step 3) -> ordered merge of the statistics (step 4).
+// -> per time chunk: KLE path contraction (step 2, on a second stream, one
+// chunk ahead) and integration with fused per-wave statistics (step 3) ->
+// ordered merge of the statistics (step 4).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,11 +25,11 @@ struct EventPool {
   ~EventPool() {
     for (auto e : ev) (void)hipEventDestroy(e);
   }
-  int record() {
+  int record(hipStream_t on_stream = nullptr) {
     if (!on) return -1;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return -1;
-    (void)hipEventRecord(e, st);
+    (void)hipEventRecord(e, on_stream ? on_stream : st);
     ev.push_back(e);
     return (int)ev.size() - 1;
   }
@@ -41,7 +42,7 @@ struct EventPool {
 };
 
 struct ChunkTimes {
-  std::vector<int> gemm0, gemm1, int1;
+  std::vector<int> gemm0, gemm1, int0, int1;
 };
 
 template <typename R>
@@ -56,13 +57,27 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
   const int64_t n_groups = (N + gs - 1) / gs;
   const int64_t lanes = n_groups * 64 * vi.WPB;
   const int bw = (int)sizeof(R);
-  void *w = nullptr, *state = nullptr;
+  // Two path buffers: the contraction of chunk k+1 runs on a second stream
+  // while the integrator consumes chunk k (the integrator is bound by issue
+  // latency at low occupancy, so the matrix-core contraction fits beside it).
+  void *w[2] = {nullptr, nullptr}, *state = nullptr;
   int rc;
-  if ((rc = c->ensure("w", (size_t)(2 * Sc + 1) * P * N * bw, &w))) return rc;
+  if ((rc = c->ensure("w", (size_t)(2 * Sc + 1) * P * N * bw, &w[0]))) return rc;
+  if ((rc = c->ensure("w1", (size_t)(2 * Sc + 1) * P * N * bw, &w[1]))) return rc;
   if ((rc = c->ensure("state", (size_t)(2 * vi.NG + vi.PM) * lanes * bw, &state))) return rc;
+  if (!c->gstream) {
+    if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess)
+      return fail(FMC_EDEVICE, "cannot create the contraction stream");
+  }
+  for (auto& e : c->gev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return fail(FMC_EDEVICE, "hipEventCreate failed");
+  hipStream_t ks = c->gstream;
+  // the contractions start after the setup work (design, basis) on the main stream
+  if (hipEventRecord(c->ev[5], c->stream) != hipSuccess || hipStreamWaitEvent(ks, c->ev[5], 0) != hipSuccess)
+    return fail(FMC_EDEVICE, "stream ordering failed");
   IntegArgs<R> a{};
   a.coef = coef;
-  a.w = (const R*)w;
   a.state = (R*)state;
   a.partial = partial;
   a.delta0 = delta0;
@@ -78,22 +93,30 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
   a.lanes = lanes;
   a.dt = (R)par->dt;
   a.wb = (R)wb;
-  for (int64_t s0 = 0; s0 < S; s0 += Sc) {
+  int64_t k = 0;
+  for (int64_t s0 = 0; s0 < S; s0 += Sc, ++k) {
     const int64_t s1 = std::min<int64_t>(S, s0 + Sc);
     const int64_t Cc = 2 * (s1 - s0) + 1;
-    ct.gemm0.push_back(evp.record());
-    hipError_t e;
+    const int b = (int)(k & 1);
+    hipError_t e = hipSuccess;
+    if (k >= 2) e = hipStreamWaitEvent(ks, c->gev[2 + b], 0);  // chunk k-2 done with w[b]
+    if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+    ct.gemm0.push_back(evp.record(ks));
     if (par->precision == FMC_F64)
-      e = launch_kle_f64(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (double*)w, c->stream);
+      e = launch_kle_f64(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (double*)w[b], ks);
     else if (par->precision == FMC_F32)
-      e = launch_kle_f64_to_f32(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w, c->stream);
+      e = launch_kle_f64_to_f32(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w[b], ks);
     else
-      e = launch_kle_bf16x3(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w, c->stream);
+      e = launch_kle_bf16x3(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w[b], ks);
     if (e != hipSuccess) return fail(FMC_EDEVICE, std::string("KLE launch: ") + hipGetErrorString(e));
-    ct.gemm1.push_back(evp.record());
+    ct.gemm1.push_back(evp.record(ks));
+    if (hipEventRecord(c->gev[b], ks) != hipSuccess || hipStreamWaitEvent(c->stream, c->gev[b], 0) != hipSuccess)
+      return fail(FMC_EDEVICE, "stream ordering failed");
+    a.w = (const R*)w[b];
     a.s_begin = s0;
     a.s_end = s1;
     a.c_base = 2 * s0;
+    ct.int0.push_back(evp.record());
     if constexpr (sizeof(R) == 8)
       e = launch_integrate_f64(vid, a, n_groups, c->stream);
     else
@@ -101,6 +124,8 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
     if (e != hipSuccess)
       return fail(FMC_EDEVICE, std::string("integrator launch: ") + hipGetErrorString(e));
     ct.int1.push_back(evp.record());
+    if (hipEventRecord(c->gev[2 + b], c->stream) != hipSuccess)
+      return fail(FMC_EDEVICE, "stream ordering failed");
   }
   return FMC_OK;
 }
@@ -281,7 +306,7 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     r->t_lhs_s = evp.secs(ev_lhs0, ev_lhs1);
     for (size_t q = 0; q < ct.gemm0.size(); ++q) {
       r->t_gemm_s += evp.secs(ct.gemm0[q], ct.gemm1[q]);
-      r->t_integrate_s += evp.secs(ct.gemm1[q], ct.int1[q]);
+      r->t_integrate_s += evp.secs(ct.int0[q], ct.int1[q]);
     }
     r->t_stats_s = evp.secs(ev_st0, ev_end);
     r->n_nonfinite = (int64_t)cn[0];

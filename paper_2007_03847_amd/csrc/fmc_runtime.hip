@@ -236,7 +236,7 @@ int kron_on_device(Context* c, const fmc_network* net, double2* Yd, int* st_dev)
   sg.add(net->gen_xdp, net->n_gen, &nd.xdp);
   if ((rc = sg.upload(c, "net"))) return rc;
   void* work = nullptr;
-  const size_t wbytes = (size_t)net->n_bus * (net->n_bus + net->n_gen) * sizeof(double2);
+  const size_t wbytes = kron_work_bytes(net->n_bus, net->n_gen);
   if ((rc = c->ensure("kron_work", wbytes, &work))) return rc;
   hipError_t e = launch_kron(nd, (double2*)work, Yd, st_dev, c->stream);
   if (e != hipSuccess) return fail(FMC_EDEVICE, std::string("kron launch: ") + hipGetErrorString(e));
@@ -421,6 +421,12 @@ int fmc_context_destroy(fmc_context* ctx) {
   for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second.second);
   c->graphs.clear();
   if (c->bstream) (void)hipStreamDestroy(c->bstream);
+  if (c->gstream) {
+    (void)hipStreamSynchronize(c->gstream);
+    (void)hipStreamDestroy(c->gstream);
+  }
+  for (auto& e : c->gev)
+    if (e) (void)hipEventDestroy(e);
   c->release_all();
   for (auto& ev : c->ev) (void)hipEventDestroy(ev);
   delete c;
@@ -562,8 +568,11 @@ int fmc_run(fmc_context* ctx, const fmc_system* sys, const fmc_disturbance* dist
   Context* c = reinterpret_cast<Context*>(ctx);
   const int rc = run_single(c, sys, dist, par, out);
   // a failed call may have left copies and kernels in flight that read staging
-  // buffers the next call rewrites: drain the stream before returning
-  if (rc != FMC_OK && rc != FMC_ENONFINITE) (void)hipStreamSynchronize(c->stream);
+  // buffers the next call rewrites: drain the streams before returning
+  if (rc != FMC_OK && rc != FMC_ENONFINITE) {
+    (void)hipStreamSynchronize(c->stream);
+    if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+  }
   return rc;
 }
 

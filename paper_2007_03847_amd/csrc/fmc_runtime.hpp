@@ -35,6 +35,8 @@ struct Context {
   std::map<std::string, int> tuned;  // autotuner cache: key -> variant id
   uint64_t alloc_gen = 0;            // bumped whenever a device buffer moves
   hipStream_t bstream = nullptr;     // capture stream of the batched form
+  hipStream_t gstream = nullptr;     // KLE contractions overlapped with the integrator
+  hipEvent_t gev[4] = {};            // [b]: paths of buffer b ready, [2+b]: buffer b consumed
   std::map<std::string, std::pair<uint64_t, hipGraphExec_t>> graphs;  // shape -> (gen, graph)
 
   int ensure(const char* name, size_t bytes, void** out);

@@ -109,7 +109,9 @@ std::vector<size_t> parts_of(const Request& r) {
   if (r.fd) {
     z[B_COEF] = (size_t)FdPack{r.n_pad}.size() * 4;
     z[B_FDBLK] = (size_t)FdLayout{r.n}.size() * 8;
-    z[B_FDAP] = (size_t)(r.n_pad / 16) * (r.n_pad / 4) * 64 * sizeof(float2);
+    z[B_FDAP] = r.par.precision == FMC_BF16X3
+                    ? fd_ap16_bytes(r.n_pad, 32 * ((r.n + 31) / 32))
+                    : (size_t)(r.n_pad / 16) * (r.n_pad / 4) * 64 * sizeof(float2);
     z[B_STATE] = (size_t)r.tiles * r.NW * 48 * 64 * 4;
     z[B_XSTATE] = (size_t)r.tiles * kFdMaxProc * 16 * 4;
   } else {
@@ -121,7 +123,7 @@ std::vector<size_t> parts_of(const Request& r) {
   z[B_MEAN] = z[B_VAR] = (size_t)(r.S + 1) * r.V * 8;
   z[B_WORK] = (size_t)(3 * r.n * r.n + 8 * r.n + 64) * 8;
   z[B_YBUF] = r.has_Y ? 0 : (size_t)r.n * r.n * 16;
-  z[B_KWORK] = r.has_Y ? 0 : (size_t)r.n_bus * (r.n_bus + r.n) * 16;
+  z[B_KWORK] = r.has_Y ? 0 : kron_work_bytes(r.n_bus, r.n);
   z[B_STATUS] = 64;
   return z;
 }
@@ -339,7 +341,11 @@ int start_request(ServeState* ss, Request& r, size_t* pin_off) {
   SCHK(launch_setup(r.sd, st));
   if (r.fd) {
     SCHK(launch_setup_fd(r.canon, r.n, r.P, r.E_d, r.prm_d, r.fdblk, st));
+    // constants and the FP32 product's Y; the BF16 x3 product's Y (never
+    // smaller) then overwrites the Y buffer
     SCHK(launch_pack_fd(r.canon, r.n, r.P, r.prm_d, r.fdblk, r.gen_d, r.n_pad, r.coef, r.fdap, st));
+    if (r.par.precision == FMC_BF16X3)
+      SCHK(launch_pack_fd_y16(r.canon, r.n, r.n_pad, 32 * ((r.n + 31) / 32), r.fdap, st));
   } else {
     SCHK(launch_pack<float>(r.canon, r.n, r.P, r.gen_d, r.bv.NG, r.bv.PM, r.coef, st));
   }
@@ -388,6 +394,8 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
       FdArgs f{};
       f.coef = r.coef;
       f.ap = r.fdap;
+      f.ap16 = r.par.precision == FMC_BF16X3 ? (const void*)r.fdap : nullptr;
+      f.n_padk = 32 * ((r.n + 31) / 32);
       f.w = r.w;
       f.state = r.state;
       f.xstate = r.xstate;
@@ -685,7 +693,7 @@ int fmc_footprint(const fmc_scenario* scen, int64_t* bytes) {
     *bytes = (int64_t)footprint_of(r);
     return FMC_OK;
   }
-  // FP64 (single-run form): design, basis, one chunk of paths, state, partials
+  // FP64 (single-run form): design, basis, two chunks of paths, state, partials
   const int64_t n = scen->sys->n_gen, P = scen->dist->n_proc, K = par->K, N = par->N;
   const int64_t V = 2 * n + P, C = 2 * S + 1;
   const int64_t bw = par->precision == FMC_F64 ? 8 : 4;
@@ -694,7 +702,7 @@ int fmc_footprint(const fmc_scenario* scen, int64_t* bytes) {
   int64_t b = 0;
   b += P * K * N * 8;                        // zeta
   b += K * C * 8;                            // basis
-  b += (2 * Sc + 1) * P * N * bw;            // one chunk of KLE paths
+  b += 2 * (2 * Sc + 1) * P * N * bw;        // two chunks of KLE paths (double buffer)
   b += (2 * n + P + 16) * groups * 64 * bw;  // state
   b += groups * (S + 1) * V * 16;            // per-group statistics
   b += 2 * (S + 1) * V * 8;                  // mean, var

@@ -38,6 +38,8 @@ namespace {
 constexpr int kT = 16;  // trajectories per tile
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // FP64 operating point of the flux-decay machines (one thread per machine),
@@ -152,6 +154,41 @@ __global__ void __launch_bounds__(256) k_pack_fd_y(const double* __restrict__ ca
   ap[q] = make_float2(yr, yi);
 }
 
+// Y for the BF16 x3 product on v_mfma_f32_16x16x32_bf16 (x = hi + lo, hi =
+// bf16(x), lo = bf16(x - hi); products hi*hi + hi*lo + lo*hi): for machine
+// block b, k-step s < n_padk/32 and lane l, the vectors Yr hi, Yr lo, Yi hi,
+// Yi lo of the 8 entries [16b + l%16][32s + 8(l/16) + e], e = 0..7.
+__global__ void __launch_bounds__(256) k_pack_fd_y16(const double* __restrict__ canon, int n,
+                                                     int n_pad, int n_padk,
+                                                     u32x4* __restrict__ ap) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int KS = n_padk / 32;
+  const int64_t total = (int64_t)(n_pad / 16) * KS * 64;
+  if (q >= total) return;
+  const int l = (int)(q % 64);
+  const int s = (int)((q / 64) % KS);
+  const int b = (int)(q / (64 * KS));
+  const int i = 16 * b + l % 16;
+  bf8_t rh, rl, ih, il;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int k = 32 * s + 8 * (l / 16) + e;
+    float yr = 0.0f, yi = 0.0f;
+    if (i < n && k < n) {
+      yr = (float)canon[(int64_t)i * n + k];
+      yi = (float)canon[(int64_t)n * n + (int64_t)i * n + k];
+    }
+    rh[e] = (__bf16)yr;
+    rl[e] = (__bf16)(yr - (float)rh[e]);
+    ih[e] = (__bf16)yi;
+    il[e] = (__bf16)(yi - (float)ih[e]);
+  }
+  ap[4 * q + 0] = __builtin_bit_cast(u32x4, rh);
+  ap[4 * q + 1] = __builtin_bit_cast(u32x4, rl);
+  ap[4 * q + 2] = __builtin_bit_cast(u32x4, ih);
+  ap[4 * q + 3] = __builtin_bit_cast(u32x4, il);
+}
+
 // Sum over the 16 lanes of a row (lanes l with equal l/16).
 __device__ __forceinline__ double row16_sum(double v) {
   v += __shfl_xor(v, 8, 16);
@@ -190,10 +227,19 @@ __device__ __forceinline__ void row_stats(double x, bool valid, double cnt, bool
 // ---------------------------------------------------------------------------
 constexpr int kQ = 8;  // machines per lane
 
+// B tile of the BF16 x3 product: hi and lo planes [16 trajectories][BS] with
+// BS = 2 n_padk + 8 (Re dE' rows, then Im dE' rows, then a bank skew).
+__host__ __device__ inline int fd_bs(int n_padk) { return 2 * n_padk + 8; }
+__host__ __device__ inline size_t fd_btile_bytes(int n_pad, int n_padk, bool bf) {
+  return bf ? (size_t)2 * 16 * fd_bs(n_padk) * 2 : (size_t)2 * n_pad * 16 * 4;
+}
+
+template <bool BF>
 __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int n_pad = a.n_pad, n = a.n, P = a.P, V = a.V;
   const int NB = n_pad / 16, NW = (NB + 1) / 2, KH = n_pad / 4;
+  const int n_padk = a.n_padk, KS16 = n_padk / 32, BS = fd_bs(n_padk);
   const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, g = l >> 4, t = l & 15;
   const bool two = 2 * wv + 1 < NB;  // wave-uniform: the second block exists
   const FdPack K{n_pad};
@@ -201,11 +247,17 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
   // values (2 buffers of [kFdMaxProc][16]), flags [16], then the RK4 sums of
   // every lane [NW][6 kQ][64] (kept here rather than in registers)
   float* cst = reinterpret_cast<float*>(smem);
-  float* bs = cst + K.size();
-  float* xs = bs + 2 * n_pad * kT;
+  unsigned char* btile = smem + (size_t)K.size() * 4;
+  float* bs = reinterpret_cast<float*>(btile);          // FP32 product: [2 n_pad][16]
+  __bf16* bh = reinterpret_cast<__bf16*>(btile);        // BF16 product: hi plane
+  __bf16* bl = bh + 16 * BS;                            //               lo plane
+  float* xs = reinterpret_cast<float*>(btile + fd_btile_bytes(n_pad, n_padk, BF));
   int* bad_t = reinterpret_cast<int*>(xs + 2 * kFdMaxProc * kT);
   float* accl = reinterpret_cast<float*>(bad_t + kT) + (int64_t)wv * 6 * kQ * 64 + l;
   for (int q = tid; q < K.size(); q += blockDim.x) cst[q] = a.coef[q];
+  // the tile's padding rows (machines n_pad..n_padk) are never written: zero
+  for (int q = tid; q < (int)(fd_btile_bytes(n_pad, n_padk, BF) / 4); q += blockDim.x)
+    reinterpret_cast<float*>(btile)[q] = 0.0f;
   __syncthreads();
 
   auto mach = [&](int q) { return 16 * (2 * wv + (q >> 2)) + 4 * g + (q & 3); };
@@ -221,6 +273,8 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
   double2* rows = a.rows + (int64_t)item * a.row_stride;
   const float2* apw = a.ap + (int64_t)(2 * wv) * KH * 64 + l;
   const float* B0 = bs + (l >> 4) * kT + (l & 15);
+  const u32x4* aq = reinterpret_cast<const u32x4*>(a.ap16) + ((int64_t)(2 * wv) * KS16 * 64 + l) * 4;
+  const int bfo = t * BS + 8 * g;  // B fragment of lane l: column t, rows 8(l/16)..
   int buf = 0;
 
   for (int64_t tile = tile0; tile < tile1; ++tile) {
@@ -322,8 +376,18 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
           dEi[q] = c0 * sd[q] - s0 * omc[q] + de * (ui * (1.0f - omc[q]) + ur * sd[q]);
           // padding machines contribute exact zeros (Y's padding columns are
           // zero, and 0 * NaN would still poison the product)
-          Bw[bo] = m < n ? dEr[q] : 0.0f;
-          Bw[bo + n_pad * kT] = m < n ? dEi[q] : 0.0f;
+          if constexpr (BF) {
+            const float er = m < n ? dEr[q] : 0.0f, ei = m < n ? dEi[q] : 0.0f;
+            const __bf16 rh = (__bf16)er, ih = (__bf16)ei;
+            const int o = t * BS + m;
+            bh[o] = rh;
+            bl[o] = (__bf16)(er - (float)rh);
+            bh[o + n_padk] = ih;
+            bl[o + n_padk] = (__bf16)(ei - (float)ih);
+          } else {
+            Bw[bo] = m < n ? dEr[q] : 0.0f;
+            Bw[bo + n_pad * kT] = m < n ? dEi[q] : 0.0f;
+          }
           const float kd = wb * ys[1][q];
           const float kf = -cm[FdPack::KE_TE] * ys[3][q] + cm[FdPack::ITE] * ys[4][q];
           const float kr = -cm[FdPack::ITF] * ys[5][q] + cm[FdPack::KF_TF2] * ys[3][q];
@@ -345,7 +409,40 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
         // -- dI = Y dE' for my machine blocks over the tile's 16 trajectories
         f32x4 ar0 = {0.f, 0.f, 0.f, 0.f}, ai0 = ar0, ar1 = ar0, ai1 = ar0;
         const float* bp = B0;
-        if (two) {
+        if constexpr (BF) {
+          // three BF16 products per real product (lo*hi, hi*lo, hi*hi), the
+          // sign of Yi flipped in its bits for the -Yi block
+          const u32x4 sgn = {0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+          for (int k = 0; k < KS16; ++k) {
+            const bf8_t rh_ = *reinterpret_cast<const bf8_t*>(bh + bfo + 32 * k);
+            const bf8_t rl_ = *reinterpret_cast<const bf8_t*>(bl + bfo + 32 * k);
+            const bf8_t ih_ = *reinterpret_cast<const bf8_t*>(bh + bfo + n_padk + 32 * k);
+            const bf8_t il_ = *reinterpret_cast<const bf8_t*>(bl + bfo + n_padk + 32 * k);
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              if (j == 1 && !two) break;
+              const u32x4* av = aq + (int64_t)(j * KS16 + k) * 64 * 4;
+              const u32x4 u0 = av[0], u1 = av[1], u2 = av[2], u3 = av[3];
+              const bf8_t yrh = __builtin_bit_cast(bf8_t, u0), yrl = __builtin_bit_cast(bf8_t, u1);
+              const bf8_t yih = __builtin_bit_cast(bf8_t, u2), yil = __builtin_bit_cast(bf8_t, u3);
+              const bf8_t nih = __builtin_bit_cast(bf8_t, u2 ^ sgn), nil = __builtin_bit_cast(bf8_t, u3 ^ sgn);
+              f32x4& ar = j == 0 ? ar0 : ar1;
+              f32x4& ai = j == 0 ? ai0 : ai1;
+              ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yrl, rh_, ar, 0, 0, 0);
+              ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yrh, rl_, ar, 0, 0, 0);
+              ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yrh, rh_, ar, 0, 0, 0);
+              ai = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yil, rh_, ai, 0, 0, 0);
+              ai = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yih, rl_, ai, 0, 0, 0);
+              ai = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yih, rh_, ai, 0, 0, 0);
+              ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nil, ih_, ar, 0, 0, 0);
+              ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, il_, ar, 0, 0, 0);
+              ar = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nih, ih_, ar, 0, 0, 0);
+              ai = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yrl, ih_, ai, 0, 0, 0);
+              ai = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yrh, il_, ai, 0, 0, 0);
+              ai = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yrh, ih_, ai, 0, 0, 0);
+            }
+          }
+        } else if (two) {
           constexpr int PF = 4;
           float2 p0[PF], p1[PF];
 #pragma unroll
@@ -502,24 +599,37 @@ hipError_t launch_pack_fd(const double* canon, int n, int P, const double* prm, 
   return hipGetLastError();
 }
 
-size_t fd_lds_bytes(int n_pad) {
+size_t fd_lds_bytes(int n_pad, int n_padk, bool bf) {
   const FdPack K{n_pad};
   const int nw = (n_pad / 16 + 1) / 2;
-  return (size_t)K.size() * 4 + (size_t)2 * n_pad * kT * 4 + (size_t)2 * kFdMaxProc * kT * 4 +
-         kT * 4 + (size_t)nw * 6 * kQ * 64 * 4;
+  return (size_t)K.size() * 4 + fd_btile_bytes(n_pad, n_padk, bf) +
+         (size_t)2 * kFdMaxProc * kT * 4 + kT * 4 + (size_t)nw * 6 * kQ * 64 * 4;
 }
 
-hipError_t launch_rk4_fd(const FdArgs& a, int64_t n_items, hipStream_t st) {
-  const size_t lds = fd_lds_bytes(a.n_pad);
+template <bool BF>
+static hipError_t launch_rk4_fd_t(const FdArgs& a, int64_t n_items, hipStream_t st) {
+  const size_t lds = fd_lds_bytes(a.n_pad, a.n_padk, BF);
   static size_t lds_set = 0;  // dynamic LDS above 64 KB must be allowed explicitly
   if (lds > lds_set) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_rk4_fd,
+    const hipError_t e = hipFuncSetAttribute((const void*)k_rk4_fd<BF>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     lds_set = lds;
   }
   const int nw = (a.n_pad / 16 + 1) / 2;
-  hipLaunchKernelGGL(k_rk4_fd, dim3((unsigned)n_items), dim3((unsigned)(nw * 64)), lds, st, a);
+  hipLaunchKernelGGL(k_rk4_fd<BF>, dim3((unsigned)n_items), dim3((unsigned)(nw * 64)), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk4_fd(const FdArgs& a, int64_t n_items, hipStream_t st) {
+  return a.ap16 ? launch_rk4_fd_t<true>(a, n_items, st) : launch_rk4_fd_t<false>(a, n_items, st);
+}
+
+hipError_t launch_pack_fd_y16(const double* canon, int n, int n_pad, int n_padk, void* ap16,
+                              hipStream_t st) {
+  const int64_t total = (int64_t)(n_pad / 16) * (n_padk / 32) * 64;
+  hipLaunchKernelGGL(k_pack_fd_y16, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, canon,
+                     n, n_pad, n_padk, (u32x4*)ap16);
   return hipGetLastError();
 }
 

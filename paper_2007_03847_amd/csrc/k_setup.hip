@@ -3,6 +3,8 @@
 // cross-sample merge of the per-group statistics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fmc_internal.hpp"
 
 namespace fmc {
@@ -136,9 +138,101 @@ __global__ void __launch_bounds__(256) k_kron(NetDev net, double2* __restrict__ 
   if (tid == 0) *status = s_bad;
 }
 
+// ---------------------------------------------------------------------------
+// Large networks (the augmented system does not fit LDS): Kron's node
+// elimination on the full admittance matrix of the buses and the generator
+// internal nodes (W = n_bus + n_gen, buses first), one launch per eliminated
+// bus k:  Y_ij -= Y_ik Y_kj / Y_kk  for all remaining i, j.  After the last bus
+// the generator block is Y_red.  The buses are eliminated in index order
+// without pivoting: the bus block of a network admittance matrix whose series
+// branches share one R/X ratio and whose shunts are loads and transient
+// reactances is diagonally dominant.  A zero pivot sets the status.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_kron_assemble(NetDev net, double2* __restrict__ A,
+                                                       int* status) {
+  const int nb = net.n_bus, ng = net.n_gen, W = nb + ng;
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0) *status = 0;  // the elimination steps only ever set -1
+  if (r >= W) return;
+  double2* row = A + (int64_t)r * W;  // zeroed before the launch
+  if (r >= nb) {
+    const int g = r - nb;
+    const double2 yg = make_double2(0.0, -1.0 / net.xdp[g]);  // 1/(j X'd)
+    row[r] = yg;
+    row[net.gen_bus[g]] = make_double2(-yg.x, -yg.y);
+    return;
+  }
+  for (int k = 0; k < net.n_branch; ++k) {
+    const int f = net.from[k], t = net.to[k];
+    if (f != r && t != r) continue;
+    const double2 y = cdiv(make_double2(1.0, 0.0), make_double2(net.r[k], net.x[k]));
+    const double2 sh = make_double2(0.0, net.b ? 0.5 * net.b[k] : 0.0);
+    row[r] = cadd(row[r], cadd(y, sh));
+    const int o = (f == r) ? t : f;
+    row[o] = csub(row[o], y);
+  }
+  row[r] = cadd(row[r], make_double2(net.lg ? net.lg[r] : 0.0, net.lb ? net.lb[r] : 0.0));
+  for (int g = 0; g < ng; ++g) {
+    if (net.gen_bus[g] != r) continue;
+    const double2 yg = make_double2(0.0, -1.0 / net.xdp[g]);
+    row[r] = cadd(row[r], yg);
+    row[nb + g] = csub(row[nb + g], yg);
+  }
+}
+
+// One elimination step: block (64, 4) covers 64 columns; row k scaled by
+// 1/Y_kk is formed once per block in LDS.
+__global__ void __launch_bounds__(256) k_kron_elim(double2* __restrict__ A, int W, int k,
+                                                   int* status) {
+  __shared__ double2 sk[64];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int j = k + 1 + blockIdx.x * 64 + tx;
+  const double2 akk = A[(int64_t)k * W + k];
+  if (!(akk.x != 0.0 || akk.y != 0.0)) {  // uniform
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tx == 0 && ty == 0) *status = -1;
+    return;
+  }
+  if (ty == 0) sk[tx] = j < W ? cdiv(A[(int64_t)k * W + j], akk) : make_double2(0.0, 0.0);
+  __syncthreads();
+  if (j >= W) return;
+  const double2 s = sk[tx];
+  for (int i = k + 1 + blockIdx.y * 4 + ty; i < W; i += gridDim.y * 4) {
+    double2* a = A + (int64_t)i * W;
+    a[j] = csub(a[j], cmul(a[k], s));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_kron_extract(const double2* __restrict__ A, int nb, int ng,
+                                                      double2* __restrict__ Yred) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= ng * ng) return;
+  const int W = nb + ng, i = q / ng, k = q % ng;
+  Yred[q] = A[(int64_t)(nb + i) * W + nb + k];
+}
+
+size_t kron_work_bytes(int n_bus, int n_gen) {
+  const size_t W = (size_t)n_bus + n_gen;
+  return W * W * sizeof(double2);
+}
+
 hipError_t launch_kron(const NetDev& net, double2* work, double2* Yred, int* status,
                        hipStream_t st) {
-  hipLaunchKernelGGL(k_kron, dim3(1), dim3(256), 0, st, net, work, Yred, status);
+  const int nb = net.n_bus, ng = net.n_gen, W = nb + ng;
+  if ((int64_t)nb * W <= kKronLdsComplex) {
+    hipLaunchKernelGGL(k_kron, dim3(1), dim3(256), 0, st, net, work, Yred, status);
+    return hipGetLastError();
+  }
+  hipError_t e = launch_fill_i64((int64_t*)work, 0, (int64_t)W * W * 2, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_kron_assemble, dim3((unsigned)((W + 255) / 256)), dim3(256), 0, st, net, work,
+                     status);
+  for (int k = 0; k < nb; ++k) {
+    const int m = W - k - 1;
+    const unsigned gx = (unsigned)((m + 63) / 64), gy = (unsigned)std::min(64, (m + 3) / 4);
+    hipLaunchKernelGGL(k_kron_elim, dim3(gx, gy), dim3(64, 4), 0, st, work, W, k, status);
+  }
+  hipLaunchKernelGGL(k_kron_extract, dim3((unsigned)((ng * ng + 255) / 256)), dim3(256), 0, st,
+                     work, nb, ng, Yred);
   return hipGetLastError();
 }
 

@@ -100,8 +100,10 @@ def test_kle_paths(ctx, P, K, N, S, prec, tol):
 
 
 # --------------------------------------------------------------- Kron
-@pytest.mark.parametrize("n_gen,seed", [(10, 39), (3, 7), (50, 11), (1, 2)])
+@pytest.mark.parametrize("n_gen,seed", [(10, 39), (3, 7), (50, 11), (1, 2), (200, 200)])
 def test_kron(ctx, n_gen, seed):
+    """Small networks reduce in LDS on one workgroup, large ones (50 and 200
+    machines: 195 and 780 buses) by node elimination over many workgroups."""
     net = workloads.network(n_gen, seed)
     Y = ctx.kron_reduce(net)
     ref = oracle.kron(net)
