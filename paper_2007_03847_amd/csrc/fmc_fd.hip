@@ -100,15 +100,18 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
   // same bits here and in the served form
   FdPlan pl{};
   fd_plan(N, kFdItems, &pl);
-  const int64_t Sc = par->time_chunk > 0 ? std::min<int64_t>(par->time_chunk, S)
-                                         : std::min<int64_t>(S, auto_chunk(S, P, N, 4));
+  // chunk: the paths of about 96 MB, and at most about 2 GB of per-tile rows
+  const int64_t rows_cap = std::max<int64_t>(8, ((int64_t)1 << 31) / (pl.tiles * V * 16) - 1);
+  const int64_t Sc = par->time_chunk > 0
+                         ? std::min<int64_t>(par->time_chunk, S)
+                         : std::min<int64_t>({S, auto_chunk(S, P, N, 4), rows_cap});
   void *w = nullptr, *state = nullptr, *xstate = nullptr, *rows = nullptr, *cnt = nullptr;
   if ((rc = c->ensure("w", (size_t)(2 * Sc + 1) * P * N * 4, &w))) return rc;
   // state: [tiles][waves][6 states x 8 machines][64 lanes], waves = ceil(NB/2)
   const int NW = (NB + 1) / 2;
   if ((rc = c->ensure("fd_state", (size_t)pl.tiles * NW * 48 * 64 * 4, &state))) return rc;
   if ((rc = c->ensure("fd_xstate", (size_t)pl.tiles * kFdMaxProc * 16 * 4, &xstate))) return rc;
-  if ((rc = c->ensure("fd_rows", (size_t)pl.n_items * (Sc + 1) * V * 16, &rows))) return rc;
+  if ((rc = c->ensure("fd_rows", (size_t)pl.tiles * (Sc + 1) * V * 16, &rows))) return rc;
   if ((rc = c->ensure("counters", 64, &cnt))) return rc;
   HIPCHK(launch_fill_i64((int64_t*)cnt, 0, 1, c->stream));
   HIPCHK(launch_fill_i64((int64_t*)cnt + 1, LLONG_MAX, 1, c->stream));
@@ -190,9 +193,8 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
     // rows completed by this chunk: s0+1..s1 (and row 0 in the first chunk)
     const int64_t first = s0 == 0 ? 0 : s0 + 1;
     HIPCHK(launch_stats_merge_rows((const double2*)rows + (first - s0) * V, (Sc + 1) * V,
-                                   pl.n_items, (int)(pl.tiles_per_item * 16), N, s1 - first + 1, V,
-                                   6 * n, par->ddof, a.off, mean_d + first * V, var_d + first * V,
-                                   c->stream));
+                                   pl.tiles, 16, N, s1 - first + 1, V, 6 * n, par->ddof, a.off,
+                                   mean_d + first * V, var_d + first * V, c->stream));
     if (out->report) {
       // per-chunk timing (the events are reused, so wait for them here)
       HIPCHK(hipEventSynchronize(e2));

@@ -80,13 +80,16 @@ struct IntegArgs {
 hipError_t launch_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int32_t* strata,
                       double* zeta, hipStream_t st);
 hipError_t launch_basis(int32_t kind, int32_t K, int64_t S, double T, double* phi, hipStream_t st);
+// max_blocks > 0 caps the workgroups (they then stride over the tiles).
 hipError_t launch_kle_f64(const double* zeta, const double* phi, int64_t phi_ld, int P, int K,
-                          int64_t N, int64_t C, int64_t c0, double* w, hipStream_t st);
+                          int64_t N, int64_t C, int64_t c0, double* w, hipStream_t st,
+                          int max_blocks = 0);
 hipError_t launch_kle_f64_to_f32(const double* zeta, const double* phi, int64_t phi_ld, int P,
                                  int K, int64_t N, int64_t C, int64_t c0, float* w,
-                                 hipStream_t st);
+                                 hipStream_t st, int max_blocks = 0);
 hipError_t launch_kle_bf16x3(const double* zeta, const double* phi, int64_t phi_ld, int P, int K,
-                             int64_t N, int64_t C, int64_t c0, float* w, hipStream_t st);
+                             int64_t N, int64_t C, int64_t c0, float* w, hipStream_t st,
+                             int max_blocks = 0);
 
 // Network reduction: device network arrays -> Y_red as (re, im) pairs [n_gen^2].
 struct NetDev {
@@ -219,8 +222,8 @@ struct FdArgs {
   double* traj;               // [n_traj][S+1][V]
   unsigned long long* nonfinite;
   long long* first_bad;
-  double2* rows;              // statistics rows [n_items][row_stride]
-  int64_t row_stride;         // elements between items' rows
+  double2* rows;              // statistics rows [tiles][row_stride] (mean, M2 per tile)
+  int64_t row_stride;         // elements between tiles' rows ((chunk + 1) * V)
   int64_t row_base;           // step held by the first row
   int n, P, V, n_pad;
   int64_t N, S, s_begin, s_end, c_base;

@@ -119,7 +119,8 @@ std::vector<size_t> parts_of(const Request& r) {
     z[B_COEF] = (size_t)PackLayout{r.bv.NG, r.bv.PM}.size() * 4;
     z[B_STATE] = (size_t)(2 * G + PQ) * r.tiles * 64 * 4 * 4;  // rows x lanes (4 waves per tile)
   }
-  z[B_PART] = (size_t)r.n_items * (r.Sc + 1) * r.V * 16;  // statistics rows of one chunk
+  // statistics rows of one chunk: per work item (classical), per tile (flux decay)
+  z[B_PART] = (size_t)(r.fd ? r.tiles : r.n_items) * (r.Sc + 1) * r.V * 16;
   z[B_MEAN] = z[B_VAR] = (size_t)(r.S + 1) * r.V * 8;
   z[B_WORK] = (size_t)(3 * r.n * r.n + 8 * r.n + 64) * 8;
   z[B_YBUF] = r.has_Y ? 0 : (size_t)r.n * r.n * 16;
@@ -505,10 +506,11 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
     // values of the flux-decay states
     const double* offs = r.fd ? r.fdblk + FdLayout{r.n}.off() : r.canon + CanonLayout{r.n, r.P}.delta0();
     const int n_off = r.fd ? 6 * r.n : r.n;
-    const int tile = (int)(r.tiles_per_item * (r.fd ? 16 : r.bv.TB));
-    SCHK(launch_stats_merge_rows(r.part + (first - r.s_prev) * r.V, (r.Sc + 1) * r.V, r.n_items,
-                                 tile, r.N, rows, r.V, n_off, r.par.ddof, offs,
-                                 r.mean + first * r.V, r.var + first * r.V, st));
+    const int64_t groups = r.fd ? r.tiles : r.n_items;
+    const int group = r.fd ? 16 : (int)(r.tiles_per_item * r.bv.TB);
+    SCHK(launch_stats_merge_rows(r.part + (first - r.s_prev) * r.V, (r.Sc + 1) * r.V, groups, group,
+                                 r.N, rows, r.V, n_off, r.par.ddof, offs, r.mean + first * r.V,
+                                 r.var + first * r.V, st));
   }
   for (auto& rp : finishing) {
     Request& r = *rp;

@@ -198,22 +198,14 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
-// Mean and M2 of a row's 16 values (invalid lanes excluded), Chan-merged into
-// the statistics row by the row's first lane.
+// Mean and M2 of a row's 16 values (invalid lanes excluded), stored by the
+// row's first lane: every tile has rows of its own, so nothing is read back.
 __device__ __forceinline__ void row_stats(double x, bool valid, double cnt, bool writer,
-                                          double2* dst, double prev) {
+                                          double2* dst) {
   const double mu = row16_sum(valid ? x : 0.0) / cnt;
   const double d = valid ? x - mu : 0.0;
   const double m2 = row16_sum(d * d);
-  if (writer) {
-    if (prev == 0.0) {
-      *dst = make_double2(mu, m2);
-    } else {
-      const double2 old = *dst;
-      const double tot = prev + cnt, dl = mu - old.x;
-      *dst = make_double2(old.x + dl * (cnt / tot), old.y + m2 + dl * dl * (prev * cnt / tot));
-    }
-  }
+  if (writer) *dst = make_double2(mu, m2);
 }
 
 }  // namespace
@@ -270,7 +262,6 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
   const float th = proc ? cst[K.proc() + pg] : 0.0f;
   const float sg = proc ? cst[K.proc() + kFdMaxProc + pg] : 0.0f;
   const int64_t colstride = (int64_t)P * a.N;
-  double2* rows = a.rows + (int64_t)item * a.row_stride;
   const float2* apw = a.ap + (int64_t)(2 * wv) * KH * 64 + l;
   const float* B0 = bs + (l >> 4) * kT + (l & 15);
   const u32x4* aq = reinterpret_cast<const u32x4*>(a.ap16) + ((int64_t)(2 * wv) * KS16 * 64 + l) * 4;
@@ -283,7 +274,7 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
     const int64_t ns = valid ? traj : a.N - 1;
     const int64_t rem = a.N - tile * kT;
     const double cnt = (double)(rem < kT ? rem : kT);
-    const double prev = (double)((tile - tile0) * kT);
+    double2* rows = a.rows + tile * a.row_stride;  // this tile's statistics rows
     const int slot = (valid && a.traj_slot) ? a.traj_slot[ns] : -1;
     // state: deviations of (delta, dw, E'q, Efd, VR, RF) of my machines; xi
     float y[6][kQ], x = 0.0f;
@@ -320,13 +311,13 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
         if (m < nl) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) {
-            row_stats((double)y[c][q], valid, cnt, t == 0, row + c * nl + m, prev);
+            row_stats((double)y[c][q], valid, cnt, t == 0, row + c * nl + m);
             if (o) o[c * nl + m] = offl[c * nl + m] + (double)y[c][q];
           }
         }
       }
       if (proc) {
-        row_stats((double)x, valid, cnt, t == 0, row + 6 * n + pg, prev);
+        row_stats((double)x, valid, cnt, t == 0, row + 6 * n + pg);
         if (o) o[6 * n + pg] = (double)x;
       }
     };

@@ -2,6 +2,8 @@
 // contraction (MFMA) for gfx950.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fmc_device.hpp"
 #include "fmc_internal.hpp"
 
@@ -98,14 +100,13 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
 template <typename OutT>
-__global__ void __launch_bounds__(256) k_kle_f64(const double* __restrict__ zeta,
-                                                 const double* __restrict__ phi, int64_t phi_ld,
-                                                 int P, int K, int64_t N, int64_t C, int64_t c0,
-                                                 OutT* __restrict__ w) {
+__device__ __forceinline__ void kle_f64_tile(const double* __restrict__ zeta,
+                                             const double* __restrict__ phi, int64_t phi_ld,
+                                             int P, int K, int64_t N, int64_t C, int64_t c0,
+                                             OutT* __restrict__ w, int64_t bx, int64_t by, int p) {
   const int lane = threadIdx.x & 63;
-  const int64_t cb = ((int64_t)blockIdx.y * 4 + (threadIdx.x >> 6)) * 16;
-  const int64_t n0 = (int64_t)blockIdx.x * 64;
-  const int p = blockIdx.z;
+  const int64_t cb = (by * 4 + (threadIdx.x >> 6)) * 16;
+  const int64_t n0 = bx * 64;
   if (cb >= C) return;  // uniform per wave
   const int li = lane & 15, lk = lane >> 4;
   const double* __restrict__ zp = zeta + (int64_t)p * K * N;
@@ -136,26 +137,40 @@ __global__ void __launch_bounds__(256) k_kle_f64(const double* __restrict__ zeta
   }
 }
 
+// The grid is a flat list of blocks striding over the (n, c, p) tiles, so a
+// launch can use fewer workgroups than tiles (to run beside another kernel).
+template <typename OutT>
+__global__ void __launch_bounds__(256) k_kle_f64(const double* __restrict__ zeta,
+                                                 const double* __restrict__ phi, int64_t phi_ld,
+                                                 int P, int K, int64_t N, int64_t C, int64_t c0,
+                                                 OutT* __restrict__ w) {
+  const int64_t tx = (N + 63) / 64, ty = (C + 63) / 64, n_tiles = tx * ty * P;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
+    kle_f64_tile<OutT>(zeta, phi, phi_ld, P, K, N, C, c0, w, tile % tx, (tile / tx) % ty,
+                       (int)(tile / (tx * ty)));
+}
 template <typename OutT>
 static hipError_t launch_kle_f64_t(const double* zeta, const double* phi, int64_t phi_ld, int P,
                                    int K, int64_t N, int64_t C, int64_t c0, OutT* w,
-                                   hipStream_t st) {
+                                   hipStream_t st, int max_blocks) {
   if (C <= 0 || N <= 0 || P <= 0) return hipSuccess;
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((C + 63) / 64), (unsigned)P);
-  hipLaunchKernelGGL(k_kle_f64<OutT>, grid, dim3(256), 0, st, zeta, phi, phi_ld, P, K, N, C, c0,
-                     w);
+  int64_t tiles = ((N + 63) / 64) * ((C + 63) / 64) * P;
+  if (max_blocks > 0) tiles = std::min<int64_t>(tiles, max_blocks);
+  hipLaunchKernelGGL(k_kle_f64<OutT>, dim3((unsigned)tiles), dim3(256), 0, st, zeta, phi, phi_ld, P,
+                     K, N, C, c0, w);
   return hipGetLastError();
 }
 
 hipError_t launch_kle_f64(const double* zeta, const double* phi, int64_t phi_ld, int P, int K,
-                          int64_t N, int64_t C, int64_t c0, double* w, hipStream_t st) {
-  return launch_kle_f64_t<double>(zeta, phi, phi_ld, P, K, N, C, c0, w, st);
+                          int64_t N, int64_t C, int64_t c0, double* w, hipStream_t st,
+                          int max_blocks) {
+  return launch_kle_f64_t<double>(zeta, phi, phi_ld, P, K, N, C, c0, w, st, max_blocks);
 }
 
 hipError_t launch_kle_f64_to_f32(const double* zeta, const double* phi, int64_t phi_ld, int P,
                                  int K, int64_t N, int64_t C, int64_t c0, float* w,
-                                 hipStream_t st) {
-  return launch_kle_f64_t<float>(zeta, phi, phi_ld, P, K, N, C, c0, w, st);
+                                 hipStream_t st, int max_blocks) {
+  return launch_kle_f64_t<float>(zeta, phi, phi_ld, P, K, N, C, c0, w, st, max_blocks);
 }
 
 // ---------------------------------------------------------------------------
@@ -171,16 +186,15 @@ __device__ __forceinline__ void split_bf16(double x, __bf16& hi, __bf16& lo) {
   lo = (__bf16)(xf - (float)hi);
 }
 
-__global__ void __launch_bounds__(256) k_kle_bf16x3(const double* __restrict__ zeta,
-                                                    const double* __restrict__ phi,
-                                                    int64_t phi_ld, int P, int K, int64_t N,
-                                                    int64_t C, int64_t c0,
-                                                    float* __restrict__ w) {
+__device__ __forceinline__ void kle_bf16x3_tile(const double* __restrict__ zeta,
+                                                const double* __restrict__ phi, int64_t phi_ld,
+                                                int P, int K, int64_t N, int64_t C, int64_t c0,
+                                                float* __restrict__ w, int64_t bx, int64_t by,
+                                                int p) {
   const int lane = threadIdx.x & 63;
-  const int64_t cb = ((int64_t)blockIdx.y * 4 + (threadIdx.x >> 6)) * 16;
-  const int64_t n0 = (int64_t)blockIdx.x * 64;
-  const int p = blockIdx.z;
-  if (cb >= C) return;
+  const int64_t cb = (by * 4 + (threadIdx.x >> 6)) * 16;
+  const int64_t n0 = bx * 64;
+  if (cb >= C) return;  // uniform per wave
   const int li = lane & 15, lk = lane >> 4;
   const double* __restrict__ zp = zeta + (int64_t)p * K * N;
   f4_t acc[4];
@@ -228,11 +242,25 @@ __global__ void __launch_bounds__(256) k_kle_bf16x3(const double* __restrict__ z
   }
 }
 
+__global__ void __launch_bounds__(256) k_kle_bf16x3(const double* __restrict__ zeta,
+                                                    const double* __restrict__ phi,
+                                                    int64_t phi_ld, int P, int K, int64_t N,
+                                                    int64_t C, int64_t c0,
+                                                    float* __restrict__ w) {
+  const int64_t tx = (N + 63) / 64, ty = (C + 63) / 64, n_tiles = tx * ty * P;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
+    kle_bf16x3_tile(zeta, phi, phi_ld, P, K, N, C, c0, w, tile % tx, (tile / tx) % ty,
+                    (int)(tile / (tx * ty)));
+}
+
 hipError_t launch_kle_bf16x3(const double* zeta, const double* phi, int64_t phi_ld, int P, int K,
-                             int64_t N, int64_t C, int64_t c0, float* w, hipStream_t st) {
+                             int64_t N, int64_t C, int64_t c0, float* w, hipStream_t st,
+                             int max_blocks) {
   if (C <= 0 || N <= 0 || P <= 0) return hipSuccess;
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)((C + 63) / 64), (unsigned)P);
-  hipLaunchKernelGGL(k_kle_bf16x3, grid, dim3(256), 0, st, zeta, phi, phi_ld, P, K, N, C, c0, w);
+  int64_t tiles = ((N + 63) / 64) * ((C + 63) / 64) * P;
+  if (max_blocks > 0) tiles = std::min<int64_t>(tiles, max_blocks);
+  hipLaunchKernelGGL(k_kle_bf16x3, dim3((unsigned)tiles), dim3(256), 0, st, zeta, phi, phi_ld, P,
+                     K, N, C, c0, w);
   return hipGetLastError();
 }
 
