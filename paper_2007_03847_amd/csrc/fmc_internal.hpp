@@ -193,15 +193,21 @@ struct FdLayout {
 };
 
 // FP32 constants of the flux-decay integrator, machine-major [n_pad][kStride]
-// (a machine's fields are immediate offsets from one address; the odd stride
-// spreads the four machines a wave reads at once over distinct LDS banks),
-// then the process block theta, sigma, xi0, machine index [4][kFdMaxProc].
+// in six groups of four fields read together (one 16-byte LDS read each); the
+// stride of 28 floats keeps rows 16-byte aligned and puts the four machines a
+// wave reads at once on distinct LDS banks.  Then the process block theta,
+// sigma, xi0, machine index [4][kFdMaxProc].
 struct FdPack {
   enum Field {
-    C0, S0, U0R, U0I, I0R, I0I, J0R, J0I, VT0R, VT0I, VT0A, RES, DMP, INV2H, XDP, XDD_T, ITDO,
-    KE_TE, ITE, ITF, KF_TF2, KA_TA, ITA, KAKF, NFIELD
+    C0, S0, U0R, U0I,        // E~0 and e^{j delta0}
+    I0R, I0I, J0R, J0I,      // I0 and I0 e^{-j delta0}
+    XDP, VT0R, VT0I, VT0A,   // X'd, Vt0 and |Vt0|
+    RES, DMP, INV2H, ITDO,   // Pm - Pe0, D, 1/(2H), 1/T'do
+    XDD_T, KE_TE, ITE, ITF,  // (Xd - X'd)/T'do, KE/TE, 1/TE, 1/TF
+    KF_TF2, KA_TA, ITA, KAKF,  // KF/TF^2, KA/TA, 1/TA, KA KF/(TF TA)
+    NFIELD
   };
-  static constexpr int kStride = 25;
+  static constexpr int kStride = 28;
   int n_pad;
   __host__ __device__ int at(int m, int f) const { return m * kStride + f; }
   __host__ __device__ int proc() const { return n_pad * kStride; }
@@ -234,7 +240,8 @@ hipError_t launch_setup_fd(const double* canon, int n, int P, const double* E, c
                            double* fd, hipStream_t st);
 hipError_t launch_pack_fd(const double* canon, int n, int P, const double* prm, const double* fd,
                           const int32_t* gen, int n_pad, float* coef, float2* ap, hipStream_t st);
-size_t fd_lds_bytes(int n_pad, int n_padk, bool bf16);
+size_t fd_lds_bytes(int n_pad, int n_padk, bool bf16, int P);
+constexpr size_t kFdMaxLds = 160 * 1024;  // LDS of a gfx950 CU
 hipError_t launch_rk4_fd(const FdArgs& a, int64_t n_items, hipStream_t st);
 hipError_t launch_pack_fd_y16(const double* canon, int n, int n_pad, int n_padk, void* ap16,
                               hipStream_t st);

@@ -273,6 +273,10 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
     if (dist->n_proc > std::min(kFdMaxProc, 4 * nw))
       return fail(FMC_EINVAL, "too many disturbance processes for the flux-decay model (at most "
                               "min(32, 4 ceil(ceil(n/16)/2)))");
+    const int n_pad = 16 * ((n + 15) / 16), n_padk = 32 * ((n + 31) / 32);
+    if (fd_lds_bytes(n_pad, n_padk, par->precision == FMC_BF16X3, dist->n_proc) > kFdMaxLds)
+      return fail(FMC_EINVAL, "flux-decay system too large for one workgroup's LDS (reduce the "
+                              "machines or the processes)");
     for (int i = 0; i < n; ++i) {
       const double* q = sys->model_params + (int64_t)i * kFdParams;
       for (int k = 0; k < kFdParams; ++k)

@@ -189,12 +189,38 @@ __global__ void __launch_bounds__(256) k_pack_fd_y16(const double* __restrict__ 
   ap[4 * q + 3] = __builtin_bit_cast(u32x4, il);
 }
 
-// Sum over the 16 lanes of a row (lanes l with equal l/16).
+// Sum over the 16 lanes of a row (lanes l with equal l/16) with DPP moves:
+// pairs (quad_perm 1,0,3,2), quads (quad_perm 2,3,0,1), half rows
+// (row_half_mirror), rows (row_mirror).  Every step adds two values in both
+// orders, so all 16 lanes end with the same bits.
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_id) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  switch (ctrl_id) {
+    case 0:
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
+      break;
+    case 1:
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
+      break;
+    case 2:
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
+      break;
+    default:
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false);
+      break;
+  }
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double row16_sum(double v) {
-  v += __shfl_xor(v, 8, 16);
-  v += __shfl_xor(v, 4, 16);
-  v += __shfl_xor(v, 2, 16);
-  v += __shfl_xor(v, 1, 16);
+  v += dpp_f64(v, 0);
+  v += dpp_f64(v, 1);
+  v += dpp_f64(v, 2);
+  v += dpp_f64(v, 3);
   return v;
 }
 
@@ -235,16 +261,16 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
   const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63, g = l >> 4, t = l & 15;
   const bool two = 2 * wv + 1 < NB;  // wave-uniform: the second block exists
   const FdPack K{n_pad};
-  // LDS: constants + process block, the dE' tile [2 n_pad][16], xi stage
-  // values (2 buffers of [kFdMaxProc][16]), flags [16], then the RK4 sums of
-  // every lane [NW][6 kQ][64] (kept here rather than in registers)
+  // LDS: constants + process block, the dE' tile, xi stage values (2 buffers
+  // of [P][16]), flags [16], then the RK4 sums of every lane [NW][6 kQ][64]
+  // (kept here rather than in registers)
   float* cst = reinterpret_cast<float*>(smem);
   unsigned char* btile = smem + (size_t)K.size() * 4;
   float* bs = reinterpret_cast<float*>(btile);          // FP32 product: [2 n_pad][16]
   __bf16* bh = reinterpret_cast<__bf16*>(btile);        // BF16 product: hi plane
   __bf16* bl = bh + 16 * BS;                            //               lo plane
   float* xs = reinterpret_cast<float*>(btile + fd_btile_bytes(n_pad, n_padk, BF));
-  int* bad_t = reinterpret_cast<int*>(xs + 2 * kFdMaxProc * kT);
+  int* bad_t = reinterpret_cast<int*>(xs + 2 * P * kT);
   float* accl = reinterpret_cast<float*>(bad_t + kT) + (int64_t)wv * 6 * kQ * 64 + l;
   for (int q = tid; q < K.size(); q += blockDim.x) cst[q] = a.coef[q];
   // the tile's padding rows (machines n_pad..n_padk) are never written: zero
@@ -344,7 +370,7 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
         const float hn = st < 2 ? h2 : dt;
         const float wst = st == 0 ? w0 : (st == 3 ? w2 : w1);
         float* Bw = bs;
-        float* X = xs + buf * (kFdMaxProc * kT);
+        float* X = xs + buf * (P * kT);
         // -- before the product: EMF deviations, the derivatives that do not
         //    need the network current, and the parts of those that do
         float omc[kQ], sd[kQ], dEr[kQ], dEi[kQ], pw[kQ], pe[kQ], pv[kQ];
@@ -354,13 +380,13 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
           const int m = mach(q);
           int mo = K.at(m, 0), bo = m * kT + t;
           asm volatile("" : "+v"(mo), "+v"(bo));  // recompute, do not keep live
-          const float* cm = cst + mo;
+          const float4* cm = reinterpret_cast<const float4*>(cst + mo);
+          const float4 g0 = cm[0], g3 = cm[3], g4 = cm[4], g5 = cm[5];
           float sh, ch;
           sincos_r(0.5f * ys[0][q], sh, ch);
           sd[q] = 2.0f * sh * ch;   // sin d
           omc[q] = 2.0f * sh * sh;  // 1 - cos d
-          const float c0 = cm[FdPack::C0], s0 = cm[FdPack::S0];
-          const float ur = cm[FdPack::U0R], ui = cm[FdPack::U0I];
+          const float c0 = g0.x, s0 = g0.y, ur = g0.z, ui = g0.w;
           const float de = ys[2][q];
           // dE' = E~0 (e^{jd} - 1) + dE'q e^{j delta}
           dEr[q] = -c0 * omc[q] - s0 * sd[q] + de * (ur * (1.0f - omc[q]) - ui * sd[q]);
@@ -379,13 +405,14 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
             Bw[bo] = m < n ? dEr[q] : 0.0f;
             Bw[bo + n_pad * kT] = m < n ? dEi[q] : 0.0f;
           }
+          // g3 = (RES, DMP, INV2H, ITDO), g4 = (XDD_T, KE_TE, ITE, ITF),
+          // g5 = (KF_TF2, KA_TA, ITA, KAKF)
           const float kd = wb * ys[1][q];
-          const float kf = -cm[FdPack::KE_TE] * ys[3][q] + cm[FdPack::ITE] * ys[4][q];
-          const float kr = -cm[FdPack::ITF] * ys[5][q] + cm[FdPack::KF_TF2] * ys[3][q];
-          pw[q] = cm[FdPack::RES] - cm[FdPack::DMP] * ys[1][q];
-          pe[q] = (ys[3][q] - ys[2][q]) * cm[FdPack::ITDO];
-          pv[q] = -cm[FdPack::ITA] * ys[4][q] + cm[FdPack::KA_TA] * ys[5][q] -
-                  cm[FdPack::KAKF] * ys[3][q];
+          const float kf = -g4.y * ys[3][q] + g4.z * ys[4][q];
+          const float kr = -g4.w * ys[5][q] + g5.x * ys[3][q];
+          pw[q] = g3.x - g3.y * ys[1][q];
+          pe[q] = (ys[3][q] - ys[2][q]) * g3.w;
+          pv[q] = -g5.z * ys[4][q] + g5.y * ys[5][q] - g5.w * ys[3][q];
           accl[(0 * kQ + q) * 64] = st == 0 ? kd : accl[(0 * kQ + q) * 64] + wgt * kd;
           accl[(3 * kQ + q) * 64] = st == 0 ? kf : accl[(3 * kQ + q) * 64] + wgt * kf;
           accl[(5 * kQ + q) * 64] = st == 0 ? kr : accl[(5 * kQ + q) * 64] + wgt * kr;
@@ -498,29 +525,27 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
           const int m = mach(q);
           int mo = K.at(m, 0);
           asm volatile("" : "+v"(mo));
-          const float* cm = cst + mo;
+          const float4* cm = reinterpret_cast<const float4*>(cst + mo);
+          const float4 g0 = cm[0], g1 = cm[1], g2 = cm[2], g3 = cm[3], g4 = cm[4], g5 = cm[5];
           const int r = q & 3;
           const float dIr = q < 4 ? ar0[r] : ar1[r], dIi = q < 4 ? ai0[r] : ai1[r];
-          const float c0 = cm[FdPack::C0], s0 = cm[FdPack::S0];
-          const float ur = cm[FdPack::U0R], ui = cm[FdPack::U0I];
-          const float i0r = cm[FdPack::I0R], i0i = cm[FdPack::I0I];
-          const float j0r = cm[FdPack::J0R], j0i = cm[FdPack::J0I];
+          const float c0 = g0.x, s0 = g0.y, ur = g0.z, ui = g0.w;
+          const float i0r = g1.x, i0i = g1.y, j0r = g1.z, j0i = g1.w;
           // dPe = Re(dE' conj I0) + Re(E~' conj dI)
           const float dpe = dEr[q] * i0r + dEi[q] * i0i + (c0 + dEr[q]) * dIr + (s0 + dEi[q]) * dIi;
           // dId = -Im(J0 (e^{-jd} - 1) + dI e^{-j delta0} e^{-jd})
           const float djr = dIr * ur + dIi * ui, dji = dIi * ur - dIr * ui;
           const float did = j0i * omc[q] + j0r * sd[q] - dji * (1.0f - omc[q]) + djr * sd[q];
           // d|Vt| with dVt = dE' - j X'd dI
-          const float xdp = cm[FdPack::XDP];
+          const float xdp = g2.x;
           const float vr_ = dEr[q] + xdp * dIi, vi_ = dEi[q] - xdp * dIr;
-          const float v0r = cm[FdPack::VT0R], v0i = cm[FdPack::VT0I];
+          const float v0r = g2.y, v0i = g2.z;
           const float vr1 = v0r + vr_, vi1 = v0i + vi_;
           const float va = sqrtf(vr1 * vr1 + vi1 * vi1);
-          const float dva = (2.0f * (v0r * vr_ + v0i * vi_) + vr_ * vr_ + vi_ * vi_) /
-                            (va + cm[FdPack::VT0A]);
-          const float kw = (pw[q] - dpe + inj[q]) * cm[FdPack::INV2H];
-          const float ke = pe[q] - cm[FdPack::XDD_T] * did;
-          const float kv = pv[q] - cm[FdPack::KA_TA] * dva;
+          const float dva = (2.0f * (v0r * vr_ + v0i * vi_) + vr_ * vr_ + vi_ * vi_) / (va + g2.w);
+          const float kw = (pw[q] - dpe + inj[q]) * g3.z;
+          const float ke = pe[q] - g4.x * did;
+          const float kv = pv[q] - g5.y * dva;
           accl[(1 * kQ + q) * 64] = st == 0 ? kw : accl[(1 * kQ + q) * 64] + wgt * kw;
           accl[(2 * kQ + q) * 64] = st == 0 ? ke : accl[(2 * kQ + q) * 64] + wgt * ke;
           accl[(4 * kQ + q) * 64] = st == 0 ? kv : accl[(4 * kQ + q) * 64] + wgt * kv;
@@ -590,16 +615,16 @@ hipError_t launch_pack_fd(const double* canon, int n, int P, const double* prm, 
   return hipGetLastError();
 }
 
-size_t fd_lds_bytes(int n_pad, int n_padk, bool bf) {
+size_t fd_lds_bytes(int n_pad, int n_padk, bool bf, int P) {
   const FdPack K{n_pad};
   const int nw = (n_pad / 16 + 1) / 2;
-  return (size_t)K.size() * 4 + fd_btile_bytes(n_pad, n_padk, bf) +
-         (size_t)2 * kFdMaxProc * kT * 4 + kT * 4 + (size_t)nw * 6 * kQ * 64 * 4;
+  return (size_t)K.size() * 4 + fd_btile_bytes(n_pad, n_padk, bf) + (size_t)2 * P * kT * 4 +
+         kT * 4 + (size_t)nw * 6 * kQ * 64 * 4;
 }
 
 template <bool BF>
 static hipError_t launch_rk4_fd_t(const FdArgs& a, int64_t n_items, hipStream_t st) {
-  const size_t lds = fd_lds_bytes(a.n_pad, a.n_padk, BF);
+  const size_t lds = fd_lds_bytes(a.n_pad, a.n_padk, BF, a.P);
   static size_t lds_set = 0;  // dynamic LDS above 64 KB must be allowed explicitly
   if (lds > lds_set) {
     const hipError_t e = hipFuncSetAttribute((const void*)k_rk4_fd<BF>,
