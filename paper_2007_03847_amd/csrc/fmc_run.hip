@@ -41,11 +41,6 @@ struct EventPool {
   }
 };
 
-// Workgroups of a contraction that runs beside the integrator: about one per
-// CU, striding over its tiles, so that it trickles alongside instead of
-// taking every free slot from the integrator.
-constexpr int kOverlapBlocks = 256;
-
 struct ChunkTimes {
   std::vector<int> gemm0, gemm1, int0, int1;
 };
@@ -108,12 +103,11 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
     if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
     ct.gemm0.push_back(evp.record(ks));
     if (par->precision == FMC_F64)
-      e = launch_kle_f64(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (double*)w[b], ks, kOverlapBlocks);
+      e = launch_kle_f64(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (double*)w[b], ks);
     else if (par->precision == FMC_F32)
-      e = launch_kle_f64_to_f32(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w[b], ks,
-                                kOverlapBlocks);
+      e = launch_kle_f64_to_f32(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w[b], ks);
     else
-      e = launch_kle_bf16x3(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w[b], ks, kOverlapBlocks);
+      e = launch_kle_bf16x3(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w[b], ks);
     if (e != hipSuccess) return fail(FMC_EDEVICE, std::string("KLE launch: ") + hipGetErrorString(e));
     ct.gemm1.push_back(evp.record(ks));
     if (hipEventRecord(c->gev[b], ks) != hipSuccess || hipStreamWaitEvent(c->stream, c->gev[b], 0) != hipSuccess)
