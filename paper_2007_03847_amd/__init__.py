@@ -365,14 +365,15 @@ def _outputs_for(ctx, sc, traj_idx, keep):
     return out, dict(mean=mean, var=var, traj=traj, report=rep)
 
 
-def _run_batch(ctx, scs, precision="f32", traj_idx=None, variant=-1, allow_nonfinite=False):
+def _run_batch(ctx, scs, precision="f32", traj_idx=None, variant=-1, allow_nonfinite=False,
+               time_chunk=0):
     keep = _Keep()
     n = len(scs)
     arr = (Scenario * n)()
     outs = (Outputs * n)()
     res = []
     for i, sc in enumerate(scs):
-        sysd, dist, par, _ = scenario_structs(sc, precision, variant, keep=keep)
+        sysd, dist, par, _ = scenario_structs(sc, precision, variant, time_chunk, keep=keep)
         arr[i] = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))
         ti = None if traj_idx is None else traj_idx[i]
         o, r = _outputs_for(ctx, sc, ti, keep)
@@ -390,11 +391,15 @@ def _run_batch(ctx, scs, precision="f32", traj_idx=None, variant=-1, allow_nonfi
 
 
 Context.run_batch = lambda self, scs, precision="f32", traj_idx=None, variant=-1, \
-    allow_nonfinite=False: _run_batch(self, scs, precision, traj_idx, variant, allow_nonfinite)
+    allow_nonfinite=False, time_chunk=0: _run_batch(self, scs, precision, traj_idx, variant,
+                                                    allow_nonfinite, time_chunk)
 Context.run_batch.__doc__ = """Batched form: a list of scenario dicts in one persistent launch.
 
 Returns one dict(mean, var[, traj], report, rc) per scenario.  traj_idx, if
-given, is a list (one entry per scenario, None allowed) of sample indices."""
+given, is a list (one entry per scenario, None allowed) of sample indices;
+time_chunk > 0 sets the steps per tick (else 250).  Variant ids 0-10 are the
+lane variants, 11-13 the FP32 matrix-core variants for up to 32, 48, 64
+machines and 14-16 their BF16 x3 forms (FMC_BF16X3 scenarios only)."""
 
 
 class Ticket:

@@ -62,18 +62,47 @@ struct Plan {
 
 std::string nm(int i, const char* what) { return "b" + std::to_string(i) + "_" + what; }
 
-// Candidates of the batched integrator for (n, P), smallest first.
-std::vector<int> batch_candidates(int n, int P) {
-  std::vector<int> v;
+// Candidates of the batched integrator for (n, P): the three smallest lane
+// variants that fit, then the smallest fitting matrix-core variant of each
+// product form (for n > 16, where the padded product is not mostly zeros).
+std::vector<int> batch_candidates(int n, int P, int precision) {
+  std::vector<int> lane, v;
+  int mc[3] = {-1, -1, -1};
   for (int i = 0; i < n_batch_variants(); ++i) {
     const BatchVariantInfo b = batch_variant(i);
-    if (b.NG >= n && b.PM >= P) v.push_back(i);
+    if (!batch_fits(b, n, P, precision)) continue;
+    if (b.cls < 3) {
+      lane.push_back(i);
+    } else if (n > 16 && (mc[b.prod] < 0 || b.NG < batch_variant(mc[b.prod]).NG)) {
+      mc[b.prod] = i;
+    }
   }
-  std::sort(v.begin(), v.end(), [](int a, int b) { return batch_variant(a).NG < batch_variant(b).NG; });
+  std::stable_sort(lane.begin(), lane.end(),
+                   [](int a, int b) { return batch_variant(a).NG < batch_variant(b).NG; });
+  if (lane.size() > 3) lane.resize(3);
+  v = lane;
+  for (int k = 1; k <= 2; ++k)
+    if (mc[k] >= 0) v.push_back(mc[k]);
   return v;
 }
 
 }  // namespace
+
+bool batch_fits(const BatchVariantInfo& b, int n, int P, int precision) {
+  return b.NG >= n && b.PM >= P && (b.prod != 2 || precision == FMC_BF16X3);
+}
+
+int default_batch_variant(int n, int P, int precision) {
+  int vid = -1;
+  for (int i = 0; i < n_batch_variants(); ++i) {
+    const BatchVariantInfo b = batch_variant(i);
+    if (!batch_fits(b, n, P, precision)) continue;
+    if (vid < 0) { vid = i; continue; }
+    const BatchVariantInfo c = batch_variant(vid);
+    if (b.NG < c.NG || (b.NG == c.NG && b.cls < c.cls)) vid = i;
+  }
+  return vid;
+}
 
 int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_outputs* outs,
                    const int* forced_variant, double* t_out);
@@ -89,9 +118,8 @@ static int batch_pick(Context* c, const fmc_scenario& sc, int* vid) {
     *vid = it->second;
     return FMC_OK;
   }
-  std::vector<int> cand = batch_candidates(n, P);
+  std::vector<int> cand = batch_candidates(n, P, par->precision);
   if (cand.empty()) return fail(FMC_EINVAL, "no batched variant for n=" + std::to_string(n) + ", P=" + std::to_string(P));
-  if (cand.size() > 3) cand.resize(3);
   int best = cand[0];
   if (cand.size() > 1) {
     const int64_t S = (int64_t)std::llround(par->T / par->dt);
@@ -167,7 +195,9 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     }
     if (p.vid < 0 || p.vid >= n_batch_variants()) return fail(FMC_EINVAL, "no batched variant");
     p.bv = batch_variant(p.vid);
-    if (p.bv.NG < p.n || p.bv.PM < p.P) return fail(FMC_EINVAL, "batched variant too small for the scenario");
+    if (!batch_fits(p.bv, p.n, p.P, p.par->precision))
+      return fail(FMC_EINVAL, "batched variant does not fit the scenario (size, or a BF16 x3 "
+                              "product for an FMC_F32 scenario)");
     p.tiles = (p.N + p.bv.TB - 1) / p.bv.TB;
     p.cost_tile = (double)p.S * p.bv.TB * (8.0 * p.bv.NG * p.bv.NG + 45.0 * p.bv.NG + 4.0 * p.P);
     char buf[256];
@@ -219,11 +249,9 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     Plan& p = plans[i];
     void* q = nullptr;
     const CanonLayout CL{p.n, p.P};
-    const PackLayout PL{p.bv.NG, p.bv.PM};
-    const int G = (p.bv.NG + p.bv.L - 1) / p.bv.L, PQ = (p.bv.PM + p.bv.L - 1) / p.bv.L;
     if ((rc = c->ensure(nm(i, "canon").c_str(), (size_t)CL.size() * 8, &q))) return rc;
     p.canon = (double*)q;
-    if ((rc = c->ensure(nm(i, "coef").c_str(), (size_t)PL.size() * 4, &q))) return rc;
+    if ((rc = c->ensure(nm(i, "coef").c_str(), batch_coef_floats(p.bv) * 4, &q))) return rc;
     p.coef = (float*)q;
     if ((rc = c->ensure(nm(i, "phi").c_str(), (size_t)p.K * p.C * 8, &q))) return rc;
     p.phi = (double*)q;
@@ -238,7 +266,7 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     if ((rc = c->ensure(nm(i, "w").c_str(), (size_t)(2 * p.Sc + 1) * p.P * p.N * 4, &q))) return rc;
     p.w = (float*)q;
     p.lanes = p.tiles * 64 * 4;
-    if ((rc = c->ensure(nm(i, "state").c_str(), (size_t)(2 * G + PQ) * p.lanes * 4, &q))) return rc;
+    if ((rc = c->ensure(nm(i, "state").c_str(), batch_state_floats(p.bv, p.tiles) * 4, &q))) return rc;
     p.state = (float*)q;
     if ((rc = c->ensure(nm(i, "part").c_str(), (size_t)p.n_items * (p.Sc + 1) * p.V * 16, &q))) return rc;
     p.part = (double2*)q;
@@ -407,7 +435,7 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
         p.sd.Y = p.ybuf;
       }
       HIPCHK(launch_setup(p.sd, st));
-      HIPCHK(launch_pack<float>(p.canon, p.n, p.P, p.gen_d, p.bv.NG, p.bv.PM, p.coef, st));
+      HIPCHK(launch_pack_batch(p.bv, p.canon, p.n, p.P, p.gen_d, p.coef, st));
       HIPCHK(launch_basis(p.par->basis, p.K, p.S, p.par->T, p.phi, st));
       if (!p.par->zeta_in)
         HIPCHK(launch_lhs(p.par->seed, (int32_t)p.M, p.N, p.par->sampler, p.strata, p.zeta, st));

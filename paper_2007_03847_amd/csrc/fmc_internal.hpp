@@ -159,15 +159,57 @@ struct BatchArgs {
   int32_t n_items;
   int32_t* head;                 // queue counter, zero before the launch
 };
+// prod: how a variant forms the network current: 0 lanes and FMAs (classes
+// 0-2), 1 FP32 matrix cores, 2 BF16 x3 matrix cores (class 3).
 struct BatchVariantInfo {
-  int id, NG, PM, L, TB, cls;
+  int id, NG, PM, L, TB, cls, prod;
 };
-constexpr int kBatchClasses = 3;
+constexpr int kBatchClasses = 4;
 int n_batch_variants();
 BatchVariantInfo batch_variant(int i);
 int persistent_blocks_per_cu(int cls);
 hipError_t launch_persistent(int cls, const BatchArgs& b, int grid, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);
+
+// Matrix-core classical variants (class 3): up to kMcMaxGen machines and
+// kMcMaxProc processes, 64 trajectories per workgroup tile.
+constexpr int kMcMaxGen = 64;
+constexpr int kMcMaxProc = 8;
+// Coefficient block of a class-3 variant (n_pad machines): machine-major
+// constants [n_pad][8] = C0 S0 I0R I0I | RES DMP INV2H 0 (two 16-byte groups),
+// the process block theta, sigma, xi0, machine index [4][kMcMaxProc], then Y
+// in the A-operand order of the variant's product (the FP32 pairs of
+// k_pack_fd_y or the BF16 hi/lo vectors of k_pack_fd_y16).
+struct McPack {
+  int n_pad;
+  static constexpr int kStride = 8;
+  static constexpr int kMaxConsts = kMcMaxGen * kStride + 4 * kMcMaxProc;
+  __host__ __device__ constexpr int n_padk() const { return 32 * ((n_pad + 31) / 32); }
+  __host__ __device__ constexpr int at(int m, int f) const { return m * kStride + f; }
+  __host__ __device__ constexpr int proc() const { return n_pad * kStride; }
+  __host__ __device__ constexpr int consts() const { return n_pad * kStride + 4 * kMcMaxProc; }
+  __host__ __device__ constexpr int frag() const { return consts(); }  // 16-byte aligned
+  __host__ __device__ constexpr int size(bool bf) const {
+    return frag() + (bf ? (n_pad / 16) * (n_padk() / 32) * 64 * 16 : (n_pad / 16) * (n_pad / 4) * 64 * 2);
+  }
+};
+hipError_t launch_pack_mc(const double* canon, int n, int P, const int32_t* gen, int n_pad, bool bf,
+                          float* coef, hipStream_t st);
+int persistent_mc_blocks_per_cu();
+hipError_t launch_persistent_mc(const BatchArgs& b, int grid, hipStream_t st);
+// State buffer of a batched variant (floats) for `tiles` trajectory tiles:
+// 2 G + PQ rows (G = ceil(NG / L), PQ = ceil(PM / L)) of 256 lanes per tile;
+// the lane classes address it [row][lanes], class 3 [tile][wave][row][64].
+inline size_t batch_state_floats(const BatchVariantInfo& b, int64_t tiles) {
+  const int G = (b.NG + b.L - 1) / b.L, PQ = (b.PM + b.L - 1) / b.L;
+  return (size_t)(2 * G + PQ) * (size_t)tiles * 64 * 4;
+}
+// Coefficient block size (floats) and packing of a batched variant.
+inline size_t batch_coef_floats(const BatchVariantInfo& b) {
+  return b.cls == 3 ? (size_t)McPack{b.NG}.size(b.prod == 2) : (size_t)PackLayout{b.NG, b.PM}.size();
+}
+hipError_t launch_pack_batch(const BatchVariantInfo& b, const double* canon, int n, int P,
+                             const int32_t* gen, float* coef, hipStream_t st);
 
 // ---- flux-decay machines with IEEE type-1 exciters ----
 // Parameter order per machine (as in the C ABI).
@@ -245,6 +287,7 @@ constexpr size_t kFdMaxLds = 160 * 1024;  // LDS of a gfx950 CU
 hipError_t launch_rk4_fd(const FdArgs& a, int64_t n_items, hipStream_t st);
 hipError_t launch_pack_fd_y16(const double* canon, int n, int n_pad, int n_padk, void* ap16,
                               hipStream_t st);
+hipError_t launch_pack_fd_y(const double* canon, int n, int n_pad, float2* ap, hipStream_t st);
 inline size_t fd_ap16_bytes(int n_pad, int n_padk) {
   return (size_t)(n_pad / 16) * (n_padk / 32) * 64 * 64;
 }

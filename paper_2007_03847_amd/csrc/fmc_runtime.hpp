@@ -74,6 +74,10 @@ int kron_on_device(Context* c, const fmc_network* net, double2* Yd, int* st_dev)
 int choose_variant(int n, int P, int64_t N);
 std::string tune_key(int n, int P, int64_t N, int precision);
 int pick_variant(Context* c, int n, int P, int64_t N, int precision);
+// Batched variants: whether one may run (n, P, precision), and the untuned
+// choice (the smallest that fits, lane variants first).
+bool batch_fits(const BatchVariantInfo& b, int n, int P, int precision);
+int default_batch_variant(int n, int P, int precision);
 int64_t auto_chunk(int64_t S, int P, int64_t N, int bytes_per);
 int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
                const fmc_params* par, fmc_outputs* out);

@@ -115,9 +115,8 @@ std::vector<size_t> parts_of(const Request& r) {
     z[B_STATE] = (size_t)r.tiles * r.NW * 48 * 64 * 4;
     z[B_XSTATE] = (size_t)r.tiles * kFdMaxProc * 16 * 4;
   } else {
-    const int G = (r.bv.NG + r.bv.L - 1) / r.bv.L, PQ = (r.bv.PM + r.bv.L - 1) / r.bv.L;
-    z[B_COEF] = (size_t)PackLayout{r.bv.NG, r.bv.PM}.size() * 4;
-    z[B_STATE] = (size_t)(2 * G + PQ) * r.tiles * 64 * 4 * 4;  // rows x lanes (4 waves per tile)
+    z[B_COEF] = batch_coef_floats(r.bv) * 4;
+    z[B_STATE] = batch_state_floats(r.bv, r.tiles) * 4;
   }
   // statistics rows of one chunk: per work item (classical), per tile (flux decay)
   z[B_PART] = (size_t)(r.fd ? r.tiles : r.n_items) * (r.Sc + 1) * r.V * 16;
@@ -168,16 +167,13 @@ int plan_request(Request& r, const fmc_system* s, const fmc_disturbance* d, cons
     return FMC_OK;
   }
   int vid = p->variant;
-  if (vid < 0) {
-    for (int i = 0; i < n_batch_variants(); ++i) {
-      const BatchVariantInfo b = batch_variant(i);
-      if (b.NG >= r.n && b.PM >= r.P && (vid < 0 || b.NG < batch_variant(vid).NG)) vid = i;
-    }
-  }
+  if (vid < 0) vid = default_batch_variant(r.n, r.P, p->precision);
   if (vid < 0 || vid >= n_batch_variants()) return fail(FMC_EINVAL, "no batched variant fits the request");
   r.vid = vid;
   r.bv = batch_variant(vid);
-  if (r.bv.NG < r.n || r.bv.PM < r.P) return fail(FMC_EINVAL, "variant too small for the request");
+  if (!batch_fits(r.bv, r.n, r.P, p->precision))
+    return fail(FMC_EINVAL, "variant does not fit the request (size, or a BF16 x3 product for "
+                            "an FMC_F32 request)");
   r.Sc = std::min<int64_t>(S, p->time_chunk > 0 ? p->time_chunk : kDefaultChunk);
   r.tiles = (r.N + r.bv.TB - 1) / r.bv.TB;
   r.cost_tile = (double)r.S * r.bv.TB * (8.0 * r.bv.NG * r.bv.NG + 45.0 * r.bv.NG + 4.0 * r.P);
@@ -348,7 +344,7 @@ int start_request(ServeState* ss, Request& r, size_t* pin_off) {
     if (r.par.precision == FMC_BF16X3)
       SCHK(launch_pack_fd_y16(r.canon, r.n, r.n_pad, 32 * ((r.n + 31) / 32), r.fdap, st));
   } else {
-    SCHK(launch_pack<float>(r.canon, r.n, r.P, r.gen_d, r.bv.NG, r.bv.PM, r.coef, st));
+    SCHK(launch_pack_batch(r.bv, r.canon, r.n, r.P, r.gen_d, r.coef, st));
   }
   SCHK(launch_basis(r.par.basis, r.K, r.S, r.par.T, r.phi, st));
   SCHK(launch_lhs(r.par.seed, (int32_t)r.M, r.N, r.par.sampler, nullptr, r.zeta, st));

@@ -641,6 +641,13 @@ hipError_t launch_rk4_fd(const FdArgs& a, int64_t n_items, hipStream_t st) {
   return a.ap16 ? launch_rk4_fd_t<true>(a, n_items, st) : launch_rk4_fd_t<false>(a, n_items, st);
 }
 
+hipError_t launch_pack_fd_y(const double* canon, int n, int n_pad, float2* ap, hipStream_t st) {
+  const int64_t total = (int64_t)(n_pad / 16) * (n_pad / 4) * 64;
+  hipLaunchKernelGGL(k_pack_fd_y, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, canon,
+                     n, n_pad, ap);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_fd_y16(const double* canon, int n, int n_pad, int n_padk, void* ap16,
                               hipStream_t st) {
   const int64_t total = (int64_t)(n_pad / 16) * (n_padk / 32) * 64;

@@ -110,3 +110,46 @@ def test_uneven_64_scenarios_sampled(ctx):
     for r in res:
         v = _np(r["var"])
         assert np.all(np.isfinite(v)) and np.all(v >= 0) and np.all(v[0] == 0)
+
+
+# Matrix-core variants (class 3): ids 11-13 FP32 product for up to 32, 48, 64
+# machines, 14-16 the BF16 x3 product.  Cases span several 64-trajectory tiles
+# with a ragged tail, eight processes (the second process slot of a lane), a
+# system above the lane variants' 50 machines, and time chunks (state kept
+# between ticks, a short last chunk).
+MC_CASES = [(20, 3, 150, 2), (33, 8, 64, 3), (47, 5, 200, 4), (61, 2, 129, 4)]
+
+
+@pytest.mark.parametrize("n,P,N,NB", MC_CASES)
+def test_batch_matrix_core_variants(ctx, n, P, N, NB):
+    sc = workloads.multimachine(n_gen=n, n_dist=P, N=N, K=30, T=0.6, dt=0.005, net_seed=300 + n,
+                                seed=40 + n)
+    sel = np.array([0, N // 2, N - 1])
+    o = oracle.run(sc, want_traj=True)
+    runs = [("f32", 11 + NB - 2), ("bf16x3", 11 + NB - 2), ("bf16x3", 14 + NB - 2)]
+    for prec, vid in runs:
+        r = ctx.run_batch([sc], precision=prec, variant=vid, traj_idx=[sel], time_chunk=50)[0]
+        em = mean_err(_np(r["mean"]), o["mean"], o["var"])
+        ev = rel_err(_np(r["var"]), o["var"])
+        et = rel_err(_np(r["traj"]), o["traj"][sel])
+        assert em <= 1e-4 and ev <= 1e-4 and et <= 2e-3, (n, prec, vid, em, ev, et)
+        assert r["report"]["variant_id"] == vid and r["report"]["n_nonfinite"] == 0
+
+
+def test_batch_matrix_core_multi_tile_items(ctx):
+    """More than 512 tiles: work items of several tiles, merged in the kernel."""
+    sc = workloads.multimachine(n_gen=20, n_dist=2, N=33000, K=20, T=0.1, dt=0.005, net_seed=321,
+                                seed=77)
+    o = oracle.run(sc)
+    for prec, vid in (("f32", 11), ("bf16x3", 14)):
+        r = ctx.run_batch([sc], precision=prec, variant=vid)[0]
+        assert mean_err(_np(r["mean"]), o["mean"], o["var"]) <= 1e-4, vid
+        assert rel_err(_np(r["var"]), o["var"]) <= 1e-4, vid
+        assert r["report"]["tile"] == 128, r["report"]["tile"]
+
+
+def test_batch_bf16_product_needs_bf16x3(ctx, fmc):
+    sc = workloads.multimachine(n_gen=20, n_dist=2, N=100, K=20, T=0.1, dt=0.005, net_seed=5, seed=5)
+    with pytest.raises(fmc.FmcError) as e:
+        ctx.run_batch([sc], precision="f32", variant=14)
+    assert e.value.code == fmc.EINVAL
