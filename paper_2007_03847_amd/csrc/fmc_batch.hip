@@ -92,15 +92,23 @@ bool batch_fits(const BatchVariantInfo& b, int n, int P, int precision) {
   return b.NG >= n && b.PM >= P && (b.prod != 2 || precision == FMC_BF16X3);
 }
 
+// Untuned choice: above 24 machines the matrix-core class (BF16 x3 product
+// for FMC_BF16X3), measured faster than the lane variants there at every
+// size; otherwise the smallest lane variant that fits.
 int default_batch_variant(int n, int P, int precision) {
+  const bool mc = n > 24;
+  const int prod = precision == FMC_BF16X3 ? 2 : 1;
   int vid = -1;
   for (int i = 0; i < n_batch_variants(); ++i) {
     const BatchVariantInfo b = batch_variant(i);
-    if (!batch_fits(b, n, P, precision)) continue;
-    if (vid < 0) { vid = i; continue; }
-    const BatchVariantInfo c = batch_variant(vid);
-    if (b.NG < c.NG || (b.NG == c.NG && b.cls < c.cls)) vid = i;
+    if (!batch_fits(b, n, P, precision) || (b.cls == 3) != mc || (mc && b.prod != prod)) continue;
+    if (vid < 0 || b.NG < batch_variant(vid).NG) vid = i;
   }
+  if (vid < 0)  // nothing of the preferred kind fits: any that does
+    for (int i = 0; i < n_batch_variants(); ++i)
+      if (batch_fits(batch_variant(i), n, P, precision) &&
+          (vid < 0 || batch_variant(i).NG < batch_variant(vid).NG))
+        vid = i;
   return vid;
 }
 

@@ -75,7 +75,7 @@ int choose_variant(int n, int P, int64_t N);
 std::string tune_key(int n, int P, int64_t N, int precision);
 int pick_variant(Context* c, int n, int P, int64_t N, int precision);
 // Batched variants: whether one may run (n, P, precision), and the untuned
-// choice (the smallest that fits, lane variants first).
+// choice of the served form.
 bool batch_fits(const BatchVariantInfo& b, int n, int P, int precision);
 int default_batch_variant(int n, int P, int precision);
 int64_t auto_chunk(int64_t S, int P, int64_t N, int bytes_per);

@@ -74,13 +74,17 @@ def test_served_alone_equals_mix(ctx):
         assert np.array_equal(_np(alone["var"]), _np(mix[i]["var"]))
 
 
-def test_served_equals_batched_form(ctx):
+@pytest.mark.parametrize("k,prec", [(1, "f32"), (4, "f32"), (4, "bf16x3")])
+def test_served_equals_batched_form(ctx, k, prec):
     """The served chunks (state kept on the device between ticks) give the
-    batched form's whole-horizon result for the same variant."""
-    sc = small_requests()[1]
-    s = ctx.submit(sc, precision="f32", time_chunk=29).wait(timeout=120)
+    batched form's whole-horizon result for the same variant (a lane variant
+    for 7 machines, the matrix-core class for 33)."""
+    sc = small_requests()[k]
+    s = ctx.submit(sc, precision=prec, time_chunk=29).wait(timeout=120)
     vid = s["report"]["variant_id"]
-    b = ctx.run_batch([sc], precision="f32", variant=vid)[0]
+    if sc["n_gen"] > 24:  # served default: matrix cores, BF16 x3 product for bf16x3
+        assert vid == (15 if prec == "bf16x3" else 12), vid
+    b = ctx.run_batch([sc], precision=prec, variant=vid)[0]
     assert rel_err(_np(s["var"]), _np(b["var"])) <= 1e-12
     assert mean_err(_np(s["mean"]), _np(b["mean"]), _np(b["var"])) <= 1e-12
 
