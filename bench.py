@@ -241,13 +241,16 @@ def fd_leg(ctx, fmc, workloads, oracle_mod, steps: int, reps: int = 2):
     ref = None
     if oracle_mod is not None:
         ref = oracle_mod.run(sc, sel=sel, want_traj=True)["traj"]
-    for form in ("f32", "bf16x3"):
-        ctx.run(sc, precision=form)  # warm
+    # bf16x3: BF16 x3 KLE paths, FP32 integration; bf16x3_net: the network
+    # product in BF16 x3 split products as well (variant 1, opt-in)
+    for form, prec, var in (("f32", "f32", -1), ("bf16x3", "bf16x3", -1),
+                            ("bf16x3_net", "bf16x3", 1)):
+        ctx.run(sc, precision=prec, variant=var)  # warm
         torch.cuda.synchronize()
         t_int = 0.0
         t0 = time.perf_counter()
         for _ in range(reps):
-            r = ctx.run(sc, precision=form)
+            r = ctx.run(sc, precision=prec, variant=var)
             t_int += r["report"]["t_integrate_s"]
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / reps
@@ -258,7 +261,7 @@ def fd_leg(ctx, fmc, workloads, oracle_mod, steps: int, reps: int = 2):
                "network_product_tflops": 8.0 * n * n * 4 * N * S / t_int / 1e12,
                "frac_of_fp32_matrix_peak": 8.0 * n * n * 4 * N * S / t_int / PEAK_FP32_MATRIX}
         if ref is not None:
-            rt = ctx.run(sc, precision=form, traj_idx=sel)["traj"].cpu().numpy()
+            rt = ctx.run(sc, precision=prec, traj_idx=sel, variant=var)["traj"].cpu().numpy()
             d = ref - ref[:, :1, :]
             num = np.abs(rt - ref).reshape(-1, rt.shape[-1]).max(axis=0)
             den = np.maximum(np.abs(d).reshape(-1, rt.shape[-1]).max(axis=0), 1e-6)

@@ -165,7 +165,16 @@ typedef struct fmc_params {
     uint64_t seed;           /* LHS design seed */
     int32_t basis, sampler, integrator, precision;
     int32_t ddof;            /* variance divisor N - ddof (1: unbiased) */
-    int32_t variant;         /* integrator kernel variant; -1 = choose (autotuner) */
+    int32_t variant;         /* integrator kernel variant; -1 = choose (autotuner).
+                                Flux-decay systems: -1 or 0 = network product in
+                                FP32; 1 (FMC_BF16X3 only) = network product as
+                                BF16 hi+lo split products, faster but with larger
+                                error (measured over 30 s: 1.5e-3 of the mean,
+                                6e-3 of the variance, against 4e-5 and 3e-4 in
+                                FP32).  Batched form: ids 14-16 (FMC_BF16X3
+                                only) likewise take the classical network
+                                product in BF16 split products; the tuner never
+                                picks them. */
     int32_t time_chunk;      /* steps per chunk; 0 = choose */
     const double *zeta_in;   /* device [M][N] FP64 coefficients replacing the
                                 sampler (M = n_proc*K), or NULL */
@@ -293,7 +302,8 @@ int fmc_cancel(fmc_context *ctx, uint64_t ticket);
 
 /* Autotuner: times every compiled integrator variant that fits the scenario
  * (machines, processes; lanes per trajectory and workgroup size differ) on a
- * short horizon at the scenario's N and precision, caches the fastest for the
+ * short horizon (three time chunks, whole run timed) at the scenario's N and
+ * precision, caches the fastest for the
  * (n, P, N bucket, precision) key in the context (used by every later call
  * with variant = -1), appends it to the JSON file named by the environment
  * variable FMC_TUNE_CACHE if set, and returns it in *variant. */

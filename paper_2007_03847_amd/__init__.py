@@ -21,6 +21,10 @@ LIB_PATH = os.path.join(_HERE, "libfmc.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2007_03847_amd.build`")
 
+# torch first: it brings up the HIP runtime and devices the process works
+# with; loading the library before it leaves the library without a device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 # ---------------------------------------------------------------- constants
@@ -373,7 +377,8 @@ def _run_batch(ctx, scs, precision="f32", traj_idx=None, variant=-1, allow_nonfi
     outs = (Outputs * n)()
     res = []
     for i, sc in enumerate(scs):
-        sysd, dist, par, _ = scenario_structs(sc, precision, variant, time_chunk, keep=keep)
+        v = variant[i] if isinstance(variant, (list, tuple)) else variant
+        sysd, dist, par, _ = scenario_structs(sc, precision, v, time_chunk, keep=keep)
         arr[i] = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))
         ti = None if traj_idx is None else traj_idx[i]
         o, r = _outputs_for(ctx, sc, ti, keep)
@@ -397,7 +402,8 @@ Context.run_batch.__doc__ = """Batched form: a list of scenario dicts in one per
 
 Returns one dict(mean, var[, traj], report, rc) per scenario.  traj_idx, if
 given, is a list (one entry per scenario, None allowed) of sample indices;
-time_chunk > 0 sets the steps per tick (else 250).  Variant ids 0-10 are the
+time_chunk > 0 sets the steps per tick (else 250); variant is one id for
+every scenario or a list of ids (-1: tuned).  Variant ids 0-10 are the
 lane variants, 11-13 the FP32 matrix-core variants for up to 32, 48, 64
 machines and 14-16 their BF16 x3 forms (FMC_BF16X3 scenarios only)."""
 
@@ -469,8 +475,8 @@ Context.submit.__doc__ = """Served form: admit one request (FmcError EBUSY / ENO
 does not fit now / ever) and return its Ticket (poll / wait / cancel)."""
 
 
-def footprint(sc: dict, precision="f64") -> int:
-    sysd, dist, par, keep = scenario_structs(sc, precision)
+def footprint(sc: dict, precision="f64", variant=-1) -> int:
+    sysd, dist, par, keep = scenario_structs(sc, precision, variant)
     s = Scenario(C.pointer(sysd), C.pointer(dist), C.pointer(par))
     b = C.c_int64(0)
     _check(_lib.fmc_footprint(C.byref(s), C.byref(b)))

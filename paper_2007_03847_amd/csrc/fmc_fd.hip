@@ -62,7 +62,7 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
   HIPCHK(launch_pack_fd(canon, n, P, prm_d, (const double*)fd, gen_d, n_pad, (float*)coef,
                         (float2*)ap, c->stream));
   // FMC_BF16X3: the network product in BF16 x3 on the matrix cores too
-  const bool bf = par->precision == FMC_BF16X3;
+  const bool bf = fd_bf16_product(par);
   const int n_padk = 32 * ((n + 31) / 32);
   void* ap16 = nullptr;
   if (bf) {
@@ -234,7 +234,7 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
     r->t_integrate_s = t_int;
     r->n_nonfinite = (int64_t)cn[0];
     r->first_nonfinite = cn[0] ? (int64_t)cn[1] : -1;
-    r->variant_id = -1;
+    r->variant_id = bf ? 1 : 0;
     r->lanes_per_traj = 1;
     r->tile = (int32_t)(pl.tiles_per_item * 16);
     r->time_chunk = (int32_t)Sc;

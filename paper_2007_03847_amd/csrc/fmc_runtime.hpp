@@ -77,6 +77,11 @@ int pick_variant(Context* c, int n, int P, int64_t N, int precision);
 // Batched variants: whether one may run (n, P, precision), and the untuned
 // choice of the served form.
 bool batch_fits(const BatchVariantInfo& b, int n, int P, int precision);
+// Flux-decay systems: the network product on BF16 x3 split products (asked
+// for with variant 1 under FMC_BF16X3), else in FP32.
+inline bool fd_bf16_product(const fmc_params* p) {
+  return p->precision == FMC_BF16X3 && p->variant == 1;
+}
 int default_batch_variant(int n, int P, int precision);
 int64_t auto_chunk(int64_t S, int P, int64_t N, int bytes_per);
 int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,

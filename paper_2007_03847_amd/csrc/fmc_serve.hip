@@ -109,7 +109,7 @@ std::vector<size_t> parts_of(const Request& r) {
   if (r.fd) {
     z[B_COEF] = (size_t)FdPack{r.n_pad}.size() * 4;
     z[B_FDBLK] = (size_t)FdLayout{r.n}.size() * 8;
-    z[B_FDAP] = r.par.precision == FMC_BF16X3
+    z[B_FDAP] = fd_bf16_product(&r.par)
                     ? fd_ap16_bytes(r.n_pad, 32 * ((r.n + 31) / 32))
                     : (size_t)(r.n_pad / 16) * (r.n_pad / 4) * 64 * sizeof(float2);
     z[B_STATE] = (size_t)r.tiles * r.NW * 48 * 64 * 4;
@@ -341,7 +341,7 @@ int start_request(ServeState* ss, Request& r, size_t* pin_off) {
     // constants and the FP32 product's Y; the BF16 x3 product's Y (never
     // smaller) then overwrites the Y buffer
     SCHK(launch_pack_fd(r.canon, r.n, r.P, r.prm_d, r.fdblk, r.gen_d, r.n_pad, r.coef, r.fdap, st));
-    if (r.par.precision == FMC_BF16X3)
+    if (fd_bf16_product(&r.par))
       SCHK(launch_pack_fd_y16(r.canon, r.n, r.n_pad, 32 * ((r.n + 31) / 32), r.fdap, st));
   } else {
     SCHK(launch_pack_batch(r.bv, r.canon, r.n, r.P, r.gen_d, r.coef, st));
@@ -391,7 +391,7 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
       FdArgs f{};
       f.coef = r.coef;
       f.ap = r.fdap;
-      f.ap16 = r.par.precision == FMC_BF16X3 ? (const void*)r.fdap : nullptr;
+      f.ap16 = fd_bf16_product(&r.par) ? (const void*)r.fdap : nullptr;
       f.n_padk = 32 * ((r.n + 31) / 32);
       f.w = r.w;
       f.state = r.state;
@@ -543,7 +543,7 @@ void write_report(ServeState* ss, Request& r) {
     std::memset(rep, 0, sizeof(*rep));
     rep->n_nonfinite = nbad;
     rep->first_nonfinite = first;
-    rep->variant_id = r.fd ? -1 : r.vid;
+    rep->variant_id = r.fd ? (fd_bf16_product(&r.par) ? 1 : 0) : r.vid;
     rep->lanes_per_traj = r.fd ? 1 : r.bv.L;
     rep->tile = (int32_t)(r.tiles_per_item * (r.fd ? 16 : r.bv.TB));
     rep->time_chunk = (int32_t)r.Sc;

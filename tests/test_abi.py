@@ -92,7 +92,12 @@ def test_fluxdecay_validation_on_host():
     sc = workloads.fluxdecay(n_gen=40, n_dist=6, N=100, K=20, T=0.1)
     b32 = fmc.footprint(sc, "f32")
     b16 = fmc.footprint(sc, "bf16x3")
-    assert b32 > 0 and b16 > 0
+    b16n = fmc.footprint(sc, "bf16x3", variant=1)  # BF16 x3 network product: its own Y copy
+    assert b32 > 0 and b16 > 0 and b16n > b16
+    for prec, v in (("f32", 1), ("bf16x3", 2), ("bf16x3", -2)):
+        with pytest.raises(fmc.FmcError) as e:
+            fmc.footprint(sc, prec, variant=v)
+        assert e.value.code == fmc.EINVAL
     # the 196-bus reduction needs its (n_bus + n_gen)^2 complex work matrix
     W = sc["net"]["n_bus"] + sc["n_gen"]
     assert b32 > W * W * 16

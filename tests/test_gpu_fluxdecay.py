@@ -57,14 +57,17 @@ def scenario(n, P, N, K, T, seed=0):
 
 
 @pytest.mark.parametrize("case", CASES)
-@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
-def test_fluxdecay_matches_oracle(ctx, case, prec):
+@pytest.mark.parametrize("prec,variant", [("f32", -1), ("bf16x3", -1), ("bf16x3", 1)])
+def test_fluxdecay_matches_oracle(ctx, case, prec, variant):
+    """FP32 network product (default) and, asked for with variant 1, the
+    BF16 x3 network product, on short horizons."""
     sc = scenario(*case)
     N = sc["N"]
     sel = np.array([0, N // 2, N - 1])
-    r = ctx.run(sc, precision=prec, traj_idx=sel)
+    r = ctx.run(sc, precision=prec, traj_idx=sel, variant=variant)
     o = oracle.run(sc, want_traj=True)
     assert r["report"]["n_nonfinite"] == 0
+    assert r["report"]["variant_id"] == (1 if variant == 1 else 0)
     em = mean_err(_np(r["mean"]), o["mean"], o["var"])
     ev = var_err(_np(r["var"]), o["var"])
     et = traj_err(_np(r["traj"]), o["traj"][sel])
@@ -108,3 +111,7 @@ def test_fluxdecay_rejections(ctx, fmc):
     with pytest.raises(fmc.FmcError) as e:  # 5 processes > 4 per wave for n <= 32
         ctx.run(scenario(12, 5, 37, 30, 0.5), precision="f32")
     assert e.value.code == fmc.EINVAL
+    for prec, v in (("f32", 1), ("bf16x3", 2)):  # the BF16 product needs FMC_BF16X3
+        with pytest.raises(fmc.FmcError) as e:
+            ctx.run(sc, precision=prec, variant=v)
+        assert e.value.code == fmc.EINVAL
