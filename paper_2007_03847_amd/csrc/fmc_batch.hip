@@ -76,7 +76,7 @@ std::vector<int> batch_candidates(int n, int P, int precision) {
   for (int i = 0; i < n_batch_variants(); ++i) {
     const BatchVariantInfo b = batch_variant(i);
     if (!batch_fits(b, n, P, precision)) continue;
-    if (b.cls < 3) {
+    if (b.prod == 0) {
       lane.push_back(i);
     } else if (n > 16 && (mc[b.prod] < 0 || b.NG < batch_variant(mc[b.prod]).NG)) {
       mc[b.prod] = i;
@@ -106,7 +106,7 @@ int default_batch_variant(int n, int P, int precision) {
     for (int i = 0; i < n_batch_variants(); ++i) {
       const BatchVariantInfo b = batch_variant(i);
       if (!batch_fits(b, n, P, precision) || b.prod == 2) continue;
-      if (pass == 0 && (b.cls == 3) != mc) continue;
+      if (pass == 0 && (b.prod != 0) != mc) continue;
       if (vid < 0 || b.NG < batch_variant(vid).NG) vid = i;
     }
   return vid;
@@ -174,6 +174,10 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
   if (nsc < 1 || !scen || !outs) return fail(FMC_EINVAL, "empty batch");
   HIPCHK(hipSetDevice(c->device));
   if (!c->bstream) HIPCHK(hipStreamCreateWithFlags(&c->bstream, hipStreamNonBlocking));
+  for (int k = 0; k < kBatchClasses; ++k)
+    if (!c->cstream[k]) HIPCHK(hipStreamCreateWithFlags(&c->cstream[k], hipStreamNonBlocking));
+  for (auto& e : c->cev)
+    if (!e) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   hipStream_t st = c->bstream;
   int rc;
   std::vector<Plan> plans(nsc);
@@ -320,7 +324,7 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
   void *status = nullptr, *counters = nullptr, *heads = nullptr;
   if ((rc = c->ensure("b_status", (size_t)nsc * 16, &status))) return rc;
   if ((rc = c->ensure("b_counters", (size_t)nsc * 16, &counters))) return rc;
-  if ((rc = c->ensure("b_heads", (size_t)n_ticks * 8 * 4, &heads))) return rc;
+  if ((rc = c->ensure("b_heads", (size_t)n_ticks * 16 * 4, &heads))) return rc;
   // ---- items (static) and, per tick and size class, the queue of the items
   // of the scenarios active in that tick (longest first)
   std::vector<BatchItem> items(n_items);
@@ -462,7 +466,7 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
       HIPCHK(launch_fill_i64((int64_t*)counters + 2 * i, 0, 1, st));
       HIPCHK(launch_fill_i64((int64_t*)counters + 2 * i + 1, LLONG_MAX, 1, st));
     }
-    HIPCHK(launch_fill_i64((int64_t*)heads, 0, n_ticks * 4, st));
+    HIPCHK(launch_fill_i64((int64_t*)heads, 0, n_ticks * 8, st));
     for (int64_t k = 0; k < n_ticks; ++k) {
       for (auto& p : plans) {
         if (p.ticks <= k) continue;
@@ -473,14 +477,31 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
         else
           HIPCHK(launch_kle_bf16x3(zeta, p.phi, p.C, p.P, p.K, p.N, 2 * (s1 - s0) + 1, 2 * s0, p.w, st));
       }
+      // the tick's size classes: one launch each; with more than one, each on
+      // its own stream (fork after the paths, join before the merges) so that
+      // the classes share the chip instead of each running partly filled
+      int n_act = 0;
+      for (int cl = 0; cl < kBatchClasses; ++cl)
+        n_act += ord_off[k * kBatchClasses + cl + 1] > ord_off[k * kBatchClasses + cl];
+      if (n_act > 1) HIPCHK(hipEventRecord(c->cev[kBatchClasses], st));
       for (int cl = 0; cl < kBatchClasses; ++cl) {
         const int64_t o0 = ord_off[k * kBatchClasses + cl], o1 = ord_off[k * kBatchClasses + cl + 1];
         if (o1 == o0) continue;
         const int grid = (int)std::min<int64_t>(o1 - o0, (int64_t)bpc[cl] * prop.multiProcessorCount);
         BatchArgs b{args_d + (size_t)k * nsc, items_d, order_d + o0, (int32_t)(o1 - o0),
-                    (int32_t*)heads + k * 8 + 2 * cl};
-        HIPCHK(launch_persistent(cl, b, grid, st));
+                    (int32_t*)heads + k * 16 + 2 * cl};
+        if (n_act > 1) {
+          HIPCHK(hipStreamWaitEvent(c->cstream[cl], c->cev[kBatchClasses], 0));
+          HIPCHK(launch_persistent(cl, b, grid, c->cstream[cl]));
+          HIPCHK(hipEventRecord(c->cev[cl], c->cstream[cl]));
+        } else {
+          HIPCHK(launch_persistent(cl, b, grid, st));
+        }
       }
+      if (n_act > 1)
+        for (int cl = 0; cl < kBatchClasses; ++cl)
+          if (ord_off[k * kBatchClasses + cl + 1] > ord_off[k * kBatchClasses + cl])
+            HIPCHK(hipStreamWaitEvent(st, c->cev[cl], 0));
       // rows completed by this tick: s0+1..s1 (and row 0 in the first chunk)
       for (auto& p : plans) {
         if (p.ticks <= k) continue;

@@ -434,6 +434,13 @@ int fmc_context_destroy(fmc_context* ctx) {
   }
   for (auto& e : c->gev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& s : c->cstream)
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  for (auto& e : c->cev)
+    if (e) (void)hipEventDestroy(e);
   c->release_all();
   for (auto& ev : c->ev) (void)hipEventDestroy(ev);
   delete c;

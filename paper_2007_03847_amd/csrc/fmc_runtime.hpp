@@ -37,6 +37,10 @@ struct Context {
   hipStream_t bstream = nullptr;     // capture stream of the batched form
   hipStream_t gstream = nullptr;     // KLE contractions overlapped with the integrator
   hipEvent_t gev[4] = {};            // [b]: paths of buffer b ready, [2+b]: buffer b consumed
+  // batched form: one stream per size class so that a tick's class launches
+  // share the chip (forked from and joined back into bstream inside the graph)
+  hipStream_t cstream[kBatchClasses] = {};
+  hipEvent_t cev[kBatchClasses + 1] = {};  // [cl]: class cl done, [kBatchClasses]: fork
   std::map<std::string, std::pair<uint64_t, hipGraphExec_t>> graphs;  // shape -> (gen, graph)
 
   int ensure(const char* name, size_t bytes, void** out);

@@ -1,4 +1,4 @@
-// k_mfma_classical.hip -- class 3 of the persistent batched integrator:
+// k_mfma_classical.hip -- classes 3-5 of the persistent batched integrator:
 // classical machines with the network current on the matrix cores (the
 // device code is in k_mfma_classical.hpp), and the packing of its
 // coefficient block.
@@ -10,7 +10,7 @@
 
 namespace fmc {
 
-// Constants of a class-3 variant from the canonical FP64 block: machine rows
+// Constants of a matrix-core variant from the canonical FP64 block: machine rows
 // [n_pad][8] (zero for padding machines, which then stay at rest), then
 // theta, sigma, xi0 and the driven machine of each process (as a float; -1
 // for unused process slots).
@@ -51,19 +51,27 @@ hipError_t launch_pack_mc(const double* canon, int n, int P, const int32_t* gen,
 
 hipError_t launch_pack_batch(const BatchVariantInfo& b, const double* canon, int n, int P,
                              const int32_t* gen, float* coef, hipStream_t st) {
-  if (b.cls == 3) return launch_pack_mc(canon, n, P, gen, b.NG, b.prod == 2, coef, st);
+  if (b.prod != 0) return launch_pack_mc(canon, n, P, gen, b.NG, b.prod == 2, coef, st);
   return launch_pack<float>(canon, n, P, gen, b.NG, b.PM, coef, st);
 }
 
-// Persistent class-3 kernel: workgroups pop work items (ranges of 64-trajectory
-// tiles of one scenario) until the queue is empty, as the lane classes do.
-#define FMC_MC_DISPATCH(NB, BF)                                                     \
-  if (it.variant == id)                                                             \
-    for (int64_t t = it.tile0; t < it.tile1; ++t)                                   \
-      mc_tile<BF != 0, NB>(a, t, S, GroupStats{rows, (t - it.tile0) * mc::kTile});  \
+// Persistent matrix-core kernels, one per block count NB (a kernel's register
+// footprint is that of its largest variant, so the 32-machine variants get
+// their own kernel and twice the waves per SIMD): workgroups pop work items
+// (ranges of 64-trajectory tiles of one scenario) until the queue is empty,
+// as the lane classes do.
+#define FMC_MC_DISPATCH(NBV, BF)                                                    \
+  if constexpr (NBV == NB)                                                          \
+    if (it.variant == id)                                                           \
+      for (int64_t t = it.tile0; t < it.tile1; ++t)                                 \
+        mc_tile<BF != 0, NBV>(a, t, S, GroupStats{rows, (t - it.tile0) * mc::kTile}); \
   ++id;
 
-__global__ void __launch_bounds__(64 * mc::kWaves) k_rk4_persistent_mc(BatchArgs b) {
+// NB = 2 is held to 256 registers (two waves per SIMD); the larger block
+// counts need more and run one wave per SIMD.
+template <int NB>
+__global__ void __launch_bounds__(64 * mc::kWaves)
+    __attribute__((amdgpu_waves_per_eu(NB == 2 ? 2 : 1))) k_rk4_persistent_mc(BatchArgs b) {
   __shared__ __attribute__((aligned(16))) mc::Lds S;
   __shared__ int s_item;
   for (;;) {
@@ -82,16 +90,27 @@ __global__ void __launch_bounds__(64 * mc::kWaves) k_rk4_persistent_mc(BatchArgs
 }
 #undef FMC_MC_DISPATCH
 
-int persistent_mc_blocks_per_cu() {
+template <int NB>
+static int blocks_per_cu() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_persistent_mc, 64 * mc::kWaves, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rk4_persistent_mc<NB>, 64 * mc::kWaves,
+                                                   0) != hipSuccess)
     return 1;
   return nb > 0 ? nb : 1;
 }
 
-hipError_t launch_persistent_mc(const BatchArgs& b, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_rk4_persistent_mc, dim3((unsigned)grid), dim3(64 * mc::kWaves), 0, st, b);
+int persistent_mc_blocks_per_cu(int nb) {
+  return nb == 2 ? blocks_per_cu<2>() : nb == 3 ? blocks_per_cu<3>() : blocks_per_cu<4>();
+}
+
+hipError_t launch_persistent_mc(int nb, const BatchArgs& b, int grid, hipStream_t st) {
+  const dim3 g((unsigned)grid), blk(64 * mc::kWaves);
+  if (nb == 2)
+    hipLaunchKernelGGL(k_rk4_persistent_mc<2>, g, blk, 0, st, b);
+  else if (nb == 3)
+    hipLaunchKernelGGL(k_rk4_persistent_mc<3>, g, blk, 0, st, b);
+  else
+    hipLaunchKernelGGL(k_rk4_persistent_mc<4>, g, blk, 0, st, b);
   return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
 // k_mfma_classical.hpp -- classical machines with the network current on the
-// matrix cores (the batched and served forms' size class for larger systems).
+// matrix cores (the batched and served forms' size classes for larger systems).
 //
 // Same deviation form as the lane-per-machine integrators: per RK4 stage
 // dE~ = E~0 (e^{j dd} - 1), dPe = Re(dE~ conj I0) + Re(E~ conj dI) with
@@ -144,6 +144,12 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
   // (sums over the 16 lanes of a row), the four waves combined in order with
   // Chan's update, then merged into the item's row.
   auto emit = [&](int64_t s) {
+    // n and the operating point pass through an empty asm so that the
+    // machine addresses are recomputed here rather than kept live (with
+    // the loaded delta0 values) across the whole run
+    int nl = n;
+    const double* d0 = a.delta0;
+    asm volatile("" : "+v"(nl), "+v"(d0));
     double2* part = S.part[pbuf][wv];
     double* o = slot >= 0 ? a.traj + ((int64_t)slot * (a.S + 1) + s) * V : nullptr;
     const double inv = wcnt > 0.0 ? 1.0 / wcnt : 0.0;
@@ -156,22 +162,22 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       const int m = mach(q);  // uniform over a row of 16 lanes
-      if (m < n) {
+      if (m < nl) {
         one((double)yd[q], m);
-        one((double)yw[q], n + m);
+        one((double)yw[q], nl + m);
         if (o) {
-          o[m] = a.delta0[m] + (double)yd[q];
-          o[n + m] = (double)yw[q];
+          o[m] = d0[m] + (double)yd[q];
+          o[nl + m] = (double)yw[q];
         }
       }
     }
     if (own0) {
-      one((double)x0, 2 * n + g);
-      if (o) o[2 * n + g] = (double)x0;
+      one((double)x0, 2 * nl + g);
+      if (o) o[2 * nl + g] = (double)x0;
     }
     if (own1) {
-      one((double)x1, 2 * n + g + 4);
-      if (o) o[2 * n + g + 4] = (double)x1;
+      one((double)x1, 2 * nl + g + 4);
+      if (o) o[2 * nl + g + 4] = (double)x1;
     }
     __syncthreads();
     double2* dst = st.rows + s * V;

@@ -60,9 +60,9 @@
   X(50, 8, 50)
 #define FMC_BATCH_VARIANTS(X) FMC_BATCH_CLASS0(X) FMC_BATCH_CLASS1(X) FMC_BATCH_CLASS2(X)
 
-// Matrix-core variants of the batched integrator (class 3, one persistent
-// kernel): X(NB blocks of 16 machines, BF), BF = 1 for the BF16 x3 product of
-// the network current, 0 for FP32.
+// Matrix-core variants of the batched integrator (classes 3-5, one persistent
+// kernel per NB): X(NB blocks of 16 machines, BF), BF = 1 for the BF16 x3
+// product of the network current, 0 for FP32.
 #define FMC_BATCH_MFMA(X) \
   X(2, 0)                 \
   X(3, 0)                 \
@@ -71,7 +71,7 @@
   X(3, 1)                 \
   X(4, 1)
 
-// Number of lane (class 0-2) variants; the class-3 ids follow them.
+// Number of lane (class 0-2) variants; the matrix-core ids follow them.
 constexpr int batch_n_lane_variants() {
   int id = 0;
 #define FMC_X(NG, PM, L) ++id;
