@@ -43,7 +43,7 @@ constexpr size_t kTickBytes = size_t(16) << 20;  // per-tick upload region (args
 constexpr int64_t kMaxItems = 1024;             // work items per request
 constexpr int kMaxActive = 256;                 // requests admitted at once
 constexpr int64_t kDefaultChunk = 200;          // steps per tick
-constexpr int64_t kDefaultChunkFd = 25;         // steps per tick of a flux-decay request
+constexpr int64_t kDefaultChunkFd = 12;         // steps per tick of a flux-decay request
 constexpr size_t kAlign = serve::kAlign;
 
 size_t al(size_t x) { return serve::align_up(x); }
@@ -244,6 +244,10 @@ struct ServeState {
   char* arena_base = nullptr;
   unsigned char* tick_dev = nullptr;  // upload region of a tick (outside the arena)
   hipStream_t st = nullptr;
+  // per tick, the size classes and the flux-decay integrators run on their
+  // own streams (forked from st after the paths, joined before the merges)
+  hipStream_t lst[kBatchClasses + 1] = {};
+  hipEvent_t lev[kBatchClasses + 2] = {};  // [k]: lane k done, [kBatchClasses + 1]: fork
   unsigned char* pin = nullptr;  // page-locked staging of a tick
   size_t pin_cap = 0;
   int n_cu = 0, bpc[kBatchClasses] = {};
@@ -486,14 +490,36 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
   pin_off += o;
   int32_t* heads = (int32_t*)ss->tick_dev;
   SCHK(launch_fill_i64((int64_t*)heads, 0, 8, st));
+  // lanes of the tick: the size classes with items, then the flux-decay
+  // integrators (one after another on the last lane)
+  bool on[kBatchClasses + 1];
+  int n_on = 0;
+  for (int k = 0; k < kBatchClasses; ++k) n_on += on[k] = off[k + 1] > off[k];
+  n_on += on[kBatchClasses] = !fd_launch.empty();
+  const bool fork = n_on > 1;
+  if (fork) SCHK(hipEventRecord(ss->lev[kBatchClasses + 1], st));
+  auto lane = [&](int k) {
+    if (!fork) return st;
+    (void)hipStreamWaitEvent(ss->lst[k], ss->lev[kBatchClasses + 1], 0);
+    return ss->lst[k];
+  };
   for (int k = 0; k < kBatchClasses; ++k) {
+    if (!on[k]) continue;
     const int64_t nk = off[k + 1] - off[k];
-    if (nk == 0) continue;
     const int grid = (int)std::min<int64_t>(nk, (int64_t)ss->bpc[k] * ss->n_cu);
     BatchArgs b{args_d, items_d, order_d + off[k], (int32_t)nk, heads + 2 * k};
-    SCHK(launch_persistent(k, b, grid, st));
+    SCHK(launch_persistent(k, b, grid, lane(k)));
   }
-  for (auto& f : fd_launch) SCHK(launch_rk4_fd(f.first, f.second, st));
+  if (on[kBatchClasses]) {
+    const hipStream_t ls = lane(kBatchClasses);
+    for (auto& f : fd_launch) SCHK(launch_rk4_fd(f.first, f.second, ls));
+  }
+  if (fork)
+    for (int k = 0; k <= kBatchClasses; ++k)
+      if (on[k]) {
+        SCHK(hipEventRecord(ss->lev[k], ss->lst[k]));
+        SCHK(hipStreamWaitEvent(st, ss->lev[k], 0));
+      }
   // rows completed by this tick: s0+1..s1 (and row 0 in a request's first chunk)
   for (int i = 0; i < na; ++i) {
     Request& r = *act[i];
@@ -632,6 +658,12 @@ int ensure_server(Context* c) {
   for (int k = 0; k < kBatchClasses; ++k) ss->bpc[k] = persistent_blocks_per_cu(k);
   if (hipStreamCreateWithFlags(&ss->st, hipStreamNonBlocking) != hipSuccess)
     return fail(FMC_EDEVICE, "cannot create the serving stream");
+  for (auto& l : ss->lst)
+    if (hipStreamCreateWithFlags(&l, hipStreamNonBlocking) != hipSuccess)
+      return fail(FMC_EDEVICE, "cannot create the serving streams");
+  for (auto& e : ss->lev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return fail(FMC_EDEVICE, "cannot create the serving events");
   c->serve = ss.release();
   c->serve->th = std::thread(server_loop, c, c->serve);
   return FMC_OK;
@@ -665,6 +697,13 @@ void serve_shutdown(Context* c) {
     (void)hipStreamSynchronize(ss->st);
     (void)hipStreamDestroy(ss->st);
   }
+  for (auto& l : ss->lst)
+    if (l) {
+      (void)hipStreamSynchronize(l);
+      (void)hipStreamDestroy(l);
+    }
+  for (auto& e : ss->lev)
+    if (e) (void)hipEventDestroy(e);
   if (ss->pin) (void)hipHostFree(ss->pin);
   delete ss;
   c->serve = nullptr;
