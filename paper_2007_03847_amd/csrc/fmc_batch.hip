@@ -297,7 +297,9 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
       p.kron = true;
       if ((rc = c->ensure(nm(i, "ybuf").c_str(), (size_t)p.n * p.n * 16, &q))) return rc;
       p.ybuf = (double2*)q;
-      if ((rc = c->ensure("b_kron_work", kron_work_bytes(p.sys->net->n_bus, p.n), &q))) return rc;
+      // one work matrix per scenario: the reductions run side by side
+      if ((rc = c->ensure(nm(i, "kwork").c_str(), kron_work_bytes(p.sys->net->n_bus, p.n), &q))) return rc;
+      p.kwork = (double2*)q;
     }
     // the captured graph touches context buffers only; results are copied out
     // after each replay (caller pointers may change between calls)
@@ -449,17 +451,32 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
   for (int k = 0; k < kBatchClasses; ++k) bpc[k] = persistent_blocks_per_cu(k);
   auto enqueue = [&]() -> int {
     HIPCHK(launch_fill_i64((int64_t*)status, 0, 2 * nsc, st));
-    for (int i = 0; i < nsc; ++i) {
-      Plan& p = plans[i];
-      if (p.kron) {
-        HIPCHK(launch_kron(p.nd, (double2*)c->bufs["b_kron_work"].p, p.ybuf, (int*)status + 4 * i + 1, st));
-        p.sd.Y = p.ybuf;
+    // per-scenario setup (reduction, operating point, packing, basis, design),
+    // scenarios spread round-robin over the side streams
+    {
+      bool used[kBatchClasses] = {};
+      HIPCHK(hipEventRecord(c->cev[kBatchClasses], st));
+      for (int i = 0; i < nsc; ++i) {
+        Plan& p = plans[i];
+        const int x = i % kBatchClasses;
+        const hipStream_t s = c->cstream[x];
+        if (!used[x]) HIPCHK(hipStreamWaitEvent(s, c->cev[kBatchClasses], 0));
+        used[x] = true;
+        if (p.kron) {
+          HIPCHK(launch_kron(p.nd, p.kwork, p.ybuf, (int*)status + 4 * i + 1, s));
+          p.sd.Y = p.ybuf;
+        }
+        HIPCHK(launch_setup(p.sd, s));
+        HIPCHK(launch_pack_batch(p.bv, p.canon, p.n, p.P, p.gen_d, p.coef, s));
+        HIPCHK(launch_basis(p.par->basis, p.K, p.S, p.par->T, p.phi, s));
+        if (!p.par->zeta_in)
+          HIPCHK(launch_lhs(p.par->seed, (int32_t)p.M, p.N, p.par->sampler, p.strata, p.zeta, s));
       }
-      HIPCHK(launch_setup(p.sd, st));
-      HIPCHK(launch_pack_batch(p.bv, p.canon, p.n, p.P, p.gen_d, p.coef, st));
-      HIPCHK(launch_basis(p.par->basis, p.K, p.S, p.par->T, p.phi, st));
-      if (!p.par->zeta_in)
-        HIPCHK(launch_lhs(p.par->seed, (int32_t)p.M, p.N, p.par->sampler, p.strata, p.zeta, st));
+      for (int x = 0; x < kBatchClasses; ++x)
+        if (used[x]) {
+          HIPCHK(hipEventRecord(c->cev[x], c->cstream[x]));
+          HIPCHK(hipStreamWaitEvent(st, c->cev[x], 0));
+        }
     }
     // counters: (nonfinite = 0, first = max) per scenario; queue heads = 0
     for (int i = 0; i < nsc; ++i) {
@@ -468,15 +485,35 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     }
     HIPCHK(launch_fill_i64((int64_t*)heads, 0, n_ticks * 8, st));
     for (int64_t k = 0; k < n_ticks; ++k) {
-      for (auto& p : plans) {
-        if (p.ticks <= k) continue;
+      // The tick's per-scenario launches of one phase (paths, merges) are
+      // small: they are spread round-robin over the side streams (forked
+      // from st, joined back) so that they run side by side.
+      auto spread = [&](auto&& launch) -> int {
+        bool used[kBatchClasses] = {};
+        HIPCHK(hipEventRecord(c->cev[kBatchClasses], st));
+        int j = 0;
+        for (auto& p : plans) {
+          if (p.ticks <= k) continue;
+          const int x = j++ % kBatchClasses;
+          if (!used[x]) HIPCHK(hipStreamWaitEvent(c->cstream[x], c->cev[kBatchClasses], 0));
+          used[x] = true;
+          HIPCHK(launch(p, c->cstream[x]));
+        }
+        for (int x = 0; x < kBatchClasses; ++x)
+          if (used[x]) {
+            HIPCHK(hipEventRecord(c->cev[x], c->cstream[x]));
+            HIPCHK(hipStreamWaitEvent(st, c->cev[x], 0));
+          }
+        return FMC_OK;
+      };
+      rc = spread([&](Plan& p, hipStream_t s) {
         const int64_t s0 = k * p.Sc, s1 = std::min<int64_t>(p.S, s0 + p.Sc);
         const double* zeta = p.par->zeta_in ? p.par->zeta_in : p.zeta;
-        if (p.par->precision == FMC_F32)
-          HIPCHK(launch_kle_f64_to_f32(zeta, p.phi, p.C, p.P, p.K, p.N, 2 * (s1 - s0) + 1, 2 * s0, p.w, st));
-        else
-          HIPCHK(launch_kle_bf16x3(zeta, p.phi, p.C, p.P, p.K, p.N, 2 * (s1 - s0) + 1, 2 * s0, p.w, st));
-      }
+        return p.par->precision == FMC_F32
+                   ? launch_kle_f64_to_f32(zeta, p.phi, p.C, p.P, p.K, p.N, 2 * (s1 - s0) + 1, 2 * s0, p.w, s)
+                   : launch_kle_bf16x3(zeta, p.phi, p.C, p.P, p.K, p.N, 2 * (s1 - s0) + 1, 2 * s0, p.w, s);
+      });
+      if (rc) return rc;
       // the tick's size classes: one launch each; with more than one, each on
       // its own stream (fork after the paths, join before the merges) so that
       // the classes share the chip instead of each running partly filled
@@ -503,15 +540,15 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
           if (ord_off[k * kBatchClasses + cl + 1] > ord_off[k * kBatchClasses + cl])
             HIPCHK(hipStreamWaitEvent(st, c->cev[cl], 0));
       // rows completed by this tick: s0+1..s1 (and row 0 in the first chunk)
-      for (auto& p : plans) {
-        if (p.ticks <= k) continue;
+      rc = spread([&](Plan& p, hipStream_t s) {
         const int64_t s0 = k * p.Sc, s1 = std::min<int64_t>(p.S, s0 + p.Sc);
         const int64_t first = s0 == 0 ? 0 : s0 + 1;
-        HIPCHK(launch_stats_merge_rows(p.part + (first - s0) * p.V, (p.Sc + 1) * p.V, p.n_items,
+        return launch_stats_merge_rows(p.part + (first - s0) * p.V, (p.Sc + 1) * p.V, p.n_items,
                                        (int)(p.tiles_per_item * p.bv.TB), p.N, s1 - first + 1, p.V,
                                        p.n, p.par->ddof, p.canon + CanonLayout{p.n, p.P}.delta0(),
-                                       p.mean + first * p.V, p.var + first * p.V, st));
-      }
+                                       p.mean + first * p.V, p.var + first * p.V, s);
+      });
+      if (rc) return rc;
     }
     return FMC_OK;
   };
