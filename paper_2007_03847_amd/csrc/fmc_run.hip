@@ -43,13 +43,26 @@ struct EventPool {
 
 struct ChunkTimes {
   std::vector<int> gemm0, gemm1, int0, int1;
+  int st0 = -1, st1 = -1;  // the last chunk's statistics merge
 };
+
+// The second stream of fmc_run (LHS design, KLE contractions, statistics
+// merges beside the integrator) and its ordering events.
+int ensure_gstream(Context* c) {
+  if (!c->gstream && hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess)
+    return fail(FMC_EDEVICE, "cannot create the contraction stream");
+  for (auto& e : c->gev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return fail(FMC_EDEVICE, "hipEventCreate failed");
+  return FMC_OK;
+}
 
 template <typename R>
 int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t S, int64_t N,
                double wb, const double* zeta, const double* phi, const R* coef,
                const double* delta0, double* partial, const int32_t* slot_d, double* traj_d,
-               unsigned long long* cnt_d, int64_t Sc, EventPool& evp, ChunkTimes& ct) {
+               unsigned long long* cnt_d, int64_t Sc, double* mean_d, double* var_d,
+               EventPool& evp, ChunkTimes& ct) {
   const VariantInfo& vi = variant(vid);
   const int V = 2 * n + P;
   const int64_t C = 2 * S + 1;
@@ -60,19 +73,23 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
   // Two path buffers: the contraction of chunk k+1 runs on a second stream
   // while the integrator consumes chunk k (the integrator is bound by issue
   // latency at low occupancy, so the matrix-core contraction fits beside it).
+  // The statistics rows of chunk k are merged on the second stream too, once
+  // the integrator has finished chunk k, so only the last chunk's merge is
+  // left after the integrator.
   void *w[2] = {nullptr, nullptr}, *state = nullptr;
   int rc;
   if ((rc = c->ensure("w", (size_t)(2 * Sc + 1) * P * N * bw, &w[0]))) return rc;
   if ((rc = c->ensure("w1", (size_t)(2 * Sc + 1) * P * N * bw, &w[1]))) return rc;
   if ((rc = c->ensure("state", (size_t)(2 * vi.NG + vi.PM) * lanes * bw, &state))) return rc;
-  if (!c->gstream) {
-    if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess)
-      return fail(FMC_EDEVICE, "cannot create the contraction stream");
-  }
-  for (auto& e : c->gev)
-    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-      return fail(FMC_EDEVICE, "hipEventCreate failed");
+  if ((rc = ensure_gstream(c))) return rc;
   hipStream_t ks = c->gstream;
+  // merge of the rows completed by chunk [s0, s1] (row 0 with the first)
+  auto merge = [&](int64_t s0, int64_t s1) -> hipError_t {
+    const int64_t first = s0 == 0 ? 0 : s0 + 1;
+    return launch_stats_merge_rows((const double2*)partial + first * V, (S + 1) * V, n_groups,
+                                   (int)gs, N, s1 - first + 1, V, n, par->ddof, delta0,
+                                   mean_d + first * V, var_d + first * V, ks);
+  };
   // the contractions start after the setup work (design, basis) on the main stream
   if (hipEventRecord(c->ev[5], c->stream) != hipSuccess || hipStreamWaitEvent(ks, c->ev[5], 0) != hipSuccess)
     return fail(FMC_EDEVICE, "stream ordering failed");
@@ -112,6 +129,11 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
     ct.gemm1.push_back(evp.record(ks));
     if (hipEventRecord(c->gev[b], ks) != hipSuccess || hipStreamWaitEvent(c->stream, c->gev[b], 0) != hipSuccess)
       return fail(FMC_EDEVICE, "stream ordering failed");
+    if (k >= 1) {  // chunk k-1's rows, after its integrator (queued behind the contraction)
+      const int64_t p0 = s0 - Sc;
+      if (hipStreamWaitEvent(ks, c->gev[2 + (1 - b)], 0) != hipSuccess || merge(p0, s0) != hipSuccess)
+        return fail(FMC_EDEVICE, "statistics merge launch failed");
+    }
     a.w = (const R*)w[b];
     a.s_begin = s0;
     a.s_end = s1;
@@ -127,6 +149,15 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
     if (hipEventRecord(c->gev[2 + b], c->stream) != hipSuccess)
       return fail(FMC_EDEVICE, "stream ordering failed");
   }
+  // the last chunk's rows, then the main stream waits for every merge
+  const int64_t last0 = (k - 1) * Sc;
+  if (hipStreamWaitEvent(ks, c->gev[2 + (int)((k - 1) & 1)], 0) != hipSuccess)
+    return fail(FMC_EDEVICE, "stream ordering failed");
+  ct.st0 = evp.record(ks);
+  if (merge(last0, S) != hipSuccess) return fail(FMC_EDEVICE, "statistics merge launch failed");
+  ct.st1 = evp.record(ks);
+  if (hipEventRecord(c->ev[6], ks) != hipSuccess || hipStreamWaitEvent(c->stream, c->ev[6], 0) != hipSuccess)
+    return fail(FMC_EDEVICE, "stream ordering failed");
   return FMC_OK;
 }
 
@@ -188,7 +219,10 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   if ((rc = c->ensure("phi", (size_t)K * C * sizeof(double), &phi))) return rc;
   HIPCHK(launch_basis(par->basis, K, S, par->T, (double*)phi, c->stream));
 
-  const int ev_lhs0 = evp.record();
+  // the design runs on the second stream, beside the setup work above; the
+  // contractions follow it there
+  if ((rc = ensure_gstream(c))) return rc;
+  const int ev_lhs0 = evp.record(c->gstream);
   const double* zeta = par->zeta_in;
   double* zeta_dev = nullptr;
   int32_t* strata_dev = nullptr;
@@ -208,10 +242,10 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
         strata_dev = (int32_t*)p;
       }
     }
-    HIPCHK(launch_lhs(par->seed, (int32_t)M, N, par->sampler, strata_dev, zeta_dev, c->stream));
+    HIPCHK(launch_lhs(par->seed, (int32_t)M, N, par->sampler, strata_dev, zeta_dev, c->gstream));
     zeta = zeta_dev;
   }
-  const int ev_lhs1 = evp.record();
+  const int ev_lhs1 = evp.record(c->gstream);
 
   // per-workgroup statistics partials, trajectory slots, counters
   const int64_t gsize = vi.group_size();
@@ -254,18 +288,6 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
 
   const int64_t Sc = par->time_chunk > 0 ? std::min<int64_t>(par->time_chunk, S)
                                          : auto_chunk(S, P, N, bw);
-  ChunkTimes ct;
-  if (f64)
-    rc = run_chunks<double>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
-                            (const double*)coef, delta0_d, (double*)partial, slot_d, traj_d,
-                            (unsigned long long*)cnt, Sc, evp, ct);
-  else
-    rc = run_chunks<float>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
-                           (const float*)coef, delta0_d, (double*)partial, slot_d, traj_d,
-                           (unsigned long long*)cnt, Sc, evp, ct);
-  if (rc) return rc;
-
-  const int ev_st0 = evp.record();
   double *mean_d = out->mean, *var_d = out->var;
   if (!dev_out) {
     void *pm = nullptr, *pv = nullptr;
@@ -274,8 +296,17 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     mean_d = (double*)pm;
     var_d = (double*)pv;
   }
-  HIPCHK(launch_stats_merge((const double2*)partial, n_groups, (int)gsize, N, S, V, n, par->ddof, delta0_d,
-                            mean_d, var_d, c->stream));
+  ChunkTimes ct;
+  if (f64)
+    rc = run_chunks<double>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
+                            (const double*)coef, delta0_d, (double*)partial, slot_d, traj_d,
+                            (unsigned long long*)cnt, Sc, mean_d, var_d, evp, ct);
+  else
+    rc = run_chunks<float>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
+                           (const float*)coef, delta0_d, (double*)partial, slot_d, traj_d,
+                           (unsigned long long*)cnt, Sc, mean_d, var_d, evp, ct);
+  if (rc) return rc;
+  // statistics: merged per chunk on the second stream, joined into c->stream
   const int ev_end = evp.record();
 
   if (!dev_out) {
@@ -308,7 +339,7 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
       r->t_gemm_s += evp.secs(ct.gemm0[q], ct.gemm1[q]);
       r->t_integrate_s += evp.secs(ct.int0[q], ct.int1[q]);
     }
-    r->t_stats_s = evp.secs(ev_st0, ev_end);
+    r->t_stats_s = evp.secs(ct.st0, ct.st1);  // the merge left after the integrator
     r->n_nonfinite = (int64_t)cn[0];
     r->first_nonfinite = cn[0] ? (int64_t)cn[1] : -1;
     r->variant_id = vid;
