@@ -46,16 +46,7 @@ struct ChunkTimes {
   int st0 = -1, st1 = -1;  // the last chunk's statistics merge
 };
 
-// The second stream of fmc_run (LHS design, KLE contractions, statistics
-// merges beside the integrator) and its ordering events.
-int ensure_gstream(Context* c) {
-  if (!c->gstream && hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess)
-    return fail(FMC_EDEVICE, "cannot create the contraction stream");
-  for (auto& e : c->gev)
-    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-      return fail(FMC_EDEVICE, "hipEventCreate failed");
-  return FMC_OK;
-}
+
 
 template <typename R>
 int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t S, int64_t N,
@@ -162,6 +153,17 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
 }
 
 }  // namespace
+
+// The second stream of fmc_run (LHS design, KLE contractions, statistics
+// merges beside the integrator) and its ordering events.
+int ensure_gstream(Context* c) {
+  if (!c->gstream && hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess)
+    return fail(FMC_EDEVICE, "cannot create the contraction stream");
+  for (auto& e : c->gev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+      return fail(FMC_EDEVICE, "hipEventCreate failed");
+  return FMC_OK;
+}
 
 #define HIPCHK(expr)                                                                          \
   do {                                                                                        \

@@ -88,6 +88,7 @@ inline bool fd_bf16_product(const fmc_params* p) {
 }
 int default_batch_variant(int n, int P, int precision);
 int64_t auto_chunk(int64_t S, int P, int64_t N, int bytes_per);
+int ensure_gstream(Context* c);  // the second stream of fmc_run and its events
 int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
                const fmc_params* par, fmc_outputs* out);
 void serve_shutdown(Context* c);
