@@ -81,9 +81,8 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
                                    (int)gs, N, s1 - first + 1, V, n, par->ddof, delta0,
                                    mean_d + first * V, var_d + first * V, ks);
   };
-  // the contractions start after the setup work (design, basis) on the main stream
-  if (hipEventRecord(c->ev[5], c->stream) != hipSuccess || hipStreamWaitEvent(ks, c->ev[5], 0) != hipSuccess)
-    return fail(FMC_EDEVICE, "stream ordering failed");
+  // (ks is already ordered after the caller's earlier work, and the design
+  // and basis are on it: the first contraction does not wait for the setup)
   IntegArgs<R> a{};
   a.coef = coef;
   a.state = (R*)state;
@@ -203,6 +202,12 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   evp.st = c->stream;
   const size_t held0 = c->held;
   const int ev_start = evp.record();
+  // The second stream (design, basis, contractions, merges) starts after the
+  // work already queued on the caller's stream, then runs beside the
+  // reduction and setup below.
+  if ((rc = ensure_gstream(c))) return rc;
+  HIPCHK(hipEventRecord(c->ev[5], c->stream));
+  HIPCHK(hipStreamWaitEvent(c->gstream, c->ev[5], 0));
 
   double* canon = nullptr;
   int32_t* gen_d = nullptr;
@@ -219,11 +224,10 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
 
   void* phi = nullptr;
   if ((rc = c->ensure("phi", (size_t)K * C * sizeof(double), &phi))) return rc;
-  HIPCHK(launch_basis(par->basis, K, S, par->T, (double*)phi, c->stream));
+  HIPCHK(launch_basis(par->basis, K, S, par->T, (double*)phi, c->gstream));
 
   // the design runs on the second stream, beside the setup work above; the
   // contractions follow it there
-  if ((rc = ensure_gstream(c))) return rc;
   const int ev_lhs0 = evp.record(c->gstream);
   const double* zeta = par->zeta_in;
   double* zeta_dev = nullptr;
