@@ -36,13 +36,12 @@ constexpr int kNP = kMcMaxGen;    // largest n_pad
 constexpr int kVM = 2 * kNP + kMcMaxProc;
 
 // Static LDS of the class: constants, per-wave dE~ tiles (the larger of the
-// FP32 and BF16 forms), per-wave xi values, two buffers of per-wave
-// statistics, per-trajectory flags.
+// FP32 and BF16 forms), two buffers of per-wave statistics, per-trajectory
+// flags.
 constexpr int kBtileFloats = (2 * kNP * kT > 16 * (2 * kNP + 8)) ? 2 * kNP * kT : 16 * (2 * kNP + 8);
 struct Lds {
   float cst[McPack::kMaxConsts];
   float btile[kWaves][kBtileFloats];
-  float xs[kWaves][kMcMaxProc * kT];
   double2 part[2][kWaves][kVM];
   int bad[kTile];
 };
@@ -116,6 +115,20 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
   const float sg0 = own0 ? S.cst[K.proc() + kMcMaxProc + g] : 0.0f;
   const float th1 = own1 ? S.cst[K.proc() + g + 4] : 0.0f;
   const float sg1 = own1 ? S.cst[K.proc() + kMcMaxProc + g + 4] : 0.0f;
+  // The injections sum_p [gen(p) = m] xi_p of a tile are one more product on
+  // the matrix cores: the 0/1 matrix [machine][process] in A-operand order
+  // (lane l: machine 16b + l%16, process 4s + l/16) against the stage values
+  // of the processes, which lane l holds itself as the B operand (process
+  // 4s + l/16 of trajectory l%16); the result lands on the lanes that own
+  // the machines, like the network current.
+  float ainj[NB][2];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int p = 4 * h + g;
+      ainj[b][h] = (p < P && (int)S.cst[K.proc() + 3 * kMcMaxProc + p] == 16 * b + t) ? 1.0f : 0.0f;
+    }
 
   // State between time chunks: [tile][wave][kRows][64], rows dd (kQ), dw
   // (kQ), the two process slots; kRows = 2 G + PQ of the host's allocation
@@ -210,7 +223,6 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
   if (a.s_begin == 0) emit(0);
 
   float* B = S.btile[wv];
-  float* X = S.xs[wv];
   __bf16* bh = reinterpret_cast<__bf16*>(B);
   __bf16* bl = bh + 16 * BS;
   const float* Bf = B + g * kT + t;
@@ -275,8 +287,6 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
           B[(n_pad + m) * kT + t] = dEi[q];
         }
       }
-      if (own0) X[g * kT + t] = sx0;
-      if (own1) X[(g + 4) * kT + t] = sx1;
       wave_lds_sync();
       // dI = Y dE~ for my machine blocks.  The coefficient pointer passes an
       // empty asm so that Y is streamed from the cache at every stage instead
@@ -334,17 +344,16 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
           }
         }
       }
-      // injections: process p drives machine gen[p]
-      float inj[kQ];
+      // injections of my machines (the matrix cores, as above)
+      f32x4 aj[NB];
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) inj[q] = 0.0f;
-      for (int p = 0; p < P; ++p) {
-        const int gm = (int)S.cst[K.proc() + 3 * kMcMaxProc + p];
-        const float xp = X[p * kT + t];
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) inj[q] += gm == mach(q) ? xp : 0.0f;
+      for (int b = 0; b < NB; ++b) {
+        aj[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        aj[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ainj[b][0], own0 ? sx0 : 0.0f, aj[b], 0, 0, 0);
+        if (P > 4)  // uniform
+          aj[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ainj[b][1], own1 ? sx1 : 0.0f, aj[b], 0, 0, 0);
       }
-      wave_lds_sync();  // tile and xi values read: the next stage may overwrite them
+      wave_lds_sync();  // the tile is read: the next stage may overwrite it
 #pragma unroll
       for (int q = 0; q < kQ; ++q) {
         int mo = K.at(mach(q), 0);
@@ -354,7 +363,7 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
         const float dIr = ar[q >> 2][q & 3], dIi = ai[q >> 2][q & 3];
         const float dpe = dEr[q] * c.z + dEi[q] * c.w + (c.x + dEr[q]) * dIr + (c.y + dEi[q]) * dIi;
         const float kd = wb * sw_[q];
-        const float kw = (e.x - dpe - e.y * sw_[q] + inj[q]) * e.z;
+        const float kw = (e.x - dpe - e.y * sw_[q] + aj[q >> 2][q & 3]) * e.z;
         ad[q] += wgt * kd;
         aw[q] += wgt * kw;
         if (sg < 3) {
