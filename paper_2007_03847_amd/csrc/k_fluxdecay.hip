@@ -509,15 +509,20 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
         }
         __syncthreads();  // every wave is done reading the dE' tile
         // -- after the product: injections, dPe, dId, d|Vt|
-        float inj[kQ];
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) inj[q] = 0.0f;
-        for (int p = 0; p < P; ++p) {
-          const int gm = (int)cst[K.proc() + 3 * kFdMaxProc + p];
-          const float xp = X[p * kT + t];
-#pragma unroll
-          for (int q = 0; q < kQ; ++q)
-            if (gm == mach(q)) inj[q] += xp;
+        // injections sum_p [gen(p) = m] xi_p as a small product on the
+        // matrix cores: the 0/1 matrix [machine][process] in A-operand order
+        // (lane l: machine 16 blk + l%16, process 4s + l/16) against the
+        // processes' stage values (B: process 4s + l/16 of trajectory l%16);
+        // the result lands on the lanes that own the machines
+        f32x4 aj0 = {0.f, 0.f, 0.f, 0.f}, aj1 = aj0;
+        for (int s4 = 0; s4 < (P + 3) / 4; ++s4) {
+          const int p = 4 * s4 + g;
+          const int gm = p < P ? (int)cst[K.proc() + 3 * kFdMaxProc + p] : -1;
+          const float xb = p < P ? X[p * kT + t] : 0.0f;
+          aj0 = __builtin_amdgcn_mfma_f32_16x16x4f32(gm == 32 * wv + t ? 1.0f : 0.0f, xb, aj0, 0, 0, 0);
+          if (two)  // wave-uniform
+            aj1 = __builtin_amdgcn_mfma_f32_16x16x4f32(gm == 32 * wv + 16 + t ? 1.0f : 0.0f, xb, aj1,
+                                                      0, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
@@ -543,7 +548,7 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
           const float vr1 = v0r + vr_, vi1 = v0i + vi_;
           const float va = sqrtf(vr1 * vr1 + vi1 * vi1);
           const float dva = (2.0f * (v0r * vr_ + v0i * vi_) + vr_ * vr_ + vi_ * vi_) / (va + g2.w);
-          const float kw = (pw[q] - dpe + inj[q]) * g3.z;
+          const float kw = (pw[q] - dpe + (q < 4 ? aj0[r] : aj1[r])) * g3.z;
           const float ke = pe[q] - g4.x * did;
           const float kv = pv[q] - g5.y * dva;
           accl[(1 * kQ + q) * 64] = st == 0 ? kw : accl[(1 * kQ + q) * 64] + wgt * kw;
