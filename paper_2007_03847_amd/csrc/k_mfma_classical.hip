@@ -71,7 +71,7 @@ hipError_t launch_pack_batch(const BatchVariantInfo& b, const double* canon, int
 // counts need more and run one wave per SIMD.
 template <int NB>
 __global__ void __launch_bounds__(64 * mc::kWaves)
-    __attribute__((amdgpu_waves_per_eu(NB == 2 ? 2 : 1))) k_rk4_persistent_mc(BatchArgs b) {
+    __attribute__((amdgpu_waves_per_eu(NB <= 3 ? 2 : 1))) k_rk4_persistent_mc(BatchArgs b) {
   __shared__ __attribute__((aligned(16))) mc::Lds S;
   __shared__ int s_item;
   for (;;) {
