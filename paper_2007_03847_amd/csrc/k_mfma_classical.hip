@@ -67,8 +67,9 @@ hipError_t launch_pack_batch(const BatchVariantInfo& b, const double* canon, int
         mc_tile<BF != 0, NBV>(a, t, S, GroupStats{rows, (t - it.tile0) * mc::kTile}); \
   ++id;
 
-// NB = 2 is held to 256 registers (two waves per SIMD); the larger block
-// counts need more and run one wave per SIMD.
+// NB = 2 and 3 are held to 256 registers (two waves per SIMD; for NB = 3 at
+// the cost of spills, measured faster: 38.8 -> 34.5 ms at 33 machines); NB = 4
+// runs one wave per SIMD (two waves with its spills measured slower).
 template <int NB>
 __global__ void __launch_bounds__(64 * mc::kWaves)
     __attribute__((amdgpu_waves_per_eu(NB <= 3 ? 2 : 1))) k_rk4_persistent_mc(BatchArgs b) {
