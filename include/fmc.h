@@ -171,7 +171,7 @@ typedef struct fmc_params {
                                 BF16 hi+lo split products, faster but with larger
                                 error (measured over 30 s: 1.5e-3 of the mean,
                                 6e-3 of the variance, against 4e-5 and 3e-4 in
-                                FP32).  Batched form: ids 14-16 (FMC_BF16X3
+                                FP32).  Batched form: ids 14-16 and 18 (FMC_BF16X3
                                 only) likewise take the classical network
                                 product in BF16 split products; the tuner never
                                 picks them. */

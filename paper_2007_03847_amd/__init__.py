@@ -405,7 +405,8 @@ given, is a list (one entry per scenario, None allowed) of sample indices;
 time_chunk > 0 sets the steps per tick (else 250); variant is one id for
 every scenario or a list of ids (-1: tuned).  Variant ids 0-10 are the
 lane variants, 11-13 the FP32 matrix-core variants for up to 32, 48, 64
-machines and 14-16 their BF16 x3 forms (FMC_BF16X3 scenarios only)."""
+machines and 14-16 their BF16 x3 forms (FMC_BF16X3 scenarios only), 17 and 18
+the same pair for up to 16 machines."""
 
 
 class Ticket:

@@ -65,7 +65,7 @@ std::string nm(int i, const char* what) { return "b" + std::to_string(i) + "_" +
 
 // Candidates of the batched integrator for (n, P): the three smallest lane
 // variants that fit, then the smallest fitting matrix-core variant with the
-// FP32 product (for n > 16, where the padded product is not mostly zeros).
+// FP32 product (for n > 8, where the padded product is not mostly zeros).
 // The BF16 x3 product variants run only when asked for by id: over long
 // horizons their statistics drift past the reduced-precision tolerance
 // (measured: 2e-4 of the mean and 5e-4 of the variance after 28 s, against
@@ -78,7 +78,7 @@ std::vector<int> batch_candidates(int n, int P, int precision) {
     if (!batch_fits(b, n, P, precision)) continue;
     if (b.prod == 0) {
       lane.push_back(i);
-    } else if (n > 16 && (mc[b.prod] < 0 || b.NG < batch_variant(mc[b.prod]).NG)) {
+    } else if (n > 8 && (mc[b.prod] < 0 || b.NG < batch_variant(mc[b.prod]).NG)) {
       mc[b.prod] = i;
     }
   }

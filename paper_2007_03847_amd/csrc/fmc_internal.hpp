@@ -160,19 +160,19 @@ struct BatchArgs {
   int32_t* head;                 // queue counter, zero before the launch
 };
 // prod: how a variant forms the network current: 0 lanes and FMAs (classes
-// 0-2), 1 FP32 matrix cores, 2 BF16 x3 matrix cores (classes 3-5, one per
-// count of 16-machine blocks: 2, 3, 4).
+// 0-2), 1 FP32 matrix cores, 2 BF16 x3 matrix cores (classes 3-6, one per
+// count of 16-machine blocks: 1, 2, 3, 4).
 struct BatchVariantInfo {
   int id, NG, PM, L, TB, cls, prod;
 };
-constexpr int kBatchClasses = 6;
+constexpr int kBatchClasses = 7;
 int n_batch_variants();
 BatchVariantInfo batch_variant(int i);
 int persistent_blocks_per_cu(int cls);
 hipError_t launch_persistent(int cls, const BatchArgs& b, int grid, hipStream_t st);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, int64_t n, hipStream_t st);
 
-// Matrix-core classical variants (classes 3-5): up to kMcMaxGen machines and
+// Matrix-core classical variants (classes 3-6): up to kMcMaxGen machines and
 // kMcMaxProc processes, 64 trajectories per workgroup tile.
 constexpr int kMcMaxGen = 64;
 constexpr int kMcMaxProc = 8;
@@ -196,12 +196,12 @@ struct McPack {
 };
 hipError_t launch_pack_mc(const double* canon, int n, int P, const int32_t* gen, int n_pad, bool bf,
                           float* coef, hipStream_t st);
-// nb: 16-machine blocks of the class (2, 3 or 4)
+// nb: 16-machine blocks of the class (1 to 4)
 int persistent_mc_blocks_per_cu(int nb);
 hipError_t launch_persistent_mc(int nb, const BatchArgs& b, int grid, hipStream_t st);
 // State buffer of a batched variant (floats) for `tiles` trajectory tiles:
 // 2 G + PQ rows (G = ceil(NG / L), PQ = ceil(PM / L)) of 256 lanes per tile;
-// the lane classes address it [row][lanes], classes 3-5 [tile][wave][row][64].
+// the lane classes address it [row][lanes], classes 3-6 [tile][wave][row][64].
 inline size_t batch_state_floats(const BatchVariantInfo& b, int64_t tiles) {
   const int G = (b.NG + b.L - 1) / b.L, PQ = (b.PM + b.L - 1) / b.L;
   return (size_t)(2 * G + PQ) * (size_t)tiles * 64 * 4;

@@ -113,10 +113,10 @@ BatchVariantInfo batch_variant(int i) {
   cls = 2;
   FMC_BATCH_CLASS2(FMC_X)
 #undef FMC_X
-  // classes 3-5 (NB = 2, 3, 4): 16 NB machines, kMcMaxProc processes, 4 lanes
+  // classes 3-6 (NB = 1 to 4): 16 NB machines, kMcMaxProc processes, 4 lanes
   // per trajectory in the state layout, 64-trajectory tiles
 #define FMC_X(NB, BF)                                                                  \
-  if (i == id) return BatchVariantInfo{id, 16 * NB, kMcMaxProc, 4, 64, 1 + NB, 1 + BF}; \
+  if (i == id) return BatchVariantInfo{id, 16 * NB, kMcMaxProc, 4, 64, 2 + NB, 1 + BF}; \
   ++id;
   FMC_BATCH_MFMA(FMC_X)
 #undef FMC_X
@@ -124,7 +124,7 @@ BatchVariantInfo batch_variant(int i) {
 }
 
 hipError_t launch_persistent(int cls, const BatchArgs& b, int grid, hipStream_t st) {
-  if (cls >= 3) return launch_persistent_mc(cls - 1, b, grid, st);
+  if (cls >= 3) return launch_persistent_mc(cls - 2, b, grid, st);
   if (cls == 0)
     hipLaunchKernelGGL(k_rk4_persistent<0>, dim3((unsigned)grid), dim3(64 * kBatchWPB), 0, st, b);
   else if (cls == 1)
@@ -135,7 +135,7 @@ hipError_t launch_persistent(int cls, const BatchArgs& b, int grid, hipStream_t 
 }
 
 int persistent_blocks_per_cu(int cls) {
-  if (cls >= 3) return persistent_mc_blocks_per_cu(cls - 1);
+  if (cls >= 3) return persistent_mc_blocks_per_cu(cls - 2);
   int nb = 0;
   hipError_t e;
   if (cls == 0)

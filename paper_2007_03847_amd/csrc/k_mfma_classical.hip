@@ -1,4 +1,4 @@
-// k_mfma_classical.hip -- classes 3-5 of the persistent batched integrator:
+// k_mfma_classical.hip -- classes 3-6 of the persistent batched integrator:
 // classical machines with the network current on the matrix cores (the
 // device code is in k_mfma_classical.hpp), and the packing of its
 // coefficient block.
@@ -67,7 +67,7 @@ hipError_t launch_pack_batch(const BatchVariantInfo& b, const double* canon, int
         mc_tile<BF != 0, NBV>(a, t, S, GroupStats{rows, (t - it.tile0) * mc::kTile}); \
   ++id;
 
-// NB = 2 and 3 are held to 256 registers (two waves per SIMD; for NB = 3 at
+// NB = 1 to 3 are held to 256 registers (two waves per SIMD; for NB = 3 at
 // the cost of spills, measured faster: 38.8 -> 34.5 ms at 33 machines); NB = 4
 // runs one wave per SIMD (two waves with its spills measured slower).
 template <int NB>
@@ -101,12 +101,17 @@ static int blocks_per_cu() {
 }
 
 int persistent_mc_blocks_per_cu(int nb) {
-  return nb == 2 ? blocks_per_cu<2>() : nb == 3 ? blocks_per_cu<3>() : blocks_per_cu<4>();
+  return nb == 1   ? blocks_per_cu<1>()
+         : nb == 2 ? blocks_per_cu<2>()
+         : nb == 3 ? blocks_per_cu<3>()
+                   : blocks_per_cu<4>();
 }
 
 hipError_t launch_persistent_mc(int nb, const BatchArgs& b, int grid, hipStream_t st) {
   const dim3 g((unsigned)grid), blk(64 * mc::kWaves);
-  if (nb == 2)
+  if (nb == 1)
+    hipLaunchKernelGGL(k_rk4_persistent_mc<1>, g, blk, 0, st, b);
+  else if (nb == 2)
     hipLaunchKernelGGL(k_rk4_persistent_mc<2>, g, blk, 0, st, b);
   else if (nb == 3)
     hipLaunchKernelGGL(k_rk4_persistent_mc<3>, g, blk, 0, st, b);

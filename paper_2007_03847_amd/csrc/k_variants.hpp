@@ -60,16 +60,19 @@
   X(50, 8, 50)
 #define FMC_BATCH_VARIANTS(X) FMC_BATCH_CLASS0(X) FMC_BATCH_CLASS1(X) FMC_BATCH_CLASS2(X)
 
-// Matrix-core variants of the batched integrator (classes 3-5, one persistent
+// Matrix-core variants of the batched integrator (classes 3-6, one persistent
 // kernel per NB): X(NB blocks of 16 machines, BF), BF = 1 for the BF16 x3
-// product of the network current, 0 for FP32.
+// product of the network current, 0 for FP32.  Ids follow the lane variants
+// in this order (the 16-machine pair came last).
 #define FMC_BATCH_MFMA(X) \
   X(2, 0)                 \
   X(3, 0)                 \
   X(4, 0)                 \
   X(2, 1)                 \
   X(3, 1)                 \
-  X(4, 1)
+  X(4, 1)                 \
+  X(1, 0)                 \
+  X(1, 1)
 
 // Number of lane (class 0-2) variants; the matrix-core ids follow them.
 constexpr int batch_n_lane_variants() {

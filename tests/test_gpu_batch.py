@@ -112,12 +112,14 @@ def test_uneven_64_scenarios_sampled(ctx):
         assert np.all(np.isfinite(v)) and np.all(v >= 0) and np.all(v[0] == 0)
 
 
-# Matrix-core variants (class 3): ids 11-13 FP32 product for up to 32, 48, 64
-# machines, 14-16 the BF16 x3 product.  Cases span several 64-trajectory tiles
-# with a ragged tail, eight processes (the second process slot of a lane), a
-# system above the lane variants' 50 machines, and time chunks (state kept
-# between ticks, a short last chunk).
-MC_CASES = [(20, 3, 150, 2), (33, 8, 64, 3), (47, 5, 200, 4), (61, 2, 129, 4)]
+# Matrix-core variants: ids 11-13 FP32 product for up to 32, 48, 64 machines,
+# 14-16 the BF16 x3 product, 17 / 18 the two for up to 16 machines.  Cases
+# span several 64-trajectory tiles with a ragged tail, eight processes (the
+# second process slot of a lane), a system above the lane variants' 50
+# machines, and time chunks (state kept between ticks, a short last chunk).
+MC_CASES = [(13, 4, 150, 1), (20, 3, 150, 2), (33, 8, 64, 3), (47, 5, 200, 4), (61, 2, 129, 4)]
+MC_F32 = {1: 17, 2: 11, 3: 12, 4: 13}
+MC_BF = {1: 18, 2: 14, 3: 15, 4: 16}
 
 
 @pytest.mark.parametrize("n,P,N,NB", MC_CASES)
@@ -126,7 +128,7 @@ def test_batch_matrix_core_variants(ctx, n, P, N, NB):
                                 seed=40 + n)
     sel = np.array([0, N // 2, N - 1])
     o = oracle.run(sc, want_traj=True)
-    runs = [("f32", 11 + NB - 2), ("bf16x3", 11 + NB - 2), ("bf16x3", 14 + NB - 2)]
+    runs = [("f32", MC_F32[NB]), ("bf16x3", MC_F32[NB]), ("bf16x3", MC_BF[NB])]
     for prec, vid in runs:
         r = ctx.run_batch([sc], precision=prec, variant=vid, traj_idx=[sel], time_chunk=50)[0]
         em = mean_err(_np(r["mean"]), o["mean"], o["var"])
