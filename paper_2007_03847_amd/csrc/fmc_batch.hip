@@ -96,11 +96,11 @@ bool batch_fits(const BatchVariantInfo& b, int n, int P, int precision) {
   return b.NG >= n && b.PM >= P && (b.prod != 2 || precision == FMC_BF16X3);
 }
 
-// Untuned choice: above 16 machines the matrix-core class with the FP32
-// product, measured faster than the lane variants there when the chip is
-// shared; otherwise the smallest lane variant that fits.
+// Untuned choice: from 12 machines on the matrix-core class with the FP32
+// product, measured faster than the lane variants there; otherwise the
+// smallest lane variant that fits.
 int default_batch_variant(int n, int P, int precision) {
-  const bool mc = n > 16;
+  const bool mc = n >= 12;
   int vid = -1;
   for (int pass = 0; pass < 2 && vid < 0; ++pass)  // pass 1: whatever fits
     for (int i = 0; i < n_batch_variants(); ++i) {
