@@ -226,9 +226,9 @@ __device__ __forceinline__ double row16_sum(double v) {
 
 // Mean and M2 of a row's 16 values (invalid lanes excluded), stored by the
 // row's first lane: every tile has rows of its own, so nothing is read back.
-__device__ __forceinline__ void row_stats(double x, bool valid, double cnt, bool writer,
+__device__ __forceinline__ void row_stats(double x, bool valid, double inv_cnt, bool writer,
                                           double2* dst) {
-  const double mu = row16_sum(valid ? x : 0.0) / cnt;
+  const double mu = row16_sum(valid ? x : 0.0) * inv_cnt;
   const double d = valid ? x - mu : 0.0;
   const double m2 = row16_sum(d * d);
   if (writer) *dst = make_double2(mu, m2);
@@ -300,6 +300,7 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
     const int64_t ns = valid ? traj : a.N - 1;
     const int64_t rem = a.N - tile * kT;
     const double cnt = (double)(rem < kT ? rem : kT);
+    const double inv_cnt = 1.0 / cnt;  // one division per tile, not per variable
     double2* rows = a.rows + tile * a.row_stride;  // this tile's statistics rows
     const int slot = (valid && a.traj_slot) ? a.traj_slot[ns] : -1;
     // state: deviations of (delta, dw, E'q, Efd, VR, RF) of my machines; xi
@@ -337,13 +338,13 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
         if (m < nl) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) {
-            row_stats((double)y[c][q], valid, cnt, t == 0, row + c * nl + m);
+            row_stats((double)y[c][q], valid, inv_cnt, t == 0, row + c * nl + m);
             if (o) o[c * nl + m] = offl[c * nl + m] + (double)y[c][q];
           }
         }
       }
       if (proc) {
-        row_stats((double)x, valid, cnt, t == 0, row + 6 * n + pg);
+        row_stats((double)x, valid, inv_cnt, t == 0, row + 6 * n + pg);
         if (o) o[6 * n + pg] = (double)x;
       }
     };
