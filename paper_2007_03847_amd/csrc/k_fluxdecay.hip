@@ -547,8 +547,14 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
           const float vr_ = dEr[q] + xdp * dIi, vi_ = dEi[q] - xdp * dIr;
           const float v0r = g2.y, v0i = g2.z;
           const float vr1 = v0r + vr_, vi1 = v0i + vi_;
-          const float va = sqrtf(vr1 * vr1 + vi1 * vi1);
-          const float dva = (2.0f * (v0r * vr_ + v0i * vi_) + vr_ * vr_ + vi_ * vi_) / (va + g2.w);
+          // |Vt| and the quotient through the hardware reciprocal square root
+          // and reciprocal (about 1 ulp each; |Vt| only scales the small
+          // deviation here, and the sum of squares is kept above zero for
+          // the padding machines, whose |Vt| is 0)
+          const float vs = fmaxf(vr1 * vr1 + vi1 * vi1, 1e-30f);
+          const float va = vs * __builtin_amdgcn_rsqf(vs);
+          const float dva = (2.0f * (v0r * vr_ + v0i * vi_) + vr_ * vr_ + vi_ * vi_) *
+                            __builtin_amdgcn_rcpf(va + g2.w);
           const float kw = (pw[q] - dpe + (q < 4 ? aj0[r] : aj1[r])) * g3.z;
           const float ke = pe[q] - g4.x * did;
           const float kv = pv[q] - g5.y * dva;
