@@ -44,6 +44,8 @@ struct Lds {
   float btile[kWaves][kBtileFloats];
   double2 part[2][kWaves][kVM];
   int bad[kTile];
+  double cw[2][kWaves];  // Chan weights of the tile's in-order wave merge
+  double pw[2];          // and of its merge into the item's earlier tiles
 };
 
 __device__ __forceinline__ double dpp_f64(double v, int ctrl_id) {
@@ -102,10 +104,28 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
     return (double)(r <= 0 ? 0 : (r < kT ? r : kT));
   };
   const double wcnt = wave_count(wv);
+  const double winv = wcnt > 0.0 ? 1.0 / wcnt : 0.0;
+
   const int slot = (valid && a.traj_slot) ? a.traj_slot[ns] : -1;
 
   __syncthreads();  // every reader of the previous tile's constants is done
   for (int q = tid; q < K.consts(); q += blockDim.x) S.cst[q] = a.coef[q];
+  if (tid == 0) {
+    // Chan weights (the same at every step of the tile): merging wave w into
+    // waves 0..w-1 uses nb / tot and cnt nb / tot, then the tile into the
+    // item's st.prev earlier samples; computed once rather than divided at
+    // every step
+    double cnt = 0.0;
+    for (int w = 0; w < kWaves; ++w) {
+      const double nb = wave_count(w), tot = cnt + nb;
+      S.cw[0][w] = tot > 0.0 ? nb / tot : 0.0;
+      S.cw[1][w] = tot > 0.0 ? cnt * nb / tot : 0.0;
+      cnt = tot;
+    }
+    const double ptot = (double)st.prev + cnt;
+    S.pw[0] = cnt / ptot;
+    S.pw[1] = (double)st.prev * cnt / ptot;
+  }
   __syncthreads();
 
   auto mach = [&](int q) { return 16 * (q >> 2) + 4 * g + (q & 3); };
@@ -165,7 +185,7 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
     asm volatile("" : "+v"(nl), "+v"(d0));
     double2* part = S.part[pbuf][wv];
     double* o = slot >= 0 ? a.traj + ((int64_t)slot * (a.S + 1) + s) * V : nullptr;
-    const double inv = wcnt > 0.0 ? 1.0 / wcnt : 0.0;
+    const double inv = winv;
     auto one = [&](double xv, int v) {
       const double mu = row16_sum(valid ? xv : 0.0) * inv;
       const double d = valid ? xv - mu : 0.0;
@@ -195,27 +215,22 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
     __syncthreads();
     double2* dst = st.rows + s * V;
     for (int v = tid; v < V; v += blockDim.x) {
-      double cnt = 0.0, mu = 0.0, M2 = 0.0;
+      // wave 0 always has valid trajectories (a tile exists only if it does)
+      double mu = S.part[pbuf][0][v].x, M2 = S.part[pbuf][0][v].y;
 #pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        const double nb = wave_count(w);
-        if (nb == 0.0) continue;
+      for (int w = 1; w < kWaves; ++w) {
+        if (wave_count(w) == 0.0) continue;  // the tile's trailing empty waves
         const double2 pt = S.part[pbuf][w][v];
-        if (cnt == 0.0) {
-          cnt = nb; mu = pt.x; M2 = pt.y;
-        } else {
-          const double tot = cnt + nb, dl = pt.x - mu;
-          mu += dl * (nb / tot);
-          M2 += pt.y + dl * dl * (cnt * nb / tot);
-          cnt = tot;
-        }
+        const double dl = pt.x - mu;
+        mu += dl * S.cw[0][w];
+        M2 += pt.y + dl * dl * S.cw[1][w];
       }
       if (st.prev == 0) {
         dst[v] = make_double2(mu, M2);
       } else {
         const double2 old = dst[v];
-        const double na = (double)st.prev, tot = na + cnt, dl = mu - old.x;
-        dst[v] = make_double2(old.x + dl * (cnt / tot), old.y + M2 + dl * dl * (na * cnt / tot));
+        const double dl = mu - old.x;
+        dst[v] = make_double2(old.x + dl * S.pw[0], old.y + M2 + dl * dl * S.pw[1]);
       }
     }
     pbuf ^= 1;  // the next step fills the other buffer: one barrier per step suffices
@@ -288,11 +303,13 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
         }
       }
       wave_lds_sync();
-      // dI = Y dE~ for my machine blocks.  The coefficient pointer passes an
-      // empty asm so that Y is streamed from the cache at every stage instead
-      // of being hoisted into (spilled) registers for the whole run.
+      // dI = Y dE~ for my machine blocks.  With one block the lane's Y
+      // fragments (8 or 16 registers) stay in registers for the whole tile;
+      // with more, the coefficient pointer passes an empty asm so that Y is
+      // streamed from the cache at every stage instead of being hoisted into
+      // (spilled) registers.
       const float* cf = a.coef;
-      asm volatile("" : "+v"(cf));
+      if constexpr (NB > 1) asm volatile("" : "+v"(cf));
       const float2* ap = reinterpret_cast<const float2*>(cf + K.frag()) + l;
       const u32x4* aq = reinterpret_cast<const u32x4*>(cf + K.frag()) + (int64_t)l * 4;
       f32x4 ar[NB], ai[NB];
