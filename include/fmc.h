@@ -69,6 +69,15 @@ extern "C" {
 /* KLE basis (Sec. IV-A). */
 #define FMC_BASIS_PAPER 0 /* eq. 7: m_1 = sqrt(1/T), m_j = sqrt(2/T) cos((j-1) pi t/T) */
 #define FMC_BASIS_EIGEN 1 /* Wiener eigenfunctions: sqrt(2/T) cos((j-1/2) pi t/T) */
+/* Traditional Monte Carlo (eq. 5, Euler-Maruyama increments) through the same
+ * path contraction: K must equal S, and m_j is 1.5/sqrt(dt) at the midpoint
+ * stage t = (j + 1/2) dt of step j and 0 at every other stage time, so the
+ * coefficient zeta_{p,j} is step j's standard normal and enters the RK4 step
+ * through its two midpoint stages (weight 4/6), giving the increment
+ * sigma sqrt(dt) zeta_{p,j} of eq. 5 up to O(theta dt) terms of the drift.
+ * It is the baseline of the paper's comparison, not a tuned path: the
+ * contraction multiplies by a one-hot basis. */
+#define FMC_BASIS_EM 2
 
 /* Sampler of the KLE coefficients (Sec. IV-B). */
 #define FMC_LHS 0 /* Latin hypercube: one draw per stratum, permuted per row */

@@ -153,7 +153,7 @@ def kron(net: dict):
 
 
 _SAMPLER = {"lhs": 0, "srs": 1}
-_BASIS = {"paper": 0, "eigen": 1}
+_BASIS = {"paper": 0, "eigen": 1, "em": 2}
 _INTEG = {"rk4": 0, "trap": 1}
 _MODEL = {"classical": 0, "fluxdecay": 1}
 

@@ -17,7 +17,9 @@
  *   philox         -> numpy.random.Philox (Philox-4x64-10)
  *   ppnd16         -> scipy.special.ndtri
  *   lhs            -> one sample per stratum, stratum bounds, bijection
- *   basis          -> orthonormality, Var W_K(t) closed form, eigen-KLE (Nystrom)
+ *   basis          -> orthonormality, Var W_K(t) closed form, eigen-KLE (Nystrom);
+ *                     EM basis: one-hot rows, the eq. 5 increment of a unit
+ *                     impulse, and the OU variance of EM paths (statistical)
  *   run (OU part)  -> OU closed-form mean/variance of the truncated KLE
  *   run (swing)    -> SMIB linearised variance (Lyapunov / Van Loan), RK4 order
  *   kron           -> SMIB reduction to E V sin(delta)/X, symmetry, full solve
@@ -252,6 +254,11 @@ int orc_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int64_t n_sel,
 /* kind 1: the eigenfunctions of the Wiener covariance min(s,t), whose        */
 /*         derivatives are sqrt(2/T) cos((j-1/2) pi t / T).                   */
 /* The cosine argument is reduced exactly in integers before the call.        */
+/* kind 2: the traditional Monte Carlo of eq. 5 written as a basis: row j is  */
+/*         one step's white-noise sample, 1.5 / sqrt(dt) at the midpoint     */
+/*         stage c = 2j + 1 of step j (RK4 weighs the two midpoint stages    */
+/*         4/6 in all, so the step's increment is sigma sqrt(dt) zeta), and  */
+/*         0 at every other stage; K = S.                                    */
 /* Output Phi[j][c], j = 0..K-1 (row j is the paper's m_{j+1}).               */
 /* ------------------------------------------------------------------------- */
 int orc_basis(int32_t kind, int32_t K, int64_t S, double T, double *Phi)
@@ -262,7 +269,9 @@ int orc_basis(int32_t kind, int32_t K, int64_t S, double T, double *Phi)
     for (int32_t j = 0; j < K; ++j) {
         for (int64_t c = 0; c < C; ++c) {
             double v;
-            if (kind == 0) {
+            if (kind == 2) {
+                v = (c == 2 * (int64_t)j + 1) ? 1.5 / sqrt(T / (double)S) : 0.0;
+            } else if (kind == 0) {
                 if (j == 0) {
                     v = a1;
                 } else {

@@ -31,7 +31,7 @@ _lib = C.CDLL(LIB_PATH)
 OK, EINVAL, ENOMEM, EBUSY, EDEVICE, ENONFINITE, ENOTCONV, ECANCELLED, EAGAIN, ETIMEDOUT = \
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 F64, F32, BF16X3 = 0, 1, 2
-BASIS = {"paper": 0, "eigen": 1}
+BASIS = {"paper": 0, "eigen": 1, "em": 2}
 SAMPLER = {"lhs": 0, "srs": 1}
 INTEGRATOR = {"rk4": 0, "trap": 1}
 PRECISION = {"f64": F64, "f32": F32, "bf16x3": BF16X3}

@@ -254,8 +254,10 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
   if (par->K < 1) return fail(FMC_EINVAL, "K must be >= 1");
   if (par->N < 2) return fail(FMC_EINVAL, "N must be >= 2");
   if (par->ddof < 0 || par->ddof >= par->N) return fail(FMC_EINVAL, "ddof must be in [0, N)");
-  if (par->basis != FMC_BASIS_PAPER && par->basis != FMC_BASIS_EIGEN)
+  if (par->basis != FMC_BASIS_PAPER && par->basis != FMC_BASIS_EIGEN && par->basis != FMC_BASIS_EM)
     return fail(FMC_EINVAL, "unknown basis");
+  if (par->basis == FMC_BASIS_EM && par->K != S)
+    return fail(FMC_EINVAL, "the EM basis needs K = S (one normal per step and process)");
   if (par->sampler != FMC_LHS && par->sampler != FMC_SRS) return fail(FMC_EINVAL, "unknown sampler");
   if (par->integrator != FMC_RK4) return fail(FMC_EINVAL, "only the RK4 integrator runs on the GPU");
   if (par->precision < FMC_F64 || par->precision > FMC_BF16X3)
@@ -494,7 +496,9 @@ int fmc_lhs(fmc_context* ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampl
 int fmc_basis(fmc_context* ctx, int32_t basis, int32_t K, int64_t S, double T, double* phi) {
   if (!ctx || !phi) return fail(FMC_EINVAL, "NULL argument");
   if (K < 1 || S < 1 || !(T > 0.0)) return fail(FMC_EINVAL, "K >= 1, S >= 1, T > 0 required");
-  if (basis != FMC_BASIS_PAPER && basis != FMC_BASIS_EIGEN) return fail(FMC_EINVAL, "unknown basis");
+  if (basis != FMC_BASIS_PAPER && basis != FMC_BASIS_EIGEN && basis != FMC_BASIS_EM)
+    return fail(FMC_EINVAL, "unknown basis");
+  if (basis == FMC_BASIS_EM && K > S) return fail(FMC_EINVAL, "the EM basis has at most S rows");
   Context* c = reinterpret_cast<Context*>(ctx);
   (void)hipSetDevice(c->device);
   hipError_t e = launch_basis(basis, K, S, T, phi, c->stream);

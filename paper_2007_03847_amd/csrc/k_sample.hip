@@ -55,6 +55,8 @@ hipError_t launch_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int3
 // KLE basis (eq. 7) at the stage times t_c = c T/(2S).  The cosine argument is
 // reduced exactly in integers: (j c) mod 4S for the paper basis,
 // ((2j+1) c) mod 8S for the eigen basis, then cospi of the reduced fraction.
+// Kind 2 is the one-hot basis of the Euler-Maruyama baseline (eq. 5): row j
+// is 1.5 / sqrt(dt) at the midpoint stage c = 2j + 1 of step j, else 0.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_basis(int32_t kind, int32_t K, int64_t S, double T,
                                                double* __restrict__ phi) {
@@ -64,7 +66,9 @@ __global__ void __launch_bounds__(256) k_basis(int32_t kind, int32_t K, int64_t 
   if (c >= C || j >= K) return;
   const double a2 = sqrt(2.0 / T);
   double v;
-  if (kind == 0) {
+  if (kind == 2) {
+    v = c == 2 * j + 1 ? 1.5 / sqrt(T / (double)S) : 0.0;
+  } else if (kind == 0) {
     if (j == 0) {
       v = sqrt(1.0 / T);
     } else {

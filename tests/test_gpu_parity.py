@@ -82,6 +82,15 @@ def test_basis(ctx, kind, K, S, T):
     assert np.max(np.abs(phi - ref)) <= 1e-15 * np.sqrt(2.0 / T) * 4
 
 
+@pytest.mark.parametrize("S,T", [(1, 0.01), (50, 0.5), (400, 4.0)])
+def test_em_basis(ctx, S, T):
+    """The one-hot basis of the traditional Monte Carlo baseline (eq. 5)."""
+    phi = _np(ctx.basis(2, S, S, T))
+    ref = oracle.basis(2, S, S, T)
+    assert np.array_equal(phi != 0, ref != 0)
+    assert np.max(np.abs(phi - ref)) <= 1e-15 * np.abs(ref).max()
+
+
 # ------------------------------------------------------------ KLE paths
 @pytest.mark.parametrize("P,K,N,S", [(1, 40, 1000, 100), (3, 100, 777, 60), (2, 5, 65, 9),
                                      (1, 1, 1, 1)])
@@ -225,3 +234,27 @@ def test_nonfinite_paths_are_counted(ctx, fmc):
     assert r["rc"] == fmc.ENONFINITE
     assert r["report"]["n_nonfinite"] > 0
     assert r["report"]["first_nonfinite"] >= 0
+
+
+@pytest.mark.parametrize("sampler", ["srs", "lhs"])
+def test_em_baseline_fp64_parity(ctx, sampler):
+    """Traditional Monte Carlo (eq. 5 increments through the one-hot basis,
+    K = S) on the 10-machine system: FP64 trajectories and statistics against
+    the oracle; FP32 statistics to the reduced-precision bound."""
+    sc = workloads.config2(N=300, T=0.4)
+    sc = dict(sc, basis="em", K=80, sampler=sampler)
+    sel = np.array([0, 150, 299])
+    r = _traj_check(ctx, sc, sel)
+    o = oracle.run(sc)
+    assert rel_err(_np(r["mean"]), o["mean"]) <= 1e-10
+    assert rel_err(_np(r["var"]), o["var"]) <= 1e-10
+    r32 = ctx.run(sc, precision="f32")
+    assert mean_err(_np(r32["mean"]), o["mean"], o["var"]) <= 1e-4
+    assert rel_err(_np(r32["var"]), o["var"]) <= 1e-4
+
+
+def test_em_basis_needs_k_equal_s(ctx, fmc):
+    sc = dict(workloads.config2(N=100, T=0.4), basis="em", K=40)
+    with pytest.raises(fmc.FmcError) as e:
+        ctx.run(sc, precision="f64")
+    assert e.value.code == fmc.EINVAL

@@ -535,3 +535,55 @@ def test_subset_run_uses_the_same_design():
     sel = np.array([3, 17, 49])
     sub = oracle.run(sc, sel=sel, want_traj=True)["traj"]
     assert np.array_equal(full[sel], sub)
+
+
+# ---- traditional Monte Carlo (eq. 5) as the one-hot "EM" basis ----
+
+def test_em_basis_rows_are_one_hot():
+    S, T = 50, 0.5
+    Phi = oracle.basis(2, S, S, T)
+    nz = np.argwhere(Phi != 0.0)
+    assert nz.shape == (S, 2)
+    assert np.array_equal(nz[:, 1], 2 * np.arange(S) + 1)  # the midpoint stage of each step
+    assert np.allclose(Phi[nz[:, 0], nz[:, 1]], 1.5 / np.sqrt(T / S), rtol=0, atol=1e-15)
+
+
+def test_em_unit_impulse_gives_the_eq5_increment():
+    """One unit normal in step j: RK4 on d xi = -theta xi dt + sigma w dt with
+    the midpoint-stage forcing 1.5/sqrt(h) (zero at the step ends) gives, by
+    RK4 applied to the linear equation, xi(t_{j+1}) = sigma sqrt(h) (1 -
+    theta h / 2 + theta^2 h^2 / 8): the EM increment sigma sqrt(h) of eq. 5 up
+    to O(theta h), and 0 before step j."""
+    h, S, theta, sigma, j = 0.01, 40, 0.5, 0.05, 7
+    sc = workloads.smib(N=2, K=S, T=S * h, dt=h, theta=theta, sigma=sigma, basis="em")
+    z = np.zeros((S, 1)); z[j, 0] = 1.0
+    r = oracle.run(sc, zeta=z, sel=np.array([0]), want_traj=True)
+    xi = r["traj"][0, :, 2]
+    assert np.all(xi[: j + 1] == 0.0)
+    th = theta * h
+    expect = sigma * np.sqrt(h) * (1.0 - th / 2.0 + th * th / 8.0)
+    assert abs(xi[j + 1] - expect) <= 1e-15 * abs(expect) + 1e-18
+    # after the impulse the free decay is the RK4 amplification per step
+    a = 1.0 - th + th ** 2 / 2 - th ** 3 / 6 + th ** 4 / 24
+    assert abs(xi[j + 2] - a * xi[j + 1]) <= 1e-15
+
+
+def test_em_paths_have_the_scheme_variance():
+    """SRS normals through the EM basis: the sample variance of xi(T) over
+    N = 4000 paths agrees, within four standard errors, with the variance of
+    the scheme xi_{s+1} = a xi_s + b zeta_s (a, b as above), which itself is
+    within O(theta h) of the OU closed form sigma^2/(2 theta)(1 - e^{-2 theta T})."""
+    h, S, theta, sigma, N = 0.01, 200, 0.5, 0.05, 4000
+    sc = workloads.smib(N=N, K=S, T=S * h, dt=h, theta=theta, sigma=sigma, basis="em",
+                        sampler="srs", seed=11)
+    r = oracle.run(sc)
+    v = r["var"][S, 2]
+    th = theta * h
+    a = 1.0 - th + th ** 2 / 2 - th ** 3 / 6 + th ** 4 / 24
+    b = sigma * np.sqrt(h) * (1.0 - th / 2.0 + th * th / 8.0)
+    v_scheme = b * b * (1.0 - a ** (2 * S)) / (1.0 - a * a)
+    v_ou = sigma ** 2 / (2 * theta) * (1.0 - np.exp(-2 * theta * S * h))
+    assert abs(v_scheme - v_ou) <= 0.01 * v_ou
+    se = v_scheme * np.sqrt(2.0 / (N - 1))
+    assert abs(v - v_scheme) <= 4.0 * se, (v, v_scheme, se)
+    assert abs(r["mean"][S, 2]) <= 4.0 * np.sqrt(v_scheme / N)
