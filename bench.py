@@ -157,7 +157,7 @@ def served_leg(ctx, fmc, workloads, oracle_mod, rates, n_max: int, seed: int = 1
     out = {"workload": "Poisson requests: 90% drawn uniformly from the 64 uneven classical "
                        "scenarios, 10% large flux-decay + IEEE type-1 requests (n=200, P=10, "
                        "T=30 s, N=5e4, K=100)",
-           "precision": "bf16x3", "time_chunk": {"classical": 200, "flux_decay": 25},
+           "precision": "bf16x3", "time_chunk": {"classical": 200, "flux_decay": 12},
            "rates": []}
     # warm-up: one request of every size class and one short flux-decay request
     for i in (0, 17, 40):
@@ -221,6 +221,94 @@ def served_leg(ctx, fmc, workloads, oracle_mod, rates, n_max: int, seed: int = 1
         out["rates"].append(ent)
         say(f"served rate {rate}/s: {n_req} requests ({int(is_large.sum())} large), p50 "
             f"{np.median(lat):.3f} s, p99 {np.quantile(lat, 0.99):.3f} s, {ts / span:.3e} traj-steps/s")
+    return out
+
+
+def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
+    """Sample-count convergence of the two estimators (the paper's comparison,
+    Sec. V-B, on synthetic systems): for N = 2..n_max, each N with a design of
+    its own (seed 1000 + N), the mean and variance of the machine-1 rotor angle
+    at the final time from (a) KLE (paper basis, K = 40 / 100) with LHS and
+    (b) traditional Monte Carlo, eq. 5 increments with simple random sampling.
+    D(N) = max - min of the estimate over N-4..N; an estimator has converged
+    at tolerance tol at the first N from which D stays below tol.  Tolerances
+    are fractions of the response's standard deviation (mean) and variance
+    (variance), both from the largest-N KLE+LHS estimate.  out_path, if given,
+    receives the estimates (numpy .npz)."""
+    import numpy as np
+    fr_m, fr_v = (0.02, 0.05, 0.1), (0.05, 0.1, 0.2)
+    out = {"definition": "D(N) = max-min of the estimate over N-4..N; N_conv(tol) = first N "
+                         "after which D stays below tol; tol as fractions of the reference "
+                         "std (mean) and variance (variance)",
+           "n_max": n_max, "tol_mean_frac_of_std": list(fr_m), "tol_var_frac_of_var": list(fr_v)}
+    # responses: the SMIB rotor angle (an infinite bus holds the angle
+    # reference) and, for the 10-machine system, whose common rotor angle is a
+    # neutral mode that drifts freely, the frequency deviation of machine 1
+    systems = {"smib": (workloads.config1(), 0, "rotor angle of the machine at t = T (rad)"),
+               "10gen": (workloads.config2(), 10, "frequency deviation of machine 1 at t = T (pu)")}
+    dump = {}
+    for name, (base, col, what) in systems.items():
+        S = fmc.steps(base)
+        ests = {}
+        for meth, over in (("kle_lhs", dict(basis="paper", sampler="lhs")),
+                           ("em_srs", dict(basis="em", sampler="srs", K=S))):
+            m = np.full(n_max + 1, np.nan); v = np.full(n_max + 1, np.nan)
+            for N in range(2, n_max + 1):
+                sc = dict(base, N=N, seed=1000 + N, **over)
+                r = ctx.run(sc, precision="f64")
+                m[N] = float(r["mean"][S, col])
+                v[N] = float(r["var"][S, col])
+            ests[meth] = (m, v)
+            dump[f"{name}_{meth}_mean"] = m
+            dump[f"{name}_{meth}_var"] = v
+            say(f"convergence {name} {meth}: done")
+        m_ref, v_ref = ests["kle_lhs"][0][n_max], ests["kle_lhs"][1][n_max]
+        entry = {"response": what, "T_s": base["T"], "K_kle": base["K"],
+                 "ref_mean": m_ref, "ref_var": v_ref}
+
+        def dcurve(e):
+            d = np.full(n_max + 1, np.inf)
+            for N in range(6, n_max + 1):
+                w = e[N - 4:N + 1]
+                d[N] = w.max() - w.min()
+            return d
+
+        def n_conv(d, tol):
+            ok = d <= tol
+            for N in range(6, n_max + 1):
+                if ok[N:].all():
+                    return N
+            return None
+        # RMS error of the estimates against the reference over ranges of N
+        # (relative to the std for the mean, to the variance for the
+        # variance); with errors ~ 1/sqrt(N) the squared ratio of the two
+        # methods' errors is their ratio of samples for equal accuracy
+        ranges = ((10, 50), (100, 200), (500, n_max))
+        rms = {}
+        for meth, (m, v) in ests.items():
+            rms[meth] = [(float(np.sqrt(np.mean((m[a:b] - m_ref) ** 2)) / np.sqrt(v_ref)),
+                          float(np.sqrt(np.mean((v[a:b] - v_ref) ** 2)) / v_ref)) for a, b in ranges]
+        entry["rms_error_ranges"] = [f"{a}-{b - 1}" for a, b in ranges]
+        entry["sample_ratio_em_over_kle"] = {
+            "mean": [(e[0] / k[0]) ** 2 for e, k in zip(rms["em_srs"], rms["kle_lhs"])],
+            "var": [(e[1] / k[1]) ** 2 for e, k in zip(rms["em_srs"], rms["kle_lhs"])]}
+        for meth, (m, v) in ests.items():
+            dm, dv = dcurve(m), dcurve(v)
+            entry[meth] = {
+                "N_conv_mean": [n_conv(dm, f * np.sqrt(v_ref)) for f in fr_m],
+                "N_conv_var": [n_conv(dv, f * v_ref) for f in fr_v],
+                "D_mean_over_std_at": {str(N): dm[N] / np.sqrt(v_ref)
+                                       for N in (10, 50, 100, 500, n_max) if N <= n_max},
+                "D_var_over_var_at": {str(N): dv[N] / v_ref
+                                      for N in (10, 50, 100, 500, n_max) if N <= n_max},
+                "rms_mean_over_std": [x[0] for x in rms[meth]],
+                "rms_var_over_var": [x[1] for x in rms[meth]]}
+        out[name] = entry
+        say(f"convergence {name}: " + json.dumps({k: {q: entry[k][q] for q in ("N_conv_mean", "N_conv_var")}
+                                                  for k in ("kle_lhs", "em_srs")})
+            + " sample ratio " + json.dumps(entry["sample_ratio_em_over_kle"]))
+    if out_path:
+        np.savez(out_path, **dump)
     return out
 
 
@@ -290,6 +378,10 @@ def main():
                     help="requests per rate of the served leg (at most)")
     ap.add_argument("--fd-steps", type=int, default=100,
                     help="horizon of the flux-decay leg in steps (0: skip)")
+    ap.add_argument("--convergence", type=int, default=0,
+                    help="run the sample-count convergence comparison up to this N (0: skip)")
+    ap.add_argument("--convergence-out", default="",
+                    help="write the convergence estimates to this .npz file")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -397,6 +489,10 @@ def main():
         batched = batched_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(),
                               args.batch_steps, "f64" in forms)
 
+    conv = None
+    if args.convergence > 0:
+        conv = convergence_leg(ctx, fmc, workloads, args.convergence, args.convergence_out)
+
     fdl = None
     if args.fd_steps > 0:
         fdl = fd_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), args.fd_steps)
@@ -452,6 +548,7 @@ def main():
         "batched": batched,
         "served": served,
         "flux_decay": fdl,
+        "convergence": conv,
     }
     print(json.dumps(line))
     ctx.close()
