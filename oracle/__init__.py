@@ -69,6 +69,7 @@ def lib():
         L.orc_ppnd16.argtypes = [C.c_double]
         L.orc_ppnd16.restype = C.c_double
         L.orc_lhs.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_int64, P, P, P]
+        L.orc_lhs_decorrelate.argtypes = [C.c_int32, C.c_int64, P, P]
         L.orc_basis.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_double, P]
         L.orc_kron.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P, C.c_int32, P, P, P, P]
         L.orc_run.argtypes = [C.POINTER(_Problem), P, C.c_int64, P, P, P, P, P, P, P, P]
@@ -128,6 +129,19 @@ def lhs(seed: int, M: int, N: int, sampler: int = 0, sel=None):
     return strata, zeta
 
 
+def lhs_decorrelate(zeta):
+    """Correlation-reducing rearrangement of a design [M][N] (rows are the
+    variables): returns the rearranged design and each entry's rank in its
+    row (int32)."""
+    z = np.array(zeta, dtype=np.float64, order="C", copy=True)
+    M, N = z.shape
+    ranks = np.zeros((M, N), dtype=np.int32)
+    rc = lib().orc_lhs_decorrelate(M, N, z.ctypes.data, ranks.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_lhs_decorrelate failed: {rc}")
+    return z, ranks
+
+
 def basis(kind: int, K: int, S: int, T: float):
     Phi = np.zeros((K, 2 * S + 1), dtype=np.float64)
     rc = lib().orc_basis(kind, K, S, T, Phi.ctypes.data)
@@ -152,7 +166,7 @@ def kron(net: dict):
     return Yr + 1j * Yi
 
 
-_SAMPLER = {"lhs": 0, "srs": 1}
+_SAMPLER = {"lhs": 0, "srs": 1, "lhs_decor": 2}
 _BASIS = {"paper": 0, "eigen": 1, "em": 2}
 _INTEG = {"rk4": 0, "trap": 1}
 _MODEL = {"classical": 0, "fluxdecay": 1}

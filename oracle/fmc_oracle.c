@@ -17,6 +17,10 @@
  *   philox         -> numpy.random.Philox (Philox-4x64-10)
  *   ppnd16         -> scipy.special.ndtri
  *   lhs            -> one sample per stratum, stratum bounds, bijection
+ *   lhs_decorrelate -> rows keep their values (LHS rows: one per stratum), a
+ *                     hand-worked 2 x 4 case, correlations reduced to the
+ *                     level of a rank-exact whitening (statistical), a single
+ *                     row left unchanged, invariance under scaling a row
  *   basis          -> orthonormality, Var W_K(t) closed form, eigen-KLE (Nystrom);
  *                     EM basis: one-hot rows, the eq. 5 increment of a unit
  *                     impulse, and the OU variance of EM paths (statistical)
@@ -214,8 +218,8 @@ static double lhs_p(int64_t s, double U, int64_t N)
     return p;
 }
 
-int orc_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int64_t n_sel,
-            const int64_t *sel, int32_t *strata, double *zeta)
+static int lhs_plain(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int64_t n_sel,
+                     const int64_t *sel, int32_t *strata, double *zeta)
 {
     if (M < 1 || N < 1) return ORC_EINVAL;
     if (!sel) n_sel = N;
@@ -244,6 +248,150 @@ int orc_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int64_t n_sel,
         }
     }
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* LHS Step 2 with correlation reduction (Sec. IV-B).  The paper leaves the   */
+/* permutation of each row open and names Cholesky-based correlation control  */
+/* as one choice.  Reading taken: one pass of rank-based correlation control  */
+/* with the identity as its target (Iman and Conover, 1982).  The M rows of   */
+/* the design are M variables observed in N samples:                          */
+/*   1. their sample covariance C (divisor N - 1) is factored C = L L^T;      */
+/*   2. the scores Z = L^{-1} (X - mean) have identity sample covariance;     */
+/*   3. each row of X is rearranged so that its values take the ranks of the  */
+/*      same row of Z: the sample with the r-th smallest score gets the r-th  */
+/*      smallest value (equal scores: the lower sample index first).          */
+/* A row keeps its values (for an LHS row, one per stratum); only their        */
+/* assignment to samples changes.  Needs N > M, finite values and a positive   */
+/* definite C, each pivot above 1e-12 of its diagonal entry (ORC_EINVAL        */
+/* otherwise).  strata (optional, [M][N]) receives the  */
+/* rank of each entry in its row, which for an LHS row is its stratum.         */
+/* ------------------------------------------------------------------------- */
+static int dbl_cmp(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+typedef struct {
+    double v;
+    int64_t n;
+} keyed_t;
+
+static int keyed_cmp(const void *a, const void *b)
+{
+    const keyed_t *x = (const keyed_t *)a, *y = (const keyed_t *)b;
+    if (x->v < y->v) return -1;
+    if (x->v > y->v) return 1;
+    return (x->n > y->n) - (x->n < y->n);
+}
+
+int orc_lhs_decorrelate(int32_t M, int64_t N, double *zeta, int32_t *strata)
+{
+    if (M < 1 || N <= M || !zeta) return ORC_EINVAL;
+    for (int64_t q = 0; q < (int64_t)M * N; ++q)
+        if (!isfinite(zeta[q])) return ORC_EINVAL;
+    double *mean = calloc(M, sizeof(double));
+    double *Cv = calloc((size_t)M * M, sizeof(double));
+    double *L = calloc((size_t)M * M, sizeof(double));
+    double *Z = malloc(sizeof(double) * (size_t)M * N);
+    int rc = ORC_OK;
+    if (!mean || !Cv || !L || !Z) { rc = ORC_ENOMEM; goto done; }
+    for (int a = 0; a < M; ++a) {
+        double s = 0.0;
+        for (int64_t n = 0; n < N; ++n) s += zeta[(int64_t)a * N + n];
+        mean[a] = s / (double)N;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int a = 0; a < M; ++a)
+        for (int b = 0; b <= a; ++b) {
+            double s = 0.0;
+            for (int64_t n = 0; n < N; ++n)
+                s += (zeta[(int64_t)a * N + n] - mean[a]) * (zeta[(int64_t)b * N + n] - mean[b]);
+            Cv[(size_t)a * M + b] = Cv[(size_t)b * M + a] = s / (double)(N - 1);
+        }
+    /* Cholesky-Banachiewicz, row by row */
+    for (int i = 0; i < M && rc == ORC_OK; ++i)
+        for (int j = 0; j <= i; ++j) {
+            double s = Cv[(size_t)i * M + j];
+            for (int k = 0; k < j; ++k) s -= L[(size_t)i * M + k] * L[(size_t)j * M + k];
+            if (i == j) {
+                /* a pivot of at most 1e-12 of its diagonal entry: the row is
+                   (to rounding) a combination of the rows before it */
+                if (!(s > 1e-12 * Cv[(size_t)i * M + i])) { rc = ORC_EINVAL; break; }
+                L[(size_t)i * M + i] = sqrt(s);
+            } else {
+                L[(size_t)i * M + j] = s / L[(size_t)j * M + j];
+            }
+        }
+    if (rc != ORC_OK) goto done;
+    /* forward substitution L z = x - mean, one sample at a time */
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n)
+        for (int i = 0; i < M; ++i) {
+            double s = zeta[(int64_t)i * N + n] - mean[i];
+            for (int k = 0; k < i; ++k) s -= L[(size_t)i * M + k] * Z[(int64_t)k * N + n];
+            Z[(int64_t)i * N + n] = s / L[(size_t)i * M + i];
+        }
+    /* rearrangement, row by row */
+#pragma omp parallel
+    {
+        keyed_t *zs = malloc(sizeof(keyed_t) * N);
+        double *xs = malloc(sizeof(double) * N);
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < M; ++i) {
+            if (!zs || !xs) continue;
+            for (int64_t n = 0; n < N; ++n) {
+                zs[n].v = Z[(int64_t)i * N + n];
+                zs[n].n = n;
+                xs[n] = zeta[(int64_t)i * N + n];
+            }
+            qsort(zs, N, sizeof(keyed_t), keyed_cmp);
+            qsort(xs, N, sizeof(double), dbl_cmp);
+            for (int64_t r = 0; r < N; ++r) {
+                zeta[(int64_t)i * N + zs[r].n] = xs[r];
+                if (strata) strata[(int64_t)i * N + zs[r].n] = (int32_t)r;
+            }
+        }
+        if (!zs || !xs) rc = ORC_ENOMEM;
+        free(zs);
+        free(xs);
+    }
+done:
+    free(mean);
+    free(Cv);
+    free(L);
+    free(Z);
+    return rc;
+}
+
+/* The design of Alg. 1 step 1.  sampler 0: LHS; 1: simple random sampling;  */
+/* 2: LHS followed by the correlation reduction above (over all N samples,    */
+/* then the selected columns are returned).                                   */
+int orc_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int64_t n_sel,
+            const int64_t *sel, int32_t *strata, double *zeta)
+{
+    if (sampler == 0 || sampler == 1) return lhs_plain(seed, M, N, sampler, n_sel, sel, strata, zeta);
+    if (sampler != 2 || M < 1 || N < 1) return ORC_EINVAL;
+    if (!sel) n_sel = N;
+    for (int64_t c = 0; c < n_sel; ++c) {
+        int64_t n = sel ? sel[c] : c;
+        if (n < 0 || n >= N) return ORC_EINVAL;
+    }
+    double *Zf = malloc(sizeof(double) * (size_t)M * N);
+    int32_t *Sf = malloc(sizeof(int32_t) * (size_t)M * N);
+    int rc = (Zf && Sf) ? lhs_plain(seed, M, N, 0, N, NULL, NULL, Zf) : ORC_ENOMEM;
+    if (rc == ORC_OK) rc = orc_lhs_decorrelate(M, N, Zf, Sf);
+    if (rc == ORC_OK)
+        for (int32_t i = 0; i < M; ++i)
+            for (int64_t c = 0; c < n_sel; ++c) {
+                int64_t n = sel ? sel[c] : c;
+                if (zeta) zeta[(int64_t)i * n_sel + c] = Zf[(int64_t)i * N + n];
+                if (strata) strata[(int64_t)i * n_sel + c] = Sf[(int64_t)i * N + n];
+            }
+    free(Zf);
+    free(Sf);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -587,3 +587,103 @@ def test_em_paths_have_the_scheme_variance():
     se = v_scheme * np.sqrt(2.0 / (N - 1))
     assert abs(v - v_scheme) <= 4.0 * se, (v, v_scheme, se)
     assert abs(r["mean"][S, 2]) <= 4.0 * np.sqrt(v_scheme / N)
+
+
+# --- correlation-reducing LHS permutation (Sec. IV-B, LHS Step 2) -----------
+
+
+def test_decorrelate_rows_keep_their_values_and_strata():
+    # Each row is only rearranged: the same values, one per stratum, and the
+    # reported rank of an entry is the stratum its value lies in.
+    M, N = 6, 64
+    st, z = oracle.lhs(3, M, N, 0)
+    z2, r = oracle.lhs_decorrelate(z)
+    assert np.array_equal(np.sort(z2, axis=1), np.sort(z, axis=1))
+    assert np.array_equal(np.sort(r, axis=1), np.tile(np.arange(N, dtype=np.int32), (M, 1)))
+    assert np.array_equal(np.floor(sp.ndtr(z2) * N).astype(np.int32), r)
+    assert not np.array_equal(z2, z)
+
+
+def test_decorrelate_hand_worked_two_by_four():
+    # Rows x1 = (-3, -1, 1, 3), x2 = (-1, -3, 3, 1): covariance 20/3, 4, 20/3,
+    # so the second score is proportional to x2 - 0.6 x1 = (0.8, -2.4, 2.4,
+    # -0.8), of ranks (2, 0, 3, 1); x2 takes its sorted values (-3, -1, 1, 3)
+    # in that order, (1, -3, 3, -1), orthogonal to x1.  The first score is x1
+    # scaled, so x1 stays.
+    x = np.array([[-3.0, -1.0, 1.0, 3.0], [-1.0, -3.0, 3.0, 1.0]])
+    z2, r = oracle.lhs_decorrelate(x)
+    assert np.array_equal(z2, np.array([[-3.0, -1.0, 1.0, 3.0], [1.0, -3.0, 3.0, -1.0]]))
+    assert np.array_equal(r, np.array([[0, 1, 2, 3], [2, 0, 3, 1]]))
+    assert float(z2[0] @ z2[1]) == 0.0
+
+
+@pytest.mark.parametrize("M,N", [(10, 500), (30, 1000)])
+def test_decorrelate_reduces_correlation(M, N):
+    # A random pairing leaves off-diagonal correlations of about 1/sqrt(N);
+    # ranks matched to whitened scores leave a small fraction of that.
+    off = ~np.eye(M, dtype=bool)
+    for seed in range(4):
+        _, z = oracle.lhs(100 + seed, M, N, 0)
+        z2, _ = oracle.lhs_decorrelate(z)
+        before = np.sqrt((np.corrcoef(z)[off] ** 2).mean())
+        after = np.sqrt((np.corrcoef(z2)[off] ** 2).mean())
+        assert before > 0.5 / math.sqrt(N)
+        assert after < 0.1 / math.sqrt(N)
+
+
+def test_decorrelate_single_row_unchanged():
+    st, z = oracle.lhs(9, 1, 40, 0)
+    z2, r = oracle.lhs_decorrelate(z)
+    assert np.array_equal(z2, z)
+    assert np.array_equal(r, st)
+
+
+def test_decorrelate_invariant_under_affine_row_maps():
+    # Scaling a row by a positive factor and shifting it changes neither the
+    # ranks of any score row nor, hence, the rearrangement.
+    M, N = 5, 80
+    _, z = oracle.lhs(21, M, N, 0)
+    a = np.array([1.0, 3.5, 0.25, 2.0, 1.0])[:, None]
+    b = np.array([0.0, -2.0, 5.0, 0.0, 1.0])[:, None]
+    _, r = oracle.lhs_decorrelate(z)
+    _, rs = oracle.lhs_decorrelate(a * z + b)
+    assert np.array_equal(r, rs)
+
+
+def test_decorrelate_ranks_match_independent_whitening():
+    # The same rearrangement from numpy's Cholesky, a triangular solve and a
+    # stable argsort.
+    M, N = 8, 120
+    _, z = oracle.lhs(5, M, N, 0)
+    Lc = np.linalg.cholesky(np.cov(z))
+    sc = sl.solve_triangular(Lc, z - z.mean(axis=1, keepdims=True), lower=True)
+    ranks = np.empty((M, N), dtype=np.int32)
+    for i in range(M):
+        ranks[i, np.argsort(sc[i], kind="stable")] = np.arange(N)
+    z2, r = oracle.lhs_decorrelate(z)
+    assert np.array_equal(r, ranks)
+    assert np.array_equal(z2, np.take_along_axis(np.sort(z, axis=1), ranks, axis=1))
+
+
+def test_decorrelate_rejects_degenerate_designs():
+    _, z = oracle.lhs(1, 4, 4, 0)
+    with pytest.raises(ValueError):
+        oracle.lhs_decorrelate(z)  # N <= M: covariance singular
+    _, z = oracle.lhs(1, 3, 30, 0)
+    dup = np.vstack([z, z[:1]])
+    with pytest.raises(ValueError):
+        oracle.lhs_decorrelate(dup)  # a repeated row
+    bad = z.copy()
+    bad[1, 7] = np.nan
+    with pytest.raises(ValueError):
+        oracle.lhs_decorrelate(bad)
+
+
+def test_lhs_decor_sampler_subset_matches_full_design():
+    st, z = oracle.lhs(8, 5, 70, 2)
+    sel = np.array([69, 0, 33, 12])
+    st_s, z_s = oracle.lhs(8, 5, 70, 2, sel=sel)
+    assert np.array_equal(z_s, z[:, sel]) and np.array_equal(st_s, st[:, sel])
+    _, z0 = oracle.lhs(8, 5, 70, 0)
+    z2, r = oracle.lhs_decorrelate(z0)
+    assert np.array_equal(z, z2) and np.array_equal(st, r)
