@@ -82,6 +82,14 @@ extern "C" {
 /* Sampler of the KLE coefficients (Sec. IV-B). */
 #define FMC_LHS 0 /* Latin hypercube: one draw per stratum, permuted per row */
 #define FMC_SRS 1 /* simple random sampling (plain Monte Carlo of the coefficients) */
+/* Latin hypercube followed by the correlation-reducing permutation of
+ * fmc_lhs_decorrelate over all N samples: the same values in every row,
+ * reassigned to samples so that the rows are close to uncorrelated (LHS
+ * Step 2 of Sec. IV-B, with Cholesky-based correlation control).  Needs
+ * M = n_proc*K <= 1024 and M < N < 2^31 (FMC_EINVAL otherwise); costs
+ * O(N^2 M) comparisons for the ranks.  fmc_run only: the batched and served
+ * forms reject it. */
+#define FMC_LHS_DECOR 2
 
 /* Time integrator. */
 #define FMC_RK4 0  /* classical Runge-Kutta, forcing taken at the stage times */
@@ -250,6 +258,23 @@ int fmc_kron_reduce(fmc_context *ctx, const fmc_network *net, double *Y_re, doub
 int fmc_lhs(fmc_context *ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampler,
             int32_t *strata, double *zeta);
 
+/* Correlation-reducing permutation of a design (Sec. IV-B, LHS Step 2: the
+ * permutation of each row is free; the paper points to Cholesky-based
+ * correlation control).  The M rows of zeta (device [M][N] FP64, in place)
+ * are M variables observed in N samples.  Their sample covariance C (divisor
+ * N - 1) is factored C = L L^T; the scores Z = L^-1 (X - mean) have identity
+ * covariance; each row is rearranged so that its values take the ranks of
+ * the same row of Z (equal scores: lower sample index first).  A row keeps
+ * its values, so an LHS row still holds one value per stratum.  strata
+ * (device [M][N] int32, may be NULL) receives each entry's rank in its row,
+ * which for an LHS row is its stratum.  Workspace: about M*N*16 + M*M*8
+ * bytes held by the context.  Synchronises the context's stream.
+ * FMC_EINVAL: M < 1, M > 1024, N <= M, N >= 2^31, or the covariance is not
+ * positive definite (a Cholesky pivot at most 1e-12 of its diagonal entry, a
+ * repeated row, a non-finite value): the design is then left unchanged and
+ * strata is unspecified. */
+int fmc_lhs_decorrelate(fmc_context *ctx, int32_t M, int64_t N, double *zeta, int32_t *strata);
+
 /* KLE basis (eq. 7, or the eigen basis) on the stage grid: phi device
  * [K][2S+1] FP64. */
 int fmc_basis(fmc_context *ctx, int32_t basis, int32_t K, int64_t S, double T, double *phi);
@@ -320,8 +345,8 @@ int fmc_autotune(fmc_context *ctx, const fmc_scenario *scen, int32_t *variant);
 
 /* Device bytes a scenario needs while it runs.  FMC_F32 / FMC_BF16X3: the
  * admission footprint of the served form (staged inputs, design, basis, one
- * time chunk of paths, state, statistics rows, results); FMC_F64: the
- * single-run form's working set.  Validation as fmc_run. */
+ * time chunk of paths, state, statistics rows, results); FMC_F64 or
+ * FMC_LHS_DECOR: the single-run form's working set.  Validation as fmc_run. */
 int fmc_footprint(const fmc_scenario *scen, int64_t *bytes);
 
 #ifdef __cplusplus

@@ -32,7 +32,7 @@ OK, EINVAL, ENOMEM, EBUSY, EDEVICE, ENONFINITE, ENOTCONV, ECANCELLED, EAGAIN, ET
     0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 F64, F32, BF16X3 = 0, 1, 2
 BASIS = {"paper": 0, "eigen": 1, "em": 2}
-SAMPLER = {"lhs": 0, "srs": 1}
+SAMPLER = {"lhs": 0, "srs": 1, "lhs_decor": 2}
 INTEGRATOR = {"rk4": 0, "trap": 1}
 PRECISION = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
 CLASSICAL, FLUXDECAY_IEEET1 = 0, 1
@@ -107,6 +107,7 @@ _sig = {
     "fmc_set_stream": ([_ctx_p, _P], C.c_int),
     "fmc_kron_reduce": ([_ctx_p, C.POINTER(Network), _P, _P], C.c_int),
     "fmc_lhs": ([_ctx_p, C.c_uint64, C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
+    "fmc_lhs_decorrelate": ([_ctx_p, C.c_int32, C.c_int64, _P, _P], C.c_int),
     "fmc_basis": ([_ctx_p, C.c_int32, C.c_int32, C.c_int64, C.c_double, _P], C.c_int),
     "fmc_kle_paths": ([_ctx_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
                        C.c_int64, _P, _P, C.c_int64, _P], C.c_int),
@@ -283,6 +284,17 @@ class Context:
         _check(_lib.fmc_lhs(self._h, seed, M, N, _enum(sampler, SAMPLER), _dptr(strata),
                             _dptr(zeta)))
         return strata, zeta
+
+    def lhs_decorrelate(self, zeta, want_strata=True):
+        """Correlation-reducing permutation of a device design [M][N] in place;
+        returns the rank of each entry in its row (int32) if asked for."""
+        t = self.torch
+        assert zeta.dtype == t.float64 and zeta.is_contiguous() and zeta.dim() == 2
+        assert zeta.device == t.device(self.device)
+        M, N = zeta.shape
+        strata = t.empty((M, N), dtype=t.int32, device=self.device) if want_strata else None
+        _check(_lib.fmc_lhs_decorrelate(self._h, M, N, _dptr(zeta), _dptr(strata)))
+        return strata
 
     def basis(self, kind, K: int, S: int, T: float):
         t = self.torch

@@ -76,6 +76,7 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
   const double* zeta = par->zeta_in;
   double* zeta_dev = nullptr;
   int32_t* strata_dev = nullptr;
+  int32_t* dc_status = nullptr;  // correlation reduction of the design, if asked for
   if (!zeta) {
     void* p = nullptr;
     if (out->zeta && dev_out) {
@@ -92,7 +93,12 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
         strata_dev = (int32_t*)p;
       }
     }
-    HIPCHK(launch_lhs(par->seed, (int32_t)M, N, par->sampler, strata_dev, zeta_dev, c->stream));
+    const bool decor = par->sampler == FMC_LHS_DECOR;
+    HIPCHK(launch_lhs(par->seed, (int32_t)M, N, decor ? FMC_LHS : par->sampler, strata_dev,
+                      zeta_dev, c->stream));
+    if (decor &&
+        (rc = decorrelate_design(c, (int32_t)M, N, zeta_dev, strata_dev, &dc_status, c->stream)))
+      return rc;
     zeta = zeta_dev;
   }
 
@@ -221,10 +227,15 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
   unsigned long long* cn = (unsigned long long*)((char*)hb + 16);
   HIPCHK(hipMemcpyAsync(status, status_d, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipMemcpyAsync(cn, cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+  status[2] = 0;
+  if (dc_status)
+    HIPCHK(hipMemcpyAsync(status + 2, dc_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   hipEvent_t e3 = c->ev[3];
   HIPCHK(hipEventRecord(e3, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   if (status[1] != 0) return fail(FMC_EINVAL, "network reduction failed (singular Y_BB)");
+  if (status[2] != 0)
+    return fail(FMC_EINVAL, "the design's sample covariance is not positive definite");
   if (status[0] != 0) return fail(FMC_ENOTCONV, "operating-point Newton solve did not converge");
   if (out->report) {
     fmc_report* r = out->report;

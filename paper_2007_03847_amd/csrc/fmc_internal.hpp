@@ -166,6 +166,10 @@ struct BatchVariantInfo {
   int id, NG, PM, L, TB, cls, prod;
 };
 constexpr int kBatchClasses = 7;
+// Correlation reduction of the design (FMC_LHS_DECOR): the Cholesky factor is
+// computed by one workgroup with the diagonal in LDS, and ranks are int32.
+constexpr int kDecorMaxM = 1024;
+constexpr int64_t kDecorMaxN = 2147483647;
 int n_batch_variants();
 BatchVariantInfo batch_variant(int i);
 int persistent_blocks_per_cu(int cls);

@@ -258,7 +258,8 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
     return fail(FMC_EINVAL, "unknown basis");
   if (par->basis == FMC_BASIS_EM && par->K != S)
     return fail(FMC_EINVAL, "the EM basis needs K = S (one normal per step and process)");
-  if (par->sampler != FMC_LHS && par->sampler != FMC_SRS) return fail(FMC_EINVAL, "unknown sampler");
+  if (par->sampler != FMC_LHS && par->sampler != FMC_SRS && par->sampler != FMC_LHS_DECOR)
+    return fail(FMC_EINVAL, "unknown sampler");
   if (par->integrator != FMC_RK4) return fail(FMC_EINVAL, "only the RK4 integrator runs on the GPU");
   if (par->precision < FMC_F64 || par->precision > FMC_BF16X3)
     return fail(FMC_EINVAL, "unknown precision");
@@ -309,6 +310,11 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
     if (dist->gen[p] < 0 || dist->gen[p] >= n) return fail(FMC_EINVAL, "disturbance machine index out of range");
     if (!(dist->theta[p] >= 0.0)) return fail(FMC_EINVAL, "theta must be >= 0");
     if (!(dist->sigma[p] >= 0.0)) return fail(FMC_EINVAL, "sigma must be >= 0");
+  }
+  if (par->sampler == FMC_LHS_DECOR && !par->zeta_in) {
+    const int64_t M = (int64_t)dist->n_proc * par->K;
+    if (M > kDecorMaxM || par->N <= M || par->N > kDecorMaxN)
+      return fail(FMC_EINVAL, "FMC_LHS_DECOR needs n_proc*K <= 1024 and n_proc*K < N < 2^31");
   }
   *S_out = S;
   return FMC_OK;
@@ -484,12 +490,36 @@ int fmc_lhs(fmc_context* ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampl
             int32_t* strata, double* zeta) {
   if (!ctx || !zeta) return fail(FMC_EINVAL, "NULL argument");
   if (M < 1 || N < 1) return fail(FMC_EINVAL, "M and N must be >= 1");
-  if (sampler != FMC_LHS && sampler != FMC_SRS) return fail(FMC_EINVAL, "unknown sampler");
+  if (sampler != FMC_LHS && sampler != FMC_SRS && sampler != FMC_LHS_DECOR)
+    return fail(FMC_EINVAL, "unknown sampler");
   if (N > (int64_t)1 << 40) return fail(FMC_EINVAL, "N too large");
+  if (sampler == FMC_LHS_DECOR && (M > kDecorMaxM || N <= M || N > kDecorMaxN))
+    return fail(FMC_EINVAL, "FMC_LHS_DECOR needs M <= 1024 and M < N < 2^31");
   Context* c = reinterpret_cast<Context*>(ctx);
   (void)hipSetDevice(c->device);
-  hipError_t e = launch_lhs(seed, M, N, sampler, strata, zeta, c->stream);
+  hipError_t e = launch_lhs(seed, M, N, sampler == FMC_SRS ? FMC_SRS : FMC_LHS, strata, zeta,
+                            c->stream);
   if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  if (sampler != FMC_LHS_DECOR) return FMC_OK;
+  return fmc_lhs_decorrelate(ctx, M, N, zeta, strata);
+}
+
+int fmc_lhs_decorrelate(fmc_context* ctx, int32_t M, int64_t N, double* zeta, int32_t* strata) {
+  if (!ctx || !zeta) return fail(FMC_EINVAL, "NULL argument");
+  if (M < 1 || M > kDecorMaxM || N <= M || N > kDecorMaxN)
+    return fail(FMC_EINVAL, "correlation reduction needs M <= 1024 and M < N < 2^31");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  (void)hipSetDevice(c->device);
+  int32_t* st_d = nullptr;
+  int rc = decorrelate_design(c, M, N, zeta, strata, &st_d, c->stream);
+  if (rc) return rc;
+  void* h = nullptr;
+  if ((rc = c->host_stage("dc_status", 64, &h))) return rc;
+  hipError_t e = hipMemcpyAsync(h, st_d, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  if (*(int32_t*)h != 0)
+    return fail(FMC_EINVAL, "the design's sample covariance is not positive definite (design left unchanged)");
   return FMC_OK;
 }
 

@@ -92,6 +92,14 @@ int ensure_gstream(Context* c);  // the second stream of fmc_run and its events
 int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
                const fmc_params* par, fmc_outputs* out);
 void serve_shutdown(Context* c);
+// Correlation-reducing permutation of a device design [M][N] in place on
+// stream st (FMC_LHS_DECOR).  strata (nullable) receives each entry's rank in
+// its row.  *status_out points at a device int32 that is 1 once the stream
+// has run if the design's covariance was not positive definite (the design is
+// then left as it was).
+int decorrelate_design(Context* c, int32_t M, int64_t N, double* zeta, int32_t* strata,
+                       int32_t** status_out, hipStream_t st);
+size_t decorrelate_workspace(int32_t M, int64_t N);
 
 // Flux-decay path: tiles of 16 trajectories, contiguous work items of
 // tiles_per_item tiles, one workgroup per item.

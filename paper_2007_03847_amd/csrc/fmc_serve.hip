@@ -722,7 +722,8 @@ int fmc_footprint(const fmc_scenario* scen, int64_t* bytes) {
   int rc = validate(scen->sys, scen->dist, scen->par, &S);
   if (rc) return rc;
   const fmc_params* par = scen->par;
-  if (par->precision != FMC_F64 && !par->zeta_in) {
+  const bool decor = par->sampler == FMC_LHS_DECOR && !par->zeta_in;
+  if (par->precision != FMC_F64 && !par->zeta_in && !decor) {
     // reduced precision: the admission footprint of the served form
     Request r;
     if ((rc = plan_request(r, scen->sys, scen->dist, par, S))) return rc;
@@ -744,6 +745,7 @@ int fmc_footprint(const fmc_scenario* scen, int64_t* bytes) {
   b += groups * (S + 1) * V * 16;            // per-group statistics
   b += 2 * (S + 1) * V * 8;                  // mean, var
   b += 2 * n * n * 16 + 64 * n;              // reduced network, coefficients
+  if (decor) b += (int64_t)decorrelate_workspace((int32_t)(P * K), N);
   *bytes = b;
   return FMC_OK;
 }
@@ -755,6 +757,8 @@ int fmc_submit(fmc_context* ctx, const fmc_scenario* scen, fmc_outputs* out, uin
   int64_t S = 0;
   int rc = validate(scen->sys, scen->dist, scen->par, &S);
   if (rc) return rc;
+  if (scen->par->sampler == FMC_LHS_DECOR)
+    return fail(FMC_EINVAL, "FMC_LHS_DECOR runs through fmc_run only");
   if (!out->mean || !out->var) return fail(FMC_EINVAL, "mean and var outputs are required");
   if (out->mem_kind != FMC_MEM_HOST && out->mem_kind != FMC_MEM_DEVICE)
     return fail(FMC_EINVAL, "unknown mem_kind");
