@@ -250,10 +250,13 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
     for name, (base, col, what) in systems.items():
         S = fmc.steps(base)
         ests = {}
-        for meth, over in (("kle_lhs", dict(basis="paper", sampler="lhs")),
-                           ("em_srs", dict(basis="em", sampler="srs", K=S))):
+        M = base["K"] * len(base["dist"]["gen"])
+        for meth, over, n_min in (("kle_lhs", dict(basis="paper", sampler="lhs"), 2),
+                                  ("em_srs", dict(basis="em", sampler="srs", K=S), 2),
+                                  ("kle_lhs_decor", dict(basis="paper", sampler="lhs_decor"),
+                                   M + 1)):
             m = np.full(n_max + 1, np.nan); v = np.full(n_max + 1, np.nan)
-            for N in range(2, n_max + 1):
+            for N in range(n_min, n_max + 1):
                 sc = dict(base, N=N, seed=1000 + N, **over)
                 r = ctx.run(sc, precision="f64")
                 m[N] = float(r["mean"][S, col])
@@ -265,6 +268,9 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
         m_ref, v_ref = ests["kle_lhs"][0][n_max], ests["kle_lhs"][1][n_max]
         entry = {"response": what, "T_s": base["T"], "K_kle": base["K"],
                  "ref_mean": m_ref, "ref_var": v_ref}
+
+        def fin(x):
+            return float(x) if np.isfinite(x) else None
 
         def dcurve(e):
             d = np.full(n_max + 1, np.inf)
@@ -286,20 +292,27 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
         ranges = ((10, 50), (100, 200), (500, n_max))
         rms = {}
         for meth, (m, v) in ests.items():
-            rms[meth] = [(float(np.sqrt(np.mean((m[a:b] - m_ref) ** 2)) / np.sqrt(v_ref)),
-                          float(np.sqrt(np.mean((v[a:b] - v_ref) ** 2)) / v_ref)) for a, b in ranges]
+            # NaN where a method has no estimate (the reduced design needs N > M)
+            rms[meth] = [(float(np.sqrt(np.nanmean((m[a:b] - m_ref) ** 2)) / np.sqrt(v_ref))
+                          if np.isfinite(m[a:b]).any() else None,
+                          float(np.sqrt(np.nanmean((v[a:b] - v_ref) ** 2)) / v_ref)
+                          if np.isfinite(v[a:b]).any() else None) for a, b in ranges]
         entry["rms_error_ranges"] = [f"{a}-{b - 1}" for a, b in ranges]
         entry["sample_ratio_em_over_kle"] = {
             "mean": [(e[0] / k[0]) ** 2 for e, k in zip(rms["em_srs"], rms["kle_lhs"])],
             "var": [(e[1] / k[1]) ** 2 for e, k in zip(rms["em_srs"], rms["kle_lhs"])]}
+        entry["sample_ratio_lhs_over_lhs_decor"] = {
+            q: [(k[i] / d[i]) ** 2 if d[i] else None
+                for k, d in zip(rms["kle_lhs"], rms["kle_lhs_decor"])]
+            for i, q in ((0, "mean"), (1, "var"))}
         for meth, (m, v) in ests.items():
             dm, dv = dcurve(m), dcurve(v)
             entry[meth] = {
                 "N_conv_mean": [n_conv(dm, f * np.sqrt(v_ref)) for f in fr_m],
                 "N_conv_var": [n_conv(dv, f * v_ref) for f in fr_v],
-                "D_mean_over_std_at": {str(N): dm[N] / np.sqrt(v_ref)
+                "D_mean_over_std_at": {str(N): fin(dm[N] / np.sqrt(v_ref))
                                        for N in (10, 50, 100, 500, n_max) if N <= n_max},
-                "D_var_over_var_at": {str(N): dv[N] / v_ref
+                "D_var_over_var_at": {str(N): fin(dv[N] / v_ref)
                                       for N in (10, 50, 100, 500, n_max) if N <= n_max},
                 "rms_mean_over_std": [x[0] for x in rms[meth]],
                 "rms_var_over_var": [x[1] for x in rms[meth]]}
@@ -309,6 +322,44 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
             + " sample ratio " + json.dumps(entry["sample_ratio_em_over_kle"]))
     if out_path:
         np.savez(out_path, **dump)
+    return out
+
+
+def decor_leg(ctx, fmc, workloads, reps: int = 3):
+    """Correlation-reducing LHS permutation (Sec. IV-B, LHS Step 2) on the
+    10-machine workload's design (M = P*K = 300 rows, N = 1e4): the design
+    alone with and without the reduction (host clock around the synchronous
+    call), the off-diagonal correlation of the rows before and after, and a
+    whole FP64 pass of the method with each design."""
+    import numpy as np
+    import torch
+    sc = workloads.config2()
+    M, N = len(sc["dist"]["gen"]) * sc["K"], sc["N"]
+    out = {"M": M, "N": N}
+    for name in ("lhs", "lhs_decor"):
+        best = float("inf")
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, z = ctx.lhs(seed=sc["seed"], M=M, N=N, sampler=name)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        zz = z.cpu().numpy()
+        c = np.corrcoef(zz)
+        off = c[~np.eye(M, dtype=bool)]
+        out[name] = {"design_ms": best * 1e3, "rms_offdiag_corr": float(np.sqrt(np.mean(off ** 2))),
+                     "max_abs_offdiag_corr": float(np.abs(off).max())}
+        sc2 = dict(sc, sampler=name)
+        vid = ctx.autotune(sc, precision="f64")
+        ctx.run(sc2, precision="f64", variant=vid)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.run(sc2, precision="f64", variant=vid)
+        torch.cuda.synchronize()
+        out[name]["run_ms"] = (time.perf_counter() - t0) / reps * 1e3
+        say(f"design {name}: {best * 1e3:.2f} ms, whole FP64 pass {out[name]['run_ms']:.2f} ms, "
+            f"rms off-diagonal correlation {out[name]['rms_offdiag_corr']:.2e}")
     return out
 
 
@@ -378,6 +429,8 @@ def main():
                     help="requests per rate of the served leg (at most)")
     ap.add_argument("--fd-steps", type=int, default=100,
                     help="horizon of the flux-decay leg in steps (0: skip)")
+    ap.add_argument("--decor-reps", type=int, default=3,
+                    help="passes of the correlation-reduced design leg (0: skip)")
     ap.add_argument("--convergence", type=int, default=0,
                     help="run the sample-count convergence comparison up to this N (0: skip)")
     ap.add_argument("--convergence-out", default="",
@@ -489,6 +542,10 @@ def main():
         batched = batched_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(),
                               args.batch_steps, "f64" in forms)
 
+    decor = None
+    if args.decor_reps > 0:
+        decor = decor_leg(ctx, fmc, workloads, args.decor_reps)
+
     conv = None
     if args.convergence > 0:
         conv = convergence_leg(ctx, fmc, workloads, args.convergence, args.convergence_out)
@@ -549,6 +606,7 @@ def main():
         "served": served,
         "flux_decay": fdl,
         "convergence": conv,
+        "lhs_decor": decor,
     }
     print(json.dumps(line))
     ctx.close()
