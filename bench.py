@@ -301,10 +301,21 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
         entry["sample_ratio_em_over_kle"] = {
             "mean": [(e[0] / k[0]) ** 2 for e, k in zip(rms["em_srs"], rms["kle_lhs"])],
             "var": [(e[1] / k[1]) ** 2 for e, k in zip(rms["em_srs"], rms["kle_lhs"])]}
-        entry["sample_ratio_lhs_over_lhs_decor"] = {
-            q: [(k[i] / d[i]) ** 2 if d[i] else None
-                for k, d in zip(rms["kle_lhs"], rms["kle_lhs_decor"])]
-            for i, q in ((0, "mean"), (1, "var"))}
+        # the reduced design exists for N > M only: both over the same N
+        md, vd = ests["kle_lhs_decor"]
+        ml, vl = ests["kle_lhs"]
+        ratio = {"mean": [], "var": []}
+        for a, b in ranges:
+            ok = np.isfinite(md[a:b])
+            for q, el, ed, ref in (("mean", ml, md, m_ref), ("var", vl, vd, v_ref)):
+                if not ok.any():
+                    ratio[q].append(None)
+                    continue
+                rl = np.mean((el[a:b][ok] - ref) ** 2)
+                rd = np.mean((ed[a:b][ok] - ref) ** 2)
+                ratio[q].append(float(rl / rd) if rd > 0 else None)
+        entry["sample_ratio_lhs_over_lhs_decor"] = ratio
+        entry["lhs_decor_first_N"] = int(M + 1)
         for meth, (m, v) in ests.items():
             dm, dv = dcurve(m), dcurve(v)
             entry[meth] = {
