@@ -94,10 +94,15 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
       }
     }
     const bool decor = par->sampler == FMC_LHS_DECOR;
-    HIPCHK(launch_lhs(par->seed, (int32_t)M, N, decor ? FMC_LHS : par->sampler, strata_dev,
+    int32_t* lhs_strata = strata_dev;
+    if (decor && !lhs_strata) {
+      if ((rc = c->ensure("dc_strata", (size_t)M * N * sizeof(int32_t), &p))) return rc;
+      lhs_strata = (int32_t*)p;
+    }
+    HIPCHK(launch_lhs(par->seed, (int32_t)M, N, decor ? FMC_LHS : par->sampler, lhs_strata,
                       zeta_dev, c->stream));
-    if (decor &&
-        (rc = decorrelate_design(c, (int32_t)M, N, zeta_dev, strata_dev, &dc_status, c->stream)))
+    if (decor && (rc = decorrelate_design(c, (int32_t)M, N, zeta_dev, strata_dev, lhs_strata,
+                                          &dc_status, c->stream)))
       return rc;
     zeta = zeta_dev;
   }

@@ -486,6 +486,9 @@ int fmc_kron_reduce(fmc_context* ctx, const fmc_network* net, double* Y_re, doub
   return FMC_OK;
 }
 
+static int decorrelate_and_check(Context* c, int32_t M, int64_t N, double* zeta, int32_t* strata,
+                                 const int32_t* lhs_strata);
+
 int fmc_lhs(fmc_context* ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampler,
             int32_t* strata, double* zeta) {
   if (!ctx || !zeta) return fail(FMC_EINVAL, "NULL argument");
@@ -497,11 +500,18 @@ int fmc_lhs(fmc_context* ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampl
     return fail(FMC_EINVAL, "FMC_LHS_DECOR needs M <= 1024 and M < N < 2^31");
   Context* c = reinterpret_cast<Context*>(ctx);
   (void)hipSetDevice(c->device);
-  hipError_t e = launch_lhs(seed, M, N, sampler == FMC_SRS ? FMC_SRS : FMC_LHS, strata, zeta,
+  int32_t* lhs_strata = strata;
+  if (sampler == FMC_LHS_DECOR && !lhs_strata) {
+    void* p = nullptr;
+    int rc = c->ensure("dc_strata", (size_t)M * N * sizeof(int32_t), &p);
+    if (rc) return rc;
+    lhs_strata = (int32_t*)p;
+  }
+  hipError_t e = launch_lhs(seed, M, N, sampler == FMC_SRS ? FMC_SRS : FMC_LHS, lhs_strata, zeta,
                             c->stream);
   if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
   if (sampler != FMC_LHS_DECOR) return FMC_OK;
-  return fmc_lhs_decorrelate(ctx, M, N, zeta, strata);
+  return decorrelate_and_check(c, M, N, zeta, strata, lhs_strata);
 }
 
 int fmc_lhs_decorrelate(fmc_context* ctx, int32_t M, int64_t N, double* zeta, int32_t* strata) {
@@ -510,8 +520,14 @@ int fmc_lhs_decorrelate(fmc_context* ctx, int32_t M, int64_t N, double* zeta, in
     return fail(FMC_EINVAL, "correlation reduction needs M <= 1024 and M < N < 2^31");
   Context* c = reinterpret_cast<Context*>(ctx);
   (void)hipSetDevice(c->device);
+  return decorrelate_and_check(c, M, N, zeta, strata, nullptr);
+}
+
+// The reduction on the context's stream, then a wait for its status.
+static int decorrelate_and_check(Context* c, int32_t M, int64_t N, double* zeta, int32_t* strata,
+                                 const int32_t* lhs_strata) {
   int32_t* st_d = nullptr;
-  int rc = decorrelate_design(c, M, N, zeta, strata, &st_d, c->stream);
+  int rc = decorrelate_design(c, M, N, zeta, strata, lhs_strata, &st_d, c->stream);
   if (rc) return rc;
   void* h = nullptr;
   if ((rc = c->host_stage("dc_status", 64, &h))) return rc;

@@ -94,11 +94,13 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
 void serve_shutdown(Context* c);
 // Correlation-reducing permutation of a device design [M][N] in place on
 // stream st (FMC_LHS_DECOR).  strata (nullable) receives each entry's rank in
-// its row.  *status_out points at a device int32 that is 1 once the stream
-// has run if the design's covariance was not positive definite (the design is
-// then left as it was).
+// its row.  lhs_strata (nullable): the strata of an LHS design as k_lhs wrote
+// them (a permutation of 0..N-1 per row), which then stand for the ranks of
+// its values; never a caller's array.  *status_out points at a device int32
+// that is 1 once the stream has run if the design's covariance was not
+// positive definite (the design is then left as it was).
 int decorrelate_design(Context* c, int32_t M, int64_t N, double* zeta, int32_t* strata,
-                       int32_t** status_out, hipStream_t st);
+                       const int32_t* lhs_strata, int32_t** status_out, hipStream_t st);
 size_t decorrelate_workspace(int32_t M, int64_t N);
 
 // Flux-decay path: tiles of 16 trajectories, contiguous work items of

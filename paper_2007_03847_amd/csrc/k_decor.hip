@@ -31,6 +31,7 @@ namespace {
 constexpr int kDcCovTile = 64;  // covariance tile edge (4x4 entries per thread)
 constexpr int kDcChunk = 16;    // samples per LDS stage of the covariance
 constexpr int kDcBlk = 32;      // block of the Cholesky factor and of the substitution
+constexpr int kDcSlab = 64;     // rows of L staged at a time by the substitution
 constexpr int kDcCholThreads = 1024;  // one thread per row below a block (M <= 1024)
 constexpr int kDcPanelRows = 384;     // rows of a block of L held in LDS (101 KB)
 
@@ -246,6 +247,7 @@ __global__ void __launch_bounds__(256) k_dc_whiten(int M, int64_t N, int spw,
   double* s_res = s_dyn;                       // [M][spw] residuals
   double* s_z = s_dyn + (size_t)M * spw;       // [kDcBlk][spw] the block's scores
   double* s_d = s_z + kDcBlk * spw;            // [kDcBlk][kDcBlk + 1] LT of the block
+  double* s_slab = s_d + kDcBlk * (kDcBlk + 1);  // [kDcBlk][kDcSlab] LT below the block
   const int j = threadIdx.x % spw, g = threadIdx.x / spw, G = 256 / spw;
   const int64_t n = (int64_t)blockIdx.x * spw + j;
   const bool ok = n < N;
@@ -270,12 +272,22 @@ __global__ void __launch_bounds__(256) k_dc_whiten(int M, int64_t N, int spw,
     // waits for the workgroup's outstanding stores
     for (int k = g; k < nb; k += G)
       if (ok) Z[(int64_t)(b0 + k) * N + n] = s_z[k * spw + j];
-    for (int i = b0 + nb + g; i < M; i += G) {
-      double acc = s_res[i * spw + j];
-#pragma unroll
-      for (int k = 0; k < kDcBlk; ++k)
-        if (k < nb) acc -= LT[(int64_t)(b0 + k) * M + i] * s_z[k * spw + j];
-      s_res[i * spw + j] = acc;
+    // rows below the block, kDcSlab at a time: the block's columns of L for
+    // those rows are staged in LDS with coalesced loads, then every thread
+    // updates its rows from there
+    for (int r0 = b0 + nb; r0 < M; r0 += kDcSlab) {
+      const int nr = std::min(kDcSlab, M - r0);
+      __syncthreads();  // the previous slab has been read
+      for (int q = threadIdx.x; q < kDcBlk * kDcSlab; q += 256) {
+        const int k = q / kDcSlab, i = q % kDcSlab;
+        s_slab[k * kDcSlab + i] = (k < nb && i < nr) ? LT[(int64_t)(b0 + k) * M + r0 + i] : 0.0;
+      }
+      __syncthreads();
+      for (int i = g; i < nr; i += G) {
+        double acc = s_res[(r0 + i) * spw + j];
+        for (int k = 0; k < nb; ++k) acc -= s_slab[k * kDcSlab + i] * s_z[k * spw + j];
+        s_res[(r0 + i) * spw + j] = acc;
+      }
     }
   }
 }
@@ -415,6 +427,16 @@ __global__ void __launch_bounds__(256) k_dc_rank(int64_t N, const double* __rest
   if (inv) inv[row + r] = (int32_t)n;
 }
 
+// inv[i][strata[i][n]] = n for a design whose strata are known (an LHS
+// design: the order of a row's values is the order of their strata).
+__global__ void __launch_bounds__(256) k_dc_invert(int64_t N, const int32_t* __restrict__ strata,
+                                                   int32_t* __restrict__ inv) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int64_t row = (int64_t)blockIdx.y * N;
+  inv[row + strata[row + n]] = (int32_t)n;
+}
+
 // out[i][n] = X[i][inv[i][Rz[i][n]]]: the entry whose row rank equals the
 // score rank of (i, n); strata[i][n] = that rank.  After a failed
 // factorisation (*status != 0) the design is copied as it is.
@@ -454,13 +476,15 @@ struct CovPlan {
 };
 
 // Samples per substitution workgroup: the largest of 16, 8, 4 whose LDS
-// (residuals, block scores, diagonal block) stays within 64 KB.
+// (residuals, block scores, diagonal block, slab of L) stays within 80 KB.
 size_t whiten_lds(int32_t M, int spw) {
-  return ((size_t)M * spw + (size_t)kDcBlk * spw + (size_t)kDcBlk * (kDcBlk + 1)) * sizeof(double);
+  return ((size_t)M * spw + (size_t)kDcBlk * spw + (size_t)kDcBlk * (kDcBlk + 1) +
+          (size_t)kDcBlk * kDcSlab) *
+         sizeof(double);
 }
 int whiten_spw(int32_t M) {
   int spw = 16;
-  while (spw > 4 && whiten_lds(M, spw) > 65536) spw /= 2;
+  while (spw > 4 && whiten_lds(M, spw) > 80 * 1024) spw /= 2;
   return spw;
 }
 
@@ -490,13 +514,13 @@ void launch_rank(int32_t M, int64_t N, const double* V, const RankBufs& b, int32
 
 size_t decorrelate_workspace(int32_t M, int64_t N) {
   const CovPlan cp(M, N);
-  return (size_t)M * N * (sizeof(double) + 6 * sizeof(int32_t)) +
+  return (size_t)M * N * (sizeof(double) + 7 * sizeof(int32_t)) +
          ((size_t)cp.n_slices + 2) * M * M * sizeof(double) + 3 * (size_t)M * sizeof(double2) +
          7 * 256;
 }
 
 int decorrelate_design(Context* c, int32_t M, int64_t N, double* zeta, int32_t* strata,
-                       int32_t** status_out, hipStream_t st) {
+                       const int32_t* lhs_strata, int32_t** status_out, hipStream_t st) {
   if (M < 1 || M > kDecorMaxM || N <= M || N > kDecorMaxN)
     return fail(FMC_EINVAL, "correlation reduction needs M <= 1024 and M < N < 2^31");
   const size_t MN = (size_t)M * N;
@@ -534,8 +558,13 @@ int decorrelate_design(Context* c, int32_t M, int64_t N, double* zeta, int32_t* 
   hipLaunchKernelGGL(k_dc_whiten, dim3((unsigned)((N + spw - 1) / spw)), dim3(256),
                      whiten_lds(M, spw), st, M, N, spw, zeta, mu, (const double*)lt, Z);
   launch_rank(M, N, Z, rb, (int32_t*)rz, nullptr, st);
-  // the design's own ranks, kept only as their inverse (the entry of each rank)
-  launch_rank(M, N, zeta, rb, nullptr, (int32_t*)inv, st);
+  // the design's own ranks, kept only as their inverse (the entry of each
+  // rank); an LHS design's strata are those ranks
+  if (lhs_strata)
+    hipLaunchKernelGGL(k_dc_invert, dim3(gs, (unsigned)M), dim3(256), 0, st, N, lhs_strata,
+                       (int32_t*)inv);
+  else
+    launch_rank(M, N, zeta, rb, nullptr, (int32_t*)inv, st);
   // Z is free once its ranks are taken: it receives the rearranged design
   hipLaunchKernelGGL(k_dc_apply, dim3(gs, (unsigned)M), dim3(256), 0, st, N, zeta,
                      (const int32_t*)inv, (const int32_t*)rz, (const int32_t*)status, Z, strata);
