@@ -48,6 +48,7 @@ class _Problem(C.Structure):
         ("basis", C.c_int32), ("sampler", C.c_int32), ("integrator", C.c_int32),
         ("ddof", C.c_int32),
         ("model", C.c_int32), ("model_params", C.c_void_p),
+        ("sigma_mat", C.c_void_p),
     ]
 
 
@@ -202,6 +203,8 @@ def problem(sc: dict):
     keep.dg = _i32(d["gen"])
     keep.th, keep.sg = _f64(d["theta"]), _f64(d["sigma"])
     keep.x0 = _f64(d.get("xi0"))
+    keep.sm = _f64(np.asarray(d["sigma_mat"], dtype=np.float64).reshape(-1)) \
+        if d.get("sigma_mat") is not None else None
     model = _enum(sc.get("model", 0), _MODEL)
     keep.mp = _f64(sc.get("model_params")) if model == 1 else None
     pb = _Problem(
@@ -214,7 +217,7 @@ def problem(sc: dict):
         N=int(sc["N"]), seed=int(sc.get("seed", 0)),
         basis=_enum(sc.get("basis", 0), _BASIS), sampler=_enum(sc.get("sampler", 0), _SAMPLER),
         integrator=_enum(sc.get("integrator", 0), _INTEG), ddof=int(sc.get("ddof", 1)),
-        model=model, model_params=_p(keep.mp))
+        model=model, model_params=_p(keep.mp), sigma_mat=_p(keep.sm))
     return pb, keep
 
 

@@ -24,7 +24,10 @@
  *   basis          -> orthonormality, Var W_K(t) closed form, eigen-KLE (Nystrom);
  *                     EM basis: one-hot rows, the eq. 5 increment of a unit
  *                     impulse, and the OU variance of EM paths (statistical)
- *   run (OU part)  -> OU closed-form mean/variance of the truncated KLE
+ *   run (OU part)  -> OU closed-form mean/variance of the truncated KLE;
+ *                     correlated disturbances: superposition of single-noise
+ *                     runs (exact), a diagonal matrix equals the vector sigma,
+ *                     cross-covariance against the truncated-KLE closed form
  *   run (swing)    -> SMIB linearised variance (Lyapunov / Van Loan), RK4 order
  *   kron           -> SMIB reduction to E V sin(delta)/X, symmetry, full solve
  */
@@ -587,6 +590,8 @@ typedef struct orc_problem {
     int32_t basis, sampler, integrator, ddof;
     int32_t model;               /* 0 classical, 1 flux decay + IEEE type-1 exciter */
     const double *model_params;  /* [n][9] for model 1 (order of FD_* below) */
+    const double *sigma_mat;     /* NULL, or [P][P]: d xi_p = -theta_p xi_p dt +      */
+                                 /* sum_q sigma_mat[p][q] dW_q (sigma is then unused) */
 } orc_problem;
 
 /* Flux-decay parameters per machine, in this order. */
@@ -601,11 +606,23 @@ typedef struct {
     double Vinf;
     const int32_t *dgen;
     const double *theta, *sigma, *xi0;
+    const double *sigma_mat; /* [P][P] or NULL */
     int fd;           /* flux-decay model */
     double *fdp;      /* [n][FD_NPARAM] */
     double *Vref;     /* [n] exciter reference */
     double *y0;       /* [ny] initial state (the operating point) */
 } model_t;
+
+/* Diffusion term of process p driven by the white noises w (eq. 4): sigma_p */
+/* w_p, or with a diffusion matrix (correlated disturbances, the m x n sigma */
+/* of Sec. III, square here) sum_q sigma_pq w_q.                            */
+static double diffusion(const model_t *m, int p, const double *w)
+{
+    if (!m->sigma_mat) return m->sigma[p] * w[p];
+    double s = 0.0;
+    for (int q = 0; q < m->P; ++q) s += m->sigma_mat[p * m->P + q] * w[q];
+    return s;
+}
 
 /* Electrical power of every machine: Pe_i = Re{ E~_i conj(I_i) },
  * I = Y E~ (+ Yinf V_inf), E~_k = E_k exp(j delta_k). */
@@ -659,7 +676,7 @@ static void rhs(const model_t *m, const double *y, const double *w, double *dy)
         dy[n + i] = (pm - Pe[i] - m->D[i] * y[n + i]) / (2.0 * m->H[i]);
     }
     for (int p = 0; p < P; ++p)
-        dy[2 * n + p] = -m->theta[p] * y[2 * n + p] + m->sigma[p] * w[p];
+        dy[2 * n + p] = -m->theta[p] * y[2 * n + p] + diffusion(m, p, w);
 }
 
 static void rhs_jac(const model_t *m, const double *y, double *J)
@@ -729,7 +746,7 @@ static void rhs_fd(const model_t *m, const double *y, const double *w, double *d
         dy[4 * n + i] = (-vr[i] + q[FD_KA] * rf[i] - q[FD_KA] * q[FD_KF] / q[FD_TF] * efd[i] +
                          q[FD_KA] * (m->Vref[i] - Vt[i])) / q[FD_TA];
     }
-    for (int p = 0; p < P; ++p) dy[6 * n + p] = -m->theta[p] * xi[p] + m->sigma[p] * w[p];
+    for (int p = 0; p < P; ++p) dy[6 * n + p] = -m->theta[p] * xi[p] + diffusion(m, p, w);
 }
 
 /* Exciter and field states at the operating point (delta0, E'q0 = E): every
@@ -792,6 +809,10 @@ static int setup_model(const orc_problem *pb, model_t *m)
     m->inf = pb->infinite_bus;
     m->Vinf = pb->V_inf;
     m->dgen = pb->dist_gen; m->theta = pb->theta; m->sigma = pb->sigma; m->xi0 = pb->xi0;
+    m->sigma_mat = pb->sigma_mat;
+    if (pb->sigma_mat)
+        for (int q = 0; q < P * P; ++q)
+            if (!isfinite(pb->sigma_mat[q])) return ORC_EINVAL;
     for (int p = 0; p < P; ++p) {
         if (pb->dist_gen[p] < 0 || pb->dist_gen[p] >= n) return ORC_EINVAL;
         if (pb->theta[p] < 0.0 || pb->sigma[p] < 0.0) return ORC_EINVAL;

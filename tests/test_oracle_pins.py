@@ -687,3 +687,63 @@ def test_lhs_decor_sampler_subset_matches_full_design():
     _, z0 = oracle.lhs(8, 5, 70, 0)
     z2, r = oracle.lhs_decorrelate(z0)
     assert np.array_equal(z, z2) and np.array_equal(st, r)
+
+
+# --- correlated disturbances: a diffusion matrix (Sec. III, eq. 4) ----------
+
+_SMAT = np.array([[0.09, 0.0, 0.03], [0.05, 0.07, 0.0], [-0.02, 0.04, 0.06]])
+
+
+def test_diffusion_matrix_unit_responses_closed_form():
+    # A unit coefficient on mode j of noise q drives process p through
+    # sigma_pq: xi_p(t) = sigma_pq int_0^t exp(-theta_p (t-s)) m_j(s) ds.
+    K = 3
+    sc = workloads.config2(N=2, T=0.5)
+    sc["dist"] = dict(sc["dist"], sigma_mat=_SMAT)
+    n, P = sc["n_gen"], 3
+    M = P * K
+    Z = np.concatenate([np.eye(M), np.zeros((M, 1))], axis=1)
+    tr = oracle.run(dict(sc, K=K, N=M + 1), zeta=Z, want_traj=True)["traj"]
+    theta = sc["dist"]["theta"]
+    S = tr.shape[1] - 1
+    for q in range(P):
+        for j in range(K):
+            col = q * K + j
+            for p in range(P):
+                xi = tr[col, :, 2 * n + p] - tr[M, :, 2 * n + p]
+                for s in range(0, S + 1, 20):
+                    t = s * sc["dt"]
+                    ref = _ou_kle_response(theta[p], _SMAT[p, q], j, t, sc["T"])
+                    # RK4 at dt = 5 ms against the exact integral: (a dt)^4 for
+                    # the fastest mode, a = 2 pi / T, is about 2e-5
+                    assert abs(xi[s] - ref) <= 1e-6 * max(abs(ref), 1e-6), (q, j, p, s)
+
+
+def test_diagonal_diffusion_matrix_equals_sigma_vector():
+    sc = workloads.config2(N=40, T=0.3, K=8)
+    a = oracle.run(sc)
+    sc2 = dict(sc, dist=dict(sc["dist"], sigma_mat=np.diag(sc["dist"]["sigma"])))
+    b = oracle.run(sc2)
+    assert np.array_equal(a["mean"], b["mean"]) and np.array_equal(a["var"], b["var"])
+
+
+def test_diffusion_matrix_cross_covariance():
+    # Sample covariance of xi_p, xi_q at t = T against (S S^T)-weighted sums of
+    # the truncated-KLE mode responses, within 5 standard errors.
+    K, N = 10, 4000
+    sc = workloads.config2(N=N, T=0.5, K=K)
+    sc["dist"] = dict(sc["dist"], sigma_mat=_SMAT)
+    n, P = sc["n_gen"], 3
+    sel = np.arange(N)
+    tr = oracle.run(sc, sel=sel, want_traj=True)["traj"]
+    xi = tr[:, -1, 2 * n:2 * n + P]
+    theta = sc["dist"]["theta"]
+    T = sc["T"]
+    R = np.array([[_ou_kle_response(theta[p], 1.0, j, T, T) for j in range(K)] for p in range(P)])
+    ref = (_SMAT @ _SMAT.T) * (R @ R.T)
+    cov = np.cov(xi.T)
+    for p in range(P):
+        for q in range(P):
+            se = math.sqrt((ref[p, p] * ref[q, q] + ref[p, q] ** 2) / N)
+            assert abs(cov[p, q] - ref[p, q]) <= 5 * se, (p, q, cov[p, q], ref[p, q])
+    assert abs(np.corrcoef(xi.T)[1, 0]) > 0.2  # the matrix does correlate them
