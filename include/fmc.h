@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define FMC_ABI_VERSION 1
+#define FMC_ABI_VERSION 2
 
 /* Status codes. */
 #define FMC_OK 0
@@ -172,6 +172,12 @@ typedef struct fmc_disturbance {
     const int32_t *gen;
     const double *theta, *sigma;
     const double *xi0; /* NULL: 0 */
+    /* NULL, or host [n_proc][n_proc] diffusion matrix (correlated
+     * disturbances, the matrix sigma of eq. 4 / Sec. III made square):
+     * d xi_p = -theta_p xi_p dt + sum_q sigma_mat[p][q] dW_q, with sigma then
+     * unused (may be NULL).  The design's rows stay the KLE coefficients of the
+     * independent W_q.  fmc_run only: the batched and served forms reject it. */
+    const double *sigma_mat;
 } fmc_disturbance;
 
 /* Alg. 1 inputs: truncation order K, sample size N, horizon T and step dt. */
@@ -345,8 +351,9 @@ int fmc_autotune(fmc_context *ctx, const fmc_scenario *scen, int32_t *variant);
 
 /* Device bytes a scenario needs while it runs.  FMC_F32 / FMC_BF16X3: the
  * admission footprint of the served form (staged inputs, design, basis, one
- * time chunk of paths, state, statistics rows, results); FMC_F64 or
- * FMC_LHS_DECOR: the single-run form's working set.  Validation as fmc_run. */
+ * time chunk of paths, state, statistics rows, results); FMC_F64,
+ * FMC_LHS_DECOR or a diffusion matrix: the single-run form's working set.
+ * Validation as fmc_run. */
 int fmc_footprint(const fmc_scenario *scen, int64_t *bytes);
 
 #ifdef __cplusplus

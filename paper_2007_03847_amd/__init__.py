@@ -39,7 +39,7 @@ CLASSICAL, FLUXDECAY_IEEET1 = 0, 1
 MODEL = {"classical": CLASSICAL, "fluxdecay": FLUXDECAY_IEEET1}
 FD_NPARAM = 9  # Xd, X'd, T'do, KA, TA, KE, TE, KF, TF
 MEM_HOST, MEM_DEVICE = 0, 1
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 _P = C.c_void_p
 
@@ -65,7 +65,8 @@ class System(C.Structure):
 
 
 class Disturbance(C.Structure):
-    _fields_ = [("n_proc", C.c_int32), ("gen", _P), ("theta", _P), ("sigma", _P), ("xi0", _P)]
+    _fields_ = [("n_proc", C.c_int32), ("gen", _P), ("theta", _P), ("sigma", _P), ("xi0", _P),
+                ("sigma_mat", _P)]
 
 
 class Params(C.Structure):
@@ -208,11 +209,13 @@ def scenario_structs(sc: dict, precision="f64", variant=-1, time_chunk=0, zeta_i
                   V_inf=float(sc.get("V_inf", 1.0)), Yinf_re=_ptr(a["Yinf_re"]),
                   Yinf_im=_ptr(a["Yinf_im"]), model=model, model_params=_ptr(a["model_params"]))
     d = sc["dist"]
+    sm = d.get("sigma_mat")
     b = dict(gen=_i32(d["gen"]), theta=_f64(d["theta"]), sigma=_f64(d["sigma"]),
-             xi0=_f64(d.get("xi0")))
+             xi0=_f64(d.get("xi0")),
+             sigma_mat=None if sm is None else _f64(np.asarray(sm, dtype=np.float64).reshape(-1)))
     keep.append(b)
     dist = Disturbance(n_proc=len(b["gen"]), gen=_ptr(b["gen"]), theta=_ptr(b["theta"]),
-                       sigma=_ptr(b["sigma"]), xi0=_ptr(b["xi0"]))
+                       sigma=_ptr(b["sigma"]), xi0=_ptr(b["xi0"]), sigma_mat=_ptr(b["sigma_mat"]))
     par = Params(T=float(sc["T"]), dt=float(sc["dt"]), K=int(sc["K"]), N=int(sc["N"]),
                  seed=int(sc.get("seed", 0)), basis=_enum(sc.get("basis", 0), BASIS),
                  sampler=_enum(sc.get("sampler", 0), SAMPLER),

@@ -106,6 +106,7 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
       return rc;
     zeta = zeta_dev;
   }
+  if (dist->sigma_mat && (rc = mix_design(c, dist, K, N, &zeta, c->stream))) return rc;
 
   // the plan is fixed (not taken from the device) so that a request gives the
   // same bits here and in the served form

@@ -182,6 +182,9 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   if (out->n_traj < 0 || (out->n_traj > 0 && (!out->traj_idx || !out->traj)))
     return fail(FMC_EINVAL, "n_traj > 0 needs traj_idx and traj");
   HIPCHK(hipSetDevice(c->device));
+  // a diffusion matrix is carried by the mixed design; the integrator sees sigma = 1
+  UnitSigma unit_sigma;
+  dist = unit_sigma.apply(dist);
   if (sys->model == FMC_FLUXDECAY_IEEET1) return run_fd(c, sys, dist, par, out, S);
   const int n = sys->n_gen, P = dist->n_proc, K = par->K;
   const int64_t N = par->N, M = (int64_t)P * K, C = 2 * S + 1;
@@ -262,6 +265,7 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
       return rc;
     zeta = zeta_dev;
   }
+  if (dist->sigma_mat && (rc = mix_design(c, dist, K, N, &zeta, c->gstream))) return rc;
   const int ev_lhs1 = evp.record(c->gstream);
 
   // per-workgroup statistics partials, trajectory slots, counters

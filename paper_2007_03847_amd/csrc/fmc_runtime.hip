@@ -305,12 +305,16 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
   if (sys->infinite_bus && (!sys->Yinf_re || !sys->Yinf_im))
     return fail(FMC_EINVAL, "infinite-bus coupling Yinf missing");
   if (dist->n_proc < 1) return fail(FMC_EINVAL, "at least one disturbance process is required");
-  if (!dist->gen || !dist->theta || !dist->sigma) return fail(FMC_EINVAL, "disturbance arrays missing");
+  if (!dist->gen || !dist->theta || (!dist->sigma && !dist->sigma_mat))
+    return fail(FMC_EINVAL, "disturbance arrays missing");
   for (int p = 0; p < dist->n_proc; ++p) {
     if (dist->gen[p] < 0 || dist->gen[p] >= n) return fail(FMC_EINVAL, "disturbance machine index out of range");
     if (!(dist->theta[p] >= 0.0)) return fail(FMC_EINVAL, "theta must be >= 0");
-    if (!(dist->sigma[p] >= 0.0)) return fail(FMC_EINVAL, "sigma must be >= 0");
+    if (!dist->sigma_mat && !(dist->sigma[p] >= 0.0)) return fail(FMC_EINVAL, "sigma must be >= 0");
   }
+  if (dist->sigma_mat)
+    for (int q = 0; q < dist->n_proc * dist->n_proc; ++q)
+      if (!std::isfinite(dist->sigma_mat[q])) return fail(FMC_EINVAL, "sigma_mat must be finite");
   if (par->sampler == FMC_LHS_DECOR && !par->zeta_in) {
     const int64_t M = (int64_t)dist->n_proc * par->K;
     if (M > kDecorMaxM || par->N <= M || par->N > kDecorMaxN)
@@ -387,6 +391,22 @@ int64_t auto_chunk(int64_t S, int P, int64_t N, int bytes_per) {
   int64_t cols = (int64_t)(target / col);
   int64_t sc = std::max<int64_t>(8, (cols - 1) / 2);
   return std::min<int64_t>(sc, S);
+}
+
+int mix_design(Context* c, const fmc_disturbance* dist, int32_t K, int64_t N, const double** zeta,
+               hipStream_t st) {
+  const int P = dist->n_proc;
+  void *s_d = nullptr, *out = nullptr, *h = nullptr;
+  int rc;
+  if ((rc = c->ensure("sigma_mat", (size_t)P * P * sizeof(double), &s_d))) return rc;
+  if ((rc = c->ensure("zeta_mix", (size_t)P * K * N * sizeof(double), &out))) return rc;
+  if ((rc = c->host_stage("sigma_mat", (size_t)P * P * sizeof(double), &h))) return rc;
+  std::memcpy(h, dist->sigma_mat, (size_t)P * P * sizeof(double));
+  hipError_t e = hipMemcpyAsync(s_d, h, (size_t)P * P * sizeof(double), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_mix_design((const double*)s_d, P, K, N, *zeta, (double*)out, st);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  *zeta = (const double*)out;
+  return FMC_OK;
 }
 
 }  // namespace fmc
@@ -488,6 +508,7 @@ int fmc_kron_reduce(fmc_context* ctx, const fmc_network* net, double* Y_re, doub
 
 static int decorrelate_and_check(Context* c, int32_t M, int64_t N, double* zeta, int32_t* strata,
                                  const int32_t* lhs_strata);
+
 
 int fmc_lhs(fmc_context* ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampler,
             int32_t* strata, double* zeta) {

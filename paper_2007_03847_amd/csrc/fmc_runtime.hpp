@@ -102,6 +102,23 @@ void serve_shutdown(Context* c);
 int decorrelate_design(Context* c, int32_t M, int64_t N, double* zeta, int32_t* strata,
                        const int32_t* lhs_strata, int32_t** status_out, hipStream_t st);
 size_t decorrelate_workspace(int32_t M, int64_t N);
+// Correlated disturbances: *zeta (device [P*K][N]) is replaced by the design
+// mixed through dist->sigma_mat (a context buffer) on stream st.
+int mix_design(Context* c, const fmc_disturbance* dist, int32_t K, int64_t N, const double** zeta,
+               hipStream_t st);
+// A copy of a disturbance whose diffusion matrix replaces sigma: sigma is
+// then 1 for every process (the mixed design carries the matrix).
+struct UnitSigma {
+  std::vector<double> one;
+  fmc_disturbance d;
+  const fmc_disturbance* apply(const fmc_disturbance* dist) {
+    if (!dist->sigma_mat) return dist;
+    one.assign((size_t)dist->n_proc, 1.0);
+    d = *dist;
+    d.sigma = one.data();
+    return &d;
+  }
+};
 
 // Flux-decay path: tiles of 16 trajectories, contiguous work items of
 // tiles_per_item tiles, one workgroup per item.

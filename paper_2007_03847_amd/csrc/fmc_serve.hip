@@ -723,7 +723,8 @@ int fmc_footprint(const fmc_scenario* scen, int64_t* bytes) {
   if (rc) return rc;
   const fmc_params* par = scen->par;
   const bool decor = par->sampler == FMC_LHS_DECOR && !par->zeta_in;
-  if (par->precision != FMC_F64 && !par->zeta_in && !decor) {
+  const bool mixed = scen->dist->sigma_mat != nullptr;
+  if (par->precision != FMC_F64 && !par->zeta_in && !decor && !mixed) {
     // reduced precision: the admission footprint of the served form
     Request r;
     if ((rc = plan_request(r, scen->sys, scen->dist, par, S))) return rc;
@@ -746,6 +747,7 @@ int fmc_footprint(const fmc_scenario* scen, int64_t* bytes) {
   b += 2 * (S + 1) * V * 8;                  // mean, var
   b += 2 * n * n * 16 + 64 * n;              // reduced network, coefficients
   if (decor) b += (int64_t)decorrelate_workspace((int32_t)(P * K), N);
+  if (mixed) b += P * K * N * 8 + P * P * 8;  // mixed design, diffusion matrix
   *bytes = b;
   return FMC_OK;
 }
@@ -759,6 +761,7 @@ int fmc_submit(fmc_context* ctx, const fmc_scenario* scen, fmc_outputs* out, uin
   if (rc) return rc;
   if (scen->par->sampler == FMC_LHS_DECOR)
     return fail(FMC_EINVAL, "FMC_LHS_DECOR runs through fmc_run only");
+  if (scen->dist->sigma_mat) return fail(FMC_EINVAL, "a diffusion matrix runs through fmc_run only");
   if (!out->mean || !out->var) return fail(FMC_EINVAL, "mean and var outputs are required");
   if (out->mem_kind != FMC_MEM_HOST && out->mem_kind != FMC_MEM_DEVICE)
     return fail(FMC_EINVAL, "unknown mem_kind");

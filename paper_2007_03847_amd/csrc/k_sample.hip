@@ -52,6 +52,31 @@ hipError_t launch_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int3
 }
 
 // ---------------------------------------------------------------------------
+// Correlated disturbances (a diffusion matrix S, eq. 4): the noise driving
+// process p is sum_q S[p][q] w_q, and since the KLE paths are linear in the
+// coefficients, the coefficients are mixed instead of the paths:
+// out[p*K + j][n] = sum_q S[p][q] in[q*K + j][n].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_mix_design(const double* __restrict__ S, int32_t P,
+                                                    int32_t K, int64_t N,
+                                                    const double* __restrict__ in,
+                                                    double* __restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int row = blockIdx.y, p = row / K, j = row % K;
+  double s = 0.0;
+  for (int q = 0; q < P; ++q) s += S[p * P + q] * in[(int64_t)(q * K + j) * N + n];
+  out[(int64_t)row * N + n] = s;
+}
+
+hipError_t launch_mix_design(const double* S, int32_t P, int32_t K, int64_t N, const double* in,
+                             double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mix_design, dim3((unsigned)((N + 255) / 256), (unsigned)(P * K)), dim3(256),
+                     0, st, S, P, K, N, in, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // KLE basis (eq. 7) at the stage times t_c = c T/(2S).  The cosine argument is
 // reduced exactly in integers: (j c) mod 4S for the paper basis,
 // ((2j+1) c) mod 8S for the eigen basis, then cospi of the reduced fraction.
