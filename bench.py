@@ -374,6 +374,31 @@ def decor_leg(ctx, fmc, workloads, reps: int = 3):
     return out
 
 
+def corr_leg(ctx, fmc, workloads, reps: int = 3):
+    """Correlated disturbances (a 3 x 3 diffusion matrix, eq. 4 with a full
+    sigma) on the 10-machine workload: a whole FP64 pass with and without the
+    matrix (the design is mixed once before the path contraction), and the
+    correlation the matrix puts between the disturbances at t = T."""
+    import numpy as np
+    import torch
+    sc = workloads.config2()
+    smat = np.array([[0.09, 0.0, 0.03], [0.05, 0.07, 0.0], [-0.02, 0.04, 0.06]])
+    mixed = dict(sc, dist=dict(sc["dist"], sigma_mat=smat))
+    vid = ctx.autotune(sc, precision="f64")
+    out = {"sigma_mat": smat.tolist()}
+    for name, s in (("vector_sigma", sc), ("sigma_mat", mixed)):
+        ctx.run(s, precision="f64", variant=vid)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = ctx.run(s, precision="f64", variant=vid)
+        torch.cuda.synchronize()
+        out[name + "_run_ms"] = (time.perf_counter() - t0) / reps * 1e3
+    say(f"diffusion matrix: whole FP64 pass {out['sigma_mat_run_ms']:.2f} ms "
+        f"(vector sigma {out['vector_sigma_run_ms']:.2f} ms)")
+    return out
+
+
 def fd_leg(ctx, fmc, workloads, oracle_mod, steps: int, reps: int = 2):
     """Large-request shape of the flux-decay model (200 machines with IEEE
     type-1 exciters, 10 OU processes, N = 5e4, K = 100) on a horizon of
@@ -441,7 +466,7 @@ def main():
     ap.add_argument("--fd-steps", type=int, default=100,
                     help="horizon of the flux-decay leg in steps (0: skip)")
     ap.add_argument("--decor-reps", type=int, default=3,
-                    help="passes of the correlation-reduced design leg (0: skip)")
+                    help="passes of the reduced-design and diffusion-matrix legs (0: skip)")
     ap.add_argument("--convergence", type=int, default=0,
                     help="run the sample-count convergence comparison up to this N (0: skip)")
     ap.add_argument("--convergence-out", default="",
@@ -553,9 +578,10 @@ def main():
         batched = batched_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(),
                               args.batch_steps, "f64" in forms)
 
-    decor = None
+    decor = corr = None
     if args.decor_reps > 0:
         decor = decor_leg(ctx, fmc, workloads, args.decor_reps)
+        corr = corr_leg(ctx, fmc, workloads, args.decor_reps)
 
     conv = None
     if args.convergence > 0:
@@ -618,6 +644,7 @@ def main():
         "flux_decay": fdl,
         "convergence": conv,
         "lhs_decor": decor,
+        "correlated_disturbances": corr,
     }
     print(json.dumps(line))
     ctx.close()
