@@ -71,6 +71,7 @@ def lib():
         L.orc_ppnd16.restype = C.c_double
         L.orc_lhs.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_int32, C.c_int64, P, P, P]
         L.orc_lhs_decorrelate.argtypes = [C.c_int32, C.c_int64, P, P]
+        L.orc_rrf_rms.argtypes = [P, C.c_int64, C.c_int64, C.c_int32, P, C.c_double, P]
         L.orc_basis.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.c_double, P]
         L.orc_kron.argtypes = [C.c_int32, C.c_int32, P, P, P, P, P, P, P, C.c_int32, P, P, P, P]
         L.orc_run.argtypes = [C.POINTER(_Problem), P, C.c_int64, P, P, P, P, P, P, P, P]
@@ -141,6 +142,18 @@ def lhs_decorrelate(zeta):
     if rc != 0:
         raise ValueError(f"orc_lhs_decorrelate failed: {rc}")
     return z, ranks
+
+
+def rrf_rms(traj, w, dt: float):
+    """RMS over the horizon of sum_v w_v y_v(t) for each trajectory [n][S+1][V]."""
+    tr = np.ascontiguousarray(traj, dtype=np.float64)
+    n, S1, V = tr.shape
+    ww = np.ascontiguousarray(w, dtype=np.float64).reshape(V)
+    out = np.zeros(n)
+    rc = lib().orc_rrf_rms(tr.ctypes.data, n, S1 - 1, V, ww.ctypes.data, dt, out.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"orc_rrf_rms failed: {rc}")
+    return out
 
 
 def basis(kind: int, K: int, S: int, T: float):

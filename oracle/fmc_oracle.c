@@ -30,6 +30,8 @@
  *                     cross-covariance against the truncated-KLE closed form
  *   run (swing)    -> SMIB linearised variance (Lyapunov / Van Loan), RK4 order
  *   kron           -> SMIB reduction to E V sin(delta)/X, symmetry, full solve
+ *   rrf_rms        -> constant and full-period sine signals, scaling, a common
+ *                     mode removed by centre-of-inertia weights
  */
 #include <complex.h>
 #include <math.h>
@@ -1011,6 +1013,32 @@ int orc_run(const orc_problem *pb, const double *zeta_in, int64_t n_sel, const i
     if (n_notconv) *n_notconv = notconv;
     if (notconv) return ORC_ENOTCONV;
     return nonfin ? ORC_ENONFINITE : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* A scalar RRF (eq. 3; Sec. V-B uses the RMS of the system frequency         */
+/* deviation over the horizon): for each trajectory y [S+1][V] on the grid    */
+/* t_s = s dt, the RMS over [0, T], T = S dt, of the linear combination       */
+/* u(t) = sum_v w_v y_v(t):  sqrt( (1/T) int_0^T u(t)^2 dt ), the integral by */
+/* the trapezoid rule on the stored points.  With w_v = H_i / sum H on the    */
+/* frequency deviations this is the RMS of the centre-of-inertia (system)     */
+/* frequency deviation.  traj [n][S+1][V], w [V], rrf [n].                    */
+/* ------------------------------------------------------------------------- */
+int orc_rrf_rms(const double *traj, int64_t n, int64_t S, int32_t V, const double *w, double dt,
+                double *rrf)
+{
+    if (n < 0 || S < 1 || V < 1 || !(dt > 0.0)) return ORC_EINVAL;
+    for (int64_t c = 0; c < n; ++c) {
+        double acc = 0.0;
+        for (int64_t s = 0; s <= S; ++s) {
+            double u = 0.0;
+            for (int v = 0; v < V; ++v) u += w[v] * traj[(c * (S + 1) + s) * V + v];
+            const double h = (s == 0 || s == S) ? 0.5 : 1.0;
+            acc += h * u * u;
+        }
+        rrf[c] = sqrt(acc * dt / ((double)S * dt));
+    }
+    return ORC_OK;
 }
 
 /* Right-hand side at one state, for tests of the model itself. */

@@ -747,3 +747,41 @@ def test_diffusion_matrix_cross_covariance():
             se = math.sqrt((ref[p, p] * ref[q, q] + ref[p, q] ** 2) / N)
             assert abs(cov[p, q] - ref[p, q]) <= 5 * se, (p, q, cov[p, q], ref[p, q])
     assert abs(np.corrcoef(xi.T)[1, 0]) > 0.2  # the matrix does correlate them
+
+
+# --- scalar RRF: RMS over the horizon (eq. 3; Sec. V-B) ---------------------
+
+
+def test_rrf_rms_constant_and_sine():
+    S, V, dt = 400, 3, 0.05
+    t = np.arange(S + 1) * dt
+    T = S * dt
+    tr = np.zeros((3, S + 1, V))
+    tr[0, :, 1] = 0.7                                  # constant: RMS = |w c|
+    tr[1, :, 1] = np.sin(2 * np.pi * 3 * t / T)        # whole periods: RMS = 1/sqrt(2)
+    tr[2, :, 0] = 2.0
+    tr[2, :, 2] = -1.0                                 # w . y = 2 w0 - w2
+    w = np.array([0.5, 2.0, 1.0])
+    r = oracle.rrf_rms(tr, w, dt)
+    assert abs(r[0] - 1.4) < 1e-14
+    assert abs(r[1] - 2.0 / math.sqrt(2.0)) < 1e-12
+    assert abs(r[2] - 0.0) < 1e-15
+
+
+def test_rrf_rms_scaling_and_coi_frame():
+    rng = np.random.default_rng(3)
+    n, S, V, dt = 5, 120, 4, 0.01
+    tr = rng.normal(size=(n, S + 1, V))
+    w = np.array([0.2, 0.3, 0.5, 0.0])
+    r = oracle.rrf_rms(tr, w, dt)
+    assert np.allclose(oracle.rrf_rms(-3.0 * tr, w, dt), 3.0 * r, rtol=1e-14)
+    # centre-of-inertia deviation: weights e_i - H/sum H remove a common mode
+    H = np.array([2.0, 3.0, 5.0])
+    wc = np.append(np.eye(3)[1] - H / H.sum(), 0.0)
+    common = tr.copy()
+    common[:, :, :3] = tr[:, :, :1]                    # every machine the same
+    assert np.all(oracle.rrf_rms(common, wc, dt) < 1e-14)
+    # trapezoid rule written out for one trajectory
+    u = tr[2] @ w
+    ref = math.sqrt(((u[0] ** 2 + u[-1] ** 2) / 2 + (u[1:-1] ** 2).sum()) * dt / (S * dt))
+    assert abs(r[2] - ref) < 1e-14
