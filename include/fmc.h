@@ -281,6 +281,19 @@ int fmc_lhs(fmc_context *ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampl
  * strata is unspecified. */
 int fmc_lhs_decorrelate(fmc_context *ctx, int32_t M, int64_t N, double *zeta, int32_t *strata);
 
+/* A scalar random response function (eq. 3) of stored trajectories: for each
+ * of the n trajectories in traj (device [n][S+1][V] FP64, the layout fmc_run
+ * writes for sampled trajectories, grid t_s = s dt), the RMS over the horizon
+ * T = S dt of u(t) = sum_v w[v] y_v(t), sqrt((1/T) int_0^T u(t)^2 dt), the
+ * integral by the trapezoid rule on the S+1 points.  With w[n_gen + i] =
+ * H_i / sum H on the frequency deviations (classical layout) this is the RMS
+ * of the system (centre-of-inertia) frequency deviation, the RRF of Sec. V-B.
+ * w: host [V]; rrf: device [n] FP64 (traj and rrf may be NULL when n = 0).
+ * Synchronises the context's stream.  FMC_EINVAL: NULL pointers, n < 0,
+ * n >= 2^31, S < 1, V < 1, dt <= 0. */
+int fmc_rrf_rms(fmc_context *ctx, const double *traj, int64_t n, int64_t S, int32_t V,
+                const double *w, double dt, double *rrf);
+
 /* KLE basis (eq. 7, or the eigen basis) on the stage grid: phi device
  * [K][2S+1] FP64. */
 int fmc_basis(fmc_context *ctx, int32_t basis, int32_t K, int64_t S, double T, double *phi);

@@ -109,6 +109,7 @@ _sig = {
     "fmc_kron_reduce": ([_ctx_p, C.POINTER(Network), _P, _P], C.c_int),
     "fmc_lhs": ([_ctx_p, C.c_uint64, C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "fmc_lhs_decorrelate": ([_ctx_p, C.c_int32, C.c_int64, _P, _P], C.c_int),
+    "fmc_rrf_rms": ([_ctx_p, _P, C.c_int64, C.c_int64, C.c_int32, _P, C.c_double, _P], C.c_int),
     "fmc_basis": ([_ctx_p, C.c_int32, C.c_int32, C.c_int64, C.c_double, _P], C.c_int),
     "fmc_kle_paths": ([_ctx_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
                        C.c_int64, _P, _P, C.c_int64, _P], C.c_int),
@@ -298,6 +299,19 @@ class Context:
         strata = t.empty((M, N), dtype=t.int32, device=self.device) if want_strata else None
         _check(_lib.fmc_lhs_decorrelate(self._h, M, N, _dptr(zeta), _dptr(strata)))
         return strata
+
+    def rrf_rms(self, traj, w, dt: float):
+        """RMS over the horizon of sum_v w[v] y_v(t) for each trajectory of a
+        device tensor [n][S+1][V] (FP64); returns a device tensor [n]."""
+        t = self.torch
+        assert traj.dtype == t.float64 and traj.is_contiguous() and traj.dim() == 3
+        assert traj.device == t.device(self.device)
+        n, S1, V = traj.shape
+        ww = np.ascontiguousarray(w, dtype=np.float64).reshape(V)
+        out = t.empty(n, dtype=t.float64, device=self.device)
+        _check(_lib.fmc_rrf_rms(self._h, _dptr(traj), n, S1 - 1, V, ww.ctypes.data, float(dt),
+                                _dptr(out)))
+        return out
 
     def basis(self, kind, K: int, S: int, T: float):
         t = self.torch

@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["fmc_runtime.hip", "fmc_run.hip", "fmc_fd.hip", "fmc_batch.hip", "fmc_serve.hip", "k_decor.hip",
+SOURCES = ["fmc_runtime.hip", "fmc_run.hip", "fmc_fd.hip", "fmc_batch.hip", "fmc_serve.hip", "k_decor.hip", "k_rrf.hip",
            "k_sample.hip", "k_setup.hip", "k_fluxdecay.hip", "k_batch.hip", "k_mfma_classical.hip",
            "k_integrate_f64.hip", "k_integrate_f32.hip"]
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -77,6 +77,8 @@ struct IntegArgs {
 };
 
 // ---- launchers (each returns hipError_t of the launch) ----
+hipError_t launch_rrf_rms(const double* traj, int64_t n, int64_t S, int32_t V, const double* w,
+                          double dt, double* rrf, hipStream_t st);
 hipError_t launch_mix_design(const double* S, int32_t P, int32_t K, int64_t N, const double* in,
                              double* out, hipStream_t st);
 hipError_t launch_lhs(uint64_t seed, int32_t M, int64_t N, int32_t sampler, int32_t* strata,

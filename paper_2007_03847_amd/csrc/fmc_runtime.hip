@@ -535,6 +535,25 @@ int fmc_lhs(fmc_context* ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampl
   return decorrelate_and_check(c, M, N, zeta, strata, lhs_strata);
 }
 
+int fmc_rrf_rms(fmc_context* ctx, const double* traj, int64_t n, int64_t S, int32_t V,
+                const double* w, double dt, double* rrf) {
+  if (!ctx || !w || (n > 0 && (!traj || !rrf))) return fail(FMC_EINVAL, "NULL argument");
+  if (n < 0 || n > INT32_MAX || S < 1 || V < 1 || !(dt > 0.0))
+    return fail(FMC_EINVAL, "need 0 <= n < 2^31, S >= 1, V >= 1, dt > 0");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  (void)hipSetDevice(c->device);
+  void *wd = nullptr, *h = nullptr;
+  int rc;
+  if ((rc = c->ensure("rrf_w", (size_t)V * sizeof(double), &wd))) return rc;
+  if ((rc = c->host_stage("rrf_w", (size_t)V * sizeof(double), &h))) return rc;
+  std::memcpy(h, w, (size_t)V * sizeof(double));
+  hipError_t e = hipMemcpyAsync(wd, h, (size_t)V * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_rrf_rms(traj, n, S, V, (const double*)wd, dt, rrf, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  return FMC_OK;
+}
+
 int fmc_lhs_decorrelate(fmc_context* ctx, int32_t M, int64_t N, double* zeta, int32_t* strata) {
   if (!ctx || !zeta) return fail(FMC_EINVAL, "NULL argument");
   if (M < 1 || M > kDecorMaxM || N <= M || N > kDecorMaxN)
