@@ -399,6 +399,38 @@ def corr_leg(ctx, fmc, workloads, reps: int = 3):
     return out
 
 
+def rrf_leg(ctx, fmc, workloads, reps: int = 3):
+    """Scalar RRF (eq. 3; Sec. V-B): every trajectory of the 10-machine
+    workload stored by one FP64 pass (N x (S+1) x V doubles), then the RMS of
+    the centre-of-inertia frequency deviation over the horizon for each, timed
+    on the host clock around the synchronous fmc_rrf_rms call."""
+    import numpy as np
+    import torch
+    sc = workloads.config2()
+    n, N = sc["n_gen"], sc["N"]
+    V = 2 * n + len(sc["dist"]["gen"])
+    H = np.asarray(sc["H"], dtype=np.float64)
+    w = np.zeros(V)
+    w[n:2 * n] = H / H.sum()
+    r = ctx.run(sc, precision="f64", traj_idx=np.arange(N))
+    traj = r["traj"]
+    rrf = ctx.rrf_rms(traj, w, sc["dt"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        rrf = ctx.rrf_rms(traj, w, sc["dt"])
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    nbytes = traj.numel() * 8
+    out = {"n_traj": N, "traj_bytes": nbytes, "ms": sec * 1e3, "GB_per_s": nbytes / sec / 1e9,
+           "rrf_mean": float(rrf.mean()), "rrf_var": float(rrf.var(unbiased=True))}
+    say(f"RRF (RMS of the centre-of-inertia frequency deviation) over {N} stored trajectories "
+        f"({nbytes / 1e9:.2f} GB): {sec * 1e3:.2f} ms, {nbytes / sec / 1e9:.0f} GB/s")
+    del traj, r
+    torch.cuda.empty_cache()
+    return out
+
+
 def fd_leg(ctx, fmc, workloads, oracle_mod, steps: int, reps: int = 2):
     """Large-request shape of the flux-decay model (200 machines with IEEE
     type-1 exciters, 10 OU processes, N = 5e4, K = 100) on a horizon of
@@ -466,7 +498,7 @@ def main():
     ap.add_argument("--fd-steps", type=int, default=100,
                     help="horizon of the flux-decay leg in steps (0: skip)")
     ap.add_argument("--decor-reps", type=int, default=3,
-                    help="passes of the reduced-design and diffusion-matrix legs (0: skip)")
+                    help="passes of the reduced-design, diffusion-matrix and RRF legs (0: skip)")
     ap.add_argument("--convergence", type=int, default=0,
                     help="run the sample-count convergence comparison up to this N (0: skip)")
     ap.add_argument("--convergence-out", default="",
@@ -578,10 +610,11 @@ def main():
         batched = batched_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(),
                               args.batch_steps, "f64" in forms)
 
-    decor = corr = None
+    decor = corr = rrf = None
     if args.decor_reps > 0:
         decor = decor_leg(ctx, fmc, workloads, args.decor_reps)
         corr = corr_leg(ctx, fmc, workloads, args.decor_reps)
+        rrf = rrf_leg(ctx, fmc, workloads, args.decor_reps)
 
     conv = None
     if args.convergence > 0:
@@ -645,6 +678,7 @@ def main():
         "convergence": conv,
         "lhs_decor": decor,
         "correlated_disturbances": corr,
+        "rrf": rrf,
     }
     print(json.dumps(line))
     ctx.close()
