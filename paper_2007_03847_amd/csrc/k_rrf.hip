@@ -12,19 +12,34 @@ namespace fmc {
 
 namespace {
 
-// One workgroup per trajectory [S+1][V]; threads stride over the time points.
+constexpr int kRrfLds = 6144;  // doubles of trajectory staged per tile (48 KB)
+
+// One workgroup per trajectory [S+1][V].  Tiles of whole time points are
+// staged in LDS with coalesced loads (the rows are V doubles long, so a
+// thread per time point reading global memory directly would stride by V);
+// thread t then forms u for time point t of the tile.
 __global__ void __launch_bounds__(256) k_rrf_rms(const double* __restrict__ traj, int64_t S,
-                                                 int32_t V, const double* __restrict__ w,
-                                                 double dt, double* __restrict__ rrf) {
+                                                 int32_t V, int32_t pts,
+                                                 const double* __restrict__ w, double dt,
+                                                 double* __restrict__ rrf) {
+  __shared__ double tile[kRrfLds];
+  __shared__ double red[256];
   const double* y = traj + (int64_t)blockIdx.x * (S + 1) * V;
   double acc = 0.0;
-  for (int64_t s = threadIdx.x; s <= S; s += 256) {
-    double u = 0.0;
-    for (int v = 0; v < V; ++v) u += w[v] * y[s * V + v];
-    const double h = (s == 0 || s == S) ? 0.5 : 1.0;
-    acc += h * u * u;
+  for (int64_t s0 = 0; s0 <= S; s0 += pts) {
+    const int np = (int)((S + 1 - s0) < pts ? (S + 1 - s0) : pts);
+    const int ne = np * V;
+    __syncthreads();  // the previous tile has been read
+    for (int e = threadIdx.x; e < ne; e += 256) tile[e] = y[s0 * V + e];
+    __syncthreads();
+    for (int q = threadIdx.x; q < np; q += 256) {
+      double u = 0.0;
+      for (int v = 0; v < V; ++v) u += w[v] * tile[q * V + v];
+      const int64_t s = s0 + q;
+      const double h = (s == 0 || s == S) ? 0.5 : 1.0;
+      acc += h * u * u;
+    }
   }
-  __shared__ double red[256];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int k = 128; k > 0; k >>= 1) {
@@ -39,7 +54,11 @@ __global__ void __launch_bounds__(256) k_rrf_rms(const double* __restrict__ traj
 hipError_t launch_rrf_rms(const double* traj, int64_t n, int64_t S, int32_t V, const double* w,
                           double dt, double* rrf, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rrf_rms, dim3((unsigned)n), dim3(256), 0, st, traj, S, V, w, dt, rrf);
+  // whole time points per tile, at most 256 (one per thread) and kRrfLds doubles;
+  // a row longer than the tile is beyond this kernel
+  if (V > kRrfLds) return hipErrorInvalidValue;
+  const int pts = V * 256 <= kRrfLds ? 256 : kRrfLds / V;
+  hipLaunchKernelGGL(k_rrf_rms, dim3((unsigned)n), dim3(256), 0, st, traj, S, V, pts, w, dt, rrf);
   return hipGetLastError();
 }
 
