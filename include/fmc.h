@@ -290,7 +290,7 @@ int fmc_lhs_decorrelate(fmc_context *ctx, int32_t M, int64_t N, double *zeta, in
  * of the system (centre-of-inertia) frequency deviation, the RRF of Sec. V-B.
  * w: host [V]; rrf: device [n] FP64 (traj and rrf may be NULL when n = 0).
  * Synchronises the context's stream.  FMC_EINVAL: NULL pointers, n < 0,
- * n >= 2^31, S < 1, V < 1, V > 6144, dt <= 0. */
+ * n >= 2^31, S < 1, V < 1, V > 2048, dt <= 0. */
 int fmc_rrf_rms(fmc_context *ctx, const double *traj, int64_t n, int64_t S, int32_t V,
                 const double *w, double dt, double *rrf);
 

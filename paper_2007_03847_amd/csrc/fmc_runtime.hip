@@ -538,8 +538,8 @@ int fmc_lhs(fmc_context* ctx, uint64_t seed, int32_t M, int64_t N, int32_t sampl
 int fmc_rrf_rms(fmc_context* ctx, const double* traj, int64_t n, int64_t S, int32_t V,
                 const double* w, double dt, double* rrf) {
   if (!ctx || !w || (n > 0 && (!traj || !rrf))) return fail(FMC_EINVAL, "NULL argument");
-  if (n < 0 || n > INT32_MAX || S < 1 || V < 1 || V > 6144 || !(dt > 0.0))
-    return fail(FMC_EINVAL, "need 0 <= n < 2^31, S >= 1, 1 <= V <= 6144, dt > 0");
+  if (n < 0 || n > INT32_MAX || S < 1 || V < 1 || V > 2048 || !(dt > 0.0))
+    return fail(FMC_EINVAL, "need 0 <= n < 2^31, S >= 1, 1 <= V <= 2048, dt > 0");
   Context* c = reinterpret_cast<Context*>(ctx);
   (void)hipSetDevice(c->device);
   void *wd = nullptr, *h = nullptr;

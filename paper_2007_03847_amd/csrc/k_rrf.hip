@@ -12,7 +12,7 @@ namespace fmc {
 
 namespace {
 
-constexpr int kRrfLds = 6144;  // doubles of trajectory staged per tile (48 KB)
+constexpr int kRrfLds = 2048;  // doubles of trajectory staged per tile (16 KB: several workgroups per CU)
 
 // One workgroup per trajectory [S+1][V].  Tiles of whole time points are
 // staged in LDS with coalesced loads (the rows are V doubles long, so a

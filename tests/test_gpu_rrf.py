@@ -18,7 +18,7 @@ def ctx(fmc):
 
 
 @pytest.mark.parametrize("n,S,V", [(1, 1, 1), (5, 120, 4), (3, 1000, 23), (300, 257, 7),
-                                   (2, 700, 61), (2, 9, 300)])
+                                   (2, 700, 61), (2, 9, 300), (2, 5, 2048)])
 def test_rrf_given_trajectories(ctx, n, S, V):
     rng = np.random.default_rng(n + S)
     tr = rng.normal(size=(n, S + 1, V))
