@@ -17,7 +17,19 @@ constexpr int kRrfLds = 2048;  // doubles of trajectory staged per tile (16 KB: 
 // One workgroup per trajectory [S+1][V].  Tiles of whole time points are
 // staged in LDS with coalesced loads (the rows are V doubles long, so a
 // thread per time point reading global memory directly would stride by V);
-// thread t then forms u for time point t of the tile.
+// thread t then forms u for time point t of the tile.  Each thread holds its
+// share of the next tile (at most kRrfLds / 256 doubles) in registers, loaded
+// while the current tile is reduced, so that a workgroup keeps a tile of
+// loads in flight beside its LDS work.
+constexpr int kRrfPer = kRrfLds / 256;
+__device__ __forceinline__ void rrf_fetch(const double* __restrict__ y, int64_t s0, int ne,
+                                          int32_t V, double (&r)[kRrfPer]) {
+#pragma unroll
+  for (int i = 0; i < kRrfPer; ++i) {
+    const int e = (int)threadIdx.x + i * 256;
+    r[i] = e < ne ? y[s0 * V + e] : 0.0;
+  }
+}
 __global__ void __launch_bounds__(256) k_rrf_rms(const double* __restrict__ traj, int64_t S,
                                                  int32_t V, int32_t pts,
                                                  const double* __restrict__ w, double dt,
@@ -26,12 +38,21 @@ __global__ void __launch_bounds__(256) k_rrf_rms(const double* __restrict__ traj
   __shared__ double red[256];
   const double* y = traj + (int64_t)blockIdx.x * (S + 1) * V;
   double acc = 0.0;
+  double r[kRrfPer];
+  int np = (int)((S + 1) < pts ? (S + 1) : pts);
+  rrf_fetch(y, 0, np * V, V, r);
   for (int64_t s0 = 0; s0 <= S; s0 += pts) {
-    const int np = (int)((S + 1 - s0) < pts ? (S + 1 - s0) : pts);
     const int ne = np * V;
     __syncthreads();  // the previous tile has been read
-    for (int e = threadIdx.x; e < ne; e += 256) tile[e] = y[s0 * V + e];
+#pragma unroll
+    for (int i = 0; i < kRrfPer; ++i) {
+      const int e = (int)threadIdx.x + i * 256;
+      if (e < ne) tile[e] = r[i];
+    }
     __syncthreads();
+    const int64_t s1 = s0 + pts;
+    const int np1 = s1 <= S ? (int)((S + 1 - s1) < pts ? (S + 1 - s1) : pts) : 0;
+    if (np1 > 0) rrf_fetch(y, s1, np1 * V, V, r);
     for (int q = threadIdx.x; q < np; q += 256) {
       double u = 0.0;
       for (int v = 0; v < V; ++v) u += w[v] * tile[q * V + v];
@@ -39,6 +60,7 @@ __global__ void __launch_bounds__(256) k_rrf_rms(const double* __restrict__ traj
       const double h = (s == 0 || s == S) ? 0.5 : 1.0;
       acc += h * u * u;
     }
+    np = np1;
   }
   red[threadIdx.x] = acc;
   __syncthreads();
