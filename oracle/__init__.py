@@ -7,7 +7,11 @@ path: the arithmetic lives in ``fmc_oracle.c`` (plain C, scalar loops, OpenMP
 over samples only), this module only marshals arguments.
 
 Parity unpinned: nothing.  Every function here is pinned by a CPU test against
-a value fixed by mathematics or by a library routine (see tests/test_oracle_*.py).
+a value fixed by mathematics or by a library routine (see tests/test_oracle_*.py);
+the multimachine network coupling (electrical power, its Jacobian, the one-axis
+machine's network quantities) is pinned away from the operating point, with
+losses, against the textbook real and dq forms and against the exact response
+of the linearised 10-machine system (tests/test_oracle_network.py).
 """
 from __future__ import annotations
 
@@ -77,6 +81,7 @@ def lib():
         L.orc_run.argtypes = [C.POINTER(_Problem), P, C.c_int64, P, P, P, P, P, P, P, P]
         L.orc_rhs.argtypes = [C.POINTER(_Problem), P, P, P]
         L.orc_initial_state.argtypes = [C.POINTER(_Problem), P, P]
+        L.orc_rhs_jac.argtypes = [C.POINTER(_Problem), P, P]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -279,6 +284,17 @@ def rhs(sc: dict, y, w):
     if rc != 0:
         raise RuntimeError(f"orc_rhs failed: {rc}")
     return dy
+
+
+def rhs_jac(sc: dict, y):
+    """Jacobian of the classical model's right-hand side at state y ([ny][ny])."""
+    pb, keep = problem(sc)
+    y = _f64(y)
+    J = np.zeros((len(y), len(y)))
+    rc = lib().orc_rhs_jac(C.byref(pb), y.ctypes.data, J.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_rhs_jac failed: {rc}")
+    return J
 
 
 def initial_state(sc: dict):

@@ -1051,6 +1051,19 @@ int orc_rhs(const orc_problem *pb, const double *y, const double *w, double *dy)
     return rc;
 }
 
+/* Jacobian d rhs / d y ([ny][ny], row = equation) of the classical model at
+ * one state, for tests of the model itself (the trapezoid's Newton matrix is
+ * built from it). */
+int orc_rhs_jac(const orc_problem *pb, const double *y, double *J)
+{
+    model_t m;
+    int rc = setup_model(pb, &m);
+    if (rc == ORC_OK && m.fd) rc = ORC_EINVAL;
+    if (rc == ORC_OK) rhs_jac(&m, y, J);
+    free_model(&m);
+    return rc;
+}
+
 /* The operating point (initial state, [ny]) and, for the flux-decay model,
  * the exciter references Vref [n] (may be NULL). */
 int orc_initial_state(const orc_problem *pb, double *y0, double *vref)
