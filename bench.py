@@ -46,6 +46,117 @@ def integrator_flops_per_traj_step(n: int, P: int) -> float:
     return 4 * stage + 13 * (2 * n + P)
 
 
+def integrator_flops_survey(n: int) -> float:
+    """The integrator's flops per trajectory-step as the scope table counts
+    them: 32 n^2 for the complex network product of four RK4 stages plus about
+    60 per machine, with the 4 n sin/cos pairs counted separately (n = 10:
+    3800 flops + 40 sin/cos pairs).  The headline roofline fraction uses this
+    count with the sin/cos pairs at zero cost."""
+    return 32.0 * n * n + 60.0 * n
+
+
+SINCOS_FLOPS = 20.0  # one sin/cos pair as a flop count (two short polynomials)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def per_output(gpu_mean, gpu_var, gpu_traj, o_mean, o_var, o_traj):
+    """Per output variable: trajectory error relative to max |oracle| of the
+    variable (or to its excursion where it starts far from zero), mean error
+    relative to max(|mean|, std), variance error relative to max |var|."""
+    import numpy as np
+    out = {}
+    if gpu_traj is not None:
+        V = o_traj.shape[-1]
+        num = np.abs(gpu_traj - o_traj).reshape(-1, V).max(axis=0)
+        den = np.abs(o_traj).reshape(-1, V).max(axis=0)
+        out["traj_rel_per_output"] = (num / np.where(den == 0, 1, den)).tolist()
+        exc = np.abs(o_traj - o_traj[:, :1, :]).reshape(-1, V).max(axis=0)
+        out["traj_rel_to_excursion_per_output"] = (num / np.maximum(exc, 1e-12)).tolist()
+    if gpu_mean is not None:
+        sm = np.maximum(np.abs(o_mean).max(axis=0), np.sqrt(o_var).max(axis=0))
+        out["mean_rel_per_output"] = (np.abs(gpu_mean - o_mean).max(axis=0)
+                                      / np.where(sm == 0, 1, sm)).tolist()
+        sv = np.abs(o_var).max(axis=0)
+        out["var_rel_per_output"] = (np.abs(gpu_var - o_var).max(axis=0)
+                                     / np.where(sv == 0, 1, sv)).tolist()
+    for k in list(out):
+        out[k.replace("_per_output", "_max")] = float(max(out[k]))
+    return out
+
+
+def config3_leg(ctx, fmc, workloads, oracle_mod, steps: int):
+    """The mixed-precision workload (the 10-machine system with N = 1e5, LHS
+    seed 3): every form timed over whole passes; error against the FP64 oracle
+    on the subset n = 0, 100, ..., 99900 of the same design (per sample, and the
+    subset's mean and variance from the GPU's trajectories), per output."""
+    import numpy as np
+    import torch
+    sc = workloads.config3()
+    n, P, N = sc["n_gen"], len(sc["dist"]["gen"]), sc["N"]
+    S = fmc.steps(sc)
+    sub = np.arange(0, N, 100)
+    out = {"workload": "10-machine classical swing model, seeded 39-bus synthetic network, "
+                       "3 OU disturbances, K=100 (300 x 1e5 LHS design, seed 3), N=1e5, "
+                       "T=20 s, dt=5 ms (4000 RK4 steps)",
+           "trajectory_steps": N * S, "error_subset": "n = 0, 100, ..., 99900 (1000 samples)"}
+    ref = None
+    if oracle_mod is not None:
+        t0 = time.perf_counter()
+        ref = oracle_mod.run(sc, sel=sub, want_traj=True)
+        t_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": len(sub) * S / t_cpu, "unit": "trajectory-steps/s",
+            "cores": oracle_mod.num_threads(), "kind": "oracle",
+            "sample": f"the 1000-sample subset ({S} steps each) in {t_cpu:.1f} s; "
+                      f"full N=1e5 extrapolated linearly: {t_cpu * N / len(sub):.0f} s"}
+        say(f"config3: oracle subset {t_cpu:.1f} s")
+    for form in ("bf16x3", "f32", "f64"):
+        vid = ctx.autotune(sc, precision=form)
+        r = ctx.run(sc, precision=form, variant=vid)
+        outs = dict(mean=r["mean"], var=r["var"])
+        torch.cuda.synchronize()
+        t_int = 0.0
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = ctx.run(sc, precision=form, variant=vid, outputs=outs)
+            t_int += r["report"]["t_integrate_s"]
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        t_int /= steps
+        rep = r["report"]
+        fs = integrator_flops_survey(n)
+        peak = PEAK_FP64_VECTOR if form == "f64" else PEAK_FP32_VECTOR
+        ent = {"value": N * S / sec, "unit": "trajectory-steps/s", "ms_per_pass": sec * 1e3,
+               "integrator_ms": t_int * 1e3, "gemm_ms": rep["t_gemm_s"] * 1e3,
+               "variant": rep["variant_id"], "time_chunk": rep["time_chunk"],
+               "integrator_tflops": fs * N * S / t_int / 1e12,
+               "integrator_frac": fs * N * S / t_int / peak,
+               "peak_tflops": peak / 1e12}
+        if ref is not None:
+            rt = ctx.run(sc, precision=form, variant=vid, traj_idx=sub)["traj"].cpu().numpy()
+            m = rt.mean(axis=0)
+            v = ((rt - m) ** 2).sum(axis=0) / (len(sub) - 1)
+            ent["error_vs_oracle_subset"] = per_output(m, v, rt, ref["mean"], ref["var"],
+                                                       ref["traj"])
+            del rt
+        out[form] = ent
+        say(f"config3 {form}: {sec * 1e3:.1f} ms per pass, integrator {t_int * 1e3:.1f} ms, "
+            f"{N * S / sec:.3e} traj-steps/s")
+    if "f64" in out:
+        for form in ("bf16x3", "f32"):
+            out[form]["speedup_vs_f64"] = out[form]["value"] / out["f64"]["value"]
+    return out
+
+
 def fd_flops_per_traj_step(n: int, P: int) -> float:
     """Algorithmic flops of one RK4 step of one flux-decay trajectory: per
     stage the complex network product (8 n^2), about 90 flops per machine
@@ -138,6 +249,145 @@ def batched_leg(ctx, fmc, workloads, oracle_mod, steps: int, with_fp64: bool):
         say(f"plain f64 sequential: {sec * 1e3:.1f} ms")
         out["plain_f64_sequential"] = {"value": ts / sec, "unit": "trajectory-steps/s",
                                        "ms_per_pass": sec * 1e3}
+    return out
+
+
+def _latency_summary(lat, is_large, span, ts, n_req, refused, rate):
+    import numpy as np
+    ent = {"rate_req_per_s": rate, "requests": n_req, "large_requests": int(is_large.sum()),
+           "p50_latency_s": float(np.median(lat)), "p99_latency_s": float(np.quantile(lat, 0.99)),
+           "max_latency_s": float(lat.max()), "makespan_s": span,
+           "completed_req_per_s": n_req / span, "trajectory_steps_per_s": ts / span,
+           "ebusy_retries": refused}
+    if (~is_large).any():
+        ent["small_p50_latency_s"] = float(np.median(lat[~is_large]))
+        ent["small_p99_latency_s"] = float(np.quantile(lat[~is_large], 0.99))
+    if is_large.any():
+        ent["large_p50_latency_s"] = float(np.median(lat[is_large]))
+        ent["large_p99_latency_s"] = float(np.quantile(lat[is_large], 0.99))
+    return ent
+
+
+def _poisson_stream(ctx, fmc, reqs, arrive, precision="bf16x3"):
+    """Open-loop client: submit each request at its arrival time (retrying
+    every millisecond while the server answers EBUSY), poll for completion.
+    Returns completion times relative to the start and the EBUSY count."""
+    import numpy as np
+    import torch
+    n_req = len(reqs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pending = {}
+    done_at = np.zeros(n_req)
+    wait_q = list(range(n_req))
+    refused = 0
+    while wait_q or pending:
+        now = time.perf_counter() - t0
+        while wait_q and arrive[wait_q[0]] <= now:
+            i = wait_q[0]
+            try:
+                pending[i] = ctx.submit(reqs[i], precision=precision)
+                wait_q.pop(0)
+            except fmc.FmcError as e:
+                if e.code != fmc.EBUSY:
+                    raise
+                refused += 1
+                break
+        for i in list(pending):
+            if pending[i].poll() is not None:
+                done_at[i] = time.perf_counter() - t0
+                del pending[i]
+        time.sleep(0.001)
+    return done_at, refused
+
+
+def serve_sweep(fmc, workloads, oracle_mod, rates, n_max: int, seconds: float, seed: int = 11,
+                small_arena_mb: int = 1024):
+    """The served form over Poisson rates: per rate min(n_max, seconds * rate)
+    requests (nine in ten drawn from the 64 uneven classical scenarios, every
+    tenth a large flux-decay request of 200 machines, T = 30 s, N = 5e4), in a
+    context of its own; p50/p99 latency of small and large requests apart,
+    completed requests and trajectory-steps per second.  Then one stream at
+    the middle rate through a small serving arena (FMC_SERVE_ARENA_BYTES), in
+    which admission by footprint refuses requests (EBUSY) and the client
+    retries; and one request of the large shape on a short horizon (N = 40)
+    against the oracle."""
+    import numpy as np
+    scs = workloads.uneven_batch()
+    large = workloads.fluxdecay()
+    out = {"workload": "Poisson requests: 90% drawn uniformly from the 64 uneven classical "
+                       "scenarios, 10% large flux-decay + IEEE type-1 requests (n=200, P=10, "
+                       "T=30 s, N=5e4, K=100)",
+           "precision": "bf16x3", "requests_per_rate": f"min({n_max}, {seconds:g} s x rate)",
+           "rates": []}
+    rng = np.random.default_rng(seed)
+
+    def stream(rate):
+        n_req = int(max(10, min(n_max, round(seconds * rate))))
+        gaps = rng.exponential(1.0 / rate, size=n_req)
+        arrive = np.cumsum(gaps) - gaps[0]
+        pick = rng.integers(0, len(scs), size=n_req)
+        is_large = np.array([i % 10 == 5 for i in range(n_req)])
+        return [large if is_large[i] else scs[pick[i]] for i in range(n_req)], arrive, is_large
+
+    def warm(ctx):
+        for i in (0, 17, 40):
+            ctx.submit(scs[i], precision="bf16x3").wait(timeout=300)
+        ctx.submit(workloads.fluxdecay(T=0.25), precision="bf16x3").wait(timeout=300)
+
+    ctx = fmc.Context(0)
+    warm(ctx)
+    say("serve sweep: warm")
+    for rate in rates:
+        reqs, arrive, is_large = stream(rate)
+        done_at, refused = _poisson_stream(ctx, fmc, reqs, arrive)
+        lat = done_at - arrive
+        ts = float(sum(r["N"] * fmc.steps(r) for r in reqs))
+        ent = _latency_summary(lat, is_large, float(done_at.max()), ts, len(reqs), refused, rate)
+        out["rates"].append(ent)
+        say(f"serve sweep rate {rate}/s: {len(reqs)} requests, p50 {ent['p50_latency_s']:.3f} s, "
+            f"p99 {ent['p99_latency_s']:.3f} s, {ent['completed_req_per_s']:.2f} req/s done")
+    ctx.close()
+    # knee: the highest rate whose completed rate keeps up with the offered rate
+    keep = [e for e in out["rates"] if e["completed_req_per_s"] >= 0.9 * e["rate_req_per_s"]]
+    out["knee_req_per_s"] = max((e["rate_req_per_s"] for e in keep), default=None)
+    out["saturation_req_per_s"] = max(e["completed_req_per_s"] for e in out["rates"])
+    out["saturation_trajectory_steps_per_s"] = max(e["trajectory_steps_per_s"] for e in out["rates"])
+    # a small arena: admission by footprint must refuse and the client retry
+    os.environ["FMC_SERVE_ARENA_BYTES"] = str(small_arena_mb << 20)
+    ctx = fmc.Context(0)
+    try:
+        rate = rates[len(rates) // 2]
+        reqs, arrive, is_large = stream(rate)
+        keep_small = ~is_large  # the large request needs more than the small arena
+        reqs = [r for r, k in zip(reqs, keep_small) if k]
+        arrive = arrive[keep_small]
+        done_at, refused = _poisson_stream(ctx, fmc, reqs, arrive)
+        lat = done_at - arrive
+        ts = float(sum(r["N"] * fmc.steps(r) for r in reqs))
+        ent = _latency_summary(lat, np.zeros(len(reqs), dtype=bool), float(done_at.max()), ts,
+                               len(reqs), refused, rate)
+        ent["arena_bytes"] = small_arena_mb << 20
+        out["small_arena"] = ent
+        say(f"small arena ({small_arena_mb} MB) at {rate}/s: {refused} EBUSY retries, "
+            f"p99 {ent['p99_latency_s']:.3f} s")
+    finally:
+        del os.environ["FMC_SERVE_ARENA_BYTES"]
+        ctx.close()
+    if oracle_mod is not None:
+        ctx = fmc.Context(0)
+        sc = workloads.fluxdecay(N=40, K=20, T=0.25)
+        r = ctx.submit(sc, precision="bf16x3").wait(timeout=300)
+        o = oracle_mod.run(sc)
+        m, v = r["mean"].cpu().numpy(), r["var"].cpu().numpy()
+        sm = np.maximum(np.abs(o["mean"]).max(axis=0), np.sqrt(o["var"]).max(axis=0))
+        out["large_shape_vs_oracle"] = {
+            "workload": "200 flux-decay machines, P=10, K=20, N=40, T=0.25 s (served)",
+            "mean_rel": float((np.abs(m - o["mean"]).max(axis=0) / np.where(sm == 0, 1, sm)).max()),
+            "var_rel": float((np.abs(v - o["var"]).max(axis=0)
+                              / np.where(np.abs(o["var"]).max(axis=0) == 0, 1,
+                                         np.abs(o["var"]).max(axis=0))).max())}
+        ctx.close()
     return out
 
 
@@ -503,6 +753,15 @@ def main():
                     help="run the sample-count convergence comparison up to this N (0: skip)")
     ap.add_argument("--convergence-out", default="",
                     help="write the convergence estimates to this .npz file")
+    ap.add_argument("--serve-sweep", default="",
+                    help="served form only: comma-separated Poisson rates, each run in its own "
+                         "context (see serve_sweep); prints the sweep as one JSON line")
+    ap.add_argument("--sweep-max", type=int, default=100,
+                    help="requests per rate of the serve sweep (at most)")
+    ap.add_argument("--sweep-seconds", type=float, default=60.0,
+                    help="arrival window per rate of the serve sweep")
+    ap.add_argument("--c3-steps", type=int, default=2,
+                    help="timed passes of the N=1e5 mixed-precision workload (0: skip)")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -516,6 +775,13 @@ def main():
 
     import paper_2007_03847_amd as fmc
     import workloads
+
+    if args.serve_sweep:
+        rates = [float(x) for x in args.serve_sweep.split(",") if x.strip()]
+        res = serve_sweep(fmc, workloads, None if args.no_cpu else oracle_mod(), rates,
+                          args.sweep_max, args.sweep_seconds)
+        print(json.dumps({"metric": "served p50/p99 latency and throughput", "serve_sweep": res}))
+        return
 
     dev = torch.device("cuda", 0)
     ctx = fmc.Context(0)
@@ -587,23 +853,31 @@ def main():
             o = oracle.run(sc, sel=cpu_sel)
             t_cpu = time.perf_counter() - t0
         say(f"cpu oracle: {n_cpu} samples in {t_cpu:.1f} s")
+        threads = oracle.num_threads()
+        # the same oracle on one thread, over a bounded sample
+        oracle.set_num_threads(1)
+        one_sel = np.linspace(0, N - 1, 32).round().astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.run(sc, sel=one_sel)
+        t_one = time.perf_counter() - t0
+        oracle.set_num_threads(threads)
         cpu = {"value": n_cpu * S / t_cpu, "unit": "trajectory-steps/s",
-               "cores": oracle.num_threads(), "kind": "oracle",
+               "cores": threads, "kind": "oracle",
                "sample": f"{n_cpu} of {N} samples of the same workload ({S} steps each), "
-                         f"FP64 C oracle with OpenMP over samples, {t_cpu:.1f} s"}
+                         f"FP64 C oracle with OpenMP over samples, {t_cpu:.1f} s",
+               "single_thread_value": len(one_sel) * S / t_one,
+               "single_thread_sample": f"{len(one_sel)} samples on 1 thread, {t_one:.2f} s",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count()}
         ot = oracle.run(sc, sel=sel, want_traj=True)["traj"]
         for form, res in results.items():
-            tr = res["traj"]
-            num = np.abs(tr - ot).reshape(-1, tr.shape[-1]).max(axis=0)
-            den = np.abs(ot).reshape(-1, tr.shape[-1]).max(axis=0)
-            e = {"traj_rel": float((num / np.where(den == 0, 1, den)).max())}
-            if n_cpu == N:
-                dm = np.abs(res["mean"] - o["mean"]).max(axis=0)
-                sm = np.maximum(np.abs(o["mean"]).max(axis=0), np.sqrt(o["var"]).max(axis=0))
-                dv = np.abs(res["var"] - o["var"]).max(axis=0) / np.abs(o["var"]).max(axis=0)
-                e["mean_rel"] = float((dm / sm).max())
-                e["var_rel"] = float(dv.max())
-            errs[form] = e
+            full = n_cpu == N
+            errs[form] = per_output(res["mean"] if full else None, res["var"] if full else None,
+                                    res["traj"], o["mean"] if full else None,
+                                    o["var"] if full else None, ot)
+
+    c3 = None
+    if args.c3_steps > 0:
+        c3 = config3_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), args.c3_steps)
 
     batched = None
     if args.batch_steps > 0:
@@ -634,9 +908,14 @@ def main():
     res = results[head]
     value = N * S / (res["ms"] * 1e-3)
     flops_step = integrator_flops_per_traj_step(n, P)
-    # dominant kernel: the integrator; algorithmic flops per launch / mean launch time
-    flops_launch = flops_step * N * res["rep"]["time_chunk"]
-    achieved = flops_step * N * S / res["t_int"] if res["t_int"] > 0 else 0.0
+    fs = integrator_flops_survey(n)
+    # dominant kernel: the integrator.  achieved = algorithmic flops per launch
+    # (all launches of a pass, averaged) / mean launch time, both from the same
+    # pass totals, so that flops_per_launch / mean_launch_ms == achieved
+    chunks = res["chunks"]
+    flops_launch = fs * N * S / chunks
+    mean_launch_s = res["t_int"] / chunks
+    achieved = flops_launch / mean_launch_s if mean_launch_s > 0 else 0.0
     peak = PEAK_FP64_VECTOR if head == "f64" else PEAK_FP32_VECTOR
     traffic, traffic_steps = measured_traffic(res["rep"]["variant_id"], head)
     if traffic is not None and traffic_steps != res["rep"]["time_chunk"]:
@@ -644,13 +923,16 @@ def main():
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
             "frac": achieved / peak, "traffic": traffic,
             "kernel": "k_rk4_group" if res["rep"]["lanes_per_traj"] > 1 else "k_rk4_lane",
-            "flops_per_launch": flops_launch,
-            "mean_launch_ms": res["t_int"] / res["chunks"] * 1e3}
+            "flops_per_traj_step": fs, "flops_per_launch": flops_launch,
+            "mean_launch_ms": mean_launch_s * 1e3, "launches_per_pass": chunks,
+            "frac_sincos_as_20_flops": (fs + 4 * n * SINCOS_FLOPS) * N * S / res["t_int"] / peak,
+            "frac_itemised_count": flops_step * N * S / res["t_int"] / peak,
+            "itemised_flops_per_traj_step": flops_step}
     forms_out = {}
     for form, r in results.items():
         forms_out[form] = {"value": N * S / (r["ms"] * 1e-3), "ms_per_step": r["ms"],
                            "integrator_ms": r["t_int"] * 1e3,
-                           "integrator_tflops": flops_step * N * S / r["t_int"] / 1e12,
+                           "integrator_tflops": fs * N * S / r["t_int"] / 1e12,
                            "gemm_ms": r["rep"]["t_gemm_s"] * 1e3,
                            "lhs_ms": r["rep"]["t_lhs_s"] * 1e3,
                            "stats_ms": r["rep"]["t_stats_s"] * 1e3,
@@ -672,6 +954,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": forms_out,
+        "mixed_precision_N1e5": c3,
         "batched": batched,
         "served": served,
         "flux_decay": fdl,

@@ -86,9 +86,9 @@ extern "C" {
  * fmc_lhs_decorrelate over all N samples: the same values in every row,
  * reassigned to samples so that the rows are close to uncorrelated (LHS
  * Step 2 of Sec. IV-B, with Cholesky-based correlation control).  Needs
- * M = n_proc*K <= 1024 and M < N < 2^31 (FMC_EINVAL otherwise); costs
- * O(N^2 M) comparisons for the ranks.  fmc_run only: the batched and served
- * forms reject it. */
+ * M = n_proc*K <= 1024 and M < N < 2^31 (FMC_EINVAL otherwise); the ranks
+ * are found by bucketing, O(N) expected work per row.  fmc_run only: the
+ * batched and served forms reject it. */
 #define FMC_LHS_DECOR 2
 
 /* Time integrator. */

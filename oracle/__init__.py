@@ -83,6 +83,7 @@ def lib():
         L.orc_initial_state.argtypes = [C.POINTER(_Problem), P, P]
         L.orc_rhs_jac.argtypes = [C.POINTER(_Problem), P, P]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -101,6 +102,11 @@ def _i32(a):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops over samples."""
+    lib().orc_set_num_threads(int(n))
 
 
 def philox(ctr, key):

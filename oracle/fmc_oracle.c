@@ -1078,6 +1078,16 @@ int orc_initial_state(const orc_problem *pb, double *y0, double *vref)
     return rc;
 }
 
+/* Threads of the OpenMP loops over samples (for the single-thread baseline). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

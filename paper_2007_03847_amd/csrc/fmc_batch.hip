@@ -192,6 +192,9 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     if (p.par->sampler == FMC_LHS_DECOR)
       return fail(FMC_EINVAL, "scenario " + std::to_string(i) +
                                   ": FMC_LHS_DECOR runs through fmc_run only");
+    if (p.par->integrator != FMC_RK4)
+      return fail(FMC_EINVAL, "scenario " + std::to_string(i) +
+                                  ": the implicit trapezoid runs through fmc_run only");
     if (p.dist->sigma_mat)
       return fail(FMC_EINVAL, "scenario " + std::to_string(i) +
                                   ": a diffusion matrix runs through fmc_run only");
@@ -432,6 +435,7 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
       a.lanes = p.lanes;
       a.dt = (float)p.par->dt;
       a.wb = (float)(2.0 * M_PI * (s->f0_hz > 0.0 ? s->f0_hz : 60.0));
+      a.recenter = s->infinite_bus ? 0 : 1;
     }
   }
   const IntegArgs<float>* args_d = nullptr;

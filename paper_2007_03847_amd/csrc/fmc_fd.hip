@@ -122,7 +122,7 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
   // state: [tiles][waves][6 states x 8 machines][64 lanes], waves = ceil(NB/2)
   const int NW = (NB + 1) / 2;
   if ((rc = c->ensure("fd_state", (size_t)pl.tiles * NW * 48 * 64 * 4, &state))) return rc;
-  if ((rc = c->ensure("fd_xstate", (size_t)pl.tiles * kFdMaxProc * 16 * 4, &xstate))) return rc;
+  if ((rc = c->ensure("fd_xstate", (size_t)pl.tiles * (kFdMaxProc + kFdOffsetRows) * 16 * 4, &xstate))) return rc;
   if ((rc = c->ensure("fd_rows", (size_t)pl.tiles * (Sc + 1) * V * 16, &rows))) return rc;
   if ((rc = c->ensure("counters", 64, &cnt))) return rc;
   HIPCHK(launch_fill_i64((int64_t*)cnt, 0, 1, c->stream));
@@ -185,6 +185,7 @@ int run_fd(Context* c, const fmc_system* sys, const fmc_disturbance* dist, const
   a.tiles_per_item = pl.tiles_per_item;
   a.dt = (float)par->dt;
   a.wb = (float)(2.0 * M_PI * f0);
+  a.recenter = sys->infinite_bus ? 0 : 1;
   double t_gemm = 0.0, t_int = 0.0;
   for (int64_t s0 = 0; s0 < S; s0 += Sc) {
     const int64_t s1 = std::min<int64_t>(S, s0 + Sc);

@@ -68,13 +68,29 @@ struct IntegArgs {
   double* traj;             // [n_traj][S+1][V]
   unsigned long long* nonfinite;
   long long* first_bad;
+  unsigned long long* notconv;  // implicit trapezoid: trajectories whose Newton solve failed
   int n, P, V;
   int64_t N, S;
   int64_t s_begin, s_end;   // steps [s_begin, s_end) of this chunk
   int64_t c_base;           // global stage column of w's first column
   int64_t lanes;            // state row stride
   R dt, wb;
+  // Nonzero for systems without an infinite bus, whose electrical powers
+  // depend on rotor-angle differences only: after every step the mean angle
+  // deviation of the machines is moved out of every machine's angle state
+  // into a per-trajectory FP64 offset, so the reduced-precision state holds
+  // the small angles relative to the mean rather than the common angle (a
+  // neutral mode that drifts by radians over long horizons, whose rounding
+  // would otherwise land on the relative angles that drive the powers).  The
+  // offset is kept in two state rows after the variant's own rows (the bits
+  // of the double).
+  int recenter;
 };
+// State rows of the per-trajectory common-angle offset: the two 32-bit
+// halves of the FP64 offset and, in the flux-decay state, the mean angle
+// left by the last step (taken out at the next step).
+constexpr int kOffsetRows = 2;
+constexpr int kFdOffsetRows = 3;
 
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_rrf_rms(const double* traj, int64_t n, int64_t S, int32_t V, const double* w,
@@ -94,6 +110,15 @@ hipError_t launch_kle_f64_to_f32(const double* zeta, const double* phi, int64_t 
 hipError_t launch_kle_bf16x3(const double* zeta, const double* phi, int64_t phi_ld, int P, int K,
                              int64_t N, int64_t C, int64_t c0, float* w, hipStream_t st,
                              int max_blocks = 0);
+// The BF16 x3 contraction on operands split once (hi and lo BF16 planes,
+// k-fastest, Kp = K rounded up to 32): launch_split_bf16 writes them from
+// FP64 rows X[k][ld] (P blocks of stride xs into blocks of stride ys).
+inline int kle_kp(int K) { return 32 * ((K + 31) / 32); }
+hipError_t launch_split_bf16(const double* X, int64_t ld, int K, int64_t items, int Kp, int P,
+                             int64_t xs, int64_t ys, void* yh, void* yl, hipStream_t st);
+hipError_t launch_kle_bf16x3_split(const void* ph, const void* pl, int Kp, const void* zh,
+                                   const void* zl, int P, int64_t N, int64_t C, int64_t c0,
+                                   float* w, hipStream_t st);
 
 // Network reduction: device network arrays -> Y_red as (re, im) pairs [n_gen^2].
 struct NetDev {
@@ -148,6 +173,11 @@ hipError_t launch_integrate_f64(int variant_id, const IntegArgs<double>& a, int6
                                 hipStream_t st);
 hipError_t launch_integrate_f32(int variant_id, const IntegArgs<float>& a, int64_t n_groups,
                                 hipStream_t st);
+// Implicit trapezoid (FP64, classical machines) on the shape of a
+// one-trajectory-per-lane variant with at most kTrapMaxGen machines.
+constexpr int kTrapMaxGen = 16;
+hipError_t launch_trap_f64(int variant_id, const IntegArgs<double>& a, int64_t n_groups,
+                           hipStream_t st);
 
 // Persistent batched integrator (FP32).
 struct BatchItem {
@@ -212,7 +242,7 @@ hipError_t launch_persistent_mc(int nb, const BatchArgs& b, int grid, hipStream_
 // the lane classes address it [row][lanes], classes 3-6 [tile][wave][row][64].
 inline size_t batch_state_floats(const BatchVariantInfo& b, int64_t tiles) {
   const int G = (b.NG + b.L - 1) / b.L, PQ = (b.PM + b.L - 1) / b.L;
-  return (size_t)(2 * G + PQ) * (size_t)tiles * 64 * 4;
+  return (size_t)(2 * G + PQ + kOffsetRows) * (size_t)tiles * 64 * 4;
 }
 // Coefficient block size (floats) and packing of a batched variant.
 inline size_t batch_coef_floats(const BatchVariantInfo& b) {
@@ -274,7 +304,9 @@ struct FdArgs {
   int n_padk;                 // n rounded up to 32 (K dimension of the BF16 product)
   const float* w;             // [cols][P][N] KLE paths of this chunk
   float* state;               // [tiles][ceil(NB/2)][48][64] deviations between chunks
-  float* xstate;              // [tiles][kFdMaxProc][16]
+  float* xstate;              // [tiles][kFdMaxProc + kFdOffsetRows][16]: processes, then the
+                              // common-angle offset (two 32-bit halves) and the pending
+                              // mean angle of each trajectory
   const double* off;          // [6n] FP64 output offsets
   const int32_t* traj_slot;   // [N] or null
   double* traj;               // [n_traj][S+1][V]
@@ -287,6 +319,7 @@ struct FdArgs {
   int64_t N, S, s_begin, s_end, c_base;
   int64_t tiles, tiles_per_item;
   float dt, wb;
+  int recenter;               // as IntegArgs::recenter
 };
 hipError_t launch_setup_fd(const double* canon, int n, int P, const double* E, const double* prm,
                            double* fd, hipStream_t st);

@@ -53,7 +53,8 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
                double wb, const double* zeta, const double* phi, const R* coef,
                const double* delta0, double* partial, const int32_t* slot_d, double* traj_d,
                unsigned long long* cnt_d, int64_t Sc, double* mean_d, double* var_d,
-               EventPool& evp, ChunkTimes& ct) {
+               int recenter, bool trap, const void* const* s16, EventPool& evp,
+               ChunkTimes& ct) {
   const VariantInfo& vi = variant(vid);
   const int V = 2 * n + P;
   const int64_t C = 2 * S + 1;
@@ -71,7 +72,7 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
   int rc;
   if ((rc = c->ensure("w", (size_t)(2 * Sc + 1) * P * N * bw, &w[0]))) return rc;
   if ((rc = c->ensure("w1", (size_t)(2 * Sc + 1) * P * N * bw, &w[1]))) return rc;
-  if ((rc = c->ensure("state", (size_t)(2 * vi.NG + vi.PM) * lanes * bw, &state))) return rc;
+  if ((rc = c->ensure("state", (size_t)(2 * vi.NG + vi.PM + kOffsetRows) * lanes * bw, &state))) return rc;
   if ((rc = ensure_gstream(c))) return rc;
   hipStream_t ks = c->gstream;
   // merge of the rows completed by chunk [s0, s1] (row 0 with the first)
@@ -92,6 +93,7 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
   a.traj = traj_d;
   a.nonfinite = cnt_d;
   a.first_bad = (long long*)(cnt_d + 1);
+  a.notconv = cnt_d + 2;
   a.n = n;
   a.P = P;
   a.V = V;
@@ -100,6 +102,7 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
   a.lanes = lanes;
   a.dt = (R)par->dt;
   a.wb = (R)wb;
+  a.recenter = recenter;
   int64_t k = 0;
   for (int64_t s0 = 0; s0 < S; s0 += Sc, ++k) {
     const int64_t s1 = std::min<int64_t>(S, s0 + Sc);
@@ -113,8 +116,9 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
       e = launch_kle_f64(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (double*)w[b], ks);
     else if (par->precision == FMC_F32)
       e = launch_kle_f64_to_f32(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w[b], ks);
-    else
-      e = launch_kle_bf16x3(zeta, phi, C, P, par->K, N, Cc, 2 * s0, (float*)w[b], ks);
+    else  // BF16 x3 on the operands split once before the first chunk
+      e = launch_kle_bf16x3_split(s16[0], s16[1], kle_kp(par->K), s16[2], s16[3], P, N, Cc,
+                                  2 * s0, (float*)w[b], ks);
     if (e != hipSuccess) return fail(FMC_EDEVICE, std::string("KLE launch: ") + hipGetErrorString(e));
     ct.gemm1.push_back(evp.record(ks));
     if (hipEventRecord(c->gev[b], ks) != hipSuccess || hipStreamWaitEvent(c->stream, c->gev[b], 0) != hipSuccess)
@@ -130,7 +134,8 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
     a.c_base = 2 * s0;
     ct.int0.push_back(evp.record());
     if constexpr (sizeof(R) == 8)
-      e = launch_integrate_f64(vid, a, n_groups, c->stream);
+      e = trap ? launch_trap_f64(vid, a, n_groups, c->stream)
+               : launch_integrate_f64(vid, a, n_groups, c->stream);
     else
       e = launch_integrate_f32(vid, a, n_groups, c->stream);
     if (e != hipSuccess)
@@ -192,11 +197,24 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   const bool dev_out = out->mem_kind == FMC_MEM_DEVICE;
   const bool f64 = par->precision == FMC_F64;
   const int bw = f64 ? 8 : 4;
-  const int vid = par->variant >= 0 ? par->variant : pick_variant(c, n, P, N, par->precision);
+  // the implicit trapezoid runs on the shapes of the one-trajectory-per-lane
+  // variants (the smallest that fits, or the one asked for)
+  const bool trap = par->integrator == FMC_TRAP;
+  int vid = par->variant >= 0 ? par->variant : (trap ? -1 : pick_variant(c, n, P, N, par->precision));
+  if (trap && vid < 0) {
+    for (int i = 0; i < n_variants(); ++i) {
+      const VariantInfo& v = variant(i);
+      if (v.L != 1 || v.NG < n || v.PM < P || v.NG > kTrapMaxGen) continue;
+      if (vid < 0 || v.NG * v.NG + v.PM < variant(vid).NG * variant(vid).NG + variant(vid).PM) vid = i;
+    }
+  }
   if (vid < 0 || vid >= n_variants())
     return fail(FMC_EINVAL, "no integrator variant for n=" + std::to_string(n) + ", P=" + std::to_string(P));
   const VariantInfo& vi = variant(vid);
   if (vi.NG < n || vi.PM < P) return fail(FMC_EINVAL, "variant too small for the system");
+  if (trap && (vi.L != 1 || vi.NG > kTrapMaxGen))
+    return fail(FMC_EINVAL, "the implicit trapezoid runs on one-trajectory-per-lane variants of at "
+                            "most 16 machines");
   const double f0 = sys->f0_hz > 0.0 ? sys->f0_hz : 60.0;
   const double wb = 2.0 * M_PI * f0;
 
@@ -266,6 +284,22 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     zeta = zeta_dev;
   }
   if (dist->sigma_mat && (rc = mix_design(c, dist, K, N, &zeta, c->gstream))) return rc;
+  // BF16 x3: the basis and the design split into BF16 hi/lo planes once
+  const void* s16[4] = {nullptr, nullptr, nullptr, nullptr};
+  if (par->precision == FMC_BF16X3) {
+    const int Kp = kle_kp(K);
+    void *pp = nullptr, *zz = nullptr;
+    if ((rc = c->ensure("phi16", (size_t)2 * C * Kp * 2, &pp))) return rc;
+    if ((rc = c->ensure("zeta16", (size_t)2 * P * N * Kp * 2, &zz))) return rc;
+    s16[0] = pp;
+    s16[1] = (const char*)pp + (size_t)C * Kp * 2;
+    s16[2] = zz;
+    s16[3] = (const char*)zz + (size_t)P * N * Kp * 2;
+    HIPCHK(launch_split_bf16((const double*)phi, C, K, C, Kp, 1, 0, 0, pp, (void*)s16[1],
+                             c->gstream));
+    HIPCHK(launch_split_bf16(zeta, N, K, N, Kp, P, (int64_t)K * N, N * Kp, zz, (void*)s16[3],
+                             c->gstream));
+  }
   const int ev_lhs1 = evp.record(c->gstream);
 
   // per-workgroup statistics partials, trajectory slots, counters
@@ -281,7 +315,8 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     unsigned long long* init = (unsigned long long*)h;
     init[0] = 0ULL;
     init[1] = (unsigned long long)LLONG_MAX;
-    HIPCHK(hipMemcpyAsync(cnt, init, 2 * sizeof(unsigned long long), hipMemcpyHostToDevice, c->stream));
+    init[2] = 0ULL;
+    HIPCHK(hipMemcpyAsync(cnt, init, 3 * sizeof(unsigned long long), hipMemcpyHostToDevice, c->stream));
   }
   int32_t* slot_d = nullptr;
   double* traj_d = nullptr;
@@ -321,11 +356,11 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   if (f64)
     rc = run_chunks<double>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
                             (const double*)coef, delta0_d, (double*)partial, slot_d, traj_d,
-                            (unsigned long long*)cnt, Sc, mean_d, var_d, evp, ct);
+                            (unsigned long long*)cnt, Sc, mean_d, var_d, sys->infinite_bus ? 0 : 1, trap, s16, evp, ct);
   else
     rc = run_chunks<float>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
                            (const float*)coef, delta0_d, (double*)partial, slot_d, traj_d,
-                           (unsigned long long*)cnt, Sc, mean_d, var_d, evp, ct);
+                           (unsigned long long*)cnt, Sc, mean_d, var_d, sys->infinite_bus ? 0 : 1, trap, s16, evp, ct);
   if (rc) return rc;
   // statistics: merged per chunk on the second stream, joined into c->stream
   const int ev_end = evp.record();
@@ -346,7 +381,7 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   int* status = (int*)hb;
   unsigned long long* cn = (unsigned long long*)((char*)hb + 16);
   HIPCHK(hipMemcpyAsync(status, status_d, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(cn, cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(cn, cnt, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
   status[2] = 0;
   if (dc_status)
     HIPCHK(hipMemcpyAsync(status + 2, dc_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -374,6 +409,9 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     r->time_chunk = (int32_t)Sc;
     r->hbm_peak_bytes = (int64_t)std::max(c->held, held0);
   }
+  if (cn[2] != 0)  // outputs are written from the last Newton iterates
+    return fail(FMC_ENOTCONV, std::to_string(cn[2]) + " sample paths had a trapezoid step whose "
+                                                      "Newton iteration did not converge");
   if (cn[0] != 0)
     return fail(FMC_ENONFINITE, std::to_string(cn[0]) + " sample paths became non-finite (first: " +
                                     std::to_string((long long)cn[1]) + ")");

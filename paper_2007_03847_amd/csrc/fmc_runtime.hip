@@ -260,7 +260,14 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
     return fail(FMC_EINVAL, "the EM basis needs K = S (one normal per step and process)");
   if (par->sampler != FMC_LHS && par->sampler != FMC_SRS && par->sampler != FMC_LHS_DECOR)
     return fail(FMC_EINVAL, "unknown sampler");
-  if (par->integrator != FMC_RK4) return fail(FMC_EINVAL, "only the RK4 integrator runs on the GPU");
+  if (par->integrator != FMC_RK4 && par->integrator != FMC_TRAP)
+    return fail(FMC_EINVAL, "unknown integrator");
+  if (par->integrator == FMC_TRAP) {
+    if (par->precision != FMC_F64 || sys->model != FMC_CLASSICAL)
+      return fail(FMC_EINVAL, "the implicit trapezoid runs in FP64 on classical machines");
+    if (sys->n_gen > kTrapMaxGen || dist->n_proc > 8)
+      return fail(FMC_EINVAL, "the implicit trapezoid takes at most 16 machines and 8 processes");
+  }
   if (par->precision < FMC_F64 || par->precision > FMC_BF16X3)
     return fail(FMC_EINVAL, "unknown precision");
   const int n = sys->n_gen;
@@ -604,9 +611,21 @@ int fmc_kle_paths(fmc_context* ctx, int32_t precision, int32_t P, int32_t K, int
     e = launch_kle_f64(zeta, phi, phi_ld, P, K, N, C, c0, (double*)w, c->stream);
   else if (precision == FMC_F32)
     e = launch_kle_f64_to_f32(zeta, phi, phi_ld, P, K, N, C, c0, (float*)w, c->stream);
-  else if (precision == FMC_BF16X3)
-    e = launch_kle_bf16x3(zeta, phi, phi_ld, P, K, N, C, c0, (float*)w, c->stream);
-  else
+  else if (precision == FMC_BF16X3) {
+    // split the operands once (the columns c0..c0+C-1 of phi only), then contract
+    const int Kp = kle_kp(K);
+    void *pp = nullptr, *zz = nullptr;
+    int rc;
+    if ((rc = c->ensure("kp_phi16", (size_t)2 * C * Kp * 2, &pp))) return rc;
+    if ((rc = c->ensure("kp_zeta16", (size_t)2 * P * N * Kp * 2, &zz))) return rc;
+    void* pl = (char*)pp + (size_t)C * Kp * 2;
+    void* zl = (char*)zz + (size_t)P * N * Kp * 2;
+    e = launch_split_bf16(phi + c0, phi_ld, K, C, Kp, 1, 0, 0, pp, pl, c->stream);
+    if (e == hipSuccess)
+      e = launch_split_bf16(zeta, N, K, N, Kp, P, (int64_t)K * N, N * Kp, zz, zl, c->stream);
+    if (e == hipSuccess)
+      e = launch_kle_bf16x3_split(pp, pl, Kp, zz, zl, P, N, C, 0, (float*)w, c->stream);
+  } else
     return fail(FMC_EINVAL, "unknown precision");
   if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
   return FMC_OK;

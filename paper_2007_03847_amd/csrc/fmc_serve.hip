@@ -113,7 +113,7 @@ std::vector<size_t> parts_of(const Request& r) {
                     ? fd_ap16_bytes(r.n_pad, 32 * ((r.n + 31) / 32))
                     : (size_t)(r.n_pad / 16) * (r.n_pad / 4) * 64 * sizeof(float2);
     z[B_STATE] = (size_t)r.tiles * r.NW * 48 * 64 * 4;
-    z[B_XSTATE] = (size_t)r.tiles * kFdMaxProc * 16 * 4;
+    z[B_XSTATE] = (size_t)r.tiles * (kFdMaxProc + kFdOffsetRows) * 16 * 4;
   } else {
     z[B_COEF] = batch_coef_floats(r.bv) * 4;
     z[B_STATE] = batch_state_floats(r.bv, r.tiles) * 4;
@@ -419,6 +419,7 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
       f.tiles_per_item = r.tiles_per_item;
       f.dt = (float)r.par.dt;
       f.wb = (float)(2.0 * M_PI * r.f0);
+      f.recenter = r.inf_bus ? 0 : 1;
       fd_launch.push_back({f, r.n_items});
       r.s_prev = s0;
       r.s_next = s1;
@@ -446,6 +447,7 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
     a.lanes = r.tiles * 64 * 4;
     a.dt = (float)r.par.dt;
     a.wb = (float)(2.0 * M_PI * r.f0);
+    a.recenter = r.inf_bus ? 0 : 1;
     const double frac = (double)(s1 - s0) / (double)r.S;
     for (int64_t k = 0; k < r.n_items; ++k) {
       BatchItem it;

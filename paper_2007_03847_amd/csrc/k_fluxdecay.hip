@@ -262,8 +262,9 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
   const bool two = 2 * wv + 1 < NB;  // wave-uniform: the second block exists
   const FdPack K{n_pad};
   // LDS: constants + process block, the dE' tile, xi stage values (2 buffers
-  // of [P][16]), flags [16], then the RK4 sums of every lane [NW][6 kQ][64]
-  // (kept here rather than in registers)
+  // of [P][16]), flags [16], each wave's sum of the angle deviations of its
+  // machines per trajectory (2 buffers of [NW][16]), then the RK4 sums of
+  // every lane [NW][6 kQ][64] (kept here rather than in registers)
   float* cst = reinterpret_cast<float*>(smem);
   unsigned char* btile = smem + (size_t)K.size() * 4;
   float* bs = reinterpret_cast<float*>(btile);          // FP32 product: [2 n_pad][16]
@@ -271,7 +272,8 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
   __bf16* bl = bh + 16 * BS;                            //               lo plane
   float* xs = reinterpret_cast<float*>(btile + fd_btile_bytes(n_pad, n_padk, BF));
   int* bad_t = reinterpret_cast<int*>(xs + 2 * P * kT);
-  float* accl = reinterpret_cast<float*>(bad_t + kT) + (int64_t)wv * 6 * kQ * 64 + l;
+  float* refb = reinterpret_cast<float*>(bad_t + kT);
+  float* accl = refb + 2 * NW * kT + (int64_t)wv * 6 * kQ * 64 + l;
   for (int q = tid; q < K.size(); q += blockDim.x) cst[q] = a.coef[q];
   // the tile's padding rows (machines n_pad..n_padk) are never written: zero
   for (int q = tid; q < (int)(fd_btile_bytes(n_pad, n_padk, BF) / 4); q += blockDim.x)
@@ -280,6 +282,13 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
 
   auto mach = [&](int q) { return 16 * (2 * wv + (q >> 2)) + 4 * g + (q & 3); };
   const float dt = a.dt, h2 = 0.5f * a.dt, dt6 = a.dt / 6.0f, wb = a.wb;
+  const float inv_n = 1.0f / (float)n;
+  // mean over the waves' published sums of trajectory t (buffer b), in wave order
+  auto mean_angle = [&](int b) {
+    float sum = 0.0f;
+    for (int ww = 0; ww < NW; ++ww) sum += refb[(b * NW + ww) * kT + t];
+    return sum * inv_n;
+  };
   const int item = blockIdx.x;
   const int64_t tile0 = (int64_t)item * a.tiles_per_item;
   const int64_t tile1 = tile0 + a.tiles_per_item < a.tiles ? tile0 + a.tiles_per_item : a.tiles;
@@ -305,8 +314,12 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
     const int slot = (valid && a.traj_slot) ? a.traj_slot[ns] : -1;
     // state: deviations of (delta, dw, E'q, Efd, VR, RF) of my machines; xi
     float y[6][kQ], x = 0.0f;
+    double coff = 0.0;  // common-angle offset of trajectory t (see FdArgs::recenter)
+    float pend = 0.0f;  // the mean angle left by the previous step
     const int64_t sbase = ((tile * NW + wv) * 6 * kQ) * 64 + l;
-    const int64_t xbase = (tile * kFdMaxProc + (proc ? pg : 0)) * kT + t;
+    const int64_t xrow = tile * (kFdMaxProc + kFdOffsetRows);
+    const int64_t xbase = (xrow + (proc ? pg : 0)) * kT + t;
+    const int64_t obase = (xrow + kFdMaxProc) * kT + t;
     if (a.s_begin == 0) {
 #pragma unroll
       for (int c = 0; c < 6; ++c)
@@ -319,6 +332,8 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
 #pragma unroll
         for (int q = 0; q < kQ; ++q) y[c][q] = a.state[sbase + (c * kQ + q) * 64];
       if (proc) x = a.xstate[xbase];
+      coff = load_offset(a.xstate, obase, obase + kT);
+      pend = a.xstate[obase + 2 * kT];
     }
     const int64_t wofs = (int64_t)(proc ? pg : 0) * a.N + ns;
 
@@ -338,8 +353,9 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
         if (m < nl) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) {
-            row_stats((double)y[c][q], valid, inv_cnt, t == 0, row + c * nl + m);
-            if (o) o[c * nl + m] = offl[c * nl + m] + (double)y[c][q];
+            const double yv = c == 0 ? coff + (double)y[0][q] : (double)y[c][q];
+            row_stats(yv, valid, inv_cnt, t == 0, row + c * nl + m);
+            if (o) o[c * nl + m] = offl[c * nl + m] + yv;
           }
         }
       }
@@ -579,18 +595,51 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
           if (q < 4 || two) y[c][q] += dt6 * accl[(c * kQ + q) * 64];
       x += dt6 * ax;
       w0 = w2; w1 = n1; w2 = n2;
+      if (a.recenter) {
+        // The mean angle of trajectory t's machines as the previous step left
+        // it (from the waves' sums published in LDS at the end of that step,
+        // visible after this step's barriers; at the first step of a chunk,
+        // carried in the state; 0 before the first step) is taken out of
+        // every angle.  A common shift leaves the network quantities
+        // unchanged whenever it is taken, as long as all machines of a
+        // trajectory take the same one.  Then this wave publishes its sum of
+        // trajectory t's angles (lanes t, t + 16, t + 32, t + 48, in order).
+        const int rb = (int)(s & 1);
+        const float ref = s == a.s_begin ? pend : mean_angle(rb ^ 1);
+        coff += (double)ref;
+        float part = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          y[0][q] -= ref;
+          if ((q < 4 || two) && mach(q) < n) part += y[0][q];
+        }
+        float wsum = __shfl(part, t, 64);
+        wsum += __shfl(part, t + 16, 64);
+        wsum += __shfl(part, t + 32, 64);
+        wsum += __shfl(part, t + 48, 64);
+        if (g == 0) refb[(rb * NW + wv) * kT + t] = wsum;
+      }
       emit(s + 1);
     }
 
     if (a.state) {
+      float pnext = 0.0f;  // the mean angle the next chunk starts by taking out
+      if (a.recenter) {
+        __syncthreads();  // every wave has published the last step's sums
+        pnext = mean_angle((int)((a.s_end - 1) & 1));
+      }
 #pragma unroll
       for (int c = 0; c < 6; ++c)
 #pragma unroll
         for (int q = 0; q < kQ; ++q) a.state[sbase + (c * kQ + q) * 64] = y[c][q];
       if (proc) a.xstate[xbase] = x;
+      if (wv == 0 && g == 0) {
+        store_offset(a.xstate, obase, obase + kT, coff);
+        a.xstate[obase + 2 * kT] = pnext;
+      }
     }
     if (a.s_end == a.S) {  // uniform over the workgroup
-      bool bad = proc && !isfinite(x);
+      bool bad = (proc && !isfinite(x)) || !isfinite(coff);
 #pragma unroll
       for (int c = 0; c < 6; ++c)
 #pragma unroll
@@ -631,7 +680,7 @@ size_t fd_lds_bytes(int n_pad, int n_padk, bool bf, int P) {
   const FdPack K{n_pad};
   const int nw = (n_pad / 16 + 1) / 2;
   return (size_t)K.size() * 4 + fd_btile_bytes(n_pad, n_padk, bf) + (size_t)2 * P * kT * 4 +
-         kT * 4 + (size_t)nw * 6 * kQ * 64 * 4;
+         kT * 4 + (size_t)2 * nw * kT * 4 + (size_t)nw * 6 * kQ * 64 * 4;
 }
 
 template <bool BF>

@@ -87,6 +87,26 @@ __device__ __forceinline__ void sincos_r(float x, float& s, float& c) {
   c = ((q + 1) & 2) ? -b : b;
 }
 
+// The FP64 common-angle offset in two state slots: the exact bits of the
+// double (two 32-bit halves for an FP32 state array), so that a run split
+// into time chunks gives the same bits as a run in one chunk.
+__device__ __forceinline__ void store_offset(float* st, int64_t i0, int64_t i1, double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  reinterpret_cast<unsigned int*>(st)[i0] = (unsigned int)b;
+  reinterpret_cast<unsigned int*>(st)[i1] = (unsigned int)(b >> 32);
+}
+__device__ __forceinline__ void store_offset(double* st, int64_t i0, int64_t, double v) {
+  st[i0] = v;
+}
+__device__ __forceinline__ double load_offset(const float* st, int64_t i0, int64_t i1) {
+  const unsigned long long lo = reinterpret_cast<const unsigned int*>(st)[i0];
+  const unsigned long long hi = reinterpret_cast<const unsigned int*>(st)[i1];
+  return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+__device__ __forceinline__ double load_offset(const double* st, int64_t i0, int64_t) {
+  return st[i0];
+}
+
 // Right-hand side of the swing equations + OU disturbances in deviation form.
 template <typename R, int NG, int PM>
 __device__ __forceinline__ void swing_rhs(const R* cfg, const R wb, const R (&yd)[NG],
@@ -139,13 +159,14 @@ __device__ __forceinline__ void swing_rhs(const R* cfg, const R wb, const R (&yd
 // lane v of the wave reduces variable v over the wave's valid trajectories.
 template <typename R, int NG, int PM>
 __device__ __forceinline__ void emit_step(const IntegArgs<R>& a, double (*tile)[65], int lane,
-                                          int cnt, int64_t s, int slot, const R (&yd)[NG],
-                                          const R (&yw)[NG], const R (&yx)[PM]) {
+                                          int cnt, int64_t s, int slot, double coff,
+                                          const R (&yd)[NG], const R (&yw)[NG],
+                                          const R (&yx)[PM]) {
   const int n = a.n, P = a.P, V = a.V;
 #pragma unroll
   for (int i = 0; i < NG; ++i) {
     if (i < n) {
-      tile[i][lane] = (double)yd[i];
+      tile[i][lane] = coff + (double)yd[i];
       tile[n + i][lane] = (double)yw[i];
     }
   }
@@ -171,7 +192,7 @@ __device__ __forceinline__ void emit_step(const IntegArgs<R>& a, double (*tile)[
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
       if (i < n) {
-        o[i] = a.delta0[i] + (double)yd[i];
+        o[i] = a.delta0[i] + (coff + (double)yd[i]);
         o[n + i] = (double)yw[i];
       }
     }
@@ -200,6 +221,7 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
   const int slot = (valid && a.traj_slot) ? a.traj_slot[ns] : -1;
 
   R yd[NG], yw[NG], yx[PM];
+  double coff = 0.0;  // common-angle offset of the trajectory (see IntegArgs::recenter)
   if (a.s_begin == 0) {
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
@@ -208,7 +230,7 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
     }
 #pragma unroll
     for (int p = 0; p < PM; ++p) yx[p] = cf[L.xi0() + p];
-    emit_step<R, NG, PM>(a, tile, lane, cnt, 0, slot, yd, yw, yx);
+    emit_step<R, NG, PM>(a, tile, lane, cnt, 0, slot, coff, yd, yw, yx);
   } else {
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
@@ -217,9 +239,12 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
     }
 #pragma unroll
     for (int p = 0; p < PM; ++p) yx[p] = a.state[(int64_t)(2 * NG + p) * a.lanes + gidx];
+    coff = load_offset(a.state, (int64_t)(2 * NG + PM) * a.lanes + gidx,
+                       (int64_t)(2 * NG + PM + 1) * a.lanes + gidx);
   }
 
   const R dt = a.dt, h2 = a.dt * R(0.5), dt6 = a.dt / R(6), wb = a.wb;
+  const R inv_n = R(1) / (R)a.n;
   // KLE path values of the next step are loaded one step ahead.
   R w0[PM], w1[PM], w2[PM];
 #pragma unroll
@@ -282,7 +307,17 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
       w1[p] = n1[p];
       w2[p] = n2[p];
     }
-    emit_step<R, NG, PM>(a, tile, lane, cnt, s + 1, slot, yd, yw, yx);
+    if (a.recenter) {  // move the mean angle of the machines into the offset
+      R sum = R(0);
+#pragma unroll
+      for (int i = 0; i < NG; ++i)
+        if (i < a.n) sum += yd[i];
+      const R ref = sum * inv_n;
+      coff += (double)ref;
+#pragma unroll
+      for (int i = 0; i < NG; ++i) yd[i] -= ref;
+    }
+    emit_step<R, NG, PM>(a, tile, lane, cnt, s + 1, slot, coff, yd, yw, yx);
   }
 
 #pragma unroll
@@ -292,9 +327,11 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
   }
 #pragma unroll
   for (int p = 0; p < PM; ++p) a.state[(int64_t)(2 * NG + p) * a.lanes + gidx] = yx[p];
+  store_offset(a.state, (int64_t)(2 * NG + PM) * a.lanes + gidx,
+               (int64_t)(2 * NG + PM + 1) * a.lanes + gidx, coff);
 
   if (a.s_end == a.S && valid) {
-    bool bad = false;
+    bool bad = !isfinite(coff);
 #pragma unroll
     for (int i = 0; i < NG; ++i) bad |= !isfinite(yd[i]) || !isfinite(yw[i]);
 #pragma unroll
@@ -523,6 +560,7 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
   };
   int nbuf = 0;
   int64_t s_first = 0;
+  double coff = 0.0;  // common-angle offset of my trajectory (see IntegArgs::recenter)
   auto emit = [&](int64_t s, const R (&yd)[G], const R (&yw)[G], const R (&yx)[PQ]) {
     if (nbuf == 0) s_first = s;
     double (*tb)[TB + 1] = tile_buf[nbuf];
@@ -530,7 +568,7 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
     for (int q = 0; q < G; ++q) {
       const int i = g * G + q;
       if (lane_on && i < n) {
-        tb[i][tl] = (double)yd[q];
+        tb[i][tl] = coff + (double)yd[q];
         tb[n + i][tl] = (double)yw[q];
       }
     }
@@ -544,7 +582,7 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
       for (int q = 0; q < G; ++q) {
         const int i = g * G + q;
         if (i < n) {
-          o[i] = a.delta0[i] + (double)yd[q];
+          o[i] = a.delta0[i] + (coff + (double)yd[q]);
           o[n + i] = (double)yw[q];
         }
       }
@@ -574,9 +612,12 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
     }
 #pragma unroll
     for (int r = 0; r < PQ; ++r) yx[r] = a.state[(int64_t)(2 * G + r) * a.lanes + lane_id];
+    coff = load_offset(a.state, (int64_t)(2 * G + PQ) * a.lanes + lane_id,
+                       (int64_t)(2 * G + PQ + 1) * a.lanes + lane_id);
   }
 
   const R dt = a.dt, h2 = a.dt * R(0.5), dt6 = a.dt / R(6);
+  const R inv_n = R(1) / (R)n;
   const int64_t colstride = (int64_t)P * N;
   // KLE path values of my processes: the two new stage columns of step s are
   // loaded one step ahead so their latency overlaps the previous step.
@@ -634,6 +675,25 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
       w1[r] = n1[r];
       w2[r] = n2[r];
     }
+    if (a.recenter) {
+      // the mean angle of the trajectory's machines: each lane's sum over its
+      // machines through the exchange row (free again: the last stage's
+      // reads ended with a wave fence), added in lane order by every lane of
+      // the trajectory (the same bits in each), then taken out of every angle
+      R part = R(0);
+#pragma unroll
+      for (int q = 0; q < G; ++q)
+        if (g * G + q < n) part += yd[q];
+      xch[tl][g] = R2{part, R(0)};
+      wave_lds_sync();
+      R sum = R(0);
+      for (int k = 0; k < L; ++k) sum += xch[tl][k].x;
+      wave_lds_sync();
+      const R ref = sum * inv_n;
+      coff += (double)ref;
+#pragma unroll
+      for (int q = 0; q < G; ++q) yd[q] -= ref;
+    }
     emit(s + 1, yd, yw, yx);
   }
 
@@ -647,10 +707,12 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
     }
 #pragma unroll
     for (int r = 0; r < PQ; ++r) a.state[(int64_t)(2 * G + r) * a.lanes + lane_id] = yx[r];
+    store_offset(a.state, (int64_t)(2 * G + PQ) * a.lanes + lane_id,
+                 (int64_t)(2 * G + PQ + 1) * a.lanes + lane_id, coff);
   }
 
   if (a.s_end == a.S) {  // uniform over the workgroup: the barriers below are safe
-    bool bad = false;
+    bool bad = !isfinite(coff);
 #pragma unroll
     for (int q = 0; q < G; ++q) bad |= !isfinite(yd[q]) || !isfinite(yw[q]);
 #pragma unroll

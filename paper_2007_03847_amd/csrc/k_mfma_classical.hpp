@@ -151,11 +151,13 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
     }
 
   // State between time chunks: [tile][wave][kRows][64], rows dd (kQ), dw
-  // (kQ), the two process slots; kRows = 2 G + PQ of the host's allocation
-  // with G = n_pad / 4 and PQ = kMcMaxProc / 4 (4 lanes per trajectory).
-  constexpr int kRows = 2 * kQ + kMcMaxProc / 4;
+  // (kQ), the two process slots, the common-angle offset (hi, lo); kRows =
+  // 2 G + PQ + kOffsetRows of the host's allocation with G = n_pad / 4 and
+  // PQ = kMcMaxProc / 4 (4 lanes per trajectory).
+  constexpr int kRows = 2 * kQ + kMcMaxProc / 4 + kOffsetRows;
   static_assert(kMcMaxProc / 4 == 2, "two process slots per lane");
   float yd[kQ], yw[kQ], x0, x1;
+  double coff = 0.0;  // common-angle offset of trajectory t (see IntegArgs::recenter)
   const int64_t sbase = (tile * kWaves + wv) * kRows * 64 + l;
   if (a.s_begin == 0) {
 #pragma unroll
@@ -170,6 +172,7 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
     }
     x0 = a.state[sbase + (2 * kQ) * 64];
     x1 = a.state[sbase + (2 * kQ + 1) * 64];
+    coff = load_offset(a.state, sbase + (2 * kQ + 2) * 64, sbase + (2 * kQ + 3) * 64);
   }
 
   int pbuf = 0;
@@ -196,10 +199,10 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
     for (int q = 0; q < kQ; ++q) {
       const int m = mach(q);  // uniform over a row of 16 lanes
       if (m < nl) {
-        one((double)yd[q], m);
+        one(coff + (double)yd[q], m);
         one((double)yw[q], nl + m);
         if (o) {
-          o[m] = d0[m] + (double)yd[q];
+          o[m] = d0[m] + (coff + (double)yd[q]);
           o[nl + m] = (double)yw[q];
         }
       }
@@ -249,6 +252,7 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
   }
 
   const float dt = a.dt, h2 = 0.5f * a.dt, dt6 = a.dt / 6.0f, wb = a.wb;
+  const float inv_n = 1.0f / (float)n;
   const int64_t colstride = (int64_t)P * N;
   const float* w = a.w;
   const int64_t wo0 = (int64_t)(own0 ? g : 0) * N + ns, wo1 = (int64_t)(own1 ? g + 4 : 0) * N + ns;
@@ -403,6 +407,22 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
     }
     x0 += dt6 * ax0;
     x1 += dt6 * ax1;
+    if (a.recenter) {
+      // the mean angle of trajectory t's machines (lanes t, t + 16, t + 32,
+      // t + 48 hold them), summed in that order by each of the four lanes
+      float part = 0.0f;
+#pragma unroll
+      for (int q = 0; q < kQ; ++q)
+        if (mach(q) < n) part += yd[q];
+      float sum = __shfl(part, t, 64);
+      sum += __shfl(part, t + 16, 64);
+      sum += __shfl(part, t + 32, 64);
+      sum += __shfl(part, t + 48, 64);
+      const float ref = sum * inv_n;
+      coff += (double)ref;
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) yd[q] -= ref;
+    }
     w00 = w02; w01 = n01; w02 = n02;
     w10 = w12; w11 = n11; w12 = n12;
     emit(s + 1);
@@ -416,9 +436,10 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
     }
     a.state[sbase + (2 * kQ) * 64] = x0;
     a.state[sbase + (2 * kQ + 1) * 64] = x1;
+    store_offset(a.state, sbase + (2 * kQ + 2) * 64, sbase + (2 * kQ + 3) * 64, coff);
   }
   if (a.s_end == a.S) {  // uniform over the workgroup
-    bool bad = (own0 && !isfinite(x0)) || (own1 && !isfinite(x1));
+    bool bad = (own0 && !isfinite(x0)) || (own1 && !isfinite(x1)) || !isfinite(coff);
 #pragma unroll
     for (int q = 0; q < kQ; ++q)
       bad |= mach(q) < n && (!isfinite(yd[q]) || !isfinite(yw[q]));

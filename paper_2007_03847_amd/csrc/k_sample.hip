@@ -118,15 +118,24 @@ hipError_t launch_basis(int32_t kind, int32_t K, int64_t S, double T, double* ph
 // ---------------------------------------------------------------------------
 // KLE path contraction (eqs. 8-9): for each process p,
 //   w[c][p][n] = sum_j phi[j][c0 + c] * zeta[p K + j][n],
-// i.e. (Phi^T)[C x K] x Z_p[K x N].  Each wave owns a 16 (c) x 64 (n) output
-// tile; four waves per workgroup stack along c.
+// i.e. (Phi^T)[C x K] x Z_p[K x N].
 //
 // FP64: v_mfma_f64_16x16x4_f64.  Operand lanes: A[i][k] at lane 16k + i,
 // B[k][j] at lane 16k + j; result register r of lane l is D[4r + l/16][l%16].
+// Each wave owns a 32 (c) x 64 (n) output tile: 2 x 4 blocks of 16 x 16 in
+// eight accumulators, so every k-step of four loads 2 + 4 operand fragments
+// for 8 matrix operations; the fragments of the next k-step are loaded while
+// the current one's operations run.  A workgroup's four waves lie along n
+// (a 32 x 256 tile: the waves share their A fragments in L1).  Operands come
+// straight from L1/L2: Phi is a few hundred KB shared by every workgroup and
+// the rows of zeta a tile touches are reused by the C/32 tiles of its n
+// range.
 // ---------------------------------------------------------------------------
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+constexpr int kKleTC = 32, kKleTN = 256;  // workgroup tile (c, n)
 
 template <typename OutT>
 __device__ __forceinline__ void kle_f64_tile(const double* __restrict__ zeta,
@@ -134,36 +143,66 @@ __device__ __forceinline__ void kle_f64_tile(const double* __restrict__ zeta,
                                              int P, int K, int64_t N, int64_t C, int64_t c0,
                                              OutT* __restrict__ w, int64_t bx, int64_t by, int p) {
   const int lane = threadIdx.x & 63;
-  const int64_t cb = (by * 4 + (threadIdx.x >> 6)) * 16;
-  const int64_t n0 = bx * 64;
-  if (cb >= C) return;  // uniform per wave
+  const int64_t cb = by * kKleTC;
+  const int64_t n0 = bx * kKleTN + (threadIdx.x >> 6) * 64;
+  if (n0 >= N) return;  // uniform per wave
   const int li = lane & 15, lk = lane >> 4;
   const double* __restrict__ zp = zeta + (int64_t)p * K * N;
-  d4_t acc[4];
+  d4_t acc[2][4];
 #pragma unroll
-  for (int b = 0; b < 4; ++b) acc[b] = d4_t{0.0, 0.0, 0.0, 0.0};
-  const int64_t ca = cb + li;
-  for (int j0 = 0; j0 < K; j0 += 4) {
-    const int j = j0 + lk;
-    const bool jv = j < K;
-    const double a = (jv && ca < C) ? phi[(int64_t)j * phi_ld + c0 + ca] : 0.0;
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t n = n0 + 16 * b + li;
-      const double bv = (jv && n < N) ? zp[(int64_t)j * N + n] : 0.0;
-      acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[b], 0, 0, 0);
-    }
+    for (int b = 0; b < 4; ++b) acc[h][b] = d4_t{0.0, 0.0, 0.0, 0.0};
+  bool cv[2], nv[4];
+  const double* ap[2];
+  const double* bp[4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t c = cb + 16 * h + li;
+    cv[h] = c < C;
+    ap[h] = phi + c0 + (cv[h] ? c : 0);
   }
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int64_t n = n0 + 16 * b + li;
-    if (n >= N) continue;
+    nv[b] = n < N;
+    bp[b] = zp + (nv[b] ? n : 0);
+  }
+  auto load = [&](int j, double (&a)[2], double (&bv)[4]) {
+    const bool jv = j < K;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) a[h] = (jv && cv[h]) ? ap[h][(int64_t)j * phi_ld] : 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = (jv && nv[b]) ? bp[b][(int64_t)j * N] : 0.0;
+  };
+  double a[2], bv[4];
+  load(lk, a, bv);
+  for (int j0 = 0; j0 < K; j0 += 4) {
+    double an[2], bn[4];
+    load(j0 + 4 + lk, an, bn);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        acc[h][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], bv[b], acc[h][b], 0, 0, 0);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) a[h] = an[h];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = bn[b];
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t c = cb + 4 * r + lk;
-      if (c < C) w[(c * P + p) * N + n] = (OutT)acc[b][r];
+      const int64_t c = cb + 16 * h + 4 * r + lk;
+      if (c >= C) continue;
+      OutT* row = w + (c * P + p) * N;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t n = n0 + 16 * b + li;
+        if (n < N) row[n] = (OutT)acc[h][b][r];
+      }
     }
-  }
 }
 
 // The grid is a flat list of blocks striding over the (n, c, p) tiles, so a
@@ -173,7 +212,8 @@ __global__ void __launch_bounds__(256) k_kle_f64(const double* __restrict__ zeta
                                                  const double* __restrict__ phi, int64_t phi_ld,
                                                  int P, int K, int64_t N, int64_t C, int64_t c0,
                                                  OutT* __restrict__ w) {
-  const int64_t tx = (N + 63) / 64, ty = (C + 63) / 64, n_tiles = tx * ty * P;
+  const int64_t tx = (N + kKleTN - 1) / kKleTN, ty = (C + kKleTC - 1) / kKleTC;
+  const int64_t n_tiles = tx * ty * P;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
     kle_f64_tile<OutT>(zeta, phi, phi_ld, P, K, N, C, c0, w, tile % tx, (tile / tx) % ty,
                        (int)(tile / (tx * ty)));
@@ -183,7 +223,7 @@ static hipError_t launch_kle_f64_t(const double* zeta, const double* phi, int64_
                                    int K, int64_t N, int64_t C, int64_t c0, OutT* w,
                                    hipStream_t st, int max_blocks) {
   if (C <= 0 || N <= 0 || P <= 0) return hipSuccess;
-  int64_t tiles = ((N + 63) / 64) * ((C + 63) / 64) * P;
+  int64_t tiles = ((N + kKleTN - 1) / kKleTN) * ((C + kKleTC - 1) / kKleTC) * P;
   if (max_blocks > 0) tiles = std::min<int64_t>(tiles, max_blocks);
   hipLaunchKernelGGL(k_kle_f64<OutT>, dim3((unsigned)tiles), dim3(256), 0, st, zeta, phi, phi_ld, P,
                      K, N, C, c0, w);
@@ -290,6 +330,172 @@ hipError_t launch_kle_bf16x3(const double* zeta, const double* phi, int64_t phi_
   if (max_blocks > 0) tiles = std::min<int64_t>(tiles, max_blocks);
   hipLaunchKernelGGL(k_kle_bf16x3, dim3((unsigned)tiles), dim3(256), 0, st, zeta, phi, phi_ld, P,
                      K, N, C, c0, w);
+  return hipGetLastError();
+}
+
+}  // namespace fmc
+
+namespace fmc {
+
+// ---------------------------------------------------------------------------
+// BF16 x3 contraction on operands split once.  x -> hi = bf16(float(x)),
+// lo = bf16(float(x) - float(hi)) as above, stored k-fastest: Phi as
+// [column][Kp] and each process's coefficients as [sample][Kp] (Kp = K
+// rounded up to 32, zero beyond K), so that a lane's eight consecutive k of
+// an operand fragment are one 16-byte load and no split is left in the
+// contraction's inner loop.
+// ---------------------------------------------------------------------------
+
+// X: rows k = 0..K-1 of `items` columns with leading dimension ld (process
+// p's block at X + p xs); Y: [item][Kp] hi and lo planes (process p's block
+// at + p ys).  A 32 (k) x 64 (item) tile is transposed through LDS so both
+// the reads and the writes are coalesced.
+__global__ void __launch_bounds__(256) k_split_bf16(const double* __restrict__ X, int64_t ld,
+                                                    int K, int64_t items, int Kp, int64_t xs,
+                                                    int64_t ys, __bf16* __restrict__ yh,
+                                                    __bf16* __restrict__ yl) {
+  __shared__ double tile[32][65];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int k0 = blockIdx.y * 32;
+  const int p = blockIdx.z;
+  const double* Xp = X + (int64_t)p * xs;
+  for (int kk = tid >> 6; kk < 32; kk += 4) {
+    const int k = k0 + kk;
+    const int64_t it = i0 + (tid & 63);
+    tile[kk][tid & 63] = (k < K && it < items) ? Xp[(int64_t)k * ld + it] : 0.0;
+  }
+  __syncthreads();
+  const int item = tid >> 2, kq = (tid & 3) * 8;
+  const int64_t it = i0 + item;
+  if (it >= items) return;
+  bf8_t h, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float xf = (float)tile[kq + e][item];
+    const __bf16 hh = (__bf16)xf;
+    h[e] = hh;
+    l[e] = (__bf16)(xf - (float)hh);
+  }
+  const int64_t o = (int64_t)p * ys + it * Kp + k0 + kq;
+  *reinterpret_cast<bf8_t*>(yh + o) = h;
+  *reinterpret_cast<bf8_t*>(yl + o) = l;
+}
+
+hipError_t launch_split_bf16(const double* X, int64_t ld, int K, int64_t items, int Kp, int P,
+                             int64_t xs, int64_t ys, void* yh, void* yl, hipStream_t st) {
+  if (items <= 0 || P <= 0 || Kp <= 0 || Kp % 32 != 0 || K > Kp) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((items + 63) / 64), (unsigned)(Kp / 32), (unsigned)P);
+  hipLaunchKernelGGL(k_split_bf16, grid, dim3(256), 0, st, X, ld, K, items, Kp, xs, ys,
+                     (__bf16*)yh, (__bf16*)yl);
+  return hipGetLastError();
+}
+
+// w[c][p][n] = sum_k Phi[c0 + c][k] Z_p[n][k] as three BF16 products per
+// pair (lo*hi + hi*lo + hi*hi, FP32 accumulation) on
+// v_mfma_f32_16x16x32_bf16.  Each wave owns a 32 (c) x 64 (n) output tile (2 x
+// 4 blocks, eight accumulators); a k-step of 32 loads 4 + 8 fragments of 16
+// bytes for 24 matrix operations, and the next k-step's fragments are loaded
+// while they run.  Four waves per workgroup along n.
+__device__ __forceinline__ void kle_bf16s_tile(const __bf16* __restrict__ ph,
+                                               const __bf16* __restrict__ pl, int Kp,
+                                               const __bf16* __restrict__ zh,
+                                               const __bf16* __restrict__ zl, int P, int64_t N,
+                                               int64_t C, int64_t c0, float* __restrict__ w,
+                                               int64_t bx, int64_t by, int p) {
+  const int lane = threadIdx.x & 63;
+  const int64_t cb = by * kKleTC;
+  const int64_t n0 = bx * kKleTN + (threadIdx.x >> 6) * 64;
+  if (n0 >= N) return;  // uniform per wave
+  const int li = lane & 15, ko = 8 * (lane >> 4);
+  f4_t acc[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[h][b] = f4_t{0.f, 0.f, 0.f, 0.f};
+  bool cv[2], nv[4];
+  int64_t ao[2], bo[4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t c = cb + 16 * h + li;
+    cv[h] = c < C;
+    ao[h] = (c0 + (cv[h] ? c : 0)) * Kp + ko;
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int64_t n = n0 + 16 * b + li;
+    nv[b] = n < N;
+    bo[b] = ((int64_t)p * N + (nv[b] ? n : 0)) * Kp + ko;
+  }
+  const bf8_t zero = {};
+  auto load = [&](int k, bf8_t (&ah)[2], bf8_t (&al)[2], bf8_t (&bh)[4], bf8_t (&bl)[4]) {
+    const bool kv = k < Kp;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      ah[h] = (kv && cv[h]) ? *reinterpret_cast<const bf8_t*>(ph + ao[h] + k) : zero;
+      al[h] = (kv && cv[h]) ? *reinterpret_cast<const bf8_t*>(pl + ao[h] + k) : zero;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      bh[b] = (kv && nv[b]) ? *reinterpret_cast<const bf8_t*>(zh + bo[b] + k) : zero;
+      bl[b] = (kv && nv[b]) ? *reinterpret_cast<const bf8_t*>(zl + bo[b] + k) : zero;
+    }
+  };
+  bf8_t ah[2], al[2], bh[4], bl[4];
+  load(0, ah, al, bh, bl);
+  for (int k = 0; k < Kp; k += 32) {
+    bf8_t ahn[2], aln[2], bhn[4], bln[4];
+    load(k + 32, ahn, aln, bhn, bln);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        acc[h][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[h], bh[b], acc[h][b], 0, 0, 0);
+        acc[h][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[h], bl[b], acc[h][b], 0, 0, 0);
+        acc[h][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[h], bh[b], acc[h][b], 0, 0, 0);
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) { ah[h] = ahn[h]; al[h] = aln[h]; }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) { bh[b] = bhn[b]; bl[b] = bln[b]; }
+  }
+  // result register r of lane l is D[4(l/16) + r][l%16]
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t c = cb + 16 * h + 4 * (lane >> 4) + r;
+      if (c >= C) continue;
+      float* row = w + (c * P + p) * N;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t n = n0 + 16 * b + li;
+        if (n < N) row[n] = acc[h][b][r];
+      }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_kle_bf16x3s(const __bf16* __restrict__ ph,
+                                                     const __bf16* __restrict__ pl, int Kp,
+                                                     const __bf16* __restrict__ zh,
+                                                     const __bf16* __restrict__ zl, int P,
+                                                     int64_t N, int64_t C, int64_t c0,
+                                                     float* __restrict__ w) {
+  const int64_t tx = (N + kKleTN - 1) / kKleTN, ty = (C + kKleTC - 1) / kKleTC;
+  const int64_t n_tiles = tx * ty * P;
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
+    kle_bf16s_tile(ph, pl, Kp, zh, zl, P, N, C, c0, w, tile % tx, (tile / tx) % ty,
+                   (int)(tile / (tx * ty)));
+}
+
+hipError_t launch_kle_bf16x3_split(const void* ph, const void* pl, int Kp, const void* zh,
+                                   const void* zl, int P, int64_t N, int64_t C, int64_t c0,
+                                   float* w, hipStream_t st) {
+  if (C <= 0 || N <= 0 || P <= 0) return hipSuccess;
+  if (Kp <= 0 || Kp % 32 != 0) return hipErrorInvalidValue;
+  const int64_t tiles = ((N + kKleTN - 1) / kKleTN) * ((C + kKleTC - 1) / kKleTC) * P;
+  hipLaunchKernelGGL(k_kle_bf16x3s, dim3((unsigned)tiles), dim3(256), 0, st, (const __bf16*)ph,
+                     (const __bf16*)pl, Kp, (const __bf16*)zh, (const __bf16*)zl, P, N, C, c0, w);
   return hipGetLastError();
 }
 

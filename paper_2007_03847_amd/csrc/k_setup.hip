@@ -393,39 +393,60 @@ template hipError_t launch_pack<double>(const double*, int, int, const int32_t*,
 template hipError_t launch_pack<float>(const double*, int, int, const int32_t*, int, int, float*,
                                        hipStream_t);
 
-// ---------------------------------------------------------------------------
-// Cross-sample statistics (Alg. 1 step 4).  Each sample group (a wave's
-// trajectories) left its exact two-pass (mean, M2) per output; they are merged
-// here in group order with Chan's pairwise update, so the result does not
-// depend on scheduling.  Angles get delta0 back (the integrator works in
-// deviations).  One thread per (step, variable).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_stats_merge(const double2* __restrict__ partial,
-                                                     int64_t gstride, int64_t n_groups,
-                                                     int group_size, int64_t N, int64_t SV,
-                                                     int V, int n, int ddof,
-                                                     const double* __restrict__ delta0,
-                                                     double* __restrict__ mean,
-                                                     double* __restrict__ var) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= SV) return;
+// Ordered merge of per-group statistics into mean and variance (Alg. 1 step
+// 4): partial[g * gstride + q] holds (mean, M2) of group g's samples for
+// q = row * V + v (group_size samples per group, the last group the rest).
+// A workgroup takes 64 consecutive q, one per lane, and splits the groups
+// into kMergeSplit contiguous ranges, one per wave: each wave merges its
+// range in group order with Chan's update (loads four groups ahead), then
+// the first wave merges the waves' results in wave order.  The order depends
+// only on the sizes, so repeated runs give the same bits; every wave reads
+// 64 consecutive pairs (1 KB) per group, and the workgroups together stream
+// the partials once.  Angles get delta0 back (the integrators work in
+// deviations).
+constexpr int kMergeSplit = 16;
+
+__device__ __forceinline__ void chan_merge(double& cnt, double& m, double& M2, double nb,
+                                           double mb, double M2b) {
+  const double tot = cnt + nb;
+  const double dlt = mb - m;
+  const double fb = tot > 0.0 ? nb / tot : 0.0;
+  m += dlt * fb;
+  M2 += M2b + dlt * dlt * (cnt * fb);
+  cnt = tot;
+}
+
+__global__ void __launch_bounds__(64 * kMergeSplit) k_stats_merge(
+    const double2* __restrict__ partial, int64_t gstride, int64_t n_groups, int group_size,
+    int64_t N, int64_t SV, int V, int n, int ddof, const double* __restrict__ delta0,
+    double* __restrict__ mean, double* __restrict__ var) {
+  __shared__ double sh[3][kMergeSplit][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+  const bool on = q < SV;
+  const int64_t per = (n_groups + kMergeSplit - 1) / kMergeSplit;
+  const int64_t g0 = wv * per, g1 = g0 + per < n_groups ? g0 + per : n_groups;
   double cnt = 0.0, m = 0.0, M2 = 0.0;
-  for (int64_t g = 0; g < n_groups; ++g) {
-    const int64_t rem = N - g * group_size;
-    const double nb = (double)(rem < group_size ? rem : group_size);
-    const double2 pt = partial[g * gstride + q];
-    if (g == 0) {
-      cnt = nb;
-      m = pt.x;
-      M2 = pt.y;
-    } else {
-      const double tot = cnt + nb;
-      const double dlt = pt.x - m;
-      m += dlt * (nb / tot);
-      M2 += pt.y + dlt * dlt * (cnt * nb / tot);
-      cnt = tot;
+  const double2* src = partial + (on ? q : 0);
+  constexpr int D = 4;
+  for (int64_t g = g0; g < g1; g += D) {
+    double2 pt[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) pt[u] = (on && g + u < g1) ? src[(g + u) * gstride] : double2{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      if (g + u >= g1) break;
+      const int64_t rem = N - (g + u) * group_size;
+      chan_merge(cnt, m, M2, (double)(rem < group_size ? rem : group_size), pt[u].x, pt[u].y);
     }
   }
+  sh[0][wv][lane] = cnt;
+  sh[1][wv][lane] = m;
+  sh[2][wv][lane] = M2;
+  __syncthreads();
+  if (wv != 0 || !on) return;
+  for (int w = 1; w < kMergeSplit; ++w)
+    chan_merge(cnt, m, M2, sh[0][w][lane], sh[1][w][lane], sh[2][w][lane]);
   const int v = (int)(q % V);
   mean[q] = m + (v < n ? delta0[v] : 0.0);
   var[q] = M2 / (double)(N - ddof);
@@ -437,8 +458,9 @@ hipError_t launch_stats_merge_rows(const double2* partial, int64_t gstride, int6
                                    hipStream_t st) {
   const int64_t SV = rows * V;
   if (SV <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_stats_merge, dim3((unsigned)((SV + 255) / 256)), dim3(256), 0, st, partial,
-                     gstride, n_groups, group_size, N, SV, V, n, ddof, delta0, mean, var);
+  hipLaunchKernelGGL(k_stats_merge, dim3((unsigned)((SV + 63) / 64)), dim3(64 * kMergeSplit), 0,
+                     st, partial, gstride, n_groups, group_size, N, SV, V, n, ddof, delta0, mean,
+                     var);
   return hipGetLastError();
 }
 

@@ -161,12 +161,11 @@ def test_long_horizon_fp32_paths(ctx):
     """28 s (5588 steps) of a 46-machine system (scenario 17 of the uneven set
     at N = 256), FP32-integration forms: one-scenario fmc_run in FP32 and
     BF16x3, the batched form with the tuned variant and with the matrix-core
-    class.  The mean stays within 1e-4 of the oracle; the variance reaches
-    about 1e-4 (measured 1.05e-4 for fmc_run in FP32; 5e-5 at N = 1024): the
-    common rotor angle is a neutral mode, so FP32 errors in the frequency
-    integrate without restoring force (an FP32 emulation on the host puts
-    the angle error at 2e-4 rad after 28 s, with or without compensated
-    summation of the angle).  The bound checked is 2e-4."""
+    class; mean and variance within the reduced-precision bound 1e-4 of the
+    oracle for every output.  The common rotor angle drifts by several radians
+    over this horizon (a neutral mode); the integrators keep it in an FP64
+    offset per trajectory, so FP32 rounding does not fall on the relative
+    angles (without that, the variance error was 1.05e-4 here)."""
     sc = dict(workloads.uneven_batch()[17], N=256)
     o = oracle.run(sc)
     runs = [ctx.run(sc, precision="f32"), ctx.run(sc, precision="bf16x3"),
@@ -175,4 +174,5 @@ def test_long_horizon_fp32_paths(ctx):
     for k, r in enumerate(runs):
         em = mean_err(_np(r["mean"]), o["mean"], o["var"])
         ev = rel_err(_np(r["var"]), o["var"])
-        assert em <= 1e-4 and ev <= 2e-4, (k, em, ev)
+        print(f"46 machines, 28 s, form {k}: mean {em:.2e}, variance {ev:.2e}", flush=True)
+        assert em <= 1e-4 and ev <= 1e-4, (k, em, ev)

@@ -118,16 +118,17 @@ def test_fluxdecay_rejections(ctx, fmc):
 
 
 def test_fluxdecay_long_horizon(ctx):
-    """30 s (6000 steps) of 37 machines at N = 256 in FP32.  The mean stays
-    within 1e-4 of the oracle; the variance of the fast exciter states drifts
-    past it (measured 2.8e-4 on V_R of one machine at 30 s, growing with the
-    horizon as FP32 rounding accumulates in the slow states that V_R follows
-    with gain KA), so the bound checked here is the measured behaviour with
-    margin, not the reduced-precision target."""
+    """30 s (6000 steps) of 37 machines at N = 256 in FP32, mean and variance
+    within the reduced-precision bound 1e-4 of the oracle for every output.
+    The common rotor angle of a system without an infinite bus is a neutral
+    mode that drifts by radians over such a horizon; the integrator keeps it
+    in an FP64 offset per trajectory, so that FP32 rounding does not fall on
+    the relative angles (before that, V_R of one machine reached 2.6e-4)."""
     sc = workloads.fluxdecay(n_gen=37, n_dist=6, N=256, K=50, T=30.0, dt=0.005, net_seed=337,
                              seed=5)
     r = ctx.run(sc, precision="f32")
     o = oracle.run(sc)
     em = mean_err(_np(r["mean"]), o["mean"], o["var"])
     ev = var_err(_np(r["var"]), o["var"])
-    assert em <= 1e-4 and ev <= 5e-4, (em, ev)
+    print(f"flux-decay 37 machines, 30 s, FP32: mean {em:.2e}, variance {ev:.2e}", flush=True)
+    assert em <= 1e-4 and ev <= 1e-4, (em, ev)

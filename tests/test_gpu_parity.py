@@ -93,7 +93,7 @@ def test_em_basis(ctx, S, T):
 
 # ------------------------------------------------------------ KLE paths
 @pytest.mark.parametrize("P,K,N,S", [(1, 40, 1000, 100), (3, 100, 777, 60), (2, 5, 65, 9),
-                                     (1, 1, 1, 1)])
+                                     (1, 1, 1, 1), (2, 150, 2049, 130), (1, 32, 256, 16)])
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-7), ("bf16x3", 4e-5)])
 def test_kle_paths(ctx, P, K, N, S, prec, tol):
     T = 0.01 * S
