@@ -294,6 +294,17 @@ int fmc_lhs_decorrelate(fmc_context *ctx, int32_t M, int64_t N, double *zeta, in
 int fmc_rrf_rms(fmc_context *ctx, const double *traj, int64_t n, int64_t S, int32_t V,
                 const double *w, double dt, double *rrf);
 
+/* fmc_rrf_rms without any allocation, for callers that cannot allocate
+ * device or pinned host memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, results and
+ * errors as fmc_rrf_rms, bit for bit, except that V is limited to 2048 by
+ * the library's static per-device scratch (the device copy of w), which
+ * every call on a device shares: calls that overlap on one device race.
+ * w is copied from host memory on the context's stream; the call
+ * synchronises that stream.  FMC_EINVAL also for V > 2048. */
+int fmc_rrf_rms_noalloc(fmc_context *ctx, const double *traj, int64_t n, int64_t S, int32_t V,
+                        const double *w, double dt, double *rrf);
+
 /* KLE basis (eq. 7, or the eigen basis) on the stage grid: phi device
  * [K][2S+1] FP64. */
 int fmc_basis(fmc_context *ctx, int32_t basis, int32_t K, int64_t S, double T, double *phi);

@@ -110,6 +110,8 @@ _sig = {
     "fmc_lhs": ([_ctx_p, C.c_uint64, C.c_int32, C.c_int64, C.c_int32, _P, _P], C.c_int),
     "fmc_lhs_decorrelate": ([_ctx_p, C.c_int32, C.c_int64, _P, _P], C.c_int),
     "fmc_rrf_rms": ([_ctx_p, _P, C.c_int64, C.c_int64, C.c_int32, _P, C.c_double, _P], C.c_int),
+    "fmc_rrf_rms_noalloc": ([_ctx_p, _P, C.c_int64, C.c_int64, C.c_int32, _P, C.c_double, _P],
+                            C.c_int),
     "fmc_basis": ([_ctx_p, C.c_int32, C.c_int32, C.c_int64, C.c_double, _P], C.c_int),
     "fmc_kle_paths": ([_ctx_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_int64,
                        C.c_int64, _P, _P, C.c_int64, _P], C.c_int),
@@ -311,6 +313,18 @@ class Context:
         out = t.empty(n, dtype=t.float64, device=self.device)
         _check(_lib.fmc_rrf_rms(self._h, _dptr(traj), n, S1 - 1, V, ww.ctypes.data, float(dt),
                                 _dptr(out)))
+        return out
+
+    def rrf_rms_noalloc(self, traj, w, dt: float, out):
+        """rrf_rms through the allocation-free entry point: the caller passes
+        the output tensor (device [n] FP64) as well."""
+        t = self.torch
+        assert traj.dtype == t.float64 and traj.is_contiguous() and traj.dim() == 3
+        assert out.dtype == t.float64 and out.is_contiguous() and out.numel() >= traj.shape[0]
+        n, S1, V = traj.shape
+        ww = np.ascontiguousarray(w, dtype=np.float64).reshape(V)
+        _check(_lib.fmc_rrf_rms_noalloc(self._h, _dptr(traj), n, S1 - 1, V, ww.ctypes.data,
+                                        float(dt), _dptr(out)))
         return out
 
     def basis(self, kind, K: int, S: int, T: float):

@@ -93,6 +93,12 @@ constexpr int kOffsetRows = 2;
 constexpr int kFdOffsetRows = 3;
 
 // ---- launchers (each returns hipError_t of the launch) ----
+// Static scratch of fmc_rrf_rms_noalloc (weights, doubles) and its per-device
+// address (rrf_scratch_init once per device with the device current).
+constexpr int kRrfStaticMaxV = 2048;
+constexpr int kMaxDevices = 64;
+hipError_t rrf_scratch_init(int device);
+double* rrf_scratch(int device);
 hipError_t launch_rrf_rms(const double* traj, int64_t n, int64_t S, int32_t V, const double* w,
                           double dt, double* rrf, hipStream_t st);
 hipError_t launch_mix_design(const double* S, int32_t P, int32_t K, int64_t N, const double* in,

@@ -442,6 +442,11 @@ int fmc_context_create(int device, size_t hbm_budget, void* stream, fmc_context*
   c->device = device;
   c->stream = (hipStream_t)stream;
   c->budget = hbm_budget ? hbm_budget : (size_t)(0.9 * (double)free_b);
+  e = rrf_scratch_init(device);  // the allocation-free entry point's scratch
+  if (e != hipSuccess) {
+    delete c;
+    return fail(FMC_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+  }
   for (auto& ev : c->ev) {
     if (hipEventCreate(&ev) != hipSuccess) {
       delete c;
@@ -556,6 +561,25 @@ int fmc_rrf_rms(fmc_context* ctx, const double* traj, int64_t n, int64_t S, int3
   std::memcpy(h, w, (size_t)V * sizeof(double));
   hipError_t e = hipMemcpyAsync(wd, h, (size_t)V * sizeof(double), hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = launch_rrf_rms(traj, n, S, V, (const double*)wd, dt, rrf, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
+  return FMC_OK;
+}
+
+int fmc_rrf_rms_noalloc(fmc_context* ctx, const double* traj, int64_t n, int64_t S, int32_t V,
+                        const double* w, double dt, double* rrf) {
+  if (!ctx || !w || (n > 0 && (!traj || !rrf))) return fail(FMC_EINVAL, "NULL argument");
+  if (n < 0 || n > INT32_MAX || S < 1 || V < 1 || !(dt > 0.0))
+    return fail(FMC_EINVAL, "need 0 <= n < 2^31, S >= 1, V >= 1, dt > 0");
+  if (V > kRrfStaticMaxV)
+    return fail(FMC_EINVAL, "V = " + std::to_string(V) + " exceeds the static scratch (" +
+                                std::to_string(kRrfStaticMaxV) + " weights)");
+  Context* c = reinterpret_cast<Context*>(ctx);
+  (void)hipSetDevice(c->device);
+  double* wd = rrf_scratch(c->device);
+  if (!wd) return fail(FMC_EDEVICE, "no scratch address for this device");
+  hipError_t e = hipMemcpyAsync(wd, w, (size_t)V * sizeof(double), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_rrf_rms(traj, n, S, V, wd, dt, rrf, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return fail(FMC_EDEVICE, hipGetErrorString(e));
   return FMC_OK;

@@ -6,11 +6,23 @@
 // (centre-of-inertia) frequency deviation, the RRF of Sec. V-B.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fmc_internal.hpp"
 
 namespace fmc {
 
+// Scratch of the allocation-free entry point (fmc_rrf_rms_noalloc): the
+// device copy of the weights, at most kRrfStaticMaxV doubles.  Each device
+// the library runs on holds its own copy until the process ends.  In host
+// code the array's name is not a device address: host code uses the address
+// hipGetSymbolAddress returned for the current device (rrf_scratch).
+static __device__ __align__(256) double scratch[kRrfStaticMaxV];
+
 namespace {
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
 
 constexpr int kRrfLds = 2048;  // doubles of trajectory staged per tile (16 KB: several workgroups per CU)
 
@@ -72,6 +84,25 @@ __global__ void __launch_bounds__(256) k_rrf_rms(const double* __restrict__ traj
 }
 
 }  // namespace
+
+// Once per device, with that device current (called by fmc_context_create):
+// the device address of `scratch`.
+hipError_t rrf_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = (double*)p;
+  return hipSuccess;
+}
+
+double* rrf_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 hipError_t launch_rrf_rms(const double* traj, int64_t n, int64_t S, int32_t V, const double* w,
                           double dt, double* rrf, hipStream_t st) {
