@@ -53,6 +53,9 @@ class _Problem(C.Structure):
         ("ddof", C.c_int32),
         ("model", C.c_int32), ("model_params", C.c_void_p),
         ("sigma_mat", C.c_void_p),
+        ("t_event", C.c_double), ("tripped", C.c_int32),
+        ("Yp_re", C.c_void_p), ("Yp_im", C.c_void_p),
+        ("Yinfp_re", C.c_void_p), ("Yinfp_im", C.c_void_p),
     ]
 
 
@@ -82,6 +85,7 @@ def lib():
         L.orc_rhs.argtypes = [C.POINTER(_Problem), P, P, P]
         L.orc_initial_state.argtypes = [C.POINTER(_Problem), P, P]
         L.orc_rhs_jac.argtypes = [C.POINTER(_Problem), P, P]
+        L.orc_rhs_post.argtypes = [C.POINTER(_Problem), P, P, P]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -205,6 +209,27 @@ class _Keep:
     """Holds the numpy arrays referenced by a _Problem."""
 
 
+def post_event_admittance(sc: dict):
+    """Reduced admittance after the scenario's event: the event's own Y, or,
+    for a generator trip on a network scenario, the network reduced without
+    the tripped generator's internal node, placed in the n x n matrix with a
+    zero row and column for the tripped machine."""
+    ev = sc["event"]
+    n = int(sc["n_gen"])
+    if ev.get("Y") is not None:
+        return np.asarray(ev["Y"], dtype=np.complex128).reshape(n, n)
+    g = int(ev.get("tripped", -1))
+    if g < 0 or sc.get("net") is None:
+        raise ValueError("an event needs its Y, or a tripped machine of a network scenario")
+    net = sc["net"]
+    keep = np.array([k for k in range(n) if k != g])
+    small = kron(dict(net, n_gen=n - 1, gen_bus=np.asarray(net["gen_bus"])[keep],
+                      gen_xdp=np.asarray(net["gen_xdp"])[keep]))
+    Yp = np.zeros((n, n), dtype=np.complex128)
+    Yp[np.ix_(keep, keep)] = small
+    return Yp
+
+
 def problem(sc: dict):
     """Build the C problem struct from a scenario dict (see workloads)."""
     keep = _Keep()
@@ -231,6 +256,14 @@ def problem(sc: dict):
         if d.get("sigma_mat") is not None else None
     model = _enum(sc.get("model", 0), _MODEL)
     keep.mp = _f64(sc.get("model_params")) if model == 1 else None
+    ev = sc.get("event")
+    keep.Ypr = keep.Ypi = keep.Yipr = keep.Yipi = None
+    if ev is not None:
+        Yp = post_event_admittance(sc)
+        keep.Ypr, keep.Ypi = _f64(Yp.real), _f64(Yp.imag)
+        if ev.get("Yinf") is not None:
+            Yip = np.asarray(ev["Yinf"], dtype=np.complex128).reshape(n)
+            keep.Yipr, keep.Yipi = _f64(Yip.real), _f64(Yip.imag)
     pb = _Problem(
         n_gen=n, f0_hz=float(sc.get("f0", 60.0)),
         H=_p(keep.H), D=_p(keep.D), E=_p(keep.E), delta0=_p(keep.d0), Pm=_p(keep.Pm),
@@ -241,7 +274,10 @@ def problem(sc: dict):
         N=int(sc["N"]), seed=int(sc.get("seed", 0)),
         basis=_enum(sc.get("basis", 0), _BASIS), sampler=_enum(sc.get("sampler", 0), _SAMPLER),
         integrator=_enum(sc.get("integrator", 0), _INTEG), ddof=int(sc.get("ddof", 1)),
-        model=model, model_params=_p(keep.mp), sigma_mat=_p(keep.sm))
+        model=model, model_params=_p(keep.mp), sigma_mat=_p(keep.sm),
+        t_event=float(ev["t"]) if ev is not None else 0.0,
+        tripped=int(ev.get("tripped", -1)) if ev is not None else -1,
+        Yp_re=_p(keep.Ypr), Yp_im=_p(keep.Ypi), Yinfp_re=_p(keep.Yipr), Yinfp_im=_p(keep.Yipi))
     return pb, keep
 
 
@@ -289,6 +325,17 @@ def rhs(sc: dict, y, w):
     rc = lib().orc_rhs(C.byref(pb), y.ctypes.data, _p(w) if len(w) else None, dy.ctypes.data)
     if rc != 0:
         raise RuntimeError(f"orc_rhs failed: {rc}")
+    return dy
+
+
+def rhs_post(sc: dict, y, w):
+    """Right-hand side of the scenario's post-event model at state y."""
+    pb, keep = problem(sc)
+    y = _f64(y); w = _f64(w)
+    dy = np.zeros_like(y)
+    rc = lib().orc_rhs_post(C.byref(pb), y.ctypes.data, _p(w) if len(w) else None, dy.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"orc_rhs_post failed: {rc}")
     return dy
 
 

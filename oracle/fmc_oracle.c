@@ -594,6 +594,14 @@ typedef struct orc_problem {
     const double *model_params;  /* [n][9] for model 1 (order of FD_* below) */
     const double *sigma_mat;     /* NULL, or [P][P]: d xi_p = -theta_p xi_p dt +      */
                                  /* sum_q sigma_mat[p][q] dW_q (sigma is then unused) */
+    /* A network event at t_event (> 0, a whole number of steps; 0: none): from  */
+    /* then on the reduced admittance is Yp and the infinite-bus coupling Yinfp  */
+    /* (NULL: unchanged), and machine `tripped` (>= 0) is disconnected: its      */
+    /* mechanical power and the disturbances injected at it are removed (the     */
+    /* caller's Yp has its row and column zero).                                 */
+    double t_event;
+    int32_t tripped;
+    const double *Yp_re, *Yp_im, *Yinfp_re, *Yinfp_im;
 } orc_problem;
 
 /* Flux-decay parameters per machine, in this order. */
@@ -613,6 +621,7 @@ typedef struct {
     double *fdp;      /* [n][FD_NPARAM] */
     double *Vref;     /* [n] exciter reference */
     double *y0;       /* [ny] initial state (the operating point) */
+    int tripped;      /* machine disconnected (post-event model), else -1 */
 } model_t;
 
 /* Diffusion term of process p driven by the white noises w (eq. 4): sigma_p */
@@ -673,7 +682,7 @@ static void rhs(const model_t *m, const double *y, const double *w, double *dy)
     for (int i = 0; i < n; ++i) {
         double pm = m->Pm[i];
         for (int p = 0; p < P; ++p)
-            if (m->dgen[p] == i) pm += y[2 * n + p];
+            if (m->dgen[p] == i && i != m->tripped) pm += y[2 * n + p];
         dy[i] = m->wb * y[n + i];
         dy[n + i] = (pm - Pe[i] - m->D[i] * y[n + i]) / (2.0 * m->H[i]);
     }
@@ -693,7 +702,7 @@ static void rhs_jac(const model_t *m, const double *y, double *J)
         for (int k = 0; k < n; ++k) J[(n + i) * ny + k] = -JP[i * n + k] / (2.0 * m->H[i]);
         J[(n + i) * ny + n + i] = -m->D[i] / (2.0 * m->H[i]);
         for (int p = 0; p < P; ++p)
-            if (m->dgen[p] == i) J[(n + i) * ny + 2 * n + p] += 1.0 / (2.0 * m->H[i]);
+            if (m->dgen[p] == i && i != m->tripped) J[(n + i) * ny + 2 * n + p] += 1.0 / (2.0 * m->H[i]);
     }
     for (int p = 0; p < P; ++p) J[(2 * n + p) * ny + 2 * n + p] = -m->theta[p];
     if (JP != Jp) free(JP);
@@ -786,6 +795,7 @@ static int setup_model(const orc_problem *pb, model_t *m)
 {
     const int n = pb->n_gen, P = pb->n_proc;
     memset(m, 0, sizeof(*m));
+    m->tripped = -1;
     if (n < 1 || n > 512 || P < 0) return ORC_EINVAL;
     m->fd = pb->model == 1;
     if (pb->model != 0 && pb->model != 1) return ORC_EINVAL;
@@ -856,6 +866,32 @@ static void free_model(model_t *m)
     free(m->y0); free(m->Vref); free(m->fdp);
 }
 
+/* The model after a network event: a shallow copy of m with the event's
+ * reduced admittance and infinite-bus coupling, and the mechanical power of
+ * a tripped machine removed (its injections are skipped by rhs).  The
+ * classical model only. */
+static int post_model(const orc_problem *pb, const model_t *m, model_t *mp)
+{
+    if (m->fd || !pb->Yp_re || !pb->Yp_im || pb->tripped < -1 || pb->tripped >= m->n)
+        return ORC_EINVAL;
+    *mp = *m;
+    mp->Y = malloc(sizeof(double complex) * m->n * m->n);
+    mp->Yinf = malloc(sizeof(double complex) * m->n);
+    mp->Pm = malloc(sizeof(double) * m->n);
+    for (int k = 0; k < m->n * m->n; ++k) mp->Y[k] = pb->Yp_re[k] + I * pb->Yp_im[k];
+    for (int i = 0; i < m->n; ++i) {
+        mp->Yinf[i] = pb->Yinfp_re ? pb->Yinfp_re[i] + I * pb->Yinfp_im[i] : m->Yinf[i];
+        mp->Pm[i] = i == pb->tripped ? 0.0 : m->Pm[i];
+    }
+    mp->tripped = pb->tripped;
+    return ORC_OK;
+}
+
+static void free_post(model_t *mp)
+{
+    free(mp->Y); free(mp->Yinf); free(mp->Pm);
+}
+
 /* White-noise surrogate of eq. 8 for every process at stage column c:
  * w_p(t_c) = sum_j zeta[p*K + j] * m_{j+1}(t_c). */
 static void kle_forcing(const double *zcol, int64_t zstride, const double *Phi, int K,
@@ -874,10 +910,11 @@ static void kle_forcing(const double *zcol, int64_t zstride, const double *Phi, 
  * classical fourth-order Runge-Kutta method with the forcing taken at the
  * stage times; integrator 1 is the implicit trapezoidal rule solved by full
  * Newton iterations.  Writes out[(S+1)][V]: delta (absolute), dw, xi. */
-static int simulate_one(const model_t *m, const double *zcol, int64_t zstride,
-                        const double *Phi, int K, int64_t S, double dt, int integrator,
-                        double *out)
+static int simulate_one(const model_t *m0, const model_t *mpost, int64_t s_event,
+                        const double *zcol, int64_t zstride, const double *Phi, int K, int64_t S,
+                        double dt, int integrator, double *out)
 {
+    const model_t *m = m0;
     const int P = m->P, ny = m->ny;
     const int64_t C = 2 * S + 1;
     double *y = calloc(ny * 8 + ny * ny + 4 * P + 8, sizeof(double));
@@ -889,6 +926,7 @@ static int simulate_one(const model_t *m, const double *zcol, int64_t zstride,
     for (int p = 0; p < P; ++p) y[ny - P + p] = m->xi0 ? m->xi0[p] : 0.0;
     memcpy(out, y, sizeof(double) * ny);
     for (int64_t s = 0; s < S; ++s) {
+        m = (mpost && s >= s_event) ? mpost : m0; /* the network after the event */
         kle_forcing(zcol, zstride, Phi, K, C, P, 2 * s, w0);
         kle_forcing(zcol, zstride, Phi, K, C, P, 2 * s + 2, w2);
         if (integrator == 0) {
@@ -962,6 +1000,19 @@ int orc_run(const orc_problem *pb, const double *zeta_in, int64_t n_sel, const i
     if (rc != ORC_OK) { free_model(&m); return rc; }
     if (pm_out) memcpy(pm_out, m.Pm, sizeof(double) * m.n);
     if (delta0_out) memcpy(delta0_out, m.d0, sizeof(double) * m.n);
+    /* the post-event model (the same machines and operating point, the       */
+    /* event's network, a tripped machine's mechanical power removed)          */
+    model_t mp;
+    int64_t s_event = 0;
+    const int has_event = pb->t_event > 0.0;
+    if (has_event) {
+        s_event = (int64_t)llround(pb->t_event / pb->dt);
+        if (s_event < 1 || s_event >= S || fabs((double)s_event * pb->dt - pb->t_event) > 1e-9 * pb->T ||
+            post_model(pb, &m, &mp) != ORC_OK) {
+            free_model(&m);
+            return ORC_EINVAL;
+        }
+    }
     if (!sel) n_sel = pb->N;
     const int M = m.P * pb->K;
     const int V = m.V;
@@ -972,18 +1023,18 @@ int orc_run(const orc_problem *pb, const double *zeta_in, int64_t n_sel, const i
     if (!zeta_in && M > 0) {
         Z = malloc(sizeof(double) * (size_t)M * n_sel);
         rc = orc_lhs(pb->seed, M, pb->N, pb->sampler, n_sel, sel, NULL, Z);
-        if (rc != ORC_OK) { free(Phi); free(Z); free_model(&m); return rc; }
+        if (rc != ORC_OK) { free(Phi); free(Z); if (has_event) free_post(&mp); free_model(&m); return rc; }
         Zuse = Z;
     }
     double *tr = traj;
     if (!tr) tr = malloc(sizeof(double) * (size_t)n_sel * (S + 1) * V);
-    if (!tr) { free(Phi); free(Z); free_model(&m); return ORC_ENOMEM; }
+    if (!tr) { free(Phi); free(Z); if (has_event) free_post(&mp); free_model(&m); return ORC_ENOMEM; }
     int64_t nonfin = 0, notconv = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : nonfin, notconv)
     for (int64_t c = 0; c < n_sel; ++c) {
         double *o = tr + (size_t)c * (S + 1) * V;
-        int r = simulate_one(&m, Zuse ? Zuse + c : NULL, n_sel, Phi, pb->K, S, pb->dt,
-                             pb->integrator, o);
+        int r = simulate_one(&m, has_event ? &mp : NULL, s_event, Zuse ? Zuse + c : NULL, n_sel,
+                             Phi, pb->K, S, pb->dt, pb->integrator, o);
         if (r == ORC_ENOTCONV) notconv++;
         int bad = 0;
         for (int64_t q = 0; q < (S + 1) * V; ++q)
@@ -1008,6 +1059,7 @@ int orc_run(const orc_problem *pb, const double *zeta_in, int64_t n_sel, const i
     if (!traj) free(tr);
     free(Phi);
     free(Z);
+    if (has_event) free_post(&mp);
     free_model(&m);
     if (n_nonfinite) *n_nonfinite = nonfin;
     if (n_notconv) *n_notconv = notconv;
@@ -1047,6 +1099,19 @@ int orc_rhs(const orc_problem *pb, const double *y, const double *w, double *dy)
     model_t m;
     int rc = setup_model(pb, &m);
     if (rc == ORC_OK) rhs(&m, y, w, dy);
+    free_model(&m);
+    return rc;
+}
+
+/* Right-hand side of the post-event model at one state. */
+int orc_rhs_post(const orc_problem *pb, const double *y, const double *w, double *dy)
+{
+    model_t m, mp;
+    int rc = setup_model(pb, &m);
+    if (rc == ORC_OK && (rc = post_model(pb, &m, &mp)) == ORC_OK) {
+        rhs(&mp, y, w, dy);
+        free_post(&mp);
+    }
     free_model(&m);
     return rc;
 }
