@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define FMC_ABI_VERSION 2
+#define FMC_ABI_VERSION 3
 
 /* Status codes. */
 #define FMC_OK 0
@@ -119,6 +119,25 @@ typedef struct fmc_network {
     const double *gen_xdp;          /* [n_gen] transient reactance, pu */
 } fmc_network;
 
+/* A network event (the case study of Sec. V-B trips a generator at t = 1 s):
+ * from step t/dt on, the reduced admittance is the post-event one, and
+ * machine `tripped` (if >= 0) is disconnected: its internal node leaves the
+ * network and its mechanical power and the disturbances injected at it are
+ * removed (it keeps turning, d dw/dt = -D dw / 2H).  The post-event
+ * admittance is Y_re/Y_im when given (host [n*n]; with a tripped machine, its
+ * row and column must be zero, and so its entry of Yinf), else the system's
+ * network reduced without the tripped machine's internal node (a network
+ * system and tripped >= 0).  Yinf_re/Yinf_im: the post-event infinite-bus
+ * coupling (host [n]) or NULL (unchanged).  t must be a whole number of steps
+ * in (0, T).  fmc_run with the classical model only: the batched and served
+ * forms and the flux-decay model reject an event. */
+typedef struct fmc_event {
+    double t;
+    int32_t tripped;                 /* machine index, or -1 */
+    const double *Y_re, *Y_im;       /* [n_gen*n_gen] or NULL */
+    const double *Yinf_re, *Yinf_im; /* [n_gen] or NULL */
+} fmc_event;
+
 /* Machine data (eq. 1 instantiated as the swing equations
  *   d delta_i/dt = w_b dw_i,  2 H_i d dw_i/dt = Pm_i + sum_{p: gen[p]=i} xi_p
  *                                              - Pe_i - D_i dw_i,
@@ -140,6 +159,7 @@ typedef struct fmc_system {
     int32_t model;                /* FMC_CLASSICAL or FMC_FLUXDECAY_IEEET1 */
     const double *model_params;   /* [n_gen][FMC_FD_NPARAM] for the flux-decay
                                      model, NULL for the classical model */
+    const fmc_event *event;       /* a network event, or NULL */
 } fmc_system;
 
 /* One-axis (flux-decay) machine with an IEEE type-1 exciter, per machine, in
@@ -226,6 +246,15 @@ typedef struct fmc_outputs {
     double *zeta;
     int32_t mem_kind;
     fmc_report *report; /* host, optional */
+    /* A scalar random response function accumulated while integrating (eq. 3;
+     * Sec. V-B evaluates the RMS of the system frequency deviation): rrf [N]
+     * (mem_kind) receives for every sample sqrt((1/T) int_0^T u(t)^2 dt), the
+     * integral by the trapezoid rule on the output grid, of u = sum_v rrf_w[v]
+     * y_v(t) (rrf_w host [V]; y the outputs, absolute angles) -- what
+     * fmc_rrf_rms gives for the sample's trajectory, without storing it.
+     * NULL: none.  fmc_run with the classical model only. */
+    double *rrf;
+    const double *rrf_w;
 } fmc_outputs;
 
 typedef struct fmc_scenario {

@@ -39,7 +39,7 @@ CLASSICAL, FLUXDECAY_IEEET1 = 0, 1
 MODEL = {"classical": CLASSICAL, "fluxdecay": FLUXDECAY_IEEET1}
 FD_NPARAM = 9  # Xd, X'd, T'do, KA, TA, KE, TE, KF, TF
 MEM_HOST, MEM_DEVICE = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 _P = C.c_void_p
 
@@ -56,12 +56,18 @@ class Network(C.Structure):
                 ("load_g", _P), ("load_b", _P), ("gen_bus", _P), ("gen_xdp", _P)]
 
 
+class Event(C.Structure):
+    _fields_ = [("t", C.c_double), ("tripped", C.c_int32), ("Y_re", _P), ("Y_im", _P),
+                ("Yinf_re", _P), ("Yinf_im", _P)]
+
+
 class System(C.Structure):
     _fields_ = [("n_gen", C.c_int32), ("f0_hz", C.c_double),
                 ("H", _P), ("D", _P), ("E", _P), ("delta0", _P), ("Pm", _P),
                 ("Y_re", _P), ("Y_im", _P), ("net", C.POINTER(Network)),
                 ("infinite_bus", C.c_int32), ("V_inf", C.c_double),
-                ("Yinf_re", _P), ("Yinf_im", _P), ("model", C.c_int32), ("model_params", _P)]
+                ("Yinf_re", _P), ("Yinf_im", _P), ("model", C.c_int32), ("model_params", _P),
+                ("event", C.POINTER(Event))]
 
 
 class Disturbance(C.Structure):
@@ -91,7 +97,7 @@ class Report(C.Structure):
 class Outputs(C.Structure):
     _fields_ = [("mean", _P), ("var", _P), ("n_traj", C.c_int32), ("traj_idx", _P),
                 ("traj", _P), ("strata", _P), ("zeta", _P), ("mem_kind", C.c_int32),
-                ("report", C.POINTER(Report))]
+                ("report", C.POINTER(Report)), ("rrf", _P), ("rrf_w", _P)]
 
 
 class Scenario(C.Structure):
@@ -205,12 +211,28 @@ def scenario_structs(sc: dict, precision="f64", variant=-1, time_chunk=0, zeta_i
     mp = sc.get("model_params")
     a["model_params"] = (np.ascontiguousarray(mp, dtype=np.float64).reshape(n, -1)
                          if model == FLUXDECAY_IEEET1 and mp is not None else None)
+    ev_p = None
+    ev = sc.get("event")
+    if ev is not None:
+        e = {}
+        if ev.get("Y") is not None:
+            Ye = np.asarray(ev["Y"], dtype=np.complex128).reshape(n, n)
+            e["Y_re"], e["Y_im"] = _f64(Ye.real), _f64(Ye.imag)
+        if ev.get("Yinf") is not None:
+            Yi = np.asarray(ev["Yinf"], dtype=np.complex128).reshape(n)
+            e["Yinf_re"], e["Yinf_im"] = _f64(Yi.real), _f64(Yi.imag)
+        keep.append(e)
+        evs = Event(t=float(ev["t"]), tripped=int(ev.get("tripped", -1)),
+                    **{k: _ptr(v) for k, v in e.items()})
+        keep.append(evs)
+        ev_p = C.pointer(evs)
     keep.append(a)
     sysd = System(n_gen=n, f0_hz=float(sc.get("f0", 60.0)), H=_ptr(a["H"]), D=_ptr(a["D"]),
                   E=_ptr(a["E"]), delta0=_ptr(a["delta0"]), Pm=_ptr(a["Pm"]),
                   Y_re=_ptr(a["Y_re"]), Y_im=_ptr(a["Y_im"]), net=net_p, infinite_bus=int(inf),
                   V_inf=float(sc.get("V_inf", 1.0)), Yinf_re=_ptr(a["Yinf_re"]),
-                  Yinf_im=_ptr(a["Yinf_im"]), model=model, model_params=_ptr(a["model_params"]))
+                  Yinf_im=_ptr(a["Yinf_im"]), model=model, model_params=_ptr(a["model_params"]),
+                  event=ev_p)
     d = sc["dist"]
     sm = d.get("sigma_mat")
     b = dict(gen=_i32(d["gen"]), theta=_f64(d["theta"]), sigma=_f64(d["sigma"]),
@@ -355,8 +377,10 @@ class Context:
 
     # ------------------------------------------------------------ whole path
     def run(self, sc: dict, precision="f64", traj_idx=None, want_design=False, variant=-1,
-            time_chunk=0, zeta_in=None, outputs=None, allow_nonfinite=False):
-        """Alg. 1 on the GPU.  Returns dict(mean, var[, traj, strata, zeta], report)."""
+            time_chunk=0, zeta_in=None, outputs=None, allow_nonfinite=False, rrf_weights=None):
+        """Alg. 1 on the GPU.  Returns dict(mean, var[, traj, strata, zeta, rrf], report);
+        rrf_weights ([V]) asks for the RRF of every sample accumulated while
+        integrating (see fmc_outputs.rrf)."""
         t = self.torch
         n = int(sc["n_gen"]); P = len(sc["dist"]["gen"]); S = steps(sc)
         V = n_out(sc); M = P * int(sc["K"]); N = int(sc["N"])
@@ -378,14 +402,22 @@ class Context:
             strata = t.empty((M, N), dtype=t.int32, device=self.device)
             zeta = t.empty((M, N), dtype=t.float64, device=self.device)
         rep = Report()
+        rrf = rrf_w = None
+        if rrf_weights is not None:
+            rrf_w = np.ascontiguousarray(rrf_weights, dtype=np.float64).reshape(V)
+            keep.append(rrf_w)
+            rrf = t.empty(N, dtype=t.float64, device=self.device)
         out = Outputs(mean=_dptr(mean), var=_dptr(var), n_traj=0 if idx is None else len(idx),
                       traj_idx=_ptr(idx), traj=_dptr(traj), strata=_dptr(strata),
-                      zeta=_dptr(zeta), mem_kind=MEM_DEVICE, report=C.pointer(rep))
+                      zeta=_dptr(zeta), mem_kind=MEM_DEVICE, report=C.pointer(rep),
+                      rrf=_dptr(rrf), rrf_w=_ptr(rrf_w))
         rc = _lib.fmc_run(self._h, C.byref(sysd), C.byref(dist), C.byref(par), C.byref(out))
         _check(rc, allow=(ENONFINITE,) if allow_nonfinite else ())
         r = dict(mean=mean, var=var, report=rep.as_dict(), rc=rc)
         if traj is not None:
             r["traj"] = traj
+        if rrf is not None:
+            r["rrf"] = rrf
         if want_design:
             r["strata"] = strata
             r["zeta"] = zeta

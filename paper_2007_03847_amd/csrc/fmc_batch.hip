@@ -192,6 +192,10 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     if (p.par->sampler == FMC_LHS_DECOR)
       return fail(FMC_EINVAL, "scenario " + std::to_string(i) +
                                   ": FMC_LHS_DECOR runs through fmc_run only");
+    if (p.sys->event)
+      return fail(FMC_EINVAL, "scenario " + std::to_string(i) + ": network events run through fmc_run only");
+    if (p.out->rrf)
+      return fail(FMC_EINVAL, "scenario " + std::to_string(i) + ": the fused RRF runs through fmc_run only");
     if (p.par->integrator != FMC_RK4)
       return fail(FMC_EINVAL, "scenario " + std::to_string(i) +
                                   ": the implicit trapezoid runs through fmc_run only");
@@ -436,6 +440,7 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
       a.dt = (float)p.par->dt;
       a.wb = (float)(2.0 * M_PI * (s->f0_hz > 0.0 ? s->f0_hz : 60.0));
       a.recenter = s->infinite_bus ? 0 : 1;
+      a.n_ref = p.n;
     }
   }
   const IntegArgs<float>* args_d = nullptr;

@@ -85,6 +85,17 @@ struct IntegArgs {
   // offset is kept in two state rows after the variant's own rows (the bits
   // of the double).
   int recenter;
+  int n_ref;  // machines in service (their mean angle is the reference; a
+              // tripped machine, whose EMF the post-event coefficients zero, is not)
+  // A scalar RRF accumulated in the epilogue (eq. 3; Sec. V-B's RMS of the
+  // system frequency deviation): with rrf_w set, each trajectory sums
+  // h_s u(t_s)^2 over its output steps in step order, u = sum_v rrf_w[v] y_v
+  // with y the outputs (absolute angles), h_s = 1/2 at s = 0 and s = S and 1
+  // otherwise; rrf_acc keeps the sums between chunks and the last chunk writes
+  // rrf[n] = sqrt(sum / S), the RMS over the horizon by the trapezoid rule.
+  const double* rrf_w;  // [V] or null
+  double* rrf_acc;      // [N]
+  double* rrf;          // [N]
 };
 // State rows of the per-trajectory common-angle offset: the two 32-bit
 // halves of the FP64 offset and, in the flux-decay state, the mean angle
@@ -151,6 +162,13 @@ struct SetupDev {
   int* status;                // 0 ok, -6 Newton failure
 };
 hipError_t launch_setup(const SetupDev& s, hipStream_t st);
+// Coefficients after a network event (CanonLayout): the operating point of
+// `pre` with the post-event admittance Yp ([n*n]) and infinite-bus coupling
+// Yinf ([n] or null) at V_inf; a tripped machine (>= 0) gets no EMF, current,
+// mechanical power or residual.
+hipError_t launch_setup_post(const double* pre, int n, int P, const double2* Yp,
+                             const double2* Yinf, double V_inf, int tripped, double* post,
+                             hipStream_t st);
 
 template <typename R>
 hipError_t launch_pack(const double* canon, int n, int P, const int32_t* gen, int NG, int PM,

@@ -53,8 +53,9 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
                double wb, const double* zeta, const double* phi, const R* coef,
                const double* delta0, double* partial, const int32_t* slot_d, double* traj_d,
                unsigned long long* cnt_d, int64_t Sc, double* mean_d, double* var_d,
-               int recenter, bool trap, const void* const* s16, EventPool& evp,
-               ChunkTimes& ct) {
+               int recenter, bool trap, const void* const* s16, const R* coef_post,
+               int64_t s_event, int n_ref_post, const double* rrf_w, double* rrf_acc,
+               double* rrf_d, EventPool& evp, ChunkTimes& ct) {
   const VariantInfo& vi = variant(vid);
   const int V = 2 * n + P;
   const int64_t C = 2 * S + 1;
@@ -103,9 +104,18 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
   a.dt = (R)par->dt;
   a.wb = (R)wb;
   a.recenter = recenter;
-  int64_t k = 0;
-  for (int64_t s0 = 0; s0 < S; s0 += Sc, ++k) {
-    const int64_t s1 = std::min<int64_t>(S, s0 + Sc);
+  a.rrf_w = rrf_w;
+  a.rrf_acc = rrf_acc;
+  a.rrf = rrf_d;
+  // With a network event, a chunk ends at the event step and the chunks from
+  // there on run with the post-event coefficients.
+  int64_t k = 0, prev0 = 0, last0 = 0;
+  for (int64_t s0 = 0, s1 = 0; s0 < S; s0 = s1, ++k) {
+    s1 = std::min<int64_t>(S, s0 + Sc);
+    if (coef_post && s0 < s_event && s1 > s_event) s1 = s_event;
+    const bool post = coef_post && s0 >= s_event;
+    a.coef = post ? coef_post : coef;
+    a.n_ref = post ? n_ref_post : n;
     const int64_t Cc = 2 * (s1 - s0) + 1;
     const int b = (int)(k & 1);
     hipError_t e = hipSuccess;
@@ -124,10 +134,11 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
     if (hipEventRecord(c->gev[b], ks) != hipSuccess || hipStreamWaitEvent(c->stream, c->gev[b], 0) != hipSuccess)
       return fail(FMC_EDEVICE, "stream ordering failed");
     if (k >= 1) {  // chunk k-1's rows, after its integrator (queued behind the contraction)
-      const int64_t p0 = s0 - Sc;
-      if (hipStreamWaitEvent(ks, c->gev[2 + (1 - b)], 0) != hipSuccess || merge(p0, s0) != hipSuccess)
+      if (hipStreamWaitEvent(ks, c->gev[2 + (1 - b)], 0) != hipSuccess || merge(prev0, s0) != hipSuccess)
         return fail(FMC_EDEVICE, "statistics merge launch failed");
     }
+    prev0 = s0;
+    last0 = s0;
     a.w = (const R*)w[b];
     a.s_begin = s0;
     a.s_end = s1;
@@ -145,7 +156,6 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
       return fail(FMC_EDEVICE, "stream ordering failed");
   }
   // the last chunk's rows, then the main stream waits for every merge
-  const int64_t last0 = (k - 1) * Sc;
   if (hipStreamWaitEvent(ks, c->gev[2 + (int)((k - 1) & 1)], 0) != hipSuccess)
     return fail(FMC_EDEVICE, "stream ordering failed");
   ct.st0 = evp.record(ks);
@@ -190,7 +200,10 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   // a diffusion matrix is carried by the mixed design; the integrator sees sigma = 1
   UnitSigma unit_sigma;
   dist = unit_sigma.apply(dist);
-  if (sys->model == FMC_FLUXDECAY_IEEET1) return run_fd(c, sys, dist, par, out, S);
+  if (sys->model == FMC_FLUXDECAY_IEEET1) {
+    if (out->rrf) return fail(FMC_EINVAL, "the fused RRF runs with the classical model");
+    return run_fd(c, sys, dist, par, out, S);
+  }
   const int n = sys->n_gen, P = dist->n_proc, K = par->K;
   const int64_t N = par->N, M = (int64_t)P * K, C = 2 * S + 1;
   const int V = 2 * n + P;
@@ -242,6 +255,56 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   if ((rc = c->ensure("coef", (size_t)PL.size() * bw, &coef))) return rc;
   HIPCHK(f64 ? launch_pack<double>(canon, n, P, gen_d, vi.NG, vi.PM, (double*)coef, c->stream)
              : launch_pack<float>(canon, n, P, gen_d, vi.NG, vi.PM, (float*)coef, c->stream));
+
+  // A network event: the post-event admittance (given, or the network reduced
+  // with the tripped machine's internal node cut off by an infinite X'd), the
+  // coefficients of the same operating point on it, and the processes at a
+  // tripped machine injecting nowhere.
+  void* coef_post = nullptr;
+  int64_t s_event = 0;
+  int n_ref_post = n;
+  if (const fmc_event* ev = sys->event) {
+    s_event = (int64_t)std::llround(ev->t / par->dt);
+    const int g = ev->tripped;
+    Stager sg;
+    std::vector<double2> Yph, Yinfh;
+    const double2 *Yp_d = nullptr, *Yinf_d = nullptr;
+    if (ev->Y_re) {
+      Yph.resize((size_t)n * n);
+      for (size_t q = 0; q < Yph.size(); ++q) Yph[q] = make_double2(ev->Y_re[q], ev->Y_im[q]);
+      sg.add(Yph.data(), Yph.size(), &Yp_d);
+    }
+    if (sys->infinite_bus) {
+      const double *yr = ev->Yinf_re ? ev->Yinf_re : sys->Yinf_re;
+      const double *yi = ev->Yinf_re ? ev->Yinf_im : sys->Yinf_im;
+      Yinfh.resize(n);
+      for (int i = 0; i < n; ++i) Yinfh[i] = make_double2(yr[i], yi[i]);
+      sg.add(Yinfh.data(), Yinfh.size(), &Yinf_d);
+    }
+    std::vector<int32_t> genp(dist->gen, dist->gen + P);
+    for (auto& q : genp)
+      if (q == g) q = -1;
+    const int32_t* genp_d = nullptr;
+    sg.add(genp.data(), genp.size(), &genp_d);
+    if ((rc = sg.upload(c, "stage_event"))) return rc;
+    if (!ev->Y_re) {
+      std::vector<double> xdp(sys->net->gen_xdp, sys->net->gen_xdp + n);
+      xdp[g] = INFINITY;  // 1/(j X'd) = 0: the internal node is cut off
+      fmc_network np = *sys->net;
+      np.gen_xdp = xdp.data();
+      void* yb = nullptr;
+      if ((rc = c->ensure("yred_post", (size_t)n * n * sizeof(double2), &yb))) return rc;
+      if ((rc = kron_on_device(c, &np, (double2*)yb, status_d + 3, "net_post"))) return rc;
+      Yp_d = (const double2*)yb;
+    }
+    void* cp = nullptr;
+    if ((rc = c->ensure("canon_post", (size_t)CL.size() * sizeof(double), &cp))) return rc;
+    HIPCHK(launch_setup_post(canon, n, P, Yp_d, Yinf_d, sys->V_inf, g, (double*)cp, c->stream));
+    if ((rc = c->ensure("coef_post", (size_t)PL.size() * bw, &coef_post))) return rc;
+    HIPCHK(f64 ? launch_pack<double>((const double*)cp, n, P, genp_d, vi.NG, vi.PM, (double*)coef_post, c->stream)
+               : launch_pack<float>((const double*)cp, n, P, genp_d, vi.NG, vi.PM, (float*)coef_post, c->stream));
+    n_ref_post = n - (g >= 0 ? 1 : 0);
+  }
 
   void* phi = nullptr;
   if ((rc = c->ensure("phi", (size_t)K * C * sizeof(double), &phi))) return rc;
@@ -342,6 +405,26 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     }
   }
 
+  // the RRF accumulated in the integrators' epilogue
+  const double* rrf_wd = nullptr;
+  double *rrf_acc = nullptr, *rrf_dev = nullptr;
+  if (out->rrf) {
+    if (!out->rrf_w) return fail(FMC_EINVAL, "rrf needs rrf_w");
+    void *p = nullptr, *h = nullptr;
+    if ((rc = c->ensure("rrf_w", (size_t)V * sizeof(double), &p))) return rc;
+    if ((rc = c->host_stage("rrf_w", (size_t)V * sizeof(double), &h))) return rc;
+    std::memcpy(h, out->rrf_w, (size_t)V * sizeof(double));
+    HIPCHK(hipMemcpyAsync(p, h, (size_t)V * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    rrf_wd = (const double*)p;
+    if ((rc = c->ensure("rrf_acc", (size_t)N * sizeof(double), &p))) return rc;
+    rrf_acc = (double*)p;
+    if (dev_out) {
+      rrf_dev = out->rrf;
+    } else {
+      if ((rc = c->ensure("rrf_out", (size_t)N * sizeof(double), &p))) return rc;
+      rrf_dev = (double*)p;
+    }
+  }
   const int64_t Sc = par->time_chunk > 0 ? std::min<int64_t>(par->time_chunk, S)
                                          : auto_chunk(S, P, N, bw);
   double *mean_d = out->mean, *var_d = out->var;
@@ -356,11 +439,15 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   if (f64)
     rc = run_chunks<double>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
                             (const double*)coef, delta0_d, (double*)partial, slot_d, traj_d,
-                            (unsigned long long*)cnt, Sc, mean_d, var_d, sys->infinite_bus ? 0 : 1, trap, s16, evp, ct);
+                            (unsigned long long*)cnt, Sc, mean_d, var_d, sys->infinite_bus ? 0 : 1, trap, s16,
+                            (const double*)coef_post, s_event, n_ref_post, rrf_wd, rrf_acc,
+                            rrf_dev, evp, ct);
   else
     rc = run_chunks<float>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
                            (const float*)coef, delta0_d, (double*)partial, slot_d, traj_d,
-                           (unsigned long long*)cnt, Sc, mean_d, var_d, sys->infinite_bus ? 0 : 1, trap, s16, evp, ct);
+                           (unsigned long long*)cnt, Sc, mean_d, var_d, sys->infinite_bus ? 0 : 1, trap, s16,
+                           (const float*)coef_post, s_event, n_ref_post, rrf_wd, rrf_acc,
+                           rrf_dev, evp, ct);
   if (rc) return rc;
   // statistics: merged per chunk on the second stream, joined into c->stream
   const int ev_end = evp.record();
@@ -371,6 +458,8 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
     HIPCHK(hipMemcpyAsync(out->var, var_d, sv, hipMemcpyDeviceToHost, c->stream));
     if (traj_d)
       HIPCHK(hipMemcpyAsync(out->traj, traj_d, (size_t)out->n_traj * sv, hipMemcpyDeviceToHost, c->stream));
+    if (rrf_dev)
+      HIPCHK(hipMemcpyAsync(out->rrf, rrf_dev, (size_t)N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (out->zeta && zeta_dev)
       HIPCHK(hipMemcpyAsync(out->zeta, zeta_dev, (size_t)M * N * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (out->strata && strata_dev)
@@ -378,16 +467,20 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   }
   void* hb = nullptr;
   if ((rc = c->host_stage("readback", 64, &hb))) return rc;
+  // status: [0] operating point, [1] reduction, [3] post-event reduction
+  // (from the device), [4] correlation reduction of the design
   int* status = (int*)hb;
-  unsigned long long* cn = (unsigned long long*)((char*)hb + 16);
-  HIPCHK(hipMemcpyAsync(status, status_d, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  unsigned long long* cn = (unsigned long long*)((char*)hb + 32);
+  status[4] = 0;
+  HIPCHK(hipMemcpyAsync(status, status_d, 4 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipMemcpyAsync(cn, cnt, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
-  status[2] = 0;
   if (dc_status)
-    HIPCHK(hipMemcpyAsync(status + 2, dc_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(status + 4, dc_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   if (status[1] != 0) return fail(FMC_EINVAL, "network reduction failed (singular Y_BB)");
-  if (status[2] != 0)
+  if (sys->event && status[3] != 0)
+    return fail(FMC_EINVAL, "post-event network reduction failed (singular Y_BB)");
+  if (status[4] != 0)
     return fail(FMC_EINVAL, "the design's sample covariance is not positive definite");
   if (status[0] != 0) return fail(FMC_ENOTCONV, "operating-point Newton solve did not converge");
 

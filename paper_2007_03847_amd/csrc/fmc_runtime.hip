@@ -217,7 +217,7 @@ static int check_network(const fmc_network* net) {
 }
 
 // Reduce a network on the device into Yd (double2 [n_gen^2]); status to *st_dev.
-int kron_on_device(Context* c, const fmc_network* net, double2* Yd, int* st_dev) {
+int kron_on_device(Context* c, const fmc_network* net, double2* Yd, int* st_dev, const char* tag) {
   int rc = check_network(net);
   if (rc) return rc;
   Stager sg;
@@ -234,7 +234,7 @@ int kron_on_device(Context* c, const fmc_network* net, double2* Yd, int* st_dev)
   sg.add(net->load_b, net->n_bus, &nd.lb);
   sg.add(net->gen_bus, net->n_gen, &nd.gen_bus);
   sg.add(net->gen_xdp, net->n_gen, &nd.xdp);
-  if ((rc = sg.upload(c, "net"))) return rc;
+  if ((rc = sg.upload(c, tag))) return rc;
   void* work = nullptr;
   const size_t wbytes = kron_work_bytes(net->n_bus, net->n_gen);
   if ((rc = c->ensure("kron_work", wbytes, &work))) return rc;
@@ -297,6 +297,30 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
       if (!(q[kFdXdp] > 0.0) || !(q[kFdTdo] > 0.0) || !(q[kFdTa] > 0.0) || !(q[kFdTe] > 0.0) ||
           !(q[kFdTf] > 0.0) || q[kFdKa] < 0.0)
         return fail(FMC_EINVAL, "flux-decay parameters: X'd, T'do, TA, TE, TF > 0 and KA >= 0");
+    }
+  }
+  if (sys->event) {
+    const fmc_event* ev = sys->event;
+    if (sys->model != FMC_CLASSICAL)
+      return fail(FMC_EINVAL, "network events run with the classical model");
+    const int64_t se = (int64_t)std::llround(ev->t / par->dt);
+    if (!(ev->t > 0.0) || se < 1 || se >= S || std::fabs((double)se * par->dt - ev->t) > 1e-9 * par->T)
+      return fail(FMC_EINVAL, "the event time must be a whole number of steps in (0, T)");
+    if (ev->tripped < -1 || ev->tripped >= n) return fail(FMC_EINVAL, "tripped machine out of range");
+    if (!ev->Y_re != !ev->Y_im || !ev->Yinf_re != !ev->Yinf_im)
+      return fail(FMC_EINVAL, "event admittances need both real and imaginary parts");
+    if (ev->Yinf_re && !sys->infinite_bus)
+      return fail(FMC_EINVAL, "a post-event infinite-bus coupling needs an infinite-bus system");
+    if (!ev->Y_re && (ev->tripped < 0 || sys->Y_re || !sys->net))
+      return fail(FMC_EINVAL, "an event needs its admittance, or a tripped machine of a network system");
+    if (ev->Y_re && ev->tripped >= 0) {
+      const int g = ev->tripped;
+      for (int k = 0; k < n; ++k)
+        if (ev->Y_re[g * n + k] != 0.0 || ev->Y_im[g * n + k] != 0.0 || ev->Y_re[k * n + g] != 0.0 ||
+            ev->Y_im[k * n + g] != 0.0)
+          return fail(FMC_EINVAL, "the tripped machine's row and column of the event admittance must be zero");
+      if (ev->Yinf_re && (ev->Yinf_re[g] != 0.0 || ev->Yinf_im[g] != 0.0))
+        return fail(FMC_EINVAL, "the tripped machine's infinite-bus coupling must be zero");
     }
   }
   if (!sys->H || !sys->D || !sys->E) return fail(FMC_EINVAL, "H, D and E are required");

@@ -74,7 +74,10 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
              int64_t* S_out);
 int stage_scenario(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
                    const char* tag, double** canon_out, int32_t** gen_out, int** status_out);
-int kron_on_device(Context* c, const fmc_network* net, double2* Yd, int* st_dev);
+// Kron reduction on the context's stream; the network's arrays are staged
+// under `tag` (a tag per network that may be in flight at the same time).
+int kron_on_device(Context* c, const fmc_network* net, double2* Yd, int* st_dev,
+                   const char* tag = "net");
 int choose_variant(int n, int P, int64_t N);
 std::string tune_key(int n, int P, int64_t N, int precision);
 int pick_variant(Context* c, int n, int P, int64_t N, int precision);

@@ -448,6 +448,7 @@ int run_tick(ServeState* ss, const std::vector<ReqP>& fresh, const std::vector<R
     a.dt = (float)r.par.dt;
     a.wb = (float)(2.0 * M_PI * r.f0);
     a.recenter = r.inf_bus ? 0 : 1;
+    a.n_ref = r.n;
     const double frac = (double)(s1 - s0) / (double)r.S;
     for (int64_t k = 0; k < r.n_items; ++k) {
       BatchItem it;
@@ -764,10 +765,13 @@ int fmc_submit(fmc_context* ctx, const fmc_scenario* scen, fmc_outputs* out, uin
   if (scen->par->sampler == FMC_LHS_DECOR)
     return fail(FMC_EINVAL, "FMC_LHS_DECOR runs through fmc_run only");
   if (scen->dist->sigma_mat) return fail(FMC_EINVAL, "a diffusion matrix runs through fmc_run only");
+  if (scen->sys->event) return fail(FMC_EINVAL, "network events run through fmc_run only");
+  if (scen->par->integrator != FMC_RK4)
+    return fail(FMC_EINVAL, "the implicit trapezoid runs through fmc_run only");
   if (!out->mean || !out->var) return fail(FMC_EINVAL, "mean and var outputs are required");
   if (out->mem_kind != FMC_MEM_HOST && out->mem_kind != FMC_MEM_DEVICE)
     return fail(FMC_EINVAL, "unknown mem_kind");
-  if (out->n_traj != 0 || out->strata || out->zeta)
+  if (out->n_traj != 0 || out->strata || out->zeta || out->rrf)
     return fail(FMC_EINVAL, "served requests return mean and var only");
   auto r = std::make_shared<Request>();
   if ((rc = plan_request(*r, scen->sys, scen->dist, scen->par, S))) return rc;

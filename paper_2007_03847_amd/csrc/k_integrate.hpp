@@ -155,6 +155,25 @@ __device__ __forceinline__ void swing_rhs(const R* cfg, const R wb, const R (&yd
   for (int p = 0; p < PM; ++p) kx[p] = -cf[L.theta() + p] * yx[p] + cf[L.sigma() + p] * wv[p];
 }
 
+// u = sum_v w_v y_v of one trajectory held whole by one lane (absolute angles
+// as the outputs store them), FP64.
+template <typename R, int NG, int PM>
+__device__ __forceinline__ double rrf_u_lane(const IntegArgs<R>& a, double coff, const R (&yd)[NG],
+                                             const R (&yw)[NG], const R (&yx)[PM]) {
+  const int n = a.n, P = a.P;
+  double u = 0.0;  // in output order: angles, speed deviations, processes
+#pragma unroll
+  for (int i = 0; i < NG; ++i)
+    if (i < n) u += a.rrf_w[i] * (a.delta0[i] + (coff + (double)yd[i]));
+#pragma unroll
+  for (int i = 0; i < NG; ++i)
+    if (i < n) u += a.rrf_w[n + i] * (double)yw[i];
+#pragma unroll
+  for (int p = 0; p < PM; ++p)
+    if (p < P) u += a.rrf_w[2 * n + p] * (double)yx[p];
+  return u;
+}
+
 // Per-wave two-pass statistics of one output time through an LDS transpose:
 // lane v of the wave reduces variable v over the wave's valid trajectories.
 template <typename R, int NG, int PM>
@@ -222,6 +241,7 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
 
   R yd[NG], yw[NG], yx[PM];
   double coff = 0.0;  // common-angle offset of the trajectory (see IntegArgs::recenter)
+  double racc = 0.0;  // the epilogue's RRF sum (see IntegArgs::rrf_w)
   if (a.s_begin == 0) {
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
@@ -231,7 +251,12 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
 #pragma unroll
     for (int p = 0; p < PM; ++p) yx[p] = cf[L.xi0() + p];
     emit_step<R, NG, PM>(a, tile, lane, cnt, 0, slot, coff, yd, yw, yx);
+    if (a.rrf_w) {
+      const double u = rrf_u_lane<R, NG, PM>(a, coff, yd, yw, yx);
+      racc = 0.5 * u * u;
+    }
   } else {
+    if (a.rrf_w) racc = a.rrf_acc[ns];
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
       yd[i] = a.state[(int64_t)i * a.lanes + gidx];
@@ -244,7 +269,7 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
   }
 
   const R dt = a.dt, h2 = a.dt * R(0.5), dt6 = a.dt / R(6), wb = a.wb;
-  const R inv_n = R(1) / (R)a.n;
+  const R inv_n = R(1) / (R)a.n_ref;
   // KLE path values of the next step are loaded one step ahead.
   R w0[PM], w1[PM], w2[PM];
 #pragma unroll
@@ -307,17 +332,25 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
       w1[p] = n1[p];
       w2[p] = n2[p];
     }
-    if (a.recenter) {  // move the mean angle of the machines into the offset
+    if (a.recenter) {  // move the mean angle of the machines in service into the offset
       R sum = R(0);
 #pragma unroll
       for (int i = 0; i < NG; ++i)
-        if (i < a.n) sum += yd[i];
+        if (i < a.n && (cf[L.c0() + i] != R(0) || cf[L.s0() + i] != R(0))) sum += yd[i];
       const R ref = sum * inv_n;
       coff += (double)ref;
 #pragma unroll
       for (int i = 0; i < NG; ++i) yd[i] -= ref;
     }
     emit_step<R, NG, PM>(a, tile, lane, cnt, s + 1, slot, coff, yd, yw, yx);
+    if (a.rrf_w) {
+      const double u = rrf_u_lane<R, NG, PM>(a, coff, yd, yw, yx);
+      racc += (s + 1 == a.S ? 0.5 : 1.0) * u * u;
+    }
+  }
+  if (a.rrf_w && valid) {
+    a.rrf_acc[gidx] = racc;
+    if (a.s_end == a.S) a.rrf[gidx] = sqrt(racc / (double)a.S);
   }
 
 #pragma unroll
@@ -531,6 +564,9 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
     for (int r = 0; r < PQ; ++r) kx[r] = -theta[r] * yx[r] + sigma[r] * wv[r];
   };
 
+  // RRF sum of trajectory tid of this tile (threads tid < TB; see IntegArgs::rrf_w)
+  double racc = 0.0;
+  if (a.rrf_w && a.s_begin > 0 && tid < cnt) racc = a.rrf_acc[tile * TB + tid];
   // Reduce the buffered steps [s_first, s_first + nb): thread q of the
   // workgroup takes rows (step, variable) q, q + 64 WPB, ...
   auto flush = [&](int64_t s_first, int nb) {
@@ -554,6 +590,18 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
         const double na = (double)st.prev, nb2 = (double)cnt, tot = na + nb2;
         const double dl = mu - old.x;
         *dst = make_double2(old.x + dl * (nb2 / tot), old.y + m2 + dl * dl * (na * nb2 / tot));
+      }
+    }
+    // the epilogue's RRF: thread j sums trajectory j's buffered steps in order
+    if (a.rrf_w && tid < cnt) {
+      for (int b = 0; b < nb; ++b) {
+        const int64_t s = s_first + b;
+        double u = 0.0;
+        for (int v = 0; v < V; ++v) {
+          const double y = tile_buf[b][v][tid];
+          u += a.rrf_w[v] * (v < n ? a.delta0[v] + y : y);
+        }
+        racc += (s == 0 || s == a.S ? 0.5 : 1.0) * u * u;
       }
     }
     __syncthreads();
@@ -617,7 +665,7 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
   }
 
   const R dt = a.dt, h2 = a.dt * R(0.5), dt6 = a.dt / R(6);
-  const R inv_n = R(1) / (R)n;
+  const R inv_n = R(1) / (R)a.n_ref;
   const int64_t colstride = (int64_t)P * N;
   // KLE path values of my processes: the two new stage columns of step s are
   // loaded one step ahead so their latency overlaps the previous step.
@@ -676,14 +724,15 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
       w2[r] = n2[r];
     }
     if (a.recenter) {
-      // the mean angle of the trajectory's machines: each lane's sum over its
-      // machines through the exchange row (free again: the last stage's
-      // reads ended with a wave fence), added in lane order by every lane of
-      // the trajectory (the same bits in each), then taken out of every angle
+      // the mean angle of the trajectory's machines in service (a tripped
+      // machine has no EMF): each lane's sum over its machines through the
+      // exchange row (free again: the last stage's reads ended with a wave
+      // fence), added in lane order by every lane of the trajectory (the same
+      // bits in each), then taken out of every angle
       R part = R(0);
 #pragma unroll
       for (int q = 0; q < G; ++q)
-        if (g * G + q < n) part += yd[q];
+        if (g * G + q < n && (c0[q] != R(0) || s0[q] != R(0))) part += yd[q];
       xch[tl][g] = R2{part, R(0)};
       wave_lds_sync();
       R sum = R(0);
@@ -698,6 +747,10 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
   }
 
   if (nbuf > 0) flush(s_first, nbuf);  // nbuf is uniform over the workgroup
+  if (a.rrf_w && tid < cnt) {
+    a.rrf_acc[tile * TB + tid] = racc;
+    if (a.s_end == a.S) a.rrf[tile * TB + tid] = sqrt(racc / (double)a.S);
+  }
 
   if (keep_state) {
 #pragma unroll
@@ -730,8 +783,15 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
   }
 }
 
+// At least two waves per SIMD (at most 256 registers per lane, VGPRs and
+// AGPRs together): left to itself the compiler spends all 256 VGPRs plus a
+// few AGPRs on the larger variants and drops them to one wave per SIMD.
+#ifndef FMC_GROUP_MIN_WAVES
+#define FMC_GROUP_MIN_WAVES 2
+#endif
 template <typename R, int NG, int PM, int L, int WPB>
-__global__ void __launch_bounds__(64 * WPB) k_rk4_group(IntegArgs<R> a) {
+__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(FMC_GROUP_MIN_WAVES)))
+k_rk4_group(IntegArgs<R> a) {
   constexpr int D = WPB == 1 ? 4 : 8;
   using Sh = GroupShape<R, NG, PM, L, WPB, D>;
   __shared__ __attribute__((aligned(16))) unsigned char lds[Sh::lds_bytes];

@@ -125,17 +125,17 @@ hipError_t launch_basis(int32_t kind, int32_t K, int64_t S, double T, double* ph
 // Each wave owns a 32 (c) x 64 (n) output tile: 2 x 4 blocks of 16 x 16 in
 // eight accumulators, so every k-step of four loads 2 + 4 operand fragments
 // for 8 matrix operations; the fragments of the next k-step are loaded while
-// the current one's operations run.  A workgroup's four waves lie along n
-// (a 32 x 256 tile: the waves share their A fragments in L1).  Operands come
-// straight from L1/L2: Phi is a few hundred KB shared by every workgroup and
-// the rows of zeta a tile touches are reused by the C/32 tiles of its n
-// range.
+// the current one's operations run.  A workgroup's four waves lie along c (a
+// 128 x 64 tile): they read the same zeta fragments, which the first brings
+// into L1 for the others, so the design (tens to hundreds of MB, beyond the
+// L2) is streamed C/128 times per chunk; Phi (a few hundred KB shared by
+// every workgroup) stays in L2.
 // ---------------------------------------------------------------------------
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-constexpr int kKleTC = 32, kKleTN = 256;  // workgroup tile (c, n)
+constexpr int kKleTC = 128, kKleTN = 64;  // workgroup tile (c, n): four waves along c
 
 template <typename OutT>
 __device__ __forceinline__ void kle_f64_tile(const double* __restrict__ zeta,
@@ -143,9 +143,9 @@ __device__ __forceinline__ void kle_f64_tile(const double* __restrict__ zeta,
                                              int P, int K, int64_t N, int64_t C, int64_t c0,
                                              OutT* __restrict__ w, int64_t bx, int64_t by, int p) {
   const int lane = threadIdx.x & 63;
-  const int64_t cb = by * kKleTC;
-  const int64_t n0 = bx * kKleTN + (threadIdx.x >> 6) * 64;
-  if (n0 >= N) return;  // uniform per wave
+  const int64_t cb = by * kKleTC + (threadIdx.x >> 6) * 32;
+  const int64_t n0 = bx * kKleTN;
+  if (cb >= C) return;  // uniform per wave
   const int li = lane & 15, lk = lane >> 4;
   const double* __restrict__ zp = zeta + (int64_t)p * K * N;
   d4_t acc[2][4];
@@ -205,6 +205,17 @@ __device__ __forceinline__ void kle_f64_tile(const double* __restrict__ zeta,
     }
 }
 
+// Tile order of a launch with one workgroup per tile.  Workgroups are
+// dealt to the eight XCDs in turn (block b to XCD b mod 8), each XCD with an
+// L2 of its own, so block b takes tile number L(b) from a contiguous range
+// per XCD; in that order the c-tiles of one (n-tile, process) are adjacent,
+// so the workgroups that stream the same coefficient rows run on one XCD and
+// share its L2.  Tile number L = ((p tx) + bx) ty + by.
+__device__ __forceinline__ int64_t kle_xcd_tile(int64_t b, int64_t n_tiles) {
+  const int64_t q = n_tiles / 8, r = n_tiles % 8, k = b % 8, j = b / 8;
+  return k < r ? k * (q + 1) + j : r * (q + 1) + (k - r) * q + j;
+}
+
 // The grid is a flat list of blocks striding over the (n, c, p) tiles, so a
 // launch can use fewer workgroups than tiles (to run beside another kernel).
 template <typename OutT>
@@ -214,9 +225,11 @@ __global__ void __launch_bounds__(256) k_kle_f64(const double* __restrict__ zeta
                                                  OutT* __restrict__ w) {
   const int64_t tx = (N + kKleTN - 1) / kKleTN, ty = (C + kKleTC - 1) / kKleTC;
   const int64_t n_tiles = tx * ty * P;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
-    kle_f64_tile<OutT>(zeta, phi, phi_ld, P, K, N, C, c0, w, tile % tx, (tile / tx) % ty,
-                       (int)(tile / (tx * ty)));
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t L = gridDim.x == n_tiles ? kle_xcd_tile(tile, n_tiles) : tile;
+    kle_f64_tile<OutT>(zeta, phi, phi_ld, P, K, N, C, c0, w, (L / ty) % tx, L % ty,
+                       (int)(L / (tx * ty)));
+  }
 }
 template <typename OutT>
 static hipError_t launch_kle_f64_t(const double* zeta, const double* phi, int64_t phi_ld, int P,
@@ -396,7 +409,7 @@ hipError_t launch_split_bf16(const double* X, int64_t ld, int K, int64_t items, 
 // v_mfma_f32_16x16x32_bf16.  Each wave owns a 32 (c) x 64 (n) output tile (2 x
 // 4 blocks, eight accumulators); a k-step of 32 loads 4 + 8 fragments of 16
 // bytes for 24 matrix operations, and the next k-step's fragments are loaded
-// while they run.  Four waves per workgroup along n.
+// while they run.  Four waves per workgroup along c, as for FP64.
 __device__ __forceinline__ void kle_bf16s_tile(const __bf16* __restrict__ ph,
                                                const __bf16* __restrict__ pl, int Kp,
                                                const __bf16* __restrict__ zh,
@@ -404,9 +417,9 @@ __device__ __forceinline__ void kle_bf16s_tile(const __bf16* __restrict__ ph,
                                                int64_t C, int64_t c0, float* __restrict__ w,
                                                int64_t bx, int64_t by, int p) {
   const int lane = threadIdx.x & 63;
-  const int64_t cb = by * kKleTC;
-  const int64_t n0 = bx * kKleTN + (threadIdx.x >> 6) * 64;
-  if (n0 >= N) return;  // uniform per wave
+  const int64_t cb = by * kKleTC + (threadIdx.x >> 6) * 32;
+  const int64_t n0 = bx * kKleTN;
+  if (cb >= C) return;  // uniform per wave
   const int li = lane & 15, ko = 8 * (lane >> 4);
   f4_t acc[2][4];
 #pragma unroll
@@ -483,9 +496,11 @@ __global__ void __launch_bounds__(256) k_kle_bf16x3s(const __bf16* __restrict__ 
                                                      float* __restrict__ w) {
   const int64_t tx = (N + kKleTN - 1) / kKleTN, ty = (C + kKleTC - 1) / kKleTC;
   const int64_t n_tiles = tx * ty * P;
-  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x)
-    kle_bf16s_tile(ph, pl, Kp, zh, zl, P, N, C, c0, w, tile % tx, (tile / tx) % ty,
-                   (int)(tile / (tx * ty)));
+  for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int64_t L = gridDim.x == n_tiles ? kle_xcd_tile(tile, n_tiles) : tile;
+    kle_bf16s_tile(ph, pl, Kp, zh, zl, P, N, C, c0, w, (L / ty) % tx, L % ty,
+                   (int)(L / (tx * ty)));
+  }
 }
 
 hipError_t launch_kle_bf16x3_split(const void* ph, const void* pl, int Kp, const void* zh,

@@ -348,6 +348,49 @@ hipError_t launch_setup(const SetupDev& s, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Coefficients after a network event: the pre-event operating point (E~0,
+// D, H, Pm, delta0, the processes) with the post-event admittance: I0 = Yp E~0
+// + Yinf V_inf, res = Pm - Re(E~0 conj I0).  A tripped machine keeps no EMF,
+// current, mechanical power or residual, so it neither drives nor sees the
+// network (its row and column of Yp are zero) and only its damping acts.
+__global__ void __launch_bounds__(256) k_setup_post(const double* __restrict__ pre, int n, int P,
+                                                    const double2* __restrict__ Yp,
+                                                    const double2* __restrict__ Yinf,
+                                                    double V_inf, int tripped,
+                                                    double* __restrict__ post) {
+  const CanonLayout L{n, P};
+  const int tid = threadIdx.x, bd = blockDim.x;
+  for (int64_t q = tid; q < L.size(); q += bd) post[q] = pre[q];
+  __syncthreads();
+  for (int64_t q = tid; q < (int64_t)n * n; q += bd) {
+    post[L.yre() + q] = Yp[q].x;
+    post[L.yim() + q] = Yp[q].y;
+  }
+  for (int i = tid; i < n; i += bd) {
+    double2 I = Yinf ? make_double2(Yinf[i].x * V_inf, Yinf[i].y * V_inf) : make_double2(0.0, 0.0);
+    for (int k = 0; k < n; ++k)
+      I = cadd(I, cmul(Yp[(int64_t)i * n + k], make_double2(pre[L.c0() + k], pre[L.s0() + k])));
+    const double er = pre[L.c0() + i], ei = pre[L.s0() + i];
+    const bool out = i == tripped;
+    const double pm = out ? 0.0 : pre[L.pm() + i];
+    const double pe = out ? 0.0 : er * I.x + ei * I.y;
+    post[L.c0() + i] = out ? 0.0 : er;
+    post[L.s0() + i] = out ? 0.0 : ei;
+    post[L.i0r() + i] = out ? 0.0 : I.x;
+    post[L.i0i() + i] = out ? 0.0 : I.y;
+    post[L.res() + i] = pm - pe;
+    post[L.pm() + i] = pm;
+  }
+}
+
+hipError_t launch_setup_post(const double* pre, int n, int P, const double2* Yp,
+                             const double2* Yinf, double V_inf, int tripped, double* post,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_setup_post, dim3(1), dim3(256), 0, st, pre, n, P, Yp, Yinf, V_inf, tripped,
+                     post);
+  return hipGetLastError();
+}
+
 // Packed, padded coefficients of a variant in its arithmetic type.
 template <typename R>
 __global__ void __launch_bounds__(256) k_pack(const double* __restrict__ cn, int n, int P,

@@ -110,13 +110,19 @@ __global__ void __launch_bounds__(64) k_trap_lane(IntegArgs<double> a) {
   double* J = mat + lane;
 
   double yd[NG], yw[NG], yx[PM];
+  double racc = 0.0;  // the epilogue's RRF sum (see IntegArgs::rrf_w)
   if (a.s_begin == 0) {
 #pragma unroll
     for (int i = 0; i < NG; ++i) { yd[i] = 0.0; yw[i] = 0.0; }
 #pragma unroll
     for (int p = 0; p < PM; ++p) yx[p] = cf[L.xi0() + p];
     emit_step<double, NG, PM>(a, tile, lane, cnt, 0, slot, 0.0, yd, yw, yx);
+    if (a.rrf_w) {
+      const double u = rrf_u_lane<double, NG, PM>(a, 0.0, yd, yw, yx);
+      racc = 0.5 * u * u;
+    }
   } else {
+    if (a.rrf_w) racc = a.rrf_acc[ns];
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
       yd[i] = a.state[(int64_t)i * a.lanes + gidx];
@@ -228,6 +234,14 @@ __global__ void __launch_bounds__(64) k_trap_lane(IntegArgs<double> a) {
 #pragma unroll
     for (int p = 0; p < PM; ++p) yx[p] = zx[p];
     emit_step<double, NG, PM>(a, tile, lane, cnt, s + 1, slot, 0.0, yd, yw, yx);
+    if (a.rrf_w) {
+      const double u = rrf_u_lane<double, NG, PM>(a, 0.0, yd, yw, yx);
+      racc += (s + 1 == a.S ? 0.5 : 1.0) * u * u;
+    }
+  }
+  if (a.rrf_w && valid) {
+    a.rrf_acc[gidx] = racc;
+    if (a.s_end == a.S) a.rrf[gidx] = sqrt(racc / (double)a.S);
   }
 
 #pragma unroll

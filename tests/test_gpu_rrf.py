@@ -63,3 +63,57 @@ def test_rrf_rejections(ctx, fmc):
     with pytest.raises(fmc.FmcError) as e:
         ctx.rrf_rms(td, np.ones(3), 0.0)
     assert e.value.code == fmc.EINVAL
+
+
+# ------------------------------------------------ RRF fused into the integrator
+def _coi_weights(sc):
+    n, P = sc["n_gen"], len(sc["dist"]["gen"])
+    w = np.zeros(2 * n + P)
+    H = np.asarray(sc["H"], dtype=np.float64)
+    w[n:2 * n] = H / H.sum()
+    return w
+
+
+FUSED = [("10gen_f64", lambda: workloads.config2(N=300, K=20, T=1.0), "f64", -1),
+         ("10gen_f64_lane", lambda: workloads.config2(N=70, K=20, T=0.5), "f64", 7),
+         ("10gen_trip_f64", lambda: dict(workloads.config2(N=130, K=20, T=1.0),
+                                         event=dict(t=0.5, tripped=2)), "f64", -1),
+         ("smib_trap", lambda: workloads.smib(N=65, K=20, T=1.0, integrator="trap"), "f64", -1),
+         ("10gen_f32", lambda: workloads.config2(N=300, K=20, T=1.0), "f32", -1),
+         ("10gen_bf16x3", lambda: workloads.config2(N=300, K=20, T=1.0), "bf16x3", -1)]
+
+
+@pytest.mark.parametrize("name,make,prec,variant", FUSED, ids=[c[0] for c in FUSED])
+def test_fused_rrf_against_oracle(ctx, name, make, prec, variant):
+    """The RRF accumulated in the integrator's epilogue (no trajectories
+    stored) against the oracle's RMS of its own trajectories of every sample:
+    1e-10 relative in FP64, 1e-4 in the reduced-precision forms; the samples'
+    mean and variance of the RRF likewise."""
+    sc = make()
+    w = _coi_weights(sc) if sc["n_gen"] > 1 else np.array([0.0, 1.0, 0.0])
+    r = ctx.run(sc, precision=prec, rrf_weights=w, variant=variant)
+    o = oracle.run(sc, want_traj=True)
+    ref = oracle.rrf_rms(o["traj"], w, sc["dt"])
+    got = r["rrf"].cpu().numpy()
+    tol = 1e-10 if prec == "f64" else 1e-4
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
+    assert abs(got.mean() - ref.mean()) <= tol * abs(ref.mean())
+    assert abs(got.var(ddof=1) - ref.var(ddof=1)) <= 2 * tol * ref.var(ddof=1)
+
+
+def test_fused_rrf_time_chunks_and_stored_trajectories(ctx):
+    sc = workloads.config2(N=200, K=20, T=1.0)
+    w = _coi_weights(sc)
+    a = ctx.run(sc, precision="f64", rrf_weights=w, traj_idx=np.arange(sc["N"]))
+    b = ctx.run(sc, precision="f64", rrf_weights=w, time_chunk=13)
+    assert np.array_equal(a["rrf"].cpu().numpy(), b["rrf"].cpu().numpy())
+    # the same quantity from the stored trajectories (fmc_rrf_rms)
+    c = ctx.rrf_rms(a["traj"], w, sc["dt"]).cpu().numpy()
+    np.testing.assert_allclose(a["rrf"].cpu().numpy(), c, rtol=1e-13, atol=0)
+
+
+def test_fused_rrf_rejections(ctx, fmc):
+    fd = workloads.fluxdecay(n_gen=12, n_dist=3, N=20, K=10, T=0.2, net_seed=312)
+    with pytest.raises(fmc.FmcError) as e:
+        ctx.run(fd, precision="f32", rrf_weights=np.ones(6 * 12 + 3))
+    assert e.value.code == fmc.EINVAL
