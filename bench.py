@@ -681,6 +681,60 @@ def rrf_leg(ctx, fmc, workloads, reps: int = 3):
     return out
 
 
+PEAK_MFMA_FP64 = 78.6e12
+PEAK_MFMA_BF16 = 2.5e15
+PEAK_HBM = 8.0e12
+
+
+def kle_leg(ctx, fmc, reps: int, copy_check: bool = False):
+    """The KLE path contraction (eqs. 8-9) alone, on the chunk shapes fmc_run
+    uses: the 10-machine workload (N = 1e4, chunks of 209 steps: 419 stage
+    columns) and the N = 1e5 workload (chunks of 41 steps: 83 columns), P = 3
+    processes, K = 100.  Each form is one fmc_kle_paths call per repetition,
+    timed with events on the context's stream; the BF16 x3 call includes the
+    hi/lo split of both operands (two short launches before the contraction,
+    which fmc_run makes once per run for the design).  Algorithmic work: 2 K
+    flops per output element; bytes: the design read once (8 B per element in
+    FP64, 4 B as BF16 hi/lo) and the paths written once."""
+    import torch
+    out = {}
+    for name, (P, K, N, C) in {"N1e4_chunk209": (3, 100, 10000, 419),
+                               "N1e5_chunk41": (3, 100, 100000, 83)}.items():
+        _, z = ctx.lhs(seed=2, M=P * K, N=N)
+        S = (C - 1) // 2
+        phi = ctx.basis(0, K, S, 0.005 * S)
+        for prec in ("f64", "f32", "bf16x3"):
+            w = ctx.kle_paths(z, phi, P, K, C, precision=prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                w = ctx.kle_paths(z, phi, P, K, C, precision=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) * 1e-3 / reps
+            flops = 2.0 * K * P * N * C
+            zb = (8 if prec != "bf16x3" else 4) * P * K * N
+            wb = w.numel() * w.element_size()
+            r = {"shape": {"P": P, "K": K, "N": N, "C": C}, "call_ms": t * 1e3,
+                 "tflops": flops / t / 1e12, "hbm_gbps": (zb + wb) / t / 1e9,
+                 "hbm_frac": (zb + wb) / t / PEAK_HBM}
+            if prec == "bf16x3":
+                r["mfma_frac"] = 3 * flops / t / PEAK_MFMA_BF16
+            else:
+                r["mfma_frac"] = flops / t / PEAK_MFMA_FP64
+            out[f"{name}_{prec}"] = r
+            say(f"kle {name} {prec}: {t * 1e6:.1f} us, {flops / t / 1e12:.1f} TFLOP/s")
+        del z, phi, w
+    if copy_check:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    return out
+
+
 def fd_leg(ctx, fmc, workloads, oracle_mod, steps: int, reps: int = 2):
     """Large-request shape of the flux-decay model (200 machines with IEEE
     type-1 exciters, 10 OU processes, N = 5e4, K = 100) on a horizon of
@@ -762,6 +816,11 @@ def main():
                     help="arrival window per rate of the serve sweep")
     ap.add_argument("--c3-steps", type=int, default=2,
                     help="timed passes of the N=1e5 mixed-precision workload (0: skip)")
+    ap.add_argument("--kle-reps", type=int, default=20,
+                    help="repetitions of the standalone KLE contraction leg (0: skip)")
+    ap.add_argument("--kle-only", action="store_true",
+                    help="run the standalone KLE contraction leg only and print it as one "
+                         "JSON line (for kernel profiles)")
     ap.add_argument("--copy-check", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -785,6 +844,11 @@ def main():
 
     dev = torch.device("cuda", 0)
     ctx = fmc.Context(0)
+    if args.kle_only:
+        res = kle_leg(ctx, fmc, max(1, args.kle_reps), args.copy_check)
+        print(json.dumps({"metric": "KLE path contraction alone", "kle_contraction": res}))
+        ctx.close()
+        return
     sc = workloads.config2()
     n, P, N, K = sc["n_gen"], len(sc["dist"]["gen"]), sc["N"], sc["K"]
     S = fmc.steps(sc)
@@ -898,6 +962,8 @@ def main():
     if args.fd_steps > 0:
         fdl = fd_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), args.fd_steps)
 
+    kle = kle_leg(ctx, fmc, args.kle_reps) if args.kle_reps > 0 else None
+
     served = None
     rates = [float(x) for x in args.serve_rates.split(",") if x.strip()]
     if rates:
@@ -955,6 +1021,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms_out,
         "mixed_precision_N1e5": c3,
+        "kle_contraction": kle,
         "batched": batched,
         "served": served,
         "flux_decay": fdl,

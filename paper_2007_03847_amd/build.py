@@ -21,6 +21,10 @@ SOURCES = ["fmc_runtime.hip", "fmc_run.hip", "fmc_fd.hip", "fmc_batch.hip", "fmc
            "k_integrate_f64.hip", "k_integrate_f32.hip", "k_trap.hip"]
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Per-source flags.  The KLE contractions keep their accumulators in the
+# matrix-operation form that reads and writes ordinary vector registers, so
+# the loop carries no copies between them and the accumulation registers.
+SOURCE_FLAGS = {"k_sample.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _newest_header() -> float:
@@ -35,7 +39,7 @@ def _compile(src: str, incremental: bool = False) -> str:
         t = os.path.getmtime(obj)
         if t > os.path.getmtime(os.path.join(CSRC, src)) and t > _newest_header():
             return obj
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -137,7 +137,7 @@ typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
 constexpr int kKleTC = 128, kKleTN = 64;  // workgroup tile (c, n): four waves along c
 
-template <typename OutT>
+template <typename OutT, typename OffT>
 __device__ __forceinline__ void kle_f64_tile(const double* __restrict__ zeta,
                                              const double* __restrict__ phi, int64_t phi_ld,
                                              int P, int K, int64_t N, int64_t C, int64_t c0,
@@ -147,48 +147,73 @@ __device__ __forceinline__ void kle_f64_tile(const double* __restrict__ zeta,
   const int64_t n0 = bx * kKleTN;
   if (cb >= C) return;  // uniform per wave
   const int li = lane & 15, lk = lane >> 4;
-  const double* __restrict__ zp = zeta + (int64_t)p * K * N;
+  // Per-lane byte offsets inside a k-step of four rows, from a base that
+  // moves with the step (the loads take a scalar base and a 32-bit offset).
+  // Columns past the edge (c >= C, n >= N) read the last valid one: they
+  // feed only output rows and columns that are never stored, so every load
+  // is unconditional and the loop carries no branch.
+  OffT ao[2], bo[4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int64_t c = cb + 16 * h + li;
+    ao[h] = (OffT)(8 * (lk * phi_ld + (c < C ? c : C - 1)));
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int64_t n = n0 + 16 * b + li;
+    bo[b] = (OffT)(8 * (lk * N + (n < N ? n : N - 1)));
+  }
+  const char* __restrict__ A = (const char*)(phi + c0);                    // row j: + 8 j phi_ld
+  const char* __restrict__ B = (const char*)(zeta + (int64_t)p * K * N);  // row j: + 8 j N
   d4_t acc[2][4];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[h][b] = d4_t{0.0, 0.0, 0.0, 0.0};
-  bool cv[2], nv[4];
-  const double* ap[2];
-  const double* bp[4];
+  auto load = [&](int j0, double (&a)[2], double (&bv)[4]) {
+    const char* Aj = A + 8 * (int64_t)j0 * phi_ld;
+    const char* Bj = B + 8 * (int64_t)j0 * N;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int64_t c = cb + 16 * h + li;
-    cv[h] = c < C;
-    ap[h] = phi + c0 + (cv[h] ? c : 0);
-  }
+    for (int h = 0; h < 2; ++h) a[h] = *(const double*)(Aj + ao[h]);
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    const int64_t n = n0 + 16 * b + li;
-    nv[b] = n < N;
-    bp[b] = zp + (nv[b] ? n : 0);
-  }
-  auto load = [&](int j, double (&a)[2], double (&bv)[4]) {
-    const bool jv = j < K;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) a[h] = (jv && cv[h]) ? ap[h][(int64_t)j * phi_ld] : 0.0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = (jv && nv[b]) ? bp[b][(int64_t)j * N] : 0.0;
+    for (int b = 0; b < 4; ++b) bv[b] = *(const double*)(Bj + bo[b]);
   };
-  double a[2], bv[4];
-  load(lk, a, bv);
-  for (int j0 = 0; j0 < K; j0 += 4) {
-    double an[2], bn[4];
-    load(j0 + 4 + lk, an, bn);
+  auto step = [&](const double (&a)[2], const double (&bv)[4]) {
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int b = 0; b < 4; ++b)
         acc[h][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], bv[b], acc[h][b], 0, 0, 0);
+  };
+  // k-steps of four rows in pairs, with two fragment sets in turn: the next
+  // step's fragments load while this step's products run.  A prefetch past
+  // the last full step re-reads that step's rows and stays unused.
+  const int K4 = K & ~3;
+  double ax[2], bx4[4], ay[2], by4[4];
+  if (K4 > 0) load(0, ax, bx4);
+  int j0 = 0;
+  for (; j0 + 8 <= K4; j0 += 8) {
+    load(j0 + 4, ay, by4);
+    step(ax, bx4);
+    load(j0 + 8 < K4 ? j0 + 8 : K4 - 4, ax, bx4);
+    step(ay, by4);
+  }
+  if (j0 < K4) step(ax, bx4);  // K4 mod 8 == 4: the fragments of row j0 are in x
+  if (K4 < K) {  // the last K mod 4 rows; lanes of rows past K contribute zero
+    const bool jv = K4 + lk < K;
+    const int64_t dj = 8 * (int64_t)(jv ? K4 : K - 1 - lk);  // the lane's row, clamped to K - 1
+    double a[2], bv[4];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) a[h] = an[h];
+    for (int h = 0; h < 2; ++h) {
+      const double v = *(const double*)(A + dj * phi_ld + ao[h]);
+      a[h] = jv ? v : 0.0;
+    }
 #pragma unroll
-    for (int b = 0; b < 4; ++b) bv[b] = bn[b];
+    for (int b = 0; b < 4; ++b) {
+      const double v = *(const double*)(B + dj * N + bo[b]);
+      bv[b] = jv ? v : 0.0;
+    }
+    step(a, bv);
   }
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -218,17 +243,20 @@ __device__ __forceinline__ int64_t kle_xcd_tile(int64_t b, int64_t n_tiles) {
 
 // The grid is a flat list of blocks striding over the (n, c, p) tiles, so a
 // launch can use fewer workgroups than tiles (to run beside another kernel).
-template <typename OutT>
-__global__ void __launch_bounds__(256) k_kle_f64(const double* __restrict__ zeta,
-                                                 const double* __restrict__ phi, int64_t phi_ld,
-                                                 int P, int K, int64_t N, int64_t C, int64_t c0,
-                                                 OutT* __restrict__ w) {
+// OffT is the type of the per-lane byte offsets: 32-bit while four rows of
+// either operand span less than 4 GiB (the loads then take a scalar base and
+// a 32-bit offset), else 64-bit.  Four waves per SIMD: eight accumulators
+// of 16 x 16 doubles (64 registers) and two k-steps of fragments.
+template <typename OutT, typename OffT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_kle_f64(const double* __restrict__ zeta, const double* __restrict__ phi, int64_t phi_ld, int P,
+          int K, int64_t N, int64_t C, int64_t c0, OutT* __restrict__ w) {
   const int64_t tx = (N + kKleTN - 1) / kKleTN, ty = (C + kKleTC - 1) / kKleTC;
   const int64_t n_tiles = tx * ty * P;
   for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int64_t L = gridDim.x == n_tiles ? kle_xcd_tile(tile, n_tiles) : tile;
-    kle_f64_tile<OutT>(zeta, phi, phi_ld, P, K, N, C, c0, w, (L / ty) % tx, L % ty,
-                       (int)(L / (tx * ty)));
+    kle_f64_tile<OutT, OffT>(zeta, phi, phi_ld, P, K, N, C, c0, w, (L / ty) % tx, L % ty,
+                             (int)(L / (tx * ty)));
   }
 }
 template <typename OutT>
@@ -238,8 +266,14 @@ static hipError_t launch_kle_f64_t(const double* zeta, const double* phi, int64_
   if (C <= 0 || N <= 0 || P <= 0) return hipSuccess;
   int64_t tiles = ((N + kKleTN - 1) / kKleTN) * ((C + kKleTC - 1) / kKleTC) * P;
   if (max_blocks > 0) tiles = std::min<int64_t>(tiles, max_blocks);
-  hipLaunchKernelGGL(k_kle_f64<OutT>, dim3((unsigned)tiles), dim3(256), 0, st, zeta, phi, phi_ld, P,
-                     K, N, C, c0, w);
+  // largest byte offset of a lane inside a k-step: 8 (3 ld + ld - 1) < 32 ld
+  const bool narrow = 32 * std::max<int64_t>(N, phi_ld) <= (int64_t)UINT32_MAX;
+  if (narrow)
+    hipLaunchKernelGGL((k_kle_f64<OutT, uint32_t>), dim3((unsigned)tiles), dim3(256), 0, st, zeta,
+                       phi, phi_ld, P, K, N, C, c0, w);
+  else
+    hipLaunchKernelGGL((k_kle_f64<OutT, int64_t>), dim3((unsigned)tiles), dim3(256), 0, st, zeta,
+                       phi, phi_ld, P, K, N, C, c0, w);
   return hipGetLastError();
 }
 
@@ -426,51 +460,51 @@ __device__ __forceinline__ void kle_bf16s_tile(const __bf16* __restrict__ ph,
   for (int h = 0; h < 2; ++h)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[h][b] = f4_t{0.f, 0.f, 0.f, 0.f};
-  bool cv[2], nv[4];
+  // Rows past the edge (c >= C, n >= N) read the last valid one: they feed
+  // only outputs that are never stored, so every load is unconditional.
   int64_t ao[2], bo[4];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int64_t c = cb + 16 * h + li;
-    cv[h] = c < C;
-    ao[h] = (c0 + (cv[h] ? c : 0)) * Kp + ko;
+    ao[h] = (c0 + (c < C ? c : C - 1)) * Kp + ko;
   }
 #pragma unroll
   for (int b = 0; b < 4; ++b) {
     const int64_t n = n0 + 16 * b + li;
-    nv[b] = n < N;
-    bo[b] = ((int64_t)p * N + (nv[b] ? n : 0)) * Kp + ko;
+    bo[b] = ((int64_t)p * N + (n < N ? n : N - 1)) * Kp + ko;
   }
-  const bf8_t zero = {};
-  auto load = [&](int k, bf8_t (&ah)[2], bf8_t (&al)[2], bf8_t (&bh)[4], bf8_t (&bl)[4]) {
-    const bool kv = k < Kp;
+  struct frag {
+    bf8_t ah[2], al[2], bh[4], bl[4];
+  };
+  auto load = [&](int k, frag& f) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      ah[h] = (kv && cv[h]) ? *reinterpret_cast<const bf8_t*>(ph + ao[h] + k) : zero;
-      al[h] = (kv && cv[h]) ? *reinterpret_cast<const bf8_t*>(pl + ao[h] + k) : zero;
+      f.ah[h] = *reinterpret_cast<const bf8_t*>(ph + ao[h] + k);
+      f.al[h] = *reinterpret_cast<const bf8_t*>(pl + ao[h] + k);
     }
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
-      bh[b] = (kv && nv[b]) ? *reinterpret_cast<const bf8_t*>(zh + bo[b] + k) : zero;
-      bl[b] = (kv && nv[b]) ? *reinterpret_cast<const bf8_t*>(zl + bo[b] + k) : zero;
+      f.bh[b] = *reinterpret_cast<const bf8_t*>(zh + bo[b] + k);
+      f.bl[b] = *reinterpret_cast<const bf8_t*>(zl + bo[b] + k);
     }
   };
-  bf8_t ah[2], al[2], bh[4], bl[4];
-  load(0, ah, al, bh, bl);
-  for (int k = 0; k < Kp; k += 32) {
-    bf8_t ahn[2], aln[2], bhn[4], bln[4];
-    load(k + 32, ahn, aln, bhn, bln);
+  auto step = [&](const frag& f) {
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        acc[h][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[h], bh[b], acc[h][b], 0, 0, 0);
-        acc[h][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[h], bl[b], acc[h][b], 0, 0, 0);
-        acc[h][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[h], bh[b], acc[h][b], 0, 0, 0);
+        acc[h][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.al[h], f.bh[b], acc[h][b], 0, 0, 0);
+        acc[h][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ah[h], f.bl[b], acc[h][b], 0, 0, 0);
+        acc[h][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ah[h], f.bh[b], acc[h][b], 0, 0, 0);
       }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) { ah[h] = ahn[h]; al[h] = aln[h]; }
-#pragma unroll
-    for (int b = 0; b < 4; ++b) { bh[b] = bhn[b]; bl[b] = bln[b]; }
+  };
+  // One fragment set: the loads of a k-step wait for the previous step's
+  // products, and the other waves of the SIMD cover that latency (the
+  // products of a step are short next to the tile's loads and stores).
+  for (int k = 0; k < Kp; k += 32) {
+    frag f;
+    load(k, f);
+    step(f);
   }
   // result register r of lane l is D[4(l/16) + r][l%16]
 #pragma unroll

@@ -93,7 +93,8 @@ def test_em_basis(ctx, S, T):
 
 # ------------------------------------------------------------ KLE paths
 @pytest.mark.parametrize("P,K,N,S", [(1, 40, 1000, 100), (3, 100, 777, 60), (2, 5, 65, 9),
-                                     (1, 1, 1, 1), (2, 150, 2049, 130), (1, 32, 256, 16)])
+                                     (1, 1, 1, 1), (2, 150, 2049, 130), (1, 32, 256, 16),
+                                     (1, 7, 100, 20), (3, 12, 130, 40)])
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-7), ("bf16x3", 4e-5)])
 def test_kle_paths(ctx, P, K, N, S, prec, tol):
     T = 0.01 * S
@@ -106,6 +107,31 @@ def test_kle_paths(ctx, P, K, N, S, prec, tol):
     ref = oracle.kle_paths(_np(z), _np(phi), P, K, c0, Cc)
     scale = np.sqrt(np.sum(_np(phi)[:, c0:c0 + Cc, None] ** 2, axis=0)).max() * np.abs(_np(z)).max()
     assert np.max(np.abs(w - ref)) <= tol * scale
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-13), ("f32", 2e-7)])
+def test_kle_paths_wide_offsets(ctx, prec, tol):
+    """More than 2^27 paths: a lane's byte offsets inside a k-step of four
+    rows no longer fit 32 bits, and the contraction takes 64-bit offsets.
+    Sampled columns (the first, the last, and some across the range) against
+    the oracle on the same columns."""
+    import torch
+    P, K, S = 1, 6, 3
+    N = (1 << 27) + 1000
+    g = torch.Generator(device="cuda").manual_seed(7)
+    z = torch.randn(P * K, N, dtype=torch.float64, device="cuda", generator=g)
+    phi = ctx.basis(0, K, S, 0.03)
+    C = 2 * S + 1
+    w = ctx.kle_paths(z, phi, P, K, C, precision=prec)
+    sel = np.unique(np.concatenate([[0, 1, N // 2, N - 2, N - 1],
+                                    np.random.default_rng(3).integers(0, N, 200)]))
+    idx = torch.as_tensor(sel, device="cuda")
+    got = _np(w[:, :, idx]).astype(np.float64)
+    zs = _np(z[:, idx])
+    del w, z
+    ref = oracle.kle_paths(zs, _np(phi), P, K, 0, C)
+    scale = np.sqrt(np.sum(_np(phi)[:, :C, None] ** 2, axis=0)).max() * np.abs(zs).max()
+    assert np.max(np.abs(got - ref)) <= tol * scale
 
 
 # --------------------------------------------------------------- Kron
