@@ -28,7 +28,7 @@ _LIB = os.path.join(_HERE, "liborc.so")
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no GPU code, no shared sources)."""
-    if force or not os.path.exists(_LIB):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC",
                "-shared", "-o", tmp, _SRC, "-lm"]
@@ -56,7 +56,35 @@ class _Problem(C.Structure):
         ("t_event", C.c_double), ("tripped", C.c_int32),
         ("Yp_re", C.c_void_p), ("Yp_im", C.c_void_p),
         ("Yinfp_re", C.c_void_p), ("Yinfp_im", C.c_void_p),
+        ("proc", C.c_void_p), ("calculus", C.c_int32),
     ]
+
+
+class _Process(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("a", C.c_double), ("b", C.c_double),
+                ("theta", C.c_double), ("mu", C.c_double * 3), ("sg", C.c_double * 3),
+                ("gain", C.c_double), ("ref", C.c_double)]
+
+
+_PROC_KIND = {"ou": 0, "gauss": 1, "beta": 2, "gamma": 3, "laplace": 4, "poly": 5}
+_CALCULUS = {"ito": 0, "stratonovich": 1}
+
+
+def _processes(specs):
+    """ctypes array of process specs from a list of dicts: kind ('ou', the
+    Table I rows 'gauss' / 'beta' / 'gamma' / 'laplace' with a, b, theta, or
+    'poly' with mu and sg, three coefficients each), gain and ref of the
+    injection gain (xi - ref)."""
+    arr = (_Process * len(specs))()
+    for q, d in zip(arr, specs):
+        q.kind = _enum(d.get("kind", "ou"), _PROC_KIND)
+        q.a, q.b, q.theta = float(d.get("a", 0.0)), float(d.get("b", 0.0)), float(d.get("theta", 0.0))
+        for k, v in enumerate(d.get("mu", (0.0, 0.0, 0.0))):
+            q.mu[k] = float(v)
+        for k, v in enumerate(d.get("sg", (0.0, 0.0, 0.0))):
+            q.sg[k] = float(v)
+        q.gain, q.ref = float(d.get("gain", 1.0)), float(d.get("ref", 0.0))
+    return arr
 
 
 _lib = None
@@ -65,8 +93,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=True)
+        build(force=False)  # compiles when the library is missing or older than the source
         L = C.CDLL(_LIB)
         P = C.c_void_p
         L.orc_philox4x64_10.argtypes = [P, P, P]
@@ -256,6 +283,7 @@ def problem(sc: dict):
         if d.get("sigma_mat") is not None else None
     model = _enum(sc.get("model", 0), _MODEL)
     keep.mp = _f64(sc.get("model_params")) if model == 1 else None
+    keep.proc = _processes(d["proc"]) if d.get("proc") is not None else None
     ev = sc.get("event")
     keep.Ypr = keep.Ypi = keep.Yipr = keep.Yipi = None
     if ev is not None:
@@ -277,7 +305,9 @@ def problem(sc: dict):
         model=model, model_params=_p(keep.mp), sigma_mat=_p(keep.sm),
         t_event=float(ev["t"]) if ev is not None else 0.0,
         tripped=int(ev.get("tripped", -1)) if ev is not None else -1,
-        Yp_re=_p(keep.Ypr), Yp_im=_p(keep.Ypi), Yinfp_re=_p(keep.Yipr), Yinfp_im=_p(keep.Yipi))
+        Yp_re=_p(keep.Ypr), Yp_im=_p(keep.Ypi), Yinfp_re=_p(keep.Yipr), Yinfp_im=_p(keep.Yipi),
+        proc=C.addressof(keep.proc) if keep.proc is not None else None,
+        calculus=_enum(sc.get("calculus", "ito"), _CALCULUS))
     return pb, keep
 
 

@@ -32,6 +32,11 @@
  *   kron           -> SMIB reduction to E V sin(delta)/X, symmetry, full solve
  *   rrf_rms        -> constant and full-period sine signals, scaling, a common
  *                     mode removed by centre-of-inertia weights
+ *   run (general   -> Table I rows: the Ito mean and second-moment equations
+ *   Ito processes)    (closed for linear drift), the stationary moments of the
+ *                     named densities; the Stratonovich shift of the Gamma
+ *                     row's mean; the wind model (eq. 11) against a plain
+ *                     Euler-Maruyama simulation of eq. 5 (statistical)
  */
 #include <complex.h>
 #include <math.h>
@@ -602,7 +607,49 @@ typedef struct orc_problem {
     double t_event;
     int32_t tripped;
     const double *Yp_re, *Yp_im, *Yinfp_re, *Yinfp_im;
+    /* General scalar Ito disturbances (eq. 4 with state-dependent drift and   */
+    /* diffusion; the rows of Table I and the wind model of eq. 11): NULL (every */
+    /* process OU as above), or one spec per process.                           */
+    const struct orc_process *proc;
+    int32_t calculus; /* ORC_ITO or ORC_STRATONOVICH (below) */
 } orc_problem;
+
+/* One disturbance process.  Table I lists, per stationary density, the drift
+ * and the squared diffusion of a unit-rate scalar Ito process; a rate theta
+ * scales both (the stationary solution of the Fokker-Planck equation, which
+ * depends on 2 mu / sigma^2 only, stays the named density):
+ *   Gaussian(a, b)  mu = -theta (xi - a),          sigma^2 = 2 theta b
+ *   Beta(a, b)      mu = -theta (xi - a/(a+b)),    sigma^2 = 2 theta xi (1 - xi)/(a+b)
+ *   Gamma(a, b)     mu = -theta (xi - a/b),        sigma^2 = 2 theta xi / b
+ *   Laplace(a, b)   mu = -theta (xi - a),          sigma^2 = theta (2 b |xi - a| + 2 b^2)
+ * (b is the variance of the Gaussian row and the scale of the Laplace row;
+ * a negative sigma^2 -- outside the support -- is taken as 0).  The wind model
+ * (eq. 11) is the polynomial kind: mu = mu0 + mu1 xi + mu2 xi^2 and sigma =
+ * sg0 + sg1 xi + sg2 xi^2.  An OU spec keeps theta[p], sigma[p] (or the
+ * diffusion matrix).  The process enters its machine's power balance as
+ * gain (xi - ref). */
+typedef struct orc_process {
+    int32_t kind;
+    double a, b, theta;
+    double mu[3], sg[3];
+    double gain, ref;
+} orc_process;
+enum { ORC_PROC_OU = 0, ORC_PROC_GAUSS = 1, ORC_PROC_BETA = 2, ORC_PROC_GAMMA = 3,
+       ORC_PROC_LAPLACE = 4, ORC_PROC_POLY = 5 };
+/* The KLE paths of eq. 8 are smooth, so eq. 9 is an ordinary differential
+ * equation whose solutions converge, as K grows, to the Stratonovich solution
+ * of eq. 4 with the same coefficients (the Wong-Zakai limit), not to the Ito
+ * solution.  ORC_ITO (default) integrates eq. 9 with the drift mu - c sigma
+ * sigma', c = 1/2, whose Stratonovich solution is the Ito process of eq. 4;
+ * ORC_STRATONOVICH integrates eq. 9 as written.  The two agree for additive
+ * noise (OU and the Gaussian row).  The one-hot basis of the traditional
+ * Monte Carlo baseline (eq. 5's normal of step j at that step's midpoint
+ * stages, weight 3/(2 sqrt(dt))) is not smooth: expanding the RK4 step, its
+ * increment is sigma sqrt(dt) zeta + (3/8) sigma sigma' zeta^2 dt + O(dt^1.5)
+ * beside the drift, so its own noise-induced drift is (3/8) sigma sigma' and
+ * ORC_ITO takes c = 3/8 there (the increments then converge to eq. 5's Ito
+ * increments as dt -> 0). */
+enum { ORC_ITO = 0, ORC_STRATONOVICH = 1 };
 
 /* Flux-decay parameters per machine, in this order. */
 enum { FD_XD, FD_XDP, FD_TDO, FD_KA, FD_TA, FD_KE, FD_TE, FD_KF, FD_TF, FD_NPARAM };
@@ -622,6 +669,8 @@ typedef struct {
     double *Vref;     /* [n] exciter reference */
     double *y0;       /* [ny] initial state (the operating point) */
     int tripped;      /* machine disconnected (post-event model), else -1 */
+    const orc_process *proc; /* [P] or NULL */
+    double ito_c;     /* drift correction -ito_c sigma sigma' (0: none) */
 } model_t;
 
 /* Diffusion term of process p driven by the white noises w (eq. 4): sigma_p */
@@ -633,6 +682,70 @@ static double diffusion(const model_t *m, int p, const double *w)
     double s = 0.0;
     for (int q = 0; q < m->P; ++q) s += m->sigma_mat[p * m->P + q] * w[q];
     return s;
+}
+
+/* Drift mu(xi), diffusion sigma(xi) and the product sigma(xi) sigma'(xi) of
+ * a non-OU process (the table in the comment of orc_process).  For the rows
+ * given by sigma^2 = g(xi): sigma = sqrt(g), sigma sigma' = g'/2 (0 where
+ * g <= 0; |xi - a| has derivative sign(xi - a)). */
+static void proc_terms(const orc_process *q, double xi, double *mu, double *sg, double *ssp)
+{
+    const double th = q->theta, a = q->a, b = q->b;
+    double g = 0.0, dg = 0.0;
+    switch (q->kind) {
+    case ORC_PROC_GAUSS:
+        *mu = -th * (xi - a);
+        g = 2.0 * th * b;
+        dg = 0.0;
+        break;
+    case ORC_PROC_BETA:
+        *mu = -th * (xi - a / (a + b));
+        g = 2.0 * th * xi * (1.0 - xi) / (a + b);
+        dg = 2.0 * th * (1.0 - 2.0 * xi) / (a + b);
+        break;
+    case ORC_PROC_GAMMA:
+        *mu = -th * (xi - a / b);
+        g = 2.0 * th * xi / b;
+        dg = 2.0 * th / b;
+        break;
+    case ORC_PROC_LAPLACE:
+        *mu = -th * (xi - a);
+        g = th * (2.0 * b * fabs(xi - a) + 2.0 * b * b);
+        dg = 2.0 * th * b * (xi > a ? 1.0 : (xi < a ? -1.0 : 0.0));
+        break;
+    default: { /* ORC_PROC_POLY */
+        *mu = q->mu[0] + q->mu[1] * xi + q->mu[2] * xi * xi;
+        const double s = q->sg[0] + q->sg[1] * xi + q->sg[2] * xi * xi;
+        *sg = s;
+        *ssp = s * (q->sg[1] + 2.0 * q->sg[2] * xi);
+        return;
+    }
+    }
+    if (g > 0.0) {
+        *sg = sqrt(g);
+        *ssp = 0.5 * dg;
+    } else {
+        *sg = 0.0;
+        *ssp = 0.0;
+    }
+}
+
+/* d xi_p / dt of eq. 9 for process p at state xi with white-noise surrogate
+ * values w (OU: -theta xi + the diffusion term above). */
+static double proc_rhs(const model_t *m, int p, double xi, const double *w)
+{
+    const orc_process *q = m->proc ? &m->proc[p] : NULL;
+    if (!q || q->kind == ORC_PROC_OU) return -m->theta[p] * xi + diffusion(m, p, w);
+    double mu, sg, ssp;
+    proc_terms(q, xi, &mu, &sg, &ssp);
+    return mu - m->ito_c * ssp + sg * w[p];
+}
+
+/* Power that process p injects into its machine. */
+static double proc_injection(const model_t *m, int p, double xi)
+{
+    const orc_process *q = m->proc ? &m->proc[p] : NULL;
+    return q ? q->gain * (xi - q->ref) : xi;
 }
 
 /* Electrical power of every machine: Pe_i = Re{ E~_i conj(I_i) },
@@ -682,12 +795,11 @@ static void rhs(const model_t *m, const double *y, const double *w, double *dy)
     for (int i = 0; i < n; ++i) {
         double pm = m->Pm[i];
         for (int p = 0; p < P; ++p)
-            if (m->dgen[p] == i && i != m->tripped) pm += y[2 * n + p];
+            if (m->dgen[p] == i && i != m->tripped) pm += proc_injection(m, p, y[2 * n + p]);
         dy[i] = m->wb * y[n + i];
         dy[n + i] = (pm - Pe[i] - m->D[i] * y[n + i]) / (2.0 * m->H[i]);
     }
-    for (int p = 0; p < P; ++p)
-        dy[2 * n + p] = -m->theta[p] * y[2 * n + p] + diffusion(m, p, w);
+    for (int p = 0; p < P; ++p) dy[2 * n + p] = proc_rhs(m, p, y[2 * n + p], w);
 }
 
 static void rhs_jac(const model_t *m, const double *y, double *J)
@@ -748,7 +860,7 @@ static void rhs_fd(const model_t *m, const double *y, const double *w, double *d
         const double *q = m->fdp + i * FD_NPARAM;
         double pm = m->Pm[i];
         for (int p = 0; p < P; ++p)
-            if (m->dgen[p] == i) pm += xi[p];
+            if (m->dgen[p] == i) pm += proc_injection(m, p, xi[p]);
         dy[i] = m->wb * dw[i];
         dy[n + i] = (pm - Pe[i] - m->D[i] * dw[i]) / (2.0 * m->H[i]);
         dy[2 * n + i] = (-eq[i] - (q[FD_XD] - q[FD_XDP]) * Id[i] + efd[i]) / q[FD_TDO];
@@ -757,7 +869,7 @@ static void rhs_fd(const model_t *m, const double *y, const double *w, double *d
         dy[4 * n + i] = (-vr[i] + q[FD_KA] * rf[i] - q[FD_KA] * q[FD_KF] / q[FD_TF] * efd[i] +
                          q[FD_KA] * (m->Vref[i] - Vt[i])) / q[FD_TA];
     }
-    for (int p = 0; p < P; ++p) dy[6 * n + p] = -m->theta[p] * xi[p] + diffusion(m, p, w);
+    for (int p = 0; p < P; ++p) dy[6 * n + p] = proc_rhs(m, p, xi[p], w);
 }
 
 /* Exciter and field states at the operating point (delta0, E'q0 = E): every
@@ -822,6 +934,26 @@ static int setup_model(const orc_problem *pb, model_t *m)
     m->Vinf = pb->V_inf;
     m->dgen = pb->dist_gen; m->theta = pb->theta; m->sigma = pb->sigma; m->xi0 = pb->xi0;
     m->sigma_mat = pb->sigma_mat;
+    m->proc = pb->proc;
+    m->ito_c = pb->calculus == ORC_ITO ? (pb->basis == 2 ? 0.375 : 0.5) : 0.0;
+    if (pb->calculus != ORC_ITO && pb->calculus != ORC_STRATONOVICH) return ORC_EINVAL;
+    if (pb->proc)
+        for (int p = 0; p < P; ++p) {
+            const orc_process *q = &pb->proc[p];
+            const double v[10] = {q->a, q->b, q->theta, q->mu[0], q->mu[1], q->mu[2],
+                                  q->sg[0], q->sg[1], q->sg[2], q->gain + q->ref};
+            for (int k = 0; k < 10; ++k)
+                if (!isfinite(v[k])) return ORC_EINVAL;
+            if (q->kind < ORC_PROC_OU || q->kind > ORC_PROC_POLY) return ORC_EINVAL;
+            if (q->kind >= ORC_PROC_GAUSS && q->kind <= ORC_PROC_LAPLACE && !(q->theta >= 0.0))
+                return ORC_EINVAL;
+            if ((q->kind == ORC_PROC_BETA || q->kind == ORC_PROC_GAMMA) && !(q->a > 0.0 && q->b > 0.0))
+                return ORC_EINVAL;
+            if ((q->kind == ORC_PROC_GAUSS || q->kind == ORC_PROC_LAPLACE) && !(q->b >= 0.0))
+                return ORC_EINVAL;
+            /* state-dependent diffusion has no column in the diffusion matrix */
+            if (pb->sigma_mat && q->kind != ORC_PROC_OU) return ORC_EINVAL;
+        }
     if (pb->sigma_mat)
         for (int q = 0; q < P * P; ++q)
             if (!isfinite(pb->sigma_mat[q])) return ORC_EINVAL;
@@ -995,6 +1127,7 @@ int orc_run(const orc_problem *pb, const double *zeta_in, int64_t n_sel, const i
     if (S < 1 || fabs((double)S * pb->dt - pb->T) > 1e-9 * pb->T) return ORC_EINVAL;
     const int64_t C = 2 * S + 1;
     if (pb->model == 1 && pb->integrator != 0) return ORC_EINVAL; /* RK4 only */
+    if (pb->proc && pb->integrator != 0) return ORC_EINVAL;       /* RK4 only */
     model_t m;
     int rc = setup_model(pb, &m);
     if (rc != ORC_OK) { free_model(&m); return rc; }
@@ -1123,7 +1256,7 @@ int orc_rhs_jac(const orc_problem *pb, const double *y, double *J)
 {
     model_t m;
     int rc = setup_model(pb, &m);
-    if (rc == ORC_OK && m.fd) rc = ORC_EINVAL;
+    if (rc == ORC_OK && (m.fd || m.proc)) rc = ORC_EINVAL; /* classical OU model only */
     if (rc == ORC_OK) rhs_jac(&m, y, J);
     free_model(&m);
     return rc;

@@ -15,7 +15,12 @@ Scenario dict keys (consumed by both ``oracle.run`` and the product binding):
   n_gen, f0, H, D, E [n], delta0 [n] or None, Pm [n] or None,
   Y (complex [n, n]) or None, net (network dict) when Y is None,
   infinite_bus, V_inf, Yinf (complex [n]),
-  dist = {gen [P] int, theta [P], sigma [P], xi0 [P] or None},
+  dist = {gen [P] int, theta [P], sigma [P], xi0 [P] or None, and optionally
+          proc [P] (general Ito processes: dicts with kind 'ou' | 'gauss' |
+          'beta' | 'gamma' | 'laplace' (Table I rows, with a, b, theta) |
+          'poly' (mu and sg, three polynomial coefficients each, eq. 11), and
+          gain, ref: the process enters its machine's power as gain (xi - ref))},
+  calculus ('ito' | 'stratonovich'),
   T, dt, K, N, seed, basis ('paper'|'eigen'), sampler ('lhs'|'srs'),
   integrator ('rk4'|'trap'), ddof, and optionally model ('classical' |
   'fluxdecay') with model_params [n, 9] (Xd, X'd, T'do, KA, TA, KE, TE, KF, TF).
@@ -173,6 +178,35 @@ def smib_fluxdecay(Xe=0.4, Xd=1.6, Xdp=0.3, Tdo=6.0, KA=30.0, TA=0.05, KE=1.0, T
         T=d["T"], dt=d["dt"], K=d["K"], N=d["N"], seed=d["seed"], basis="paper",
         sampler="lhs", integrator="rk4", ddof=1, model="fluxdecay",
         model_params=np.array([[Xd, Xdp, Tdo, KA, TA, KE, TE, KF, TF]]))
+
+
+# The polynomial Ito model of the per-unit wind power identified in the
+# paper's case study (eq. 11): drift and diffusion coefficients of 1, P, P^2.
+WIND_MU = (0.0535, -0.0899, 0.0349)
+WIND_SIGMA = (-0.410, 0.919, -0.505)
+
+
+def with_processes(sc: dict, specs, calculus: str = "ito", xi0=None) -> dict:
+    """A copy of scenario ``sc`` whose P disturbances are the general Ito
+    processes ``specs`` (one dict per process, module docstring), with the
+    initial values ``xi0`` (default: zero)."""
+    d = dict(sc["dist"])
+    P = len(d["gen"])
+    assert len(specs) == P
+    d["proc"] = [dict(s) for s in specs]
+    if xi0 is not None:
+        d["xi0"] = np.asarray(xi0, dtype=np.float64).reshape(P)
+    out = dict(sc, dist=d, calculus=calculus)
+    return out
+
+
+def wind_smib(N=1000, K=100, T=60.0, dt=0.01, seed=11, gain=1.0, P0=0.9, **kw):
+    """The single machine driven by the wind model of eq. 11: the wind power
+    P_t starts at P0 and enters the machine as gain (P_t - P0), so that t = 0
+    is the operating point."""
+    sc = smib(N=N, K=K, T=T, dt=dt, seed=seed, **kw)
+    spec = dict(kind="poly", mu=WIND_MU, sg=WIND_SIGMA, gain=gain, ref=P0)
+    return with_processes(sc, [spec], xi0=[P0])
 
 
 def config1(**kw):
