@@ -4,7 +4,8 @@
  * Power Systems Under Continuous Random Disturbances" (arXiv 2007.03847).
  *
  * The method (Alg. 1 of the paper): model each continuous disturbance as an
- * Ito process (eq. 4; here Ornstein-Uhlenbeck, the Gaussian row of Table I),
+ * Ito process (eq. 4: Ornstein-Uhlenbeck by default, or the general scalar
+ * processes of fmc_process: Table I's rows and the wind model of eq. 11),
  * replace each driving Wiener increment by its Karhunen-Loeve expansion
  * truncated at order K (eqs. 6-8), draw the M = P*K standard-normal
  * coefficients by Latin hypercube sampling (Sec. IV-B), rebuild every
@@ -46,7 +47,7 @@
 extern "C" {
 #endif
 
-#define FMC_ABI_VERSION 3
+#define FMC_ABI_VERSION 4
 
 /* Status codes. */
 #define FMC_OK 0
@@ -184,9 +185,51 @@ typedef struct fmc_system {
 #define FMC_FD_TF 8    /* rate-feedback time constant (s) */
 #define FMC_FD_NPARAM 9
 
-/* Ornstein-Uhlenbeck disturbances (eq. 4 with mu = -theta xi, constant
- * sigma): d xi_p = -theta_p xi_p dt + sigma_p dW_p, added to Pm of machine
- * gen[p].  Host arrays of length n_proc. */
+/* General scalar Ito disturbances (eq. 4 with state-dependent drift mu and
+ * diffusion sigma; Sec. III, Table I; the wind model of eq. 11).  Table I gives,
+ * per stationary density, the drift and squared diffusion of a unit-rate
+ * process; the rate theta (>= 0) scales both, which keeps the named density
+ * stationary:
+ *   FMC_PROC_GAUSS   (a, b >= 0): mu = -theta (xi - a),        sigma^2 = 2 theta b
+ *   FMC_PROC_BETA    (a, b > 0):  mu = -theta (xi - a/(a+b)),  sigma^2 = 2 theta xi (1 - xi)/(a+b)
+ *   FMC_PROC_GAMMA   (a, b > 0):  mu = -theta (xi - a/b),      sigma^2 = 2 theta xi / b
+ *   FMC_PROC_LAPLACE (a, b >= 0): mu = -theta (xi - a),        sigma^2 = theta (2b |xi - a| + 2b^2)
+ * (b is the Gaussian row's variance and the Laplace row's scale; where
+ * sigma^2 < 0, outside the support, sigma is 0), and
+ *   FMC_PROC_POLY: mu = mu[0] + mu[1] xi + mu[2] xi^2,  sigma = sg[0] + sg[1] xi + sg[2] xi^2
+ * (eq. 11 is of this form).  FMC_PROC_OU keeps theta[p] and sigma[p] of
+ * fmc_disturbance (or its sigma_mat).  Every process enters the power balance
+ * of machine gen[p] as gain (xi - ref): gain 1 and ref 0 give the OU
+ * convention.  Fields a kind does not use are ignored (they must be finite). */
+#define FMC_PROC_OU 0
+#define FMC_PROC_GAUSS 1
+#define FMC_PROC_BETA 2
+#define FMC_PROC_GAMMA 3
+#define FMC_PROC_LAPLACE 4
+#define FMC_PROC_POLY 5
+typedef struct fmc_process {
+    int32_t kind;
+    double a, b, theta;
+    double mu[3], sg[3];
+    double gain, ref;
+} fmc_process;
+
+/* Which solution of eq. 4 the paths approximate.  The KLE paths (eq. 8) are
+ * smooth, so eq. 9 is an ordinary differential equation whose solutions
+ * converge, as K grows, to the Stratonovich solution of eq. 4 (the
+ * Wong-Zakai limit).  FMC_ITO integrates eq. 9 with the drift mu - c sigma
+ * sigma', c = 1/2, whose Stratonovich solution is the Ito process of eq. 4;
+ * with the one-hot basis FMC_BASIS_EM, whose RK4 step carries a noise-induced
+ * drift of (3/8) sigma sigma' of its own, c = 3/8.  FMC_STRATONOVICH
+ * integrates eq. 9 as written.  The two agree for additive noise (OU and the
+ * Gaussian row). */
+#define FMC_ITO 0
+#define FMC_STRATONOVICH 1
+
+/* The disturbances: by default Ornstein-Uhlenbeck processes (eq. 4 with
+ * mu = -theta xi, constant sigma): d xi_p = -theta_p xi_p dt + sigma_p dW_p,
+ * added to Pm of machine gen[p]; proc makes any of them a general process
+ * (fmc_process above).  Host arrays of length n_proc. */
 typedef struct fmc_disturbance {
     int32_t n_proc;
     const int32_t *gen;
@@ -198,6 +241,12 @@ typedef struct fmc_disturbance {
      * unused (may be NULL).  The design's rows stay the KLE coefficients of the
      * independent W_q.  fmc_run only: the batched and served forms reject it. */
     const double *sigma_mat;
+    /* NULL (every process OU), or host [n_proc] process specs (fmc_process).
+     * fmc_run with FMC_RK4 and the classical model only: the implicit
+     * trapezoid, the flux-decay model and the batched and served forms
+     * reject them, as does sigma_mat with a non-OU process. */
+    const fmc_process *proc;
+    int32_t calculus; /* FMC_ITO (0) or FMC_STRATONOVICH */
 } fmc_disturbance;
 
 /* Alg. 1 inputs: truncation order K, sample size N, horizon T and step dt. */

@@ -39,7 +39,7 @@ CLASSICAL, FLUXDECAY_IEEET1 = 0, 1
 MODEL = {"classical": CLASSICAL, "fluxdecay": FLUXDECAY_IEEET1}
 FD_NPARAM = 9  # Xd, X'd, T'do, KA, TA, KE, TE, KF, TF
 MEM_HOST, MEM_DEVICE = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 _P = C.c_void_p
 
@@ -70,9 +70,19 @@ class System(C.Structure):
                 ("event", C.POINTER(Event))]
 
 
+class Process(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("a", C.c_double), ("b", C.c_double),
+                ("theta", C.c_double), ("mu", C.c_double * 3), ("sg", C.c_double * 3),
+                ("gain", C.c_double), ("ref", C.c_double)]
+
+
+PROC_KIND = {"ou": 0, "gauss": 1, "beta": 2, "gamma": 3, "laplace": 4, "poly": 5}
+CALCULUS = {"ito": 0, "stratonovich": 1}
+
+
 class Disturbance(C.Structure):
     _fields_ = [("n_proc", C.c_int32), ("gen", _P), ("theta", _P), ("sigma", _P), ("xi0", _P),
-                ("sigma_mat", _P)]
+                ("sigma_mat", _P), ("proc", C.POINTER(Process)), ("calculus", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -239,8 +249,22 @@ def scenario_structs(sc: dict, precision="f64", variant=-1, time_chunk=0, zeta_i
              xi0=_f64(d.get("xi0")),
              sigma_mat=None if sm is None else _f64(np.asarray(sm, dtype=np.float64).reshape(-1)))
     keep.append(b)
+    procs = None
+    if d.get("proc") is not None:
+        procs = (Process * len(d["proc"]))()
+        for q, spec in zip(procs, d["proc"]):
+            q.kind = _enum(spec.get("kind", "ou"), PROC_KIND)
+            q.a, q.b = float(spec.get("a", 0.0)), float(spec.get("b", 0.0))
+            q.theta = float(spec.get("theta", 0.0))
+            for j, v in enumerate(spec.get("mu", (0.0, 0.0, 0.0))):
+                q.mu[j] = float(v)
+            for j, v in enumerate(spec.get("sg", (0.0, 0.0, 0.0))):
+                q.sg[j] = float(v)
+            q.gain, q.ref = float(spec.get("gain", 1.0)), float(spec.get("ref", 0.0))
+        keep.append(procs)
     dist = Disturbance(n_proc=len(b["gen"]), gen=_ptr(b["gen"]), theta=_ptr(b["theta"]),
-                       sigma=_ptr(b["sigma"]), xi0=_ptr(b["xi0"]), sigma_mat=_ptr(b["sigma_mat"]))
+                       sigma=_ptr(b["sigma"]), xi0=_ptr(b["xi0"]), sigma_mat=_ptr(b["sigma_mat"]),
+                       proc=procs, calculus=_enum(sc.get("calculus", "ito"), CALCULUS))
     par = Params(T=float(sc["T"]), dt=float(sc["dt"]), K=int(sc["K"]), N=int(sc["N"]),
                  seed=int(sc.get("seed", 0)), basis=_enum(sc.get("basis", 0), BASIS),
                  sampler=_enum(sc.get("sampler", 0), SAMPLER),

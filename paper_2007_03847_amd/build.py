@@ -18,7 +18,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 SOURCES = ["fmc_runtime.hip", "fmc_run.hip", "fmc_fd.hip", "fmc_batch.hip", "fmc_serve.hip", "k_decor.hip", "k_rrf.hip",
            "k_sample.hip", "k_setup.hip", "k_fluxdecay.hip", "k_batch.hip", "k_mfma_classical.hip",
-           "k_integrate_f64.hip", "k_integrate_f32.hip", "k_trap.hip"]
+           "k_integrate_f64.hip", "k_integrate_f32.hip", "k_integrate_gen_f64.hip",
+           "k_integrate_gen_f32.hip", "k_trap.hip"]
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # Per-source flags.  The KLE contractions keep their accumulators in the

@@ -202,6 +202,9 @@ int run_batch_impl(Context* c, int32_t nsc, const fmc_scenario* scen, fmc_output
     if (p.dist->sigma_mat)
       return fail(FMC_EINVAL, "scenario " + std::to_string(i) +
                                   ": a diffusion matrix runs through fmc_run only");
+    if (p.dist->proc)
+      return fail(FMC_EINVAL, "scenario " + std::to_string(i) +
+                                  ": general Ito processes run through fmc_run only");
     if (p.sys->model != FMC_CLASSICAL)
       return fail(FMC_EINVAL, "scenario " + std::to_string(i) +
                                   ": the batched form runs classical machines (flux-decay "

@@ -96,7 +96,18 @@ struct IntegArgs {
   const double* rrf_w;  // [V] or null
   double* rrf_acc;      // [N]
   double* rrf;          // [N]
+  // General Ito disturbances (eq. 4 with state-dependent drift and diffusion):
+  // null (every process OU, from the packed theta and sigma), or [P][kSdeCols]
+  // rows of the normalised form below, one per process.
+  const R* sde;
 };
+// A process row: form (1: sigma = c0 + c1 xi + c2 xi^2; 2: sigma = sqrt(g),
+// g = c0 + c1 xi + c2 xi^2 + c3 |xi - r|, sigma = 0 where g <= 0), drift
+// m0 + m1 xi + m2 xi^2, the drift correction -k sigma sigma' (k = 1/2, 3/8
+// or 0 by calculus and basis), and the injection gain (xi - ref).
+constexpr int kSdeCols = 12;
+enum SdeCol { SDE_FORM, SDE_M0, SDE_M1, SDE_M2, SDE_C0, SDE_C1, SDE_C2, SDE_C3, SDE_R, SDE_K,
+              SDE_GAIN, SDE_REF };
 // State rows of the per-trajectory common-angle offset: the two 32-bit
 // halves of the FP64 offset and, in the flux-decay state, the mean angle
 // left by the last step (taken out at the next step).
@@ -195,6 +206,12 @@ int n_variants();
 const VariantInfo& variant(int i);
 hipError_t launch_integrate_f64(int variant_id, const IntegArgs<double>& a, int64_t n_groups,
                                 hipStream_t st);
+// General Ito processes (IntegArgs::sde set): the one-trajectory-per-lane
+// variants, compiled separately.
+hipError_t launch_integrate_gen_f64(int variant_id, const IntegArgs<double>& a, int64_t n_groups,
+                                    hipStream_t st);
+hipError_t launch_integrate_gen_f32(int variant_id, const IntegArgs<float>& a, int64_t n_groups,
+                                    hipStream_t st);
 hipError_t launch_integrate_f32(int variant_id, const IntegArgs<float>& a, int64_t n_groups,
                                 hipStream_t st);
 // Implicit trapezoid (FP64, classical machines) on the shape of a

@@ -48,6 +48,68 @@ struct ChunkTimes {
 
 
 
+// The general Ito processes as normalised rows (IntegArgs::sde), from the
+// rows of Table I (rate theta scaling drift and squared diffusion) and the
+// polynomial form of eq. 11; an OU spec becomes the polynomial form with
+// drift -theta xi and constant diffusion sigma.  PM rows (the variant's
+// process slots; rows past n_proc are zero: no drift, diffusion or
+// injection).  False when every process is the plain OU of theta and sigma
+// (no table).
+static bool sde_table(const fmc_disturbance* dist, int basis, int PM, std::vector<double>& t) {
+  if (!dist->proc) return false;
+  const int P = dist->n_proc;
+  t.assign((size_t)PM * kSdeCols, 0.0);
+  // Wong-Zakai: the KLE ODE's limit is the Stratonovich solution; the Ito
+  // process needs -sigma sigma'/2 in the drift, the one-hot basis (whose RK4
+  // step carries (3/8) sigma sigma' of its own) -3/8.
+  const double k =
+      dist->calculus == FMC_ITO ? (basis == FMC_BASIS_EM ? 0.375 : 0.5) : 0.0;
+  for (int p = 0; p < P; ++p) {
+    const fmc_process& q = dist->proc[p];
+    double* r = &t[(size_t)p * kSdeCols];
+    const double th = q.theta, a = q.a, b = q.b;
+    r[SDE_FORM] = 2.0;
+    r[SDE_M1] = -th;
+    switch (q.kind) {
+      case FMC_PROC_OU:
+        r[SDE_FORM] = 1.0;
+        r[SDE_M1] = -dist->theta[p];
+        r[SDE_C0] = dist->sigma[p];
+        break;
+      case FMC_PROC_GAUSS:  // mu = -theta (xi - a), sigma^2 = 2 theta b
+        r[SDE_M0] = th * a;
+        r[SDE_C0] = 2.0 * th * b;
+        break;
+      case FMC_PROC_BETA:  // mu = -theta (xi - a/(a+b)), sigma^2 = 2 theta xi (1 - xi)/(a+b)
+        r[SDE_M0] = th * a / (a + b);
+        r[SDE_C1] = 2.0 * th / (a + b);
+        r[SDE_C2] = -2.0 * th / (a + b);
+        break;
+      case FMC_PROC_GAMMA:  // mu = -theta (xi - a/b), sigma^2 = 2 theta xi / b
+        r[SDE_M0] = th * a / b;
+        r[SDE_C1] = 2.0 * th / b;
+        break;
+      case FMC_PROC_LAPLACE:  // mu = -theta (xi - a), sigma^2 = theta (2b|xi - a| + 2b^2)
+        r[SDE_M0] = th * a;
+        r[SDE_C0] = 2.0 * th * b * b;
+        r[SDE_C3] = 2.0 * th * b;
+        r[SDE_R] = a;
+        break;
+      default:  // FMC_PROC_POLY
+        r[SDE_FORM] = 1.0;
+        for (int j = 0; j < 3; ++j) {
+          r[SDE_M0 + j] = q.mu[j];
+          r[SDE_C0 + j] = q.sg[j];
+        }
+        break;
+    }
+    r[SDE_K] = k;
+    r[SDE_GAIN] = q.gain;
+    r[SDE_REF] = q.ref;
+  }
+  return true;
+}
+
 template <typename R>
 int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t S, int64_t N,
                double wb, const double* zeta, const double* phi, const R* coef,
@@ -55,7 +117,7 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
                unsigned long long* cnt_d, int64_t Sc, double* mean_d, double* var_d,
                int recenter, bool trap, const void* const* s16, const R* coef_post,
                int64_t s_event, int n_ref_post, const double* rrf_w, double* rrf_acc,
-               double* rrf_d, EventPool& evp, ChunkTimes& ct) {
+               double* rrf_d, const R* sde, EventPool& evp, ChunkTimes& ct) {
   const VariantInfo& vi = variant(vid);
   const int V = 2 * n + P;
   const int64_t C = 2 * S + 1;
@@ -107,6 +169,7 @@ int run_chunks(Context* c, const fmc_params* par, int vid, int n, int P, int64_t
   a.rrf_w = rrf_w;
   a.rrf_acc = rrf_acc;
   a.rrf = rrf_d;
+  a.sde = sde;
   // With a network event, a chunk ends at the event step and the chunks from
   // there on run with the post-event coefficients.
   int64_t k = 0, prev0 = 0, last0 = 0;
@@ -210,14 +273,17 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   const bool dev_out = out->mem_kind == FMC_MEM_DEVICE;
   const bool f64 = par->precision == FMC_F64;
   const int bw = f64 ? 8 : 4;
-  // the implicit trapezoid runs on the shapes of the one-trajectory-per-lane
-  // variants (the smallest that fits, or the one asked for)
+  // the implicit trapezoid and the general Ito processes run on the shapes of
+  // the one-trajectory-per-lane variants (the smallest that fits, or the one
+  // asked for)
   const bool trap = par->integrator == FMC_TRAP;
-  int vid = par->variant >= 0 ? par->variant : (trap ? -1 : pick_variant(c, n, P, N, par->precision));
-  if (trap && vid < 0) {
+  const bool lane_only = trap || dist->proc != nullptr;
+  int vid = par->variant >= 0 ? par->variant
+                              : (lane_only ? -1 : pick_variant(c, n, P, N, par->precision));
+  if (lane_only && vid < 0) {
     for (int i = 0; i < n_variants(); ++i) {
       const VariantInfo& v = variant(i);
-      if (v.L != 1 || v.NG < n || v.PM < P || v.NG > kTrapMaxGen) continue;
+      if (v.L != 1 || v.NG < n || v.PM < P || (trap && v.NG > kTrapMaxGen)) continue;
       if (vid < 0 || v.NG * v.NG + v.PM < variant(vid).NG * variant(vid).NG + variant(vid).PM) vid = i;
     }
   }
@@ -228,6 +294,8 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   if (trap && (vi.L != 1 || vi.NG > kTrapMaxGen))
     return fail(FMC_EINVAL, "the implicit trapezoid runs on one-trajectory-per-lane variants of at "
                             "most 16 machines");
+  if (dist->proc && vi.L != 1)
+    return fail(FMC_EINVAL, "general Ito processes run on one-trajectory-per-lane variants");
   const double f0 = sys->f0_hz > 0.0 ? sys->f0_hz : 60.0;
   const double wb = 2.0 * M_PI * f0;
 
@@ -425,6 +493,23 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
       rrf_dev = (double*)p;
     }
   }
+  // the general Ito processes' rows, in the integrator's arithmetic type
+  const void* sde_d = nullptr;
+  {
+    std::vector<double> tab;
+    if (sde_table(dist, par->basis, variant(vid).PM, tab)) {
+      void *p = nullptr, *h = nullptr;
+      const size_t bytes = tab.size() * bw;
+      if ((rc = c->ensure("sde", bytes, &p))) return rc;
+      if ((rc = c->host_stage("sde", bytes, &h))) return rc;
+      for (size_t q = 0; q < tab.size(); ++q) {
+        if (f64) ((double*)h)[q] = tab[q];
+        else ((float*)h)[q] = (float)tab[q];
+      }
+      HIPCHK(hipMemcpyAsync(p, h, bytes, hipMemcpyHostToDevice, c->stream));
+      sde_d = p;
+    }
+  }
   const int64_t Sc = par->time_chunk > 0 ? std::min<int64_t>(par->time_chunk, S)
                                          : auto_chunk(S, P, N, bw);
   double *mean_d = out->mean, *var_d = out->var;
@@ -441,13 +526,13 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
                             (const double*)coef, delta0_d, (double*)partial, slot_d, traj_d,
                             (unsigned long long*)cnt, Sc, mean_d, var_d, sys->infinite_bus ? 0 : 1, trap, s16,
                             (const double*)coef_post, s_event, n_ref_post, rrf_wd, rrf_acc,
-                            rrf_dev, evp, ct);
+                            rrf_dev, (const double*)sde_d, evp, ct);
   else
     rc = run_chunks<float>(c, par, vid, n, P, S, N, wb, zeta, (const double*)phi,
                            (const float*)coef, delta0_d, (double*)partial, slot_d, traj_d,
                            (unsigned long long*)cnt, Sc, mean_d, var_d, sys->infinite_bus ? 0 : 1, trap, s16,
                            (const float*)coef_post, s_event, n_ref_post, rrf_wd, rrf_acc,
-                           rrf_dev, evp, ct);
+                           rrf_dev, (const float*)sde_d, evp, ct);
   if (rc) return rc;
   // statistics: merged per chunk on the second stream, joined into c->stream
   const int ev_end = evp.record();

@@ -346,6 +346,28 @@ int validate(const fmc_system* sys, const fmc_disturbance* dist, const fmc_param
   if (dist->sigma_mat)
     for (int q = 0; q < dist->n_proc * dist->n_proc; ++q)
       if (!std::isfinite(dist->sigma_mat[q])) return fail(FMC_EINVAL, "sigma_mat must be finite");
+  if (dist->calculus != FMC_ITO && dist->calculus != FMC_STRATONOVICH)
+    return fail(FMC_EINVAL, "calculus must be FMC_ITO or FMC_STRATONOVICH");
+  if (dist->proc) {
+    if (par->integrator != FMC_RK4 || sys->model != FMC_CLASSICAL)
+      return fail(FMC_EINVAL, "general Ito processes run with FMC_RK4 on classical machines");
+    for (int p = 0; p < dist->n_proc; ++p) {
+      const fmc_process& q = dist->proc[p];
+      const double v[11] = {q.a, q.b, q.theta, q.mu[0], q.mu[1], q.mu[2],
+                            q.sg[0], q.sg[1], q.sg[2], q.gain, q.ref};
+      for (double x : v)
+        if (!std::isfinite(x)) return fail(FMC_EINVAL, "process parameters must be finite");
+      if (q.kind < FMC_PROC_OU || q.kind > FMC_PROC_POLY) return fail(FMC_EINVAL, "unknown process kind");
+      if (q.kind >= FMC_PROC_GAUSS && q.kind <= FMC_PROC_LAPLACE && !(q.theta >= 0.0))
+        return fail(FMC_EINVAL, "a Table I process needs theta >= 0");
+      if ((q.kind == FMC_PROC_BETA || q.kind == FMC_PROC_GAMMA) && !(q.a > 0.0 && q.b > 0.0))
+        return fail(FMC_EINVAL, "the Beta and Gamma rows need a, b > 0");
+      if ((q.kind == FMC_PROC_GAUSS || q.kind == FMC_PROC_LAPLACE) && !(q.b >= 0.0))
+        return fail(FMC_EINVAL, "the Gaussian and Laplace rows need b >= 0");
+      if (dist->sigma_mat && q.kind != FMC_PROC_OU)
+        return fail(FMC_EINVAL, "a state-dependent diffusion has no column in sigma_mat");
+    }
+  }
   if (par->sampler == FMC_LHS_DECOR && !par->zeta_in) {
     const int64_t M = (int64_t)dist->n_proc * par->K;
     if (M > kDecorMaxM || par->N <= M || par->N > kDecorMaxN)
@@ -704,9 +726,15 @@ int fmc_autotune(fmc_context* ctx, const fmc_scenario* scen, int32_t* variant_ou
   if ((rc = c->ensure("tune_var", (size_t)(St + 1) * V * sizeof(double), &v))) return rc;
   int best = -1;
   double best_t = 0.0;
+  // the implicit trapezoid and the general Ito processes run on the
+  // one-trajectory-per-lane variants only (fmc_run picks among those itself,
+  // so such a choice is returned but not kept for the scenario's shape)
+  const bool trap = scen->par->integrator == FMC_TRAP;
+  const bool lane_only = trap || scen->dist->proc != nullptr;
   for (int id = 0; id < n_variants(); ++id) {
     const VariantInfo& vi = variant(id);
     if (vi.NG < n || vi.PM < P) continue;
+    if (lane_only && (vi.L != 1 || (trap && vi.NG > kTrapMaxGen))) continue;
     par.variant = id;
     fmc_report rep;
     fmc_outputs out{};
@@ -729,9 +757,11 @@ int fmc_autotune(fmc_context* ctx, const fmc_scenario* scen, int32_t* variant_ou
     }
   }
   if (best < 0) return fail(FMC_EINVAL, "no integrator variant fits the scenario");
-  const std::string key = tune_key(n, P, N, scen->par->precision);
-  c->tuned[key] = best;
-  save_tune_entry(key, best);
+  if (!lane_only) {
+    const std::string key = tune_key(n, P, N, scen->par->precision);
+    c->tuned[key] = best;
+    save_tune_entry(key, best);
+  }
   *variant_out = best;
   return FMC_OK;
 }

@@ -765,6 +765,7 @@ int fmc_submit(fmc_context* ctx, const fmc_scenario* scen, fmc_outputs* out, uin
   if (scen->par->sampler == FMC_LHS_DECOR)
     return fail(FMC_EINVAL, "FMC_LHS_DECOR runs through fmc_run only");
   if (scen->dist->sigma_mat) return fail(FMC_EINVAL, "a diffusion matrix runs through fmc_run only");
+  if (scen->dist->proc) return fail(FMC_EINVAL, "general Ito processes run through fmc_run only");
   if (scen->sys->event) return fail(FMC_EINVAL, "network events run through fmc_run only");
   if (scen->par->integrator != FMC_RK4)
     return fail(FMC_EINVAL, "the implicit trapezoid runs through fmc_run only");

@@ -107,18 +107,51 @@ __device__ __forceinline__ double load_offset(const double* st, int64_t i0, int6
   return st[i0];
 }
 
-// Right-hand side of the swing equations + OU disturbances in deviation form.
-template <typename R, int NG, int PM>
-__device__ __forceinline__ void swing_rhs(const R* cfg, const R wb, const R (&yd)[NG],
-                                          const R (&yw)[NG], const R (&yx)[PM],
-                                          const R (&wv)[PM], R (&kd)[NG], R (&kw)[NG],
-                                          R (&kx)[PM]) {
+// d xi/dt of eq. 9 for a general Ito process (one row of IntegArgs::sde) at
+// state x with white-noise surrogate value w, and the power it injects into
+// its machine, gain (x - ref).
+template <typename R, typename Ptr>
+__device__ __forceinline__ R sde_rhs(Ptr q, R x, R w, R& inj) {
+  const R mu = q[SDE_M0] + x * (q[SDE_M1] + x * q[SDE_M2]);
+  R sg, ssp;  // sigma and sigma sigma'
+  if (q[SDE_FORM] == R(2)) {
+    const R d = x - q[SDE_R];
+    const R g = q[SDE_C0] + x * (q[SDE_C1] + x * q[SDE_C2]) + q[SDE_C3] * fabs(d);
+    const R sgn = d > R(0) ? R(1) : (d < R(0) ? R(-1) : R(0));
+    const R dg = q[SDE_C1] + R(2) * q[SDE_C2] * x + q[SDE_C3] * sgn;
+    const bool pos = g > R(0);
+    sg = pos ? sqrt(g) : R(0);
+    ssp = pos ? R(0.5) * dg : R(0);
+  } else {
+    sg = q[SDE_C0] + x * (q[SDE_C1] + x * q[SDE_C2]);
+    ssp = sg * (q[SDE_C1] + R(2) * q[SDE_C2] * x);
+  }
+  inj = q[SDE_GAIN] * (x - q[SDE_REF]);
+  return mu - q[SDE_K] * ssp + sg * w;
+}
+
+// Right-hand side of the swing equations + the disturbances in deviation
+// form: OU from the packed theta and sigma, or (GEN) the general processes of
+// sdeg.  GEN is a separate instantiation so that the OU kernels keep their
+// register allocation.
+template <typename R, int NG, int PM, bool GEN>
+__device__ __forceinline__ void swing_rhs(const R* cfg, const R* sdeg, const R wb,
+                                          const R (&yd)[NG], const R (&yw)[NG],
+                                          const R (&yx)[PM], const R (&wv)[PM], R (&kd)[NG],
+                                          R (&kw)[NG], R (&kx)[PM]) {
   constexpr PackLayout L{NG, PM};
   // Re-derive the pointer at every stage: the compiler then streams the
   // machine data through scalar loads instead of keeping it live in (spilled)
   // registers across stages and steps.
   asm volatile("" : "+s"(cfg));
   const cptr<R> cf = (cptr<R>)cfg;
+  // general processes first: their injections feed the machines
+  R xin[GEN ? PM : 1];
+  if constexpr (GEN) {
+    const cptr<R> sq = (cptr<R>)sdeg;
+#pragma unroll
+    for (int p = 0; p < PM; ++p) kx[p] = sde_rhs<R>(sq + p * kSdeCols, yx[p], wv[p], xin[p]);
+  }
   R dc[NG], ds[NG];
 #pragma unroll
   for (int k = 0; k < NG; ++k) {
@@ -147,12 +180,19 @@ __device__ __forceinline__ void swing_rhs(const R* cfg, const R wb, const R (&yd
                   (cf[L.c0() + i] + dc[i]) * ir + (cf[L.s0() + i] + ds[i]) * ii;
     R F = cf[L.res() + i] - dpe - cf[L.dmp() + i] * yw[i];
 #pragma unroll
-    for (int p = 0; p < PM; ++p) F += cf[L.binc() + i * PM + p] * yx[p];
+    for (int p = 0; p < PM; ++p) {
+      if constexpr (GEN)
+        F += cf[L.binc() + i * PM + p] * xin[p];
+      else
+        F += cf[L.binc() + i * PM + p] * yx[p];
+    }
     kd[i] = wb * yw[i];
     kw[i] = F * cf[L.inv2h() + i];
   }
+  if constexpr (!GEN) {
 #pragma unroll
-  for (int p = 0; p < PM; ++p) kx[p] = -cf[L.theta() + p] * yx[p] + cf[L.sigma() + p] * wv[p];
+    for (int p = 0; p < PM; ++p) kx[p] = -cf[L.theta() + p] * yx[p] + cf[L.sigma() + p] * wv[p];
+  }
 }
 
 // u = sum_v w_v y_v of one trajectory held whole by one lane (absolute angles
@@ -222,7 +262,7 @@ __device__ __forceinline__ void emit_step(const IntegArgs<R>& a, double (*tile)[
   __syncthreads();
 }
 
-template <typename R, int NG, int PM>
+template <typename R, int NG, int PM, bool GEN = false>
 __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
   constexpr PackLayout L{NG, PM};
   constexpr int VM = 2 * NG + PM;
@@ -292,7 +332,7 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
     R ad[NG], aw[NG], ax[PM];
     R td[NG], tw[NG], tx[PM];
     // stage 1
-    swing_rhs<R, NG, PM>(cf, wb, yd, yw, yx, w0, kd, kw, kx);
+    swing_rhs<R, NG, PM, GEN>(cf, GEN ? a.sde : nullptr, wb, yd, yw, yx, w0, kd, kw, kx);
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
       ad[i] = kd[i]; aw[i] = kw[i];
@@ -301,7 +341,7 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
 #pragma unroll
     for (int p = 0; p < PM; ++p) { ax[p] = kx[p]; tx[p] = yx[p] + h2 * kx[p]; }
     // stage 2
-    swing_rhs<R, NG, PM>(cf, wb, td, tw, tx, w1, kd, kw, kx);
+    swing_rhs<R, NG, PM, GEN>(cf, GEN ? a.sde : nullptr, wb, td, tw, tx, w1, kd, kw, kx);
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
       ad[i] += R(2) * kd[i]; aw[i] += R(2) * kw[i];
@@ -310,7 +350,7 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
 #pragma unroll
     for (int p = 0; p < PM; ++p) { ax[p] += R(2) * kx[p]; tx[p] = yx[p] + h2 * kx[p]; }
     // stage 3
-    swing_rhs<R, NG, PM>(cf, wb, td, tw, tx, w1, kd, kw, kx);
+    swing_rhs<R, NG, PM, GEN>(cf, GEN ? a.sde : nullptr, wb, td, tw, tx, w1, kd, kw, kx);
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
       ad[i] += R(2) * kd[i]; aw[i] += R(2) * kw[i];
@@ -319,7 +359,7 @@ __global__ void __launch_bounds__(64) k_rk4_lane(IntegArgs<R> a) {
 #pragma unroll
     for (int p = 0; p < PM; ++p) { ax[p] += R(2) * kx[p]; tx[p] = yx[p] + dt * kx[p]; }
     // stage 4
-    swing_rhs<R, NG, PM>(cf, wb, td, tw, tx, w2, kd, kw, kx);
+    swing_rhs<R, NG, PM, GEN>(cf, GEN ? a.sde : nullptr, wb, td, tw, tx, w2, kd, kw, kx);
 #pragma unroll
     for (int i = 0; i < NG; ++i) {
       yd[i] += dt6 * (ad[i] + kd[i]);

@@ -9,6 +9,8 @@ hipError_t launch_integrate_f32(int variant_id, const IntegArgs<float>& a, int64
   int id = 0;
 #define FMC_X(NG, PM, L, WPB)                                                              \
   if (variant_id == id) {                                                                  \
+    if (a.sde) /* general Ito processes: their own instantiations */                      \
+      return launch_integrate_gen_f32(variant_id, a, n_groups, st);                      \
     if constexpr (L == 1)                                                                  \
       hipLaunchKernelGGL((k_rk4_lane<float, NG, PM>), dim3((unsigned)n_groups), dim3(64), 0,   \
                          st, a);                                                           \

@@ -48,7 +48,7 @@ def test_binding_exposes_every_symbol():
 
 def test_abi_version(lib):
     lib.fmc_abi_version.restype = C.c_int
-    assert lib.fmc_abi_version() == 3
+    assert lib.fmc_abi_version() == 4
 
 
 def test_footprint_and_validation_on_host():
