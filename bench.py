@@ -93,6 +93,32 @@ def per_output(gpu_mean, gpu_var, gpu_traj, o_mean, o_var, o_traj):
     return out
 
 
+def config1_leg(ctx, fmc, workloads, oracle_mod, steps: int):
+    """The single machine against an infinite bus (H = 3.5 s, D = 2, Pm = 0.8,
+    E = 1.1, X = 0.5; one OU disturbance, theta = 0.5, sigma = 0.05; T = 10 s,
+    dt = 0.01 s, K = 40, N = 1000) in FP64: trajectory-steps/s over whole runs
+    and the error of every output against the FP64 oracle."""
+    import numpy as np
+    import torch
+    sc = workloads.config1()
+    N, S = sc["N"], fmc.steps(sc)
+    ctx.run(sc, precision="f64")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = ctx.run(sc, precision="f64")
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    res = {"workload": "SMIB, N=1000, K=40, T=10 s, dt=0.01 s (1000 RK4 steps), FP64",
+           "ms_per_pass": t * 1e3, "trajectory_steps_per_s": N * S / t}
+    if oracle_mod is not None:
+        o = oracle_mod.run(sc)
+        res["error_vs_oracle"] = per_output(r["mean"].cpu().numpy(), r["var"].cpu().numpy(),
+                                            None, o["mean"], o["var"], None)
+    say(f"config1 f64: {t * 1e3:.2f} ms per pass, {N * S / t:.3e} traj-steps/s")
+    return res
+
+
 def config3_leg(ctx, fmc, workloads, oracle_mod, steps: int):
     """The mixed-precision workload (the 10-machine system with N = 1e5, LHS
     seed 3): every form timed over whole passes; error against the FP64 oracle
@@ -219,8 +245,18 @@ def batched_leg(ctx, fmc, workloads, oracle_mod, steps: int, with_fp64: bool):
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / steps
         say(f"batched {form}: {sec * 1e3:.1f} ms per pass")
+        # roofline of the summed integrator work (the scope table's count per
+        # trajectory-step, 32 n^2 + 60 n, summed over the scenarios) against
+        # the FP32 vector peak, and against the 78.6 TFLOP/s this build can
+        # reach without packed FP32
+        flops = sum(sc["N"] * fmc.steps(sc) * integrator_flops_survey(sc["n_gen"]) for sc in scs)
         entry = {"value": ts / sec, "unit": "trajectory-steps/s", "ms_per_pass": sec * 1e3,
-                 "variants": sorted({r["report"]["variant_id"] for r in res})}
+                 "variants": sorted({r["report"]["variant_id"] for r in res}),
+                 "roofline": {"bound": "alu", "flops_per_pass": flops,
+                              "achieved_tflops": flops / sec / 1e12,
+                              "peak_tflops": PEAK_FP32_VECTOR / 1e12,
+                              "frac": flops / sec / PEAK_FP32_VECTOR,
+                              "frac_of_unpacked_fp32": flops / sec / (PEAK_FP32_VECTOR / 2)}}
         if oracle_mod is not None:
             r = res[small]
             m, v = r["mean"].cpu().numpy(), r["var"].cpu().numpy()
@@ -281,8 +317,14 @@ def _poisson_stream(ctx, fmc, reqs, arrive, precision="bf16x3"):
     done_at = np.zeros(n_req)
     wait_q = list(range(n_req))
     refused = 0
+    refused_req = set()
+    last_note = 0.0
     while wait_q or pending:
         now = time.perf_counter() - t0
+        if now - last_note >= 30.0:  # a progress line while a long stream drains
+            last_note = now
+            say(f"stream: {now:.0f} s, {n_req - len(wait_q) - len(pending)} of {n_req} done, "
+                f"{len(pending)} in flight")
         while wait_q and arrive[wait_q[0]] <= now:
             i = wait_q[0]
             try:
@@ -292,26 +334,29 @@ def _poisson_stream(ctx, fmc, reqs, arrive, precision="bf16x3"):
                 if e.code != fmc.EBUSY:
                     raise
                 refused += 1
+                refused_req.add(i)
                 break
         for i in list(pending):
             if pending[i].poll() is not None:
                 done_at[i] = time.perf_counter() - t0
                 del pending[i]
         time.sleep(0.001)
+    _poisson_stream.refused_requests = len(refused_req)
     return done_at, refused
 
 
-def serve_sweep(fmc, workloads, oracle_mod, rates, n_max: int, seconds: float, seed: int = 11,
-                small_arena_mb: int = 1024):
+def serve_sweep(fmc, workloads, oracle_mod, rates, n_max: int, seconds: float, seed: int = 11):
     """The served form over Poisson rates: per rate min(n_max, seconds * rate)
     requests (nine in ten drawn from the 64 uneven classical scenarios, every
     tenth a large flux-decay request of 200 machines, T = 30 s, N = 5e4), in a
     context of its own; p50/p99 latency of small and large requests apart,
     completed requests and trajectory-steps per second.  Then one stream at
-    the middle rate through a small serving arena (FMC_SERVE_ARENA_BYTES), in
-    which admission by footprint refuses requests (EBUSY) and the client
-    retries; and one request of the large shape on a short horizon (N = 40)
-    against the oracle."""
+    the highest rate of the call, without the large requests, through a small
+    serving arena (FMC_SERVE_ARENA_BYTES: 1.2 times the largest small request's
+    footprint, so that two large ones never fit together), in which admission
+    by footprint refuses requests (EBUSY) and the client retries; and one
+    request of the large shape on a short horizon (N = 40) against the
+    oracle."""
     import numpy as np
     scs = workloads.uneven_batch()
     large = workloads.fluxdecay()
@@ -354,10 +399,11 @@ def serve_sweep(fmc, workloads, oracle_mod, rates, n_max: int, seconds: float, s
     out["saturation_req_per_s"] = max(e["completed_req_per_s"] for e in out["rates"])
     out["saturation_trajectory_steps_per_s"] = max(e["trajectory_steps_per_s"] for e in out["rates"])
     # a small arena: admission by footprint must refuse and the client retry
-    os.environ["FMC_SERVE_ARENA_BYTES"] = str(small_arena_mb << 20)
+    arena = int(1.2 * max(fmc.footprint(sc, precision="bf16x3") for sc in scs))
+    os.environ["FMC_SERVE_ARENA_BYTES"] = str(arena)
     ctx = fmc.Context(0)
     try:
-        rate = rates[len(rates) // 2]
+        rate = max(rates)
         reqs, arrive, is_large = stream(rate)
         keep_small = ~is_large  # the large request needs more than the small arena
         reqs = [r for r, k in zip(reqs, keep_small) if k]
@@ -367,9 +413,10 @@ def serve_sweep(fmc, workloads, oracle_mod, rates, n_max: int, seconds: float, s
         ts = float(sum(r["N"] * fmc.steps(r) for r in reqs))
         ent = _latency_summary(lat, np.zeros(len(reqs), dtype=bool), float(done_at.max()), ts,
                                len(reqs), refused, rate)
-        ent["arena_bytes"] = small_arena_mb << 20
+        ent["arena_bytes"] = arena
+        ent["requests_refused_at_least_once"] = _poisson_stream.refused_requests
         out["small_arena"] = ent
-        say(f"small arena ({small_arena_mb} MB) at {rate}/s: {refused} EBUSY retries, "
+        say(f"small arena ({arena >> 20} MB) at {rate}/s: {refused} EBUSY retries, "
             f"p99 {ent['p99_latency_s']:.3f} s")
     finally:
         del os.environ["FMC_SERVE_ARENA_BYTES"]
@@ -477,9 +524,12 @@ def served_leg(ctx, fmc, workloads, oracle_mod, rates, n_max: int, seed: int = 1
 def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
     """Sample-count convergence of the two estimators (the paper's comparison,
     Sec. V-B, on synthetic systems): for N = 2..n_max, each N with a design of
-    its own (seed 1000 + N), the mean and variance of the machine-1 rotor angle
-    at the final time from (a) KLE (paper basis, K = 40 / 100) with LHS and
-    (b) traditional Monte Carlo, eq. 5 increments with simple random sampling.
+    its own (seed 1000 + N), the mean and variance of a response from (a) KLE
+    (paper basis, K = 40 / 100 / 6) with LHS and (b) traditional Monte Carlo,
+    eq. 5 increments with simple random sampling.  Responses: the SMIB rotor
+    angle and a 10-machine frequency deviation at the final time, and the
+    case-study RRF (the RMS centre-of-inertia frequency deviation over 60 s
+    under the wind model of eq. 11 with a generator trip at t = 1 s).
     D(N) = max - min of the estimate over N-4..N; an estimator has converged
     at tolerance tol at the first N from which D stays below tol.  Tolerances
     are fractions of the response's standard deviation (mean) and variance
@@ -494,13 +544,22 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
     # responses: the SMIB rotor angle (an infinite bus holds the angle
     # reference) and, for the 10-machine system, whose common rotor angle is a
     # neutral mode that drifts freely, the frequency deviation of machine 1
+    # and the case-study shape of Sec. V-B: the wind model of eq. 11, a
+    # generator trip at t = 1 s, the RMS centre-of-inertia frequency deviation
+    # over 60 s as the response (the RRF accumulated in the integrator), KLE
+    # order 6 as in the paper
+    wt = workloads.wind_trip()
     systems = {"smib": (workloads.config1(), 0, "rotor angle of the machine at t = T (rad)"),
-               "10gen": (workloads.config2(), 10, "frequency deviation of machine 1 at t = T (pu)")}
+               "10gen": (workloads.config2(), 10, "frequency deviation of machine 1 at t = T (pu)"),
+               "wind_trip_rrf": (wt, None, "RMS centre-of-inertia frequency deviation over "
+                                           "[0, 60 s] (pu), wind model of eq. 11 on one machine, "
+                                           "generator trip at t = 1 s")}
     dump = {}
     for name, (base, col, what) in systems.items():
         S = fmc.steps(base)
         ests = {}
         M = base["K"] * len(base["dist"]["gen"])
+        rrf_w = workloads.coi_frequency_weights(base) if col is None else None
         for meth, over, n_min in (("kle_lhs", dict(basis="paper", sampler="lhs"), 2),
                                   ("em_srs", dict(basis="em", sampler="srs", K=S), 2),
                                   ("kle_lhs_decor", dict(basis="paper", sampler="lhs_decor"),
@@ -508,9 +567,15 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
             m = np.full(n_max + 1, np.nan); v = np.full(n_max + 1, np.nan)
             for N in range(n_min, n_max + 1):
                 sc = dict(base, N=N, seed=1000 + N, **over)
-                r = ctx.run(sc, precision="f64")
-                m[N] = float(r["mean"][S, col])
-                v[N] = float(r["var"][S, col])
+                if col is None:
+                    r = ctx.run(sc, precision="f64", rrf_weights=rrf_w)
+                    y = r["rrf"].cpu().numpy()
+                    m[N] = float(y.mean())
+                    v[N] = float(y.var(ddof=1))
+                else:
+                    r = ctx.run(sc, precision="f64")
+                    m[N] = float(r["mean"][S, col])
+                    v[N] = float(r["var"][S, col])
             ests[meth] = (m, v)
             dump[f"{name}_{meth}_mean"] = m
             dump[f"{name}_{meth}_var"] = v
@@ -814,6 +879,8 @@ def main():
                     help="requests per rate of the serve sweep (at most)")
     ap.add_argument("--sweep-seconds", type=float, default=60.0,
                     help="arrival window per rate of the serve sweep")
+    ap.add_argument("--c1", type=int, default=1,
+                    help="run the single-machine FP64 leg (1) or not (0)")
     ap.add_argument("--c3-steps", type=int, default=2,
                     help="timed passes of the N=1e5 mixed-precision workload (0: skip)")
     ap.add_argument("--kle-reps", type=int, default=20,
@@ -939,6 +1006,9 @@ def main():
                                     res["traj"], o["mean"] if full else None,
                                     o["var"] if full else None, ot)
 
+    c1 = config1_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), 10) \
+        if args.c1 else None
+
     c3 = None
     if args.c3_steps > 0:
         c3 = config3_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), args.c3_steps)
@@ -1020,6 +1090,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "forms": forms_out,
+        "smib_N1e3": c1,
         "mixed_precision_N1e5": c3,
         "kle_contraction": kle,
         "batched": batched,

@@ -441,7 +441,8 @@ template hipError_t launch_pack<float>(const double*, int, int, const int32_t*, 
 // q = row * V + v (group_size samples per group, the last group the rest).
 // A workgroup takes 64 consecutive q, one per lane, and splits the groups
 // into kMergeSplit contiguous ranges, one per wave: each wave merges its
-// range in group order with Chan's update (loads four groups ahead), then
+// range in group order with Chan's update (loads eight groups ahead, so
+// that about 10 MB of partials are in flight over the workgroups), then
 // the first wave merges the waves' results in wave order.  The order depends
 // only on the sizes, so repeated runs give the same bits; every wave reads
 // 64 consecutive pairs (1 KB) per group, and the workgroups together stream
@@ -471,7 +472,7 @@ __global__ void __launch_bounds__(64 * kMergeSplit) k_stats_merge(
   const int64_t g0 = wv * per, g1 = g0 + per < n_groups ? g0 + per : n_groups;
   double cnt = 0.0, m = 0.0, M2 = 0.0;
   const double2* src = partial + (on ? q : 0);
-  constexpr int D = 4;
+  constexpr int D = 8;
   for (int64_t g = g0; g < g1; g += D) {
     double2 pt[D];
 #pragma unroll

@@ -151,3 +151,20 @@ def test_rejections(ctx, fmc):
     with pytest.raises(fmc.FmcError) as e:
         ctx.run(fdp, precision="f32")
     assert e.value.code == fmc.EINVAL
+
+
+@pytest.mark.parametrize("basis", ["paper", "em"])
+def test_wind_trip_case_study_rrf(ctx, basis):
+    """The case-study shape (eq. 11 wind process, generator trip at t = 1 s,
+    RMS centre-of-inertia frequency deviation), shortened to 3 s, with the
+    KLE basis (K = 6) and the traditional one-hot basis (K = S)."""
+    sc = workloads.wind_trip(N=70, T=3.0, dt=0.01)
+    if basis == "em":
+        sc = dict(sc, basis="em", sampler="srs", K=300)
+    w = workloads.coi_frequency_weights(sc)
+    r = ctx.run(sc, precision="f64", rrf_weights=w, traj_idx=np.array([0, 69]))
+    o = oracle.run(sc, want_traj=True)
+    rr = oracle.rrf_rms(o["traj"], w, sc["dt"])
+    assert np.max(np.abs(_np(r["rrf"]) - rr)) <= 1e-10 * np.max(np.abs(rr))
+    assert rel_err(_np(r["traj"]), o["traj"][[0, 69]]) <= 1e-10
+    assert mean_err(_np(r["mean"]), o["mean"], o["var"]) <= 1e-10

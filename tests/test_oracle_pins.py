@@ -127,6 +127,48 @@ def test_strata_permutations_are_uniform():
     assert chi2 < 60.0, chi2  # 23 dof: p ~ 4e-5
 
 
+@pytest.mark.parametrize("N,M", [(16, 20000), (100, 6000), (1000, 3000)])
+def test_strata_permutations_are_uniform_beyond_one_bit(N, M):
+    """The permutation of larger rows (N = 16: a 4-bit Feistel network;
+    N = 100, 1000: cycle-walked on 8 and 10 bits): over M rows, the stratum
+    of each sample is uniform over [0, N) (chi-square on the N x N position
+    counts), the strata of samples 0 and 1 are a uniform pair of distinct
+    values, and successive differences are uniform.  A round function that
+    mixes too little leaves structure in one of these."""
+    st, _ = oracle.lhs(seed=17, M=M, N=N)
+    # position: counts[i][v] = rows whose sample i has stratum v
+    counts = np.zeros((N, N))
+    for i in range(N):
+        counts[i] += np.bincount(st[:, i], minlength=N)
+    exp = M / N
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    dof = (N - 1) ** 2
+    assert abs(chi2 - dof) < 6.0 * np.sqrt(2.0 * dof), (chi2, dof)
+    # pairs of samples 0 and 1 (N (N - 1) cells; for N = 1000 the pair
+    # space is too large for M rows: the low decimal digits of each instead)
+    a, b = st[:, 0].astype(np.int64), st[:, 1].astype(np.int64)
+    assert np.all(a != b)
+    if N <= 100:
+        idx = a * N + b
+        pc = np.bincount(idx, minlength=N * N).reshape(N, N)
+        cells = pc[~np.eye(N, dtype=bool)]
+        e = M / (N * (N - 1))
+        chi = ((cells - e) ** 2 / e).sum()
+        dof = N * (N - 1) - 1
+    else:
+        pc = np.bincount((a % 10) * 10 + (b % 10), minlength=100)
+        e = M / 100.0
+        chi = ((pc - e) ** 2 / e).sum()  # near-uniform: distinct values barely bias the digits
+        dof = 99
+    assert abs(chi - dof) < 6.0 * np.sqrt(2.0 * dof), (chi, dof)
+    # successive differences (mod N), over all positions
+    d = np.diff(st.astype(np.int64), axis=1) % N
+    dc = np.bincount(d.ravel(), minlength=N)[1:]  # 0 never occurs
+    e = d.size / (N - 1)
+    chi = ((dc - e) ** 2 / e).sum()
+    assert abs(chi - (N - 2)) < 6.0 * np.sqrt(2.0 * (N - 2)), chi
+
+
 def test_lhs_row_means_are_small():
     N = 1000
     _, z = oracle.lhs(seed=1, M=40, N=N)

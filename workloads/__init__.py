@@ -209,6 +209,32 @@ def wind_smib(N=1000, K=100, T=60.0, dt=0.01, seed=11, gain=1.0, P0=0.9, **kw):
     return with_processes(sc, [spec], xi0=[P0])
 
 
+def wind_trip(N=1000, K=6, T=60.0, dt=0.01, seed=21, gain=10.0, P0=0.9, tripped=3, t_trip=1.0,
+              **kw):
+    """The case-study shape of the paper (Sec. V-B) on the 10-machine
+    synthetic system: one wind process of eq. 11 (per unit of the farm's
+    rating) entering a machine as gain (P_t - P0), and a generator trip at
+    t_trip; the response is the RMS of the centre-of-inertia frequency
+    deviation over [0, T] (rrf_weights: H_i / sum H on the speed deviations).
+    KLE order K = 6 as in the paper's comparison."""
+    sc = multimachine(n_dist=1, N=N, K=K, T=T, dt=dt, seed=seed, **kw)
+    spec = dict(kind="poly", mu=WIND_MU, sg=WIND_SIGMA, gain=gain, ref=P0)
+    sc = with_processes(sc, [spec], xi0=[P0])
+    sc["event"] = dict(t=t_trip, tripped=tripped)
+    return sc
+
+
+def coi_frequency_weights(sc: dict):
+    """rrf_weights of the centre-of-inertia frequency deviation: H_i / sum H
+    on the speed deviations, zero elsewhere."""
+    n = int(sc["n_gen"])
+    P = len(sc["dist"]["gen"])
+    w = np.zeros(2 * n + P)
+    H = np.asarray(sc["H"], dtype=np.float64)
+    w[n:2 * n] = H / H.sum()
+    return w
+
+
 def config1(**kw):
     """SMIB, N=1000, K=40, T=10 s, dt=0.01 s (1000 RK4 steps), seed 1."""
     return smib(**kw)
