@@ -879,6 +879,9 @@ def main():
                     help="requests per rate of the serve sweep (at most)")
     ap.add_argument("--sweep-seconds", type=float, default=60.0,
                     help="arrival window per rate of the serve sweep")
+    ap.add_argument("--plain-f64", action="store_true",
+                    help="batched leg: also run every scenario in turn through fmc_run in FP64 "
+                         "(the plain reference; about 90 s)")
     ap.add_argument("--c1", type=int, default=1,
                     help="run the single-machine FP64 leg (1) or not (0)")
     ap.add_argument("--c3-steps", type=int, default=2,
@@ -1016,7 +1019,7 @@ def main():
     batched = None
     if args.batch_steps > 0:
         batched = batched_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(),
-                              args.batch_steps, "f64" in forms)
+                              args.batch_steps, args.plain_f64)
 
     decor = corr = rrf = None
     if args.decor_reps > 0:
