@@ -548,14 +548,18 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
     # generator trip at t = 1 s, the RMS centre-of-inertia frequency deviation
     # over 60 s as the response (the RRF accumulated in the integrator), KLE
     # order 6 as in the paper
-    wt = workloads.wind_trip()
-    systems = {"smib": (workloads.config1(), 0, "rotor angle of the machine at t = T (rad)"),
-               "10gen": (workloads.config2(), 10, "frequency deviation of machine 1 at t = T (pu)"),
+    # (20 ms steps, and N up to 400 only: every N is a run of its own, and a
+    # 60 s run of a thousand samples takes about a tenth of a second)
+    wt = workloads.wind_trip(dt=0.02)
+    systems = {"smib": (workloads.config1(), 0, "rotor angle of the machine at t = T (rad)", n_max),
+               "10gen": (workloads.config2(), 10, "frequency deviation of machine 1 at t = T (pu)",
+                         n_max),
                "wind_trip_rrf": (wt, None, "RMS centre-of-inertia frequency deviation over "
                                            "[0, 60 s] (pu), wind model of eq. 11 on one machine, "
-                                           "generator trip at t = 1 s")}
+                                           "generator trip at t = 1 s, dt = 20 ms",
+                                 min(n_max, 400))}
     dump = {}
-    for name, (base, col, what) in systems.items():
+    for name, (base, col, what, n_max) in systems.items():
         S = fmc.steps(base)
         ests = {}
         M = base["K"] * len(base["dist"]["gen"])
@@ -565,7 +569,11 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
                                   ("kle_lhs_decor", dict(basis="paper", sampler="lhs_decor"),
                                    M + 1)):
             m = np.full(n_max + 1, np.nan); v = np.full(n_max + 1, np.nan)
+            t_note = time.perf_counter()
             for N in range(n_min, n_max + 1):
+                if time.perf_counter() - t_note > 30.0:
+                    t_note = time.perf_counter()
+                    say(f"convergence {name} {meth}: N = {N}")
                 sc = dict(base, N=N, seed=1000 + N, **over)
                 if col is None:
                     r = ctx.run(sc, precision="f64", rrf_weights=rrf_w)
@@ -581,8 +589,23 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
             dump[f"{name}_{meth}_var"] = v
             say(f"convergence {name} {meth}: done")
         m_ref, v_ref = ests["kle_lhs"][0][n_max], ests["kle_lhs"][1][n_max]
-        entry = {"response": what, "T_s": base["T"], "K_kle": base["K"],
+        entry = {"response": what, "T_s": base["T"], "K_kle": base["K"], "n_max": n_max,
                  "ref_mean": m_ref, "ref_var": v_ref}
+        if col is None:
+            # sample paths of the disturbance (the paper's Fig. 5): five KLE
+            # paths (K = 6) and three of the traditional scheme, in the .npz;
+            # their roughness, the mean |increment| per sqrt(dt), in the JSON
+            xc = 2 * base["n_gen"]
+            for meth, over, k in (("kle_lhs", dict(basis="paper", sampler="lhs"), 5),
+                                  ("em_srs", dict(basis="em", sampler="srs", K=S), 3)):
+                sc = dict(base, N=8, seed=7, **over)
+                rp = ctx.run(sc, precision="f64", traj_idx=np.arange(k))
+                paths = rp["traj"].cpu().numpy()[:, :, xc]
+                dump[f"{name}_{meth}_paths"] = paths
+                entry[f"{meth}_paths"] = {
+                    "n": k, "min": float(paths.min()), "max": float(paths.max()),
+                    "mean_abs_increment_per_sqrt_dt":
+                        float(np.mean(np.abs(np.diff(paths, axis=1))) / np.sqrt(base["dt"]))}
 
         def fin(x):
             return float(x) if np.isfinite(x) else None
@@ -604,7 +627,7 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
         # (relative to the std for the mean, to the variance for the
         # variance); with errors ~ 1/sqrt(N) the squared ratio of the two
         # methods' errors is their ratio of samples for equal accuracy
-        ranges = ((10, 50), (100, 200), (500, n_max))
+        ranges = ((10, 50), (100, 200), (max(200, n_max // 2), n_max))
         rms = {}
         for meth, (m, v) in ests.items():
             # NaN where a method has no estimate (the reduced design needs N > M)
@@ -613,9 +636,11 @@ def convergence_leg(ctx, fmc, workloads, n_max: int, out_path: str = ""):
                           float(np.sqrt(np.nanmean((v[a:b] - v_ref) ** 2)) / v_ref)
                           if np.isfinite(v[a:b]).any() else None) for a, b in ranges]
         entry["rms_error_ranges"] = [f"{a}-{b - 1}" for a, b in ranges]
+        def sq_ratio(a, b):
+            return (a / b) ** 2 if a is not None and b else None
         entry["sample_ratio_em_over_kle"] = {
-            "mean": [(e[0] / k[0]) ** 2 for e, k in zip(rms["em_srs"], rms["kle_lhs"])],
-            "var": [(e[1] / k[1]) ** 2 for e, k in zip(rms["em_srs"], rms["kle_lhs"])]}
+            "mean": [sq_ratio(e[0], k[0]) for e, k in zip(rms["em_srs"], rms["kle_lhs"])],
+            "var": [sq_ratio(e[1], k[1]) for e, k in zip(rms["em_srs"], rms["kle_lhs"])]}
         # the reduced design exists for N > M only: both over the same N
         md, vd = ests["kle_lhs_decor"]
         ml, vl = ests["kle_lhs"]
@@ -868,8 +893,9 @@ def main():
                     help="horizon of the flux-decay leg in steps (0: skip)")
     ap.add_argument("--decor-reps", type=int, default=3,
                     help="passes of the reduced-design, diffusion-matrix and RRF legs (0: skip)")
-    ap.add_argument("--convergence", type=int, default=0,
-                    help="run the sample-count convergence comparison up to this N (0: skip)")
+    ap.add_argument("--convergence", type=int, default=300,
+                    help="run the sample-count convergence comparison up to this N (0: skip; "
+                         "1000 as in the paper takes about three minutes)")
     ap.add_argument("--convergence-out", default="",
                     help="write the convergence estimates to this .npz file")
     ap.add_argument("--serve-sweep", default="",
