@@ -905,6 +905,10 @@ def main():
                     help="requests per rate of the serve sweep (at most)")
     ap.add_argument("--sweep-seconds", type=float, default=60.0,
                     help="arrival window per rate of the serve sweep")
+    ap.add_argument("--time-chunk", type=int, default=0,
+                    help="time chunk of the forms' runs in steps (0: the library's choice; the "
+                         "whole horizon leaves one statistics merge over all rows, after the "
+                         "integrator)")
     ap.add_argument("--plain-f64", action="store_true",
                     help="batched leg: also run every scenario in turn through fmc_run in FP64 "
                          "(the plain reference; about 90 s)")
@@ -960,7 +964,7 @@ def main():
         say(f"{form}: variant {vid}")
         outs = None
         for _ in range(args.warmup):
-            r = ctx.run(sc, precision=form, variant=vid)
+            r = ctx.run(sc, precision=form, variant=vid, time_chunk=args.time_chunk)
             outs = dict(mean=r["mean"], var=r["var"])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -968,7 +972,7 @@ def main():
         n_launch = 0
         reps = []
         for _ in range(args.steps):
-            r = ctx.run(sc, precision=form, outputs=outs, variant=vid)
+            r = ctx.run(sc, precision=form, outputs=outs, variant=vid, time_chunk=args.time_chunk)
             outs = dict(mean=r["mean"], var=r["var"])
             reps.append(r["report"])
         torch.cuda.synchronize()
