@@ -33,58 +33,94 @@ using cptr = const __attribute__((address_space(4))) R*;
 // enough for |k| < 2^20, far beyond the angles met here), then the Taylor
 // polynomials of sin and cos in r^2 (terms through r^15 / r^16 in FP64, r^9 /
 // r^10 in FP32; truncation below half an ulp on |r| <= pi/4), and the quadrant
-// of k.
-__device__ __forceinline__ void sincos_r(double x, double& s, double& c) {
-  const double k = rint(x * 0.63661977236758134308);  // 2/pi
-  double r = fma(-k, 0x1.921fb54442d18p+0, x);
-  r = fma(-k, 0x1.1a62633145c07p-54, r);
-  const double r2 = r * r;
-  double ps = -1.0 / 1307674368000.0;
-  ps = fma(ps, r2, 1.0 / 6227020800.0);
-  ps = fma(ps, r2, -1.0 / 39916800.0);
-  ps = fma(ps, r2, 1.0 / 362880.0);
-  ps = fma(ps, r2, -1.0 / 5040.0);
-  ps = fma(ps, r2, 1.0 / 120.0);
-  ps = fma(ps, r2, -1.0 / 6.0);
-  const double sr = fma(r * r2, ps, r);
-  double pc = 1.0 / 20922789888000.0;
-  pc = fma(pc, r2, -1.0 / 87178291200.0);
-  pc = fma(pc, r2, 1.0 / 479001600.0);
-  pc = fma(pc, r2, -1.0 / 3628800.0);
-  pc = fma(pc, r2, 1.0 / 40320.0);
-  pc = fma(pc, r2, -1.0 / 720.0);
-  pc = fma(pc, r2, 1.0 / 24.0);
-  pc = fma(pc, r2, -0.5);
-  const double cr = fma(r2, pc, 1.0);
-  const int q = (int)k;
-  const double a = (q & 1) ? cr : sr;
-  const double b = (q & 1) ? sr : cr;
-  s = (q & 2) ? -a : a;
-  c = ((q + 1) & 2) ? -b : b;
+// of k.  When every active lane of the wave has |x| < 0.78 (the usual case:
+// the argument is half an angle's deviation from the operating point), k is 0
+// for all of them, the reduction leaves r = x exactly and the quadrant step is
+// the identity, so both are skipped by a wave-uniform branch with the same
+// bits as the full path.
+__device__ __forceinline__ bool sincos_all_small(bool small) {
+  return __builtin_amdgcn_ballot_w64(!small) == 0;
 }
 
-__device__ __forceinline__ void sincos_r(float x, float& s, float& c) {
-  const float k = rintf(x * 0x1.45f306p-1f);  // 2/pi
-  float r = fmaf(-k, 0x1.921fb6p+0f, x);
-  r = fmaf(-k, -0x1.777a5cp-25f, r);
-  r = fmaf(-k, -0x1.ee59dap-50f, r);
+// a*b + c as the three-operand FMA: the coefficients below stay in registers
+// of their own, read but never overwritten (the two-operand form ties the
+// addend to the result and costs a copy of the coefficient per use)
+__device__ __forceinline__ double fma3(double a, double b, double c) {
+  double d;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
+// the polynomials on the reduced argument r
+__device__ __forceinline__ void sincos_poly(double r, double& sr, double& cr) {
+  const double r2 = r * r;
+  double ps = -1.0 / 1307674368000.0;
+  ps = fma3(ps, r2, 1.0 / 6227020800.0);
+  ps = fma3(ps, r2, -1.0 / 39916800.0);
+  ps = fma3(ps, r2, 1.0 / 362880.0);
+  ps = fma3(ps, r2, -1.0 / 5040.0);
+  ps = fma3(ps, r2, 1.0 / 120.0);
+  ps = fma3(ps, r2, -1.0 / 6.0);
+  sr = fma(r * r2, ps, r);
+  double pc = 1.0 / 20922789888000.0;
+  pc = fma3(pc, r2, -1.0 / 87178291200.0);
+  pc = fma3(pc, r2, 1.0 / 479001600.0);
+  pc = fma3(pc, r2, -1.0 / 3628800.0);
+  pc = fma3(pc, r2, 1.0 / 40320.0);
+  pc = fma3(pc, r2, -1.0 / 720.0);
+  pc = fma3(pc, r2, 1.0 / 24.0);
+  pc = fma(pc, r2, -0.5);
+  cr = fma(r2, pc, 1.0);
+}
+
+__device__ __forceinline__ void sincos_poly(float r, float& sr, float& cr) {
   const float r2 = r * r;
   float ps = 1.0f / 362880.0f;
   ps = fmaf(ps, r2, -1.0f / 5040.0f);
   ps = fmaf(ps, r2, 1.0f / 120.0f);
   ps = fmaf(ps, r2, -1.0f / 6.0f);
-  const float sr = fmaf(r * r2, ps, r);
+  sr = fmaf(r * r2, ps, r);
   float pc = -1.0f / 3628800.0f;
   pc = fmaf(pc, r2, 1.0f / 40320.0f);
   pc = fmaf(pc, r2, -1.0f / 720.0f);
   pc = fmaf(pc, r2, 1.0f / 24.0f);
   pc = fmaf(pc, r2, -0.5f);
-  const float cr = fmaf(r2, pc, 1.0f);
-  const int q = (int)k;
-  const float a = (q & 1) ? cr : sr;
-  const float b = (q & 1) ? sr : cr;
-  s = (q & 2) ? -a : a;
-  c = ((q + 1) & 2) ? -b : b;
+  cr = fmaf(r2, pc, 1.0f);
+}
+
+__device__ __forceinline__ void sincos_r(double x, double& s, double& c) {
+  if (sincos_all_small(fabs(x) < 0.78)) [[likely]] {
+    sincos_poly(x, s, c);
+  } else {
+    const double k = rint(x * 0.63661977236758134308);  // 2/pi
+    double r = fma(-k, 0x1.921fb54442d18p+0, x);
+    r = fma(-k, 0x1.1a62633145c07p-54, r);
+    double sr, cr;
+    sincos_poly(r, sr, cr);
+    const int q = (int)k;
+    const double a = (q & 1) ? cr : sr;
+    const double b = (q & 1) ? sr : cr;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+  }
+}
+
+__device__ __forceinline__ void sincos_r(float x, float& s, float& c) {
+  if (sincos_all_small(fabsf(x) < 0.78f)) [[likely]] {
+    sincos_poly(x, s, c);
+  } else {
+    const float k = rintf(x * 0x1.45f306p-1f);  // 2/pi
+    float r = fmaf(-k, 0x1.921fb6p+0f, x);
+    r = fmaf(-k, -0x1.777a5cp-25f, r);
+    r = fmaf(-k, -0x1.ee59dap-50f, r);
+    float sr, cr;
+    sincos_poly(r, sr, cr);
+    const int q = (int)k;
+    const float a = (q & 1) ? cr : sr;
+    const float b = (q & 1) ? sr : cr;
+    s = (q & 2) ? -a : a;
+    c = ((q + 1) & 2) ? -b : b;
+  }
 }
 
 // The FP64 common-angle offset in two state slots: the exact bits of the
@@ -536,6 +572,13 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
     wofs[r] = own[r] ? (int64_t)p * N + ns : 0;
   }
 
+  // the process slots p >= P of my trajectory's exchange row stay zero
+  if (g == 0) {
+#pragma unroll
+    for (int p = 0; p < PM; ++p) xch[tl][NGP + p] = R2{R(0), R(0)};
+  }
+  wave_lds_sync();
+
   auto rhs = [&](const R (&yd)[G], const R (&yw)[G], const R (&yx)[PQ], const R (&wv)[PQ],
                  R (&kd)[G], R (&kw)[G], R (&kx)[PQ]) {
     R dc[G], ds[G];
@@ -582,13 +625,13 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
     R inj[G];
 #pragma unroll
     for (int q = 0; q < G; ++q) inj[q] = R(0);
+    // every process slot, the padding ones included (zero, as their columns
+    // of binc): no branch on P between the exchange reads and their use
 #pragma unroll
     for (int p = 0; p < PM; ++p) {
-      if (p < P) {
-        const R xp = xch[tl][NGP + p].x;
+      const R xp = xch[tl][NGP + p].x;
 #pragma unroll
-        for (int q = 0; q < G; ++q) inj[q] += binc[q][p] * xp;
-      }
+      for (int q = 0; q < G; ++q) inj[q] += binc[q][p] * xp;
     }
     wave_lds_sync();
 #pragma unroll
