@@ -192,10 +192,13 @@ __device__ __forceinline__ void swing_rhs(const R* cfg, const R* sdeg, const R w
 #pragma unroll
   for (int k = 0; k < NG; ++k) {
     R sh, ch;
-    sincos_r(yd[k] * R(0.5), sh, ch);
+    const R c0 = cf[L.c0() + k], s0 = cf[L.s0() + k];
+    // a machine without EMF (padding, or tripped by an event) gives dE = 0 at
+    // any angle; its angle, shifted by every recentering, is not passed on,
+    // so it cannot push the wave off the small-angle branch of sin/cos
+    sincos_r(c0 != R(0) || s0 != R(0) ? yd[k] * R(0.5) : R(0), sh, ch);
     const R sd = R(2) * sh * ch;   // sin d
     const R omc = R(2) * sh * sh;  // 1 - cos d
-    const R c0 = cf[L.c0() + k], s0 = cf[L.s0() + k];
     dc[k] = -(c0 * omc + s0 * sd);
     ds[k] = c0 * sd - s0 * omc;
   }
@@ -559,6 +562,9 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
 #pragma unroll
     for (int p = 0; p < PM; ++p) binc[q][p] = on ? cf[Lp.binc() + i * PM + p] : R(0);
   }
+  bool live[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) live[q] = lane_on && (c0[q] != R(0) || s0[q] != R(0));
   // my processes p = g + L r
   R theta[PQ], sigma[PQ];
   bool own[PQ];
@@ -585,7 +591,10 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
 #pragma unroll
     for (int q = 0; q < G; ++q) {
       R sh, ch;
-      sincos_r(yd[q] * R(0.5), sh, ch);
+      // idle lanes (whose exchange row is shared scratch) and machines without
+      // EMF (padding, tripped) give dE = 0 at any angle: their angles are not
+      // passed on, so they cannot push the wave off the small-angle branch
+      sincos_r(live[q] ? yd[q] * R(0.5) : R(0), sh, ch);
       const R sd = R(2) * sh * ch;
       const R omc = R(2) * sh * sh;
       dc[q] = -(c0[q] * omc + s0[q] * sd);
