@@ -76,8 +76,10 @@ struct IntegArgs {
   int64_t lanes;            // state row stride
   R dt, wb;
   // Nonzero for systems without an infinite bus, whose electrical powers
-  // depend on rotor-angle differences only: after every step the mean angle
-  // deviation of the machines is moved out of every machine's angle state
+  // depend on rotor-angle differences only: after every step (every eighth
+  // step of the absolute count in the group kernel, whose lanes share the
+  // sum through LDS) the mean angle deviation of the machines is moved out of
+  // every machine's angle state
   // into a per-trajectory FP64 offset, so the reduced-precision state holds
   // the small angles relative to the mean rather than the common angle (a
   // neutral mode that drifts by radians over long horizons, whose rounding

@@ -815,7 +815,9 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
       w1[r] = n1[r];
       w2[r] = n2[r];
     }
-    if (a.recenter) {
+    if (a.recenter && ((s + 1) & 7) == 0) {
+      // every eighth step (of the absolute step count, so time chunks keep the
+      // bits; the common angle moves by milliradians in between):
       // the mean angle of the trajectory's machines in service (a tripped
       // machine has no EMF): each lane's sum over its machines through the
       // exchange row (free again: the last stage's reads ended with a wave
