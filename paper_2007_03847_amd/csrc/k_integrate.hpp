@@ -499,6 +499,33 @@ struct GroupShape {
   static constexpr size_t lds_bytes = tile_bytes + xch_bytes + (TB + 1) * sizeof(int);
 };
 
+// Mean and sum of squared deviations of row[0, cnt) (cnt >= 1) in one pass
+// over LDS: with the shift k = row[0] and d = x - k, mean = k + S1/cnt
+// and M2 = S2 - S1^2/cnt (S1, S2 the sums of d and d^2, each in four partial
+// sums over entries j mod 4, added in a fixed order).  The shift is one of the
+// samples, so (mean - k)^2 <= (cnt - 1) M2 / cnt and the subtraction loses at
+// most a factor cnt of relative accuracy (about 1e-14 here); equal entries
+// give M2 = 0 exactly.
+__device__ __forceinline__ void row_stats(const double* row, int cnt, double& mu, double& m2) {
+  const double k = row[0];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+  int j = 0;
+#pragma unroll 1
+  for (; j + 3 < cnt; j += 4) {
+    const double d0 = row[j] - k, d1 = row[j + 1] - k, d2 = row[j + 2] - k, d3 = row[j + 3] - k;
+    s0 += d0; s1 += d1; s2 += d2; s3 += d3;
+    q0 = fma(d0, d0, q0); q1 = fma(d1, d1, q1); q2 = fma(d2, d2, q2); q3 = fma(d3, d3, q3);
+  }
+  if (j < cnt) { const double d = row[j] - k; s0 += d; q0 = fma(d, d, q0); }
+  if (j + 1 < cnt) { const double d = row[j + 1] - k; s1 += d; q1 = fma(d, d, q1); }
+  if (j + 2 < cnt) { const double d = row[j + 2] - k; s2 += d; q2 = fma(d, d, q2); }
+  const double S1 = (s0 + s1) + (s2 + s3), S2 = (q0 + q1) + (q2 + q3);
+  const double dm = S1 / (double)cnt;
+  mu = k + dm;
+  m2 = fma(-S1, dm, S2);
+}
+
 // Where a group run leaves its statistics: rows[(s)*V + v] = (mean, M2) of the
 // group's samples; prev > 0 means the rows already hold the statistics of prev
 // earlier samples, and the group's are merged in with Chan's update (a fixed
@@ -665,15 +692,8 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
     __syncthreads();
     for (int rv = tid; rv < nb * V; rv += 64 * WPB) {
       const int b = rv / V, v = rv % V;
-      const double* row = tile_buf[b][v];
-      double sm = 0.0;
-      for (int j = 0; j < cnt; ++j) sm += row[j];
-      const double mu = sm / (double)cnt;
-      double m2 = 0.0;
-      for (int j = 0; j < cnt; ++j) {
-        const double d = row[j] - mu;
-        m2 += d * d;
-      }
+      double mu, m2;
+      row_stats(tile_buf[b][v], cnt, mu, m2);
       double2* dst = st.rows + (s_first + b) * V + v;
       if (st.prev == 0) {
         *dst = make_double2(mu, m2);
