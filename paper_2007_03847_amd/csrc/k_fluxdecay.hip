@@ -400,9 +400,7 @@ __global__ void __launch_bounds__(512) k_rk4_fd(FdArgs a) {
           const float4* cm = reinterpret_cast<const float4*>(cst + mo);
           const float4 g0 = cm[0], g3 = cm[3], g4 = cm[4], g5 = cm[5];
           float sh, ch;
-          // a padding machine (all constants zero) gives dE' = 0 at any
-          // angle: its angle is not passed to sin/cos (see sincos_r)
-          sincos_r(g0.x != 0.0f || g0.y != 0.0f ? 0.5f * ys[0][q] : 0.0f, sh, ch);
+          sincos_r_nb(0.5f * ys[0][q], sh, ch);
           sd[q] = 2.0f * sh * ch;   // sin d
           omc[q] = 2.0f * sh * sh;  // 1 - cos d
           const float c0 = g0.x, s0 = g0.y, ur = g0.z, ui = g0.w;

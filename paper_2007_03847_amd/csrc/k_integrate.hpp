@@ -28,16 +28,16 @@ namespace fmc {
 template <typename R>
 using cptr = const __attribute__((address_space(4))) R*;
 
-// sin and cos together: Cody-Waite reduction x = k pi/2 + r, |r| <= pi/4,
-// with pi/2 split into two (FP64) or three (FP32) parts applied by FMA (exact
-// enough for |k| < 2^20, far beyond the angles met here), then the Taylor
-// polynomials of sin and cos in r^2 (terms through r^15 / r^16 in FP64, r^9 /
-// r^10 in FP32; truncation below half an ulp on |r| <= pi/4), and the quadrant
-// of k.  When every active lane of the wave has |x| < 0.78 (the usual case:
-// the argument is half an angle's deviation from the operating point), k is 0
-// for all of them, the reduction leaves r = x exactly and the quadrant step is
-// the identity, so both are skipped by a wave-uniform branch with the same
-// bits as the full path.
+// sin and cos together (sincos_r_nb): Cody-Waite reduction x = k pi/2 + r,
+// |r| <= pi/4, with pi/2 split into two (FP64) or three (FP32) parts applied
+// by FMA (exact enough for |k| < 2^20, far beyond the angles met here), then
+// the Taylor polynomials of sin and cos in r^2 (terms through r^15 / r^16 in
+// FP64, r^9 / r^10 in FP32; truncation below half an ulp on |r| <= pi/4), and
+// the quadrant of k.  When every active lane of the wave has |x| < 0.78 (the
+// usual case: the argument is half an angle's deviation from the operating
+// point), k is 0 for all of them, the reduction leaves r = x exactly and the
+// quadrant step is the identity: sincos_many then skips both with one
+// wave-uniform branch, with the same bits as the full path.
 __device__ __forceinline__ bool sincos_all_small(bool small) {
   return __builtin_amdgcn_ballot_w64(!small) == 0;
 }
@@ -51,24 +51,29 @@ __device__ __forceinline__ double fma3(double a, double b, double c) {
   return d;
 }
 
-// the polynomials on the reduced argument r
+// the polynomials on the reduced argument r; F3 selects the three-operand
+// FMA for the Horner steps (the same rounding as fma(), so the same bits):
+// worth it where the coefficients stay resident in vector registers, not
+// where register pressure would have them rematerialised at every use
+template <bool F3 = true>
 __device__ __forceinline__ void sincos_poly(double r, double& sr, double& cr) {
+  auto f = [](double a, double b, double c) { return F3 ? fma3(a, b, c) : fma(a, b, c); };
   const double r2 = r * r;
   double ps = -1.0 / 1307674368000.0;
-  ps = fma3(ps, r2, 1.0 / 6227020800.0);
-  ps = fma3(ps, r2, -1.0 / 39916800.0);
-  ps = fma3(ps, r2, 1.0 / 362880.0);
-  ps = fma3(ps, r2, -1.0 / 5040.0);
-  ps = fma3(ps, r2, 1.0 / 120.0);
-  ps = fma3(ps, r2, -1.0 / 6.0);
+  ps = f(ps, r2, 1.0 / 6227020800.0);
+  ps = f(ps, r2, -1.0 / 39916800.0);
+  ps = f(ps, r2, 1.0 / 362880.0);
+  ps = f(ps, r2, -1.0 / 5040.0);
+  ps = f(ps, r2, 1.0 / 120.0);
+  ps = f(ps, r2, -1.0 / 6.0);
   sr = fma(r * r2, ps, r);
   double pc = 1.0 / 20922789888000.0;
-  pc = fma3(pc, r2, -1.0 / 87178291200.0);
-  pc = fma3(pc, r2, 1.0 / 479001600.0);
-  pc = fma3(pc, r2, -1.0 / 3628800.0);
-  pc = fma3(pc, r2, 1.0 / 40320.0);
-  pc = fma3(pc, r2, -1.0 / 720.0);
-  pc = fma3(pc, r2, 1.0 / 24.0);
+  pc = f(pc, r2, -1.0 / 87178291200.0);
+  pc = f(pc, r2, 1.0 / 479001600.0);
+  pc = f(pc, r2, -1.0 / 3628800.0);
+  pc = f(pc, r2, 1.0 / 40320.0);
+  pc = f(pc, r2, -1.0 / 720.0);
+  pc = f(pc, r2, 1.0 / 24.0);
   pc = fma(pc, r2, -0.5);
   cr = fma(r2, pc, 1.0);
 }
@@ -88,38 +93,52 @@ __device__ __forceinline__ void sincos_poly(float r, float& sr, float& cr) {
   cr = fmaf(r2, pc, 1.0f);
 }
 
-__device__ __forceinline__ void sincos_r(double x, double& s, double& c) {
-  if (sincos_all_small(fabs(x) < 0.78)) [[likely]] {
-    sincos_poly(x, s, c);
-  } else {
-    const double k = rint(x * 0.63661977236758134308);  // 2/pi
-    double r = fma(-k, 0x1.921fb54442d18p+0, x);
-    r = fma(-k, 0x1.1a62633145c07p-54, r);
-    double sr, cr;
-    sincos_poly(r, sr, cr);
-    const int q = (int)k;
-    const double a = (q & 1) ? cr : sr;
-    const double b = (q & 1) ? sr : cr;
-    s = (q & 2) ? -a : a;
-    c = ((q + 1) & 2) ? -b : b;
-  }
+// The reduction always taken, with no branch: for callers that evaluate the
+// sin/cos of several machines per lane back to back, where a branch per call
+// would keep the compiler from interleaving them.
+__device__ __forceinline__ void sincos_r_nb(double x, double& s, double& c) {
+  const double k = rint(x * 0.63661977236758134308);  // 2/pi
+  double r = fma(-k, 0x1.921fb54442d18p+0, x);
+  r = fma(-k, 0x1.1a62633145c07p-54, r);
+  double sr, cr;
+  sincos_poly<false>(r, sr, cr);
+  const int q = (int)k;
+  const double a = (q & 1) ? cr : sr;
+  const double b = (q & 1) ? sr : cr;
+  s = (q & 2) ? -a : a;
+  c = ((q + 1) & 2) ? -b : b;
 }
 
-__device__ __forceinline__ void sincos_r(float x, float& s, float& c) {
-  if (sincos_all_small(fabsf(x) < 0.78f)) [[likely]] {
-    sincos_poly(x, s, c);
+__device__ __forceinline__ void sincos_r_nb(float x, float& s, float& c) {
+  const float k = rintf(x * 0x1.45f306p-1f);  // 2/pi
+  float r = fmaf(-k, 0x1.921fb6p+0f, x);
+  r = fmaf(-k, -0x1.777a5cp-25f, r);
+  r = fmaf(-k, -0x1.ee59dap-50f, r);
+  float sr, cr;
+  sincos_poly(r, sr, cr);
+  const int q = (int)k;
+  const float a = (q & 1) ? cr : sr;
+  const float b = (q & 1) ? sr : cr;
+  s = (q & 2) ? -a : a;
+  c = ((q + 1) & 2) ? -b : b;
+}
+
+// sin and cos of a lane's N angles with one wave-uniform decision: the
+// small-angle form for all of them when every active lane's angles are below
+// 0.78 (the same bits as the full path), else the full path; in
+// both branches the N evaluations are straight-line code the compiler can
+// interleave.
+template <typename R, int N>
+__device__ __forceinline__ void sincos_many(const R (&x)[N], R (&s)[N], R (&c)[N]) {
+  bool small = true;
+#pragma unroll
+  for (int k = 0; k < N; ++k) small = small && fabs(x[k]) < R(0.78);
+  if (sincos_all_small(small)) [[likely]] {
+#pragma unroll
+    for (int k = 0; k < N; ++k) sincos_poly(x[k], s[k], c[k]);
   } else {
-    const float k = rintf(x * 0x1.45f306p-1f);  // 2/pi
-    float r = fmaf(-k, 0x1.921fb6p+0f, x);
-    r = fmaf(-k, -0x1.777a5cp-25f, r);
-    r = fmaf(-k, -0x1.ee59dap-50f, r);
-    float sr, cr;
-    sincos_poly(r, sr, cr);
-    const int q = (int)k;
-    const float a = (q & 1) ? cr : sr;
-    const float b = (q & 1) ? sr : cr;
-    s = (q & 2) ? -a : a;
-    c = ((q + 1) & 2) ? -b : b;
+#pragma unroll
+    for (int k = 0; k < N; ++k) sincos_r_nb(x[k], s[k], c[k]);
   }
 }
 
@@ -191,12 +210,11 @@ __device__ __forceinline__ void swing_rhs(const R* cfg, const R* sdeg, const R w
   R dc[NG], ds[NG];
 #pragma unroll
   for (int k = 0; k < NG; ++k) {
+    // the branch-free form: a lane's machines are interleaved by the compiler
+    // around the scalar loads of their data
     R sh, ch;
+    sincos_r_nb(yd[k] * R(0.5), sh, ch);
     const R c0 = cf[L.c0() + k], s0 = cf[L.s0() + k];
-    // a machine without EMF (padding, or tripped by an event) gives dE = 0 at
-    // any angle; its angle, shifted by every recentering, is not passed on,
-    // so it cannot push the wave off the small-angle branch of sin/cos
-    sincos_r(c0 != R(0) || s0 != R(0) ? yd[k] * R(0.5) : R(0), sh, ch);
     const R sd = R(2) * sh * ch;   // sin d
     const R omc = R(2) * sh * sh;  // 1 - cos d
     dc[k] = -(c0 * omc + s0 * sd);
@@ -614,14 +632,16 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
 
   auto rhs = [&](const R (&yd)[G], const R (&yw)[G], const R (&yx)[PQ], const R (&wv)[PQ],
                  R (&kd)[G], R (&kw)[G], R (&kx)[PQ]) {
-    R dc[G], ds[G];
+    R dc[G], ds[G], hx[G], shs[G], chs[G];
+    // idle lanes (whose exchange row is shared scratch) and machines without
+    // EMF (padding, tripped) give dE = 0 at any angle: their angles are not
+    // passed on, so they cannot push the wave off the small-angle branch
+#pragma unroll
+    for (int q = 0; q < G; ++q) hx[q] = live[q] ? yd[q] * R(0.5) : R(0);
+    sincos_many(hx, shs, chs);
 #pragma unroll
     for (int q = 0; q < G; ++q) {
-      R sh, ch;
-      // idle lanes (whose exchange row is shared scratch) and machines without
-      // EMF (padding, tripped) give dE = 0 at any angle: their angles are not
-      // passed on, so they cannot push the wave off the small-angle branch
-      sincos_r(live[q] ? yd[q] * R(0.5) : R(0), sh, ch);
+      const R sh = shs[q], ch = chs[q];
       const R sd = R(2) * sh * ch;
       const R omc = R(2) * sh * sh;
       dc[q] = -(c0[q] * omc + s0[q] * sd);

@@ -290,9 +290,10 @@ __device__ __forceinline__ void mc_tile(const IntegArgs<float>& a, int64_t tile,
         asm volatile("" : "+v"(mo));  // reread the constants, do not keep them live
         const float4 c = *reinterpret_cast<const float4*>(S.cst + mo);  // C0 S0 I0R I0I
         float sh, ch;
-        // a padding machine (E~0 = 0) gives dE = 0 at any angle: its angle
-        // is not passed to sin/cos (see sincos_r)
-        sincos_r(c.x != 0.0f || c.y != 0.0f ? 0.5f * sd_[q] : 0.0f, sh, ch);
+        // the branch-free form: the four or eight machines of a lane are
+        // interleaved by the compiler (a padding machine, E~0 = 0, gives dE = 0
+        // at any angle)
+        sincos_r_nb(0.5f * sd_[q], sh, ch);
         const float sdd = 2.0f * sh * ch, omc = 2.0f * sh * sh;
         dEr[q] = -(c.x * omc + c.y * sdd);  // zero for padding machines (E~0 = 0)
         dEi[q] = c.x * sdd - c.y * omc;

@@ -47,11 +47,9 @@ __device__ __forceinline__ void rhs_and_jac(const double* cfg, double wb, const 
 #pragma unroll
   for (int k = 0; k < NG; ++k) {
     double sh, ch;
-    const double c0 = cf[L.c0() + k], s0 = cf[L.s0() + k];
-    // a machine without EMF (padding, tripped) gives dE = 0 at any angle:
-    // its drifting angle is not passed to sin/cos (see sincos_r)
-    sincos_r(c0 != 0.0 || s0 != 0.0 ? yd[k] * 0.5 : 0.0, sh, ch);
+    sincos_r_nb(yd[k] * 0.5, sh, ch);
     const double sd = 2.0 * sh * ch, omc = 2.0 * sh * sh;
+    const double c0 = cf[L.c0() + k], s0 = cf[L.s0() + k];
     dc[k] = -(c0 * omc + s0 * sd);
     ds[k] = c0 * sd - s0 * omc;
   }
