@@ -273,11 +273,11 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   const bool dev_out = out->mem_kind == FMC_MEM_DEVICE;
   const bool f64 = par->precision == FMC_F64;
   const int bw = f64 ? 8 : 4;
-  // the implicit trapezoid and the general Ito processes run on the shapes of
-  // the one-trajectory-per-lane variants (the smallest that fits, or the one
-  // asked for)
+  // the implicit trapezoid runs on the shapes of the one-trajectory-per-lane
+  // variants (the smallest that fits, or the one asked for); the general Ito
+  // processes run on every variant, by default the one tuned for the shape
   const bool trap = par->integrator == FMC_TRAP;
-  const bool lane_only = trap || dist->proc != nullptr;
+  const bool lane_only = trap;
   int vid = par->variant >= 0 ? par->variant
                               : (lane_only ? -1 : pick_variant(c, n, P, N, par->precision));
   if (lane_only && vid < 0) {
@@ -294,8 +294,6 @@ int run_single(Context* c, const fmc_system* sys, const fmc_disturbance* dist,
   if (trap && (vi.L != 1 || vi.NG > kTrapMaxGen))
     return fail(FMC_EINVAL, "the implicit trapezoid runs on one-trajectory-per-lane variants of at "
                             "most 16 machines");
-  if (dist->proc && vi.L != 1)
-    return fail(FMC_EINVAL, "general Ito processes run on one-trajectory-per-lane variants");
   const double f0 = sys->f0_hz > 0.0 ? sys->f0_hz : 60.0;
   const double wb = 2.0 * M_PI * f0;
 

@@ -726,15 +726,16 @@ int fmc_autotune(fmc_context* ctx, const fmc_scenario* scen, int32_t* variant_ou
   if ((rc = c->ensure("tune_var", (size_t)(St + 1) * V * sizeof(double), &v))) return rc;
   int best = -1;
   double best_t = 0.0;
-  // the implicit trapezoid and the general Ito processes run on the
-  // one-trajectory-per-lane variants only (fmc_run picks among those itself,
-  // so such a choice is returned but not kept for the scenario's shape)
+  // the implicit trapezoid runs on the one-trajectory-per-lane variants only
+  // (fmc_run picks among those itself); a choice for it, or for general Ito
+  // processes, is returned but not kept for the scenario's shape, whose
+  // cached variant serves the OU form
   const bool trap = scen->par->integrator == FMC_TRAP;
-  const bool lane_only = trap || scen->dist->proc != nullptr;
+  const bool keep = !trap && scen->dist->proc == nullptr;
   for (int id = 0; id < n_variants(); ++id) {
     const VariantInfo& vi = variant(id);
     if (vi.NG < n || vi.PM < P) continue;
-    if (lane_only && (vi.L != 1 || (trap && vi.NG > kTrapMaxGen))) continue;
+    if (trap && (vi.L != 1 || vi.NG > kTrapMaxGen)) continue;
     par.variant = id;
     fmc_report rep;
     fmc_outputs out{};
@@ -757,7 +758,7 @@ int fmc_autotune(fmc_context* ctx, const fmc_scenario* scen, int32_t* variant_ou
     }
   }
   if (best < 0) return fail(FMC_EINVAL, "no integrator variant fits the scenario");
-  if (!lane_only) {
+  if (keep) {
     const std::string key = tune_key(n, P, N, scen->par->precision);
     c->tuned[key] = best;
     save_tune_entry(key, best);

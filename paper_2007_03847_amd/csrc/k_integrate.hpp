@@ -558,8 +558,11 @@ struct GroupStats {
 // machines g*G .. g*G+G-1 (rows of Y in registers) and processes g, g+L, ...;
 // per stage the lanes exchange the rotated EMF deviations of their machines
 // and the stage values of their processes through LDS.  keep_state stores the
-// state for a following chunk.
-template <typename R, int NG, int PM, int L, int WPB, int D>
+// state for a following chunk.  GEN: the processes are the general Ito
+// processes of a.sde; the owner lane of a process evaluates its drift and
+// diffusion and publishes the power it injects, gain (xi - ref), in the
+// process's exchange slot (where the OU form publishes xi itself).
+template <typename R, int NG, int PM, int L, int WPB, int D, bool GEN = false>
 __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
                                           unsigned char* lds, GroupStats st, bool keep_state) {
   using Sh = GroupShape<R, NG, PM, L, WPB, D>;
@@ -610,6 +613,20 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
   bool live[G];
 #pragma unroll
   for (int q = 0; q < G; ++q) live[q] = lane_on && (c0[q] != R(0) || s0[q] != R(0));
+  // GEN: the gain and reference of my processes' injections
+  R pgain[PQ], pref[PQ];
+#pragma unroll
+  for (int r = 0; r < PQ; ++r) {
+    pgain[r] = R(0);
+    pref[r] = R(0);
+    if constexpr (GEN) {
+      const int p = g + L * r;
+      if (lane_on && p < a.P) {
+        pgain[r] = a.sde[p * kSdeCols + SDE_GAIN];
+        pref[r] = a.sde[p * kSdeCols + SDE_REF];
+      }
+    }
+  }
   // my processes p = g + L r
   R theta[PQ], sigma[PQ];
   bool own[PQ];
@@ -648,9 +665,21 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
       ds[q] = c0[q] * sd - s0[q] * omc;
       xch[tl][g * G + q] = R2{dc[q], ds[q]};
     }
+    R gk[PQ];  // GEN: the processes' derivatives
 #pragma unroll
-    for (int r = 0; r < PQ; ++r)
-      if (own[r]) xch[tl][NGP + g + L * r] = R2{yx[r], R(0)};
+    for (int r = 0; r < PQ; ++r) {
+      R pub = yx[r];
+      if constexpr (GEN) {
+        // the injected power from registers (it feeds the exchange, on the
+        // stage's critical path); the drift and diffusion rows load behind it
+        // (rows past P are zero; a lane that owns no process reads row 0)
+        const int p = g + L * r;
+        R inj;
+        gk[r] = sde_rhs<R>(a.sde + (own[r] ? p : 0) * kSdeCols, yx[r], wv[r], inj);
+        pub = pgain[r] * (yx[r] - pref[r]);
+      }
+      if (own[r]) xch[tl][NGP + g + L * r] = R2{pub, R(0)};
+    }
     wave_lds_sync();
     // two accumulator pairs (even / odd columns) halve the FMA dependency chains
     R ir[G], ii[G], jr[G], ji[G];
@@ -700,7 +729,12 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
       kw[q] = F * inv2h[q];
     }
 #pragma unroll
-    for (int r = 0; r < PQ; ++r) kx[r] = -theta[r] * yx[r] + sigma[r] * wv[r];
+    for (int r = 0; r < PQ; ++r) {
+      if constexpr (GEN)
+        kx[r] = own[r] ? gk[r] : R(0);
+      else
+        kx[r] = -theta[r] * yx[r] + sigma[r] * wv[r];
+    }
   };
 
   // RRF sum of trajectory tid of this tile (threads tid < TB; see IntegArgs::rrf_w)
@@ -931,6 +965,18 @@ k_rk4_group(IntegArgs<R> a) {
   __shared__ __attribute__((aligned(16))) unsigned char lds[Sh::lds_bytes];
   GroupStats st{reinterpret_cast<double2*>(a.partial) + (int64_t)blockIdx.x * (a.S + 1) * a.V, 0};
   group_run<R, NG, PM, L, WPB, D>(a, blockIdx.x, lds, st, true);
+}
+
+// The same for general Ito processes (IntegArgs::sde), instantiated in their
+// own translation units.
+template <typename R, int NG, int PM, int L, int WPB>
+__global__ void __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(FMC_GROUP_MIN_WAVES)))
+k_rk4_group_gen(IntegArgs<R> a) {
+  constexpr int D = WPB == 1 ? 4 : 8;
+  using Sh = GroupShape<R, NG, PM, L, WPB, D>;
+  __shared__ __attribute__((aligned(16))) unsigned char lds[Sh::lds_bytes];
+  GroupStats st{reinterpret_cast<double2*>(a.partial) + (int64_t)blockIdx.x * (a.S + 1) * a.V, 0};
+  group_run<R, NG, PM, L, WPB, D, true>(a, blockIdx.x, lds, st, true);
 }
 
 }  // namespace fmc
