@@ -811,10 +811,15 @@ def kle_leg(ctx, fmc, reps: int, copy_check: bool = False):
                  "hbm_frac": (zb + wb) / t / PEAK_HBM}
             if prec == "bf16x3":
                 r["mfma_frac"] = 3 * flops / t / PEAK_MFMA_BF16
+                # fmc_run splits the design once per run and only the basis
+                # per chunk; this call splits both (the kernel trace under
+                # profiles/ separates the split from the contraction)
+                r["includes_design_split"] = True
             else:
                 r["mfma_frac"] = flops / t / PEAK_MFMA_FP64
             out[f"{name}_{prec}"] = r
-            say(f"kle {name} {prec}: {t * 1e6:.1f} us, {flops / t / 1e12:.1f} TFLOP/s")
+            note = " (with the hi/lo split of the design)" if prec == "bf16x3" else ""
+            say(f"kle {name} {prec}{note}: {t * 1e6:.1f} us, {flops / t / 1e12:.1f} TFLOP/s")
         del z, phi, w
     if copy_check:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
