@@ -119,6 +119,40 @@ def config1_leg(ctx, fmc, workloads, oracle_mod, steps: int):
     return res
 
 
+def general_leg(ctx, fmc, workloads, oracle_mod, steps: int):
+    """General Ito disturbances on the 10-machine workload (N = 1e4, K = 100,
+    4000 steps): Table I's Beta and Gamma rows and the wind model of eq. 11 in
+    place of the OU processes, FP64 and FP32 on the variant tuned for the
+    shape, with the error of sampled trajectories against the FP64 oracle."""
+    import numpy as np
+    import torch
+    sc = workloads.config2_general()
+    N, S = sc["N"], fmc.steps(sc)
+    sel = np.array([0, 1, N // 2, N - 1])
+    ot = oracle_mod.run(sc, sel=sel, want_traj=True)["traj"] if oracle_mod is not None else None
+    out = {"workload": "10-machine system, N=1e4, K=100, T=20 s, dt=5 ms; Beta (a=6, b=9), Gamma "
+                       "(a=4, b=20) and eq. 11 wind processes (Ito reading)",
+           "trajectory_steps": N * S}
+    for form in ("f64", "f32"):
+        r = ctx.run(sc, precision=form)
+        outs = dict(mean=r["mean"], var=r["var"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = ctx.run(sc, precision=form, outputs=outs)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        res = {"ms_per_pass": t * 1e3, "trajectory_steps_per_s": N * S / t,
+               "variant": r["report"]["variant_id"],
+               "lanes_per_traj": r["report"]["lanes_per_traj"]}
+        if ot is not None:
+            rt = ctx.run(sc, precision=form, traj_idx=sel)["traj"].cpu().numpy()
+            res["error_vs_oracle"] = per_output(None, None, rt, None, None, ot)
+        out[form] = res
+        say(f"general processes {form}: {t * 1e3:.2f} ms per pass, {N * S / t:.3e} traj-steps/s")
+    return out
+
+
 def config3_leg(ctx, fmc, workloads, oracle_mod, steps: int):
     """The mixed-precision workload (the 10-machine system with N = 1e5, LHS
     seed 3): every form timed over whole passes; error against the FP64 oracle
@@ -919,6 +953,8 @@ def main():
                          "(the plain reference; about 90 s)")
     ap.add_argument("--c1", type=int, default=1,
                     help="run the single-machine FP64 leg (1) or not (0)")
+    ap.add_argument("--gen-steps", type=int, default=2,
+                    help="timed passes of the general-Ito-process workload (0: skip)")
     ap.add_argument("--c3-steps", type=int, default=2,
                     help="timed passes of the N=1e5 mixed-precision workload (0: skip)")
     ap.add_argument("--kle-reps", type=int, default=20,
@@ -1047,6 +1083,9 @@ def main():
     c1 = config1_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), 10) \
         if args.c1 else None
 
+    gen = general_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), args.gen_steps) \
+        if args.gen_steps > 0 else None
+
     c3 = None
     if args.c3_steps > 0:
         c3 = config3_leg(ctx, fmc, workloads, None if args.no_cpu else oracle_mod(), args.c3_steps)
@@ -1130,6 +1169,7 @@ def main():
         "forms": forms_out,
         "smib_N1e3": c1,
         "mixed_precision_N1e5": c3,
+        "general_processes": gen,
         "kle_contraction": kle,
         "batched": batched,
         "served": served,

@@ -46,11 +46,29 @@ static const std::vector<VariantInfo>& lane_table() {
 int n_variants() { return (int)lane_table().size(); }
 const VariantInfo& variant(int i) { return lane_table()[i]; }
 
-// Cost model used when no tuned choice is cached: per-step work of one
-// workgroup-wave times the number of waves that run back to back on the busiest
-// SIMD (1024 SIMDs, occupancy ignored), plus a padding penalty.
+// Choice used when no tuned one is cached.  A lanes-per-trajectory variant
+// with one machine per lane (L >= NG >= n) and at most as many padding
+// machines as real ones comes first: the fewest padding machines, then four
+// waves per workgroup (measured on the 10-machine
+// workload at N = 1e4: L = 10 x 4 waves 9.9 ms per FP64 pass, the other
+// L = 10 shapes 12.3-12.7, L = 16 17-23, two machines per lane 11.9, one
+// trajectory per lane 102).  Otherwise a cost model: per-step work of one
+// workgroup-wave times the number of waves that run back to back on the
+// busiest SIMD (1024 SIMDs, occupancy ignored), plus a padding penalty.
 int choose_variant(int n, int P, int64_t N) {
   int best = -1;
+  for (const auto& v : lane_table()) {
+    if (v.L == 1 || v.G() != 1 || v.NG < n || v.NG > 2 * n || v.PM < std::max(P, 1)) continue;
+    if (best < 0) {
+      best = v.id;
+      continue;
+    }
+    const VariantInfo& b = lane_table()[best];
+    const bool better = v.NG < b.NG || (v.NG == b.NG && v.L < b.L) ||
+                        (v.NG == b.NG && v.L == b.L && v.WPB == 4 && b.WPB != 4);
+    if (better) best = v.id;
+  }
+  if (best >= 0) return best;
   double best_cost = 0.0;
   for (const auto& v : lane_table()) {
     if (v.NG < n || v.PM < std::max(P, 1)) continue;

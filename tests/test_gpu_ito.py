@@ -71,11 +71,7 @@ def test_smib_processes_fp64(ctx, name, make):
 def mixed_10gen(N=200, T=2.0, K=20, **kw):
     """The 10-machine system with a Beta, a Gamma and the wind process (each
     starting at its reference, so t = 0 is the operating point)."""
-    sc = workloads.config2(N=N, K=K, T=T, **kw)
-    specs = [dict(kind="beta", a=6.0, b=9.0, theta=0.5, gain=2.0, ref=0.4),
-             dict(kind="gamma", a=4.0, b=20.0, theta=1.0, gain=3.0, ref=0.2),
-             dict(kind="poly", mu=workloads.WIND_MU, sg=workloads.WIND_SIGMA, gain=5.0, ref=0.85)]
-    return workloads.with_processes(sc, specs, xi0=[0.4, 0.2, 0.85])
+    return workloads.config2_general(N=N, K=K, T=T, **kw)
 
 
 def test_multimachine_mixed_processes_fp64(ctx):

@@ -247,6 +247,17 @@ def config2(**kw):
     return multimachine(**d)
 
 
+def config2_general(**kw):
+    """The 10-machine system with Table I's Beta and Gamma rows and the wind
+    model of eq. 11 in place of its three OU processes (each starting at its
+    reference, so t = 0 is the operating point)."""
+    sc = config2(**kw)
+    specs = [dict(kind="beta", a=6.0, b=9.0, theta=0.5, gain=2.0, ref=0.4),
+             dict(kind="gamma", a=4.0, b=20.0, theta=1.0, gain=3.0, ref=0.2),
+             dict(kind="poly", mu=WIND_MU, sg=WIND_SIGMA, gain=5.0, ref=0.85)]
+    return with_processes(sc, specs, xi0=[0.4, 0.2, 0.85])
+
+
 def config3(**kw):
     """The 10-machine system with N = 1e5 (mixed-precision workload), seed 3."""
     d = dict(N=100_000, seed=3)
