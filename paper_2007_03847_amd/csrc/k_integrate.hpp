@@ -564,7 +564,8 @@ struct GroupStats {
 // process's exchange slot (where the OU form publishes xi itself).
 template <typename R, int NG, int PM, int L, int WPB, int D, bool GEN = false>
 __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
-                                          unsigned char* lds, GroupStats st, bool keep_state) {
+                                          unsigned char* lds, GroupStats st, bool keep_state,
+                                          const R* sde_rows = nullptr) {
   using Sh = GroupShape<R, NG, PM, L, WPB, D>;
   using R2 = typename Sh::R2;
   constexpr PackLayout Lp{NG, PM};
@@ -675,7 +676,7 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
         // (rows past P are zero; a lane that owns no process reads row 0)
         const int p = g + L * r;
         R inj;
-        gk[r] = sde_rhs<R>(a.sde + (own[r] ? p : 0) * kSdeCols, yx[r], wv[r], inj);
+        gk[r] = sde_rhs<R>(sde_rows + (own[r] ? p : 0) * kSdeCols, yx[r], wv[r], inj);
         pub = pgain[r] * (yx[r] - pref[r]);
       }
       if (own[r]) xch[tl][NGP + g + L * r] = R2{pub, R(0)};
@@ -975,8 +976,13 @@ k_rk4_group_gen(IntegArgs<R> a) {
   constexpr int D = WPB == 1 ? 4 : 8;
   using Sh = GroupShape<R, NG, PM, L, WPB, D>;
   __shared__ __attribute__((aligned(16))) unsigned char lds[Sh::lds_bytes];
+  // the processes' rows (PM of them, zero past P) staged in LDS once: they
+  // are read by the owner lanes at every stage
+  __shared__ R sde_l[PM * kSdeCols];
+  for (int i = threadIdx.x; i < PM * kSdeCols; i += 64 * WPB) sde_l[i] = a.sde[i];
+  __syncthreads();
   GroupStats st{reinterpret_cast<double2*>(a.partial) + (int64_t)blockIdx.x * (a.S + 1) * a.V, 0};
-  group_run<R, NG, PM, L, WPB, D, true>(a, blockIdx.x, lds, st, true);
+  group_run<R, NG, PM, L, WPB, D, true>(a, blockIdx.x, lds, st, true, sde_l);
 }
 
 }  // namespace fmc
