@@ -208,8 +208,8 @@ int n_variants();
 const VariantInfo& variant(int i);
 hipError_t launch_integrate_f64(int variant_id, const IntegArgs<double>& a, int64_t n_groups,
                                 hipStream_t st);
-// General Ito processes (IntegArgs::sde set): the one-trajectory-per-lane
-// variants, compiled separately.
+// General Ito processes (IntegArgs::sde set): every variant, compiled
+// separately.
 hipError_t launch_integrate_gen_f64(int variant_id, const IntegArgs<double>& a, int64_t n_groups,
                                     hipStream_t st);
 hipError_t launch_integrate_gen_f32(int variant_id, const IntegArgs<float>& a, int64_t n_groups,

@@ -672,8 +672,9 @@ __device__ __forceinline__ void group_run(const IntegArgs<R>& a, int64_t tile,
       R pub = yx[r];
       if constexpr (GEN) {
         // the injected power from registers (it feeds the exchange, on the
-        // stage's critical path); the drift and diffusion rows load behind it
-        // (rows past P are zero; a lane that owns no process reads row 0)
+        // stage's critical path); the drift and diffusion come from the rows
+        // staged in LDS (rows past P are zero; a lane that owns no process
+        // reads row 0)
         const int p = g + L * r;
         R inj;
         gk[r] = sde_rhs<R>(sde_rows + (own[r] ? p : 0) * kSdeCols, yx[r], wv[r], inj);
